@@ -1,0 +1,82 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the oracle's timing leg.
+
+Nothing here computes any part of the method: it only draws points of the integration domain
+(loop momenta in the ball |q| <= R, imaginary times in [0, beta)), external momenta, VEGAS
+grids and histograms with the shapes and value ranges of the workloads, from numpy's
+seeded PCG64 stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+R_BALL = 6.0
+BETA = 25.0
+
+
+def dim(n: int) -> int:
+    """Integration dimension 3n + (n - 1): n loop momenta, n - 1 free interaction times."""
+    return 4 * n - 1
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def loop_points(n: int, N: int, seed: int, R: float = R_BALL, beta: float = BETA,
+                fermi_fraction: float = 0.25, special: bool = True) -> np.ndarray:
+    """x[N, D] float32: momenta Cartesian (r uniform in [0, R], direction uniform on the sphere),
+    a fraction of them placed within 0.05 of the Fermi surface |q| = 1, and times uniform in
+    [0, beta).  With `special`, the first rows hold edge cases: q = 0, equal times on two lines,
+    a time at exactly 0 and times at the top of the range."""
+    g = rng(seed)
+    D = dim(n)
+    x = np.empty((N, D), dtype=np.float64)
+    for i in range(n):
+        r = R * g.random(N)
+        near = g.random(N) < fermi_fraction
+        r[near] = 1.0 + 0.1 * (g.random(near.sum()) - 0.5)
+        c = 2.0 * g.random(N) - 1.0
+        s = np.sqrt(1.0 - c * c)
+        ph = 2.0 * np.pi * g.random(N)
+        x[:, 3 * i] = r * s * np.cos(ph)
+        x[:, 3 * i + 1] = r * s * np.sin(ph)
+        x[:, 3 * i + 2] = r * c
+    x[:, 3 * n:] = beta * g.random((N, n - 1))
+    x = x.astype(np.float32)
+    if special and N >= 8:
+        x[0, 0:3] = 0.0                     # a loop momentum at the origin
+        if n >= 2:
+            x[1, 3 * n] = 0.0               # tau_1 exactly at the in-vertex time
+            x[2, 3 * n] = np.float32(beta) * np.float32(0.999999)
+        if n >= 3:
+            x[3, 3 * n + 1] = x[3, 3 * n]   # two lines at the same time
+        x[4, 0:3] = np.array([0.0, 0.0, 1.0], dtype=np.float32)   # on the Fermi surface
+    return x
+
+
+def k_grid(K: int, kmax: float = 3.0) -> np.ndarray:
+    """K external momenta evenly in [0, kmax] (both ends included), float32."""
+    return np.linspace(0.0, kmax, K).astype(np.float32)
+
+
+def vegas_grid(D: int, B: int, seed: int, jitter: float = 0.8) -> np.ndarray:
+    """A non-uniform, strictly increasing grid of B bins per dimension: edges[D, B+1] float32
+    with edges[:, 0] = 0 and edges[:, B] = 1."""
+    g = rng(seed)
+    w = 1.0 + jitter * (g.random((D, B)) * 2 - 1)
+    w = w / w.sum(axis=1, keepdims=True)
+    e = np.zeros((D, B + 1))
+    e[:, 1:] = np.cumsum(w, axis=1)
+    e[:, B] = 1.0
+    return e.astype(np.float32)
+
+
+def histogram(D: int, B: int, seed: int) -> np.ndarray:
+    """A positive per-bin importance histogram [D, B] float64 with a peaked profile."""
+    g = rng(seed)
+    xb = (np.arange(B) + 0.5) / B
+    h = np.empty((D, B))
+    for d in range(D):
+        c = g.random()
+        h[d] = np.exp(-((xb - c) ** 2) / (2 * 0.05 ** 2)) + 0.01 + 0.01 * g.random(B)
+    return h
