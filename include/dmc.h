@@ -1,0 +1,160 @@
+/* dmc.h -- C ABI of the MI355X diagrammatic Monte Carlo hot path.
+ *
+ * What the library computes (paper: "An AI-powered Technology Stack for Solving Many-Electron
+ * Field Theory", arXiv:2403.18840):
+ *   Sigma^(n)(k, i w_0) = int dV sum_t W_t^(n)(V) e^{i w_0 tau_out}      (eq. sigma_integration)
+ * for the 3D uniform electron gas (eq. ueg_action) with the Yukawa interaction of
+ * eq. interaction_ct, at the lowest fermionic Matsubara frequency w_0 = pi / beta, estimated by
+ * importance sampling (eq. nf_mcmc_estimator_qft_final_revised with alpha = 1) under a VEGAS map
+ * (Sec. IV) or a learned flow (eq. NFtransform, eq. coupling_layer).  Units: k_F = E_F = 1,
+ * eps_k = k^2 - mu, V(q) = 8 pi gamma / (q^2 + lambda), gamma = alpha r_s.
+ *
+ * Conventions for every call:
+ *  - Every call returns dmc_status; DMC_OK is 0.  On error nothing is enqueued and no handle is
+ *    changed; dmc_last_error() returns a thread-local message for the last failing call.
+ *  - Handles are library-owned (create / destroy pairs).  They are not thread-safe; distinct
+ *    handles are independent.
+ *  - Pointers documented "device" are caller-owned device memory of the current HIP device;
+ *    pointers documented "host" are caller-owned host memory read during the call only.
+ *  - Device work is enqueued on `stream` (a hipStream_t passed as void*; NULL = default stream).
+ *    Only dmc_estimate, dmc_sampler_refine and the *_read calls synchronise that stream.
+ *  - Sample layout is structure-of-arrays: x[d * ld + i] is coordinate d of sample i, with
+ *    ld >= n.  For order n the dimension is D = 4n - 1: loop momenta q_0..q_{n-1} as Cartesian
+ *    triples (coordinates 0..3n-1), then the times tau_1..tau_{n-1} of interaction lines
+ *    1..n-1 (line 0 sits at tau = 0).  External momenta point along z.
+ */
+#ifndef DMC_H
+#define DMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMC_OK = 0,
+    DMC_E_INVALID = -1, /* bad argument: null pointer, size out of range, inconsistent instances */
+    DMC_E_NOMEM = -2,   /* a host or device allocation failed */
+    DMC_E_DEVICE = -3,  /* a HIP runtime call failed; the HIP error string is in dmc_last_error */
+    DMC_E_COMPILE = -4, /* run-time compilation of a graph kernel failed; the log is in dmc_last_error */
+    DMC_E_STATE = -5,   /* call out of order (e.g. a second eval_batch before accumulate) */
+    DMC_E_NUMERIC = -6  /* estimate: some sample weights were non-finite and were dropped */
+} dmc_status;
+
+enum { DMC_MAX_ORDER = 6, DMC_MAX_K = 64, DMC_MAX_GROUPS = 8, DMC_MAX_INSTANCES = 64 };
+
+/* Derivative roots (deriv_mask bits): d/dmu (chemical potential), d/dlambda (screening),
+ * d/dk (external momentum), each the (m, l) = (1, 0), (0, 1) coefficient of
+ * eq. sigma_xi_dmu_dlambda or the momentum derivative of eq. deltam_partitions. */
+enum { DMC_D_MU = 1, DMC_D_LAMBDA = 2, DMC_D_K = 4 };
+
+typedef struct dmc_graph dmc_graph;
+typedef struct dmc_sampler dmc_sampler;
+typedef struct dmc_accum dmc_accum;
+
+typedef struct {
+    int32_t order;         /* n interaction lines, 1..DMC_MAX_ORDER */
+    uint32_t deriv_mask;   /* derivative roots to build; 0 = value only */
+    int32_t diagram_index; /* -1 = all diagrams; otherwise only diagram #i of the exported list */
+    int32_t reserved;      /* must be 0 */
+} dmc_graph_spec;
+
+typedef struct {
+    int32_t order, dim, n_diagrams, n_root_classes;
+    int32_t n_momenta, n_g_leaves, n_v_leaves, n_groups;
+    /* operation counts of the emitted code per sample: [0] add, [1] mul, [2] fma, [3] transcendental.
+     * ops_sample: once per sample (k-independent part, per lambda group already multiplied in at
+     * evaluation); ops_k: once per (sample, k) for one lambda group; ops_naive: the plain sum of
+     * products over diagrams per (sample, k) before hoisting and common-subexpression elimination. */
+    int64_t ops_sample[4];
+    int64_t ops_k[4];
+    int64_t ops_naive[4];
+} dmc_graph_info;
+
+/* One physical instance: all instances in one eval_batch share beta and mu; instances that
+ * share lambda are evaluated once and differ only by the factor (gamma / gamma_group)^n. */
+typedef struct {
+    double beta, mu, lambda, gamma;
+} dmc_instance;
+
+const char* dmc_last_error(void);
+const char* dmc_version(void);
+
+/* ---- graph (Sec. II: diagrams as a computational graph; Sec. V.A: front end / IR / back end) ----
+ * Enumerates all connected, one-particle-irreducible self-energy diagrams of the given order
+ * with no zero-momentum interaction line (Hartree tadpoles vanish by q != 0 in eq. ueg_action),
+ * weight (-1)^(n+F) 2^F, routes their momenta, builds the leaf-deduplicated graph, hoists the
+ * k- and lambda-independent part and removes repeated products.  Host only; the device code is
+ * compiled lazily at the first evaluation.  *out is library-owned: free with dmc_graph_destroy. */
+dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out);
+dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* out);
+/* Text export of the diagram list, one diagram per line:
+ *   "<sigma_0> ... <sigma_{2n-1}> | w <weight> | ext <line> | G src dst c_0..c_{n-1} c_k ; ... | V ..."
+ * buf may be NULL to query the length; *len receives the byte count without the final NUL. */
+dmc_status dmc_graph_export_diagrams(const dmc_graph* g, char* buf, size_t cap, size_t* len);
+/* Generated device source for the given number of lambda groups (for inspection). */
+dmc_status dmc_graph_source(const dmc_graph* g, int32_t n_groups, char* buf, size_t cap, size_t* len);
+void dmc_graph_destroy(dmc_graph* g);
+
+/* ---- accumulator (FP64 running sums; the only FP64 arithmetic on the device) ----
+ * Holds, per (lambda group, k, Re/Im, root), sum w and sum w^2 in FP64 plus the sample count
+ * and the count of non-finite weights.  n_roots = 1 + popcount(deriv_mask) of the graph used. */
+dmc_status dmc_accum_create(int32_t n_groups, int32_t n_k, int32_t n_roots, dmc_accum** out);
+dmc_status dmc_accum_reset(dmc_accum* acc, void* stream);
+void dmc_accum_destroy(dmc_accum* acc);
+
+/* ---- sampler (Sec. IV: VEGAS map; Appendix A: flow) ----
+ * kind DMC_SAMPLER_UNIFORM: unit-cube uniforms through the physical map;
+ * kind DMC_SAMPLER_VEGAS: uniforms through a per-dimension grid of n_bins bins, then the map.
+ * Physical map: r = R y, cos(theta) = 2y - 1, phi = 2 pi y per loop, tau_j = beta y; Jacobian
+ * prod_i 4 pi R r_i^2 * beta^(n-1) times the grid Jacobian. */
+enum { DMC_SAMPLER_UNIFORM = 0, DMC_SAMPLER_VEGAS = 1 };
+dmc_status dmc_sampler_create(int32_t kind, int32_t order, int32_t n_bins, double beta, double qmax,
+                              dmc_sampler** out);
+/* Draw samples first_index .. first_index + n - 1 of the Philox4x32-10 stream `seed`
+ * (counter (i mod 2^32, i div 2^32, d div 4, 0), key (seed mod 2^32, seed div 2^32)).
+ * x: device float[D][ld]; jac: device float[n]. */
+dmc_status dmc_sample(dmc_sampler* s, uint64_t seed, uint64_t first_index, int64_t n, float* x, int64_t ld,
+                      float* jac, void* stream);
+/* Grid edges, host double[D][n_bins + 1]: read or replace (edges must rise from 0 to 1). */
+dmc_status dmc_sampler_get_grid(const dmc_sampler* s, double* edges);
+dmc_status dmc_sampler_set_grid(dmc_sampler* s, const double* edges, void* stream);
+/* One VEGAS refinement from the histogram gathered by dmc_accumulate since the last refine
+ * (smoothing, compression with exponent alpha, equal-weight re-gridding; Lepage 1978).
+ * Synchronises `stream`.  Clears the histogram. */
+dmc_status dmc_sampler_refine(dmc_sampler* s, double alpha, void* stream);
+dmc_status dmc_sampler_read_histogram(dmc_sampler* s, double* hist /* host [D][n_bins] */, void* stream);
+void dmc_sampler_destroy(dmc_sampler* s);
+
+/* ---- evaluation (the hot kernel) ----
+ * For each sample i < n and each external k_ext[j] (host float[n_k]) evaluates the compiled
+ * graph, forms w = f(x_i) J_i for every instance group and Re/Im part, and writes per-block FP64
+ * partial sums into `acc` (folded by dmc_accumulate).  Instances: host array of n_inst; all must
+ * share beta and mu.
+ * f_out (nullable): device float[n_groups][n_roots][n_k][2][n]: the integrand f without J.
+ * imp_out (nullable): device float[n]: sum over groups, k, Re/Im of |w|, for VEGAS adaptation. */
+dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
+                          const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
+                          float* imp_out, void* stream);
+
+/* Fold the block partials of the last dmc_eval_batch into the running sums in a fixed order.
+ * If sampler is not NULL, also add sum over samples in each (dimension, bin) of imp^2 to the
+ * sampler's VEGAS histogram; imp is the imp_out buffer of that eval_batch, and the samples must be
+ * the sampler's last dmc_sample call (the bins are recomputed from the Philox counters). */
+dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* sampler, const float* imp, void* stream);
+
+/* Mean and standard error of the mean per instance, root, k and Re/Im:
+ * mean, stderr_: host double[n_inst][n_roots][n_k][2].  n_nonfinite: host (nullable).  Uses the
+ * instances of the last eval_batch.  Synchronises `stream`.  Returns DMC_E_NUMERIC (with valid
+ * finite-sample estimates) when non-finite weights were dropped. */
+dmc_status dmc_estimate(dmc_accum* acc, double* mean, double* stderr_, int64_t* n_samples, int64_t* n_nonfinite,
+                        void* stream);
+/* Raw FP64 sums: host double[n_groups][n_roots][n_k][2][2] as (sum w, sum w^2). */
+dmc_status dmc_accum_read(dmc_accum* acc, double* sums, int64_t* n_samples, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMC_H */

@@ -1,0 +1,273 @@
+"""Python binding of the dmc C ABI (include/dmc.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; torch is used for device memory
+and streams.  Importing this module does not need a GPU; calls that launch kernels do, and they
+fail loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmc.so")
+
+DMC_OK = 0
+STATUS = {0: "DMC_OK", -1: "DMC_E_INVALID", -2: "DMC_E_NOMEM", -3: "DMC_E_DEVICE", -4: "DMC_E_COMPILE",
+          -5: "DMC_E_STATE", -6: "DMC_E_NUMERIC"}
+D_MU, D_LAMBDA, D_K = 1, 2, 4
+SAMPLER_UNIFORM, SAMPLER_VEGAS = 0, 1
+
+# every symbol include/dmc.h declares
+ABI_SYMBOLS = [
+    "dmc_last_error", "dmc_version", "dmc_compile_graph", "dmc_graph_query", "dmc_graph_export_diagrams",
+    "dmc_graph_source", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
+    "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
+    "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
+    "dmc_accum_read",
+]
+
+
+class DmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GraphSpec(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("deriv_mask", ctypes.c_uint32), ("diagram_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_diagrams", ctypes.c_int32),
+                ("n_root_classes", ctypes.c_int32), ("n_momenta", ctypes.c_int32), ("n_g_leaves", ctypes.c_int32),
+                ("n_v_leaves", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("ops_sample", ctypes.c_int64 * 4),
+                ("ops_k", ctypes.c_int64 * 4), ("ops_naive", ctypes.c_int64 * 4)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+U64 = ctypes.c_uint64
+F64 = ctypes.c_double
+
+
+def lib():
+    """Load libdmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime with the same soname; load it first so that the library
+    # binds to that one runtime instead of bringing a second one into the process
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "dmc_last_error": (ctypes.c_char_p, []),
+        "dmc_version": (ctypes.c_char_p, []),
+        "dmc_compile_graph": (I32, [ctypes.POINTER(GraphSpec), ctypes.POINTER(P)]),
+        "dmc_graph_query": (I32, [P, ctypes.POINTER(GraphInfo)]),
+        "dmc_graph_export_diagrams": (I32, [P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "dmc_graph_source": (I32, [P, I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "dmc_graph_destroy": (None, [P]),
+        "dmc_accum_create": (I32, [I32, I32, I32, ctypes.POINTER(P)]),
+        "dmc_accum_reset": (I32, [P, P]),
+        "dmc_accum_destroy": (None, [P]),
+        "dmc_sampler_create": (I32, [I32, I32, I32, F64, F64, ctypes.POINTER(P)]),
+        "dmc_sample": (I32, [P, U64, U64, I64, P, I64, P, P]),
+        "dmc_sampler_get_grid": (I32, [P, P]),
+        "dmc_sampler_set_grid": (I32, [P, P, P]),
+        "dmc_sampler_refine": (I32, [P, F64, P]),
+        "dmc_sampler_read_histogram": (I32, [P, P, P]),
+        "dmc_sampler_destroy": (None, [P]),
+        "dmc_eval_batch": (I32, [P, P, I32, P, I32, P, I64, P, I64, P, P, P, P]),
+        "dmc_accumulate": (I32, [P, P, P, P]),
+        "dmc_estimate": (I32, [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
+        "dmc_accum_read": (I32, [P, P, ctypes.POINTER(I64), P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st, allow=()):
+    if st != DMC_OK and st not in allow:
+        raise DmcError(st, lib().dmc_last_error().decode())
+    return st
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype_name, what):
+    """Device pointer of a contiguous CUDA tensor of the given dtype (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError(f"{what} must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def dim(order: int) -> int:
+    return 4 * order - 1
+
+
+class Graph:
+    """A compiled diagram graph (dmc_compile_graph)."""
+
+    def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1):
+        self.h = P()
+        spec = GraphSpec(order, deriv_mask, diagram_index, 0)
+        _check(lib().dmc_compile_graph(ctypes.byref(spec), ctypes.byref(self.h)))
+        self.order = order
+        self.deriv_mask = deriv_mask
+        self.n_roots = 1 + bin(deriv_mask).count("1")
+
+    def info(self) -> GraphInfo:
+        gi = GraphInfo()
+        _check(lib().dmc_graph_query(self.h, ctypes.byref(gi)))
+        return gi
+
+    def _text(self, fn, *pre):
+        n = ctypes.c_size_t()
+        _check(fn(self.h, *pre, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(fn(self.h, *pre, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def export(self) -> str:
+        return self._text(lib().dmc_graph_export_diagrams)
+
+    def source(self, n_groups: int = 1) -> str:
+        return self._text(lib().dmc_graph_source, I32(n_groups))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dmc_graph_destroy(self.h)
+            self.h = None
+
+
+class Accumulator:
+    """FP64 running sums (dmc_accum_*)."""
+
+    def __init__(self, n_groups: int, n_k: int, n_roots: int = 1):
+        self.h = P()
+        _check(lib().dmc_accum_create(n_groups, n_k, n_roots, ctypes.byref(self.h)))
+        self.n_groups, self.n_k, self.n_roots = n_groups, n_k, n_roots
+
+    def reset(self, stream=None):
+        _check(lib().dmc_accum_reset(self.h, _stream(stream)))
+
+    def read(self, stream=None):
+        import numpy as np
+        out = np.zeros((self.n_groups, self.n_roots, self.n_k, 2, 2), dtype=np.float64)
+        n = I64()
+        _check(lib().dmc_accum_read(self.h, out.ctypes.data_as(P), ctypes.byref(n), _stream(stream)))
+        return out, n.value
+
+    def estimate(self, n_inst: int, stream=None):
+        """(mean, stderr) as complex arrays [n_inst][n_roots][n_k], plus (n_samples, n_nonfinite)."""
+        import numpy as np
+        m = np.zeros((n_inst, self.n_roots, self.n_k, 2))
+        e = np.zeros_like(m)
+        ns, nf = I64(), I64()
+        _check(lib().dmc_estimate(self.h, m.ctypes.data_as(P), e.ctypes.data_as(P), ctypes.byref(ns),
+                                  ctypes.byref(nf), _stream(stream)), allow=(-6,))
+        return m[..., 0] + 1j * m[..., 1], e[..., 0] + 1j * e[..., 1], ns.value, nf.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dmc_accum_destroy(self.h)
+            self.h = None
+
+
+class Sampler:
+    """Philox4x32-10 sampler through a VEGAS grid (or uniform) and the physical map."""
+
+    def __init__(self, kind: int, order: int, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0):
+        self.h = P()
+        _check(lib().dmc_sampler_create(kind, order, n_bins, beta, qmax, ctypes.byref(self.h)))
+        self.kind, self.order, self.dim = kind, order, dim(order)
+        self.n_bins = n_bins if kind == SAMPLER_VEGAS else 1
+
+    def sample(self, seed: int, first: int, x, jac, stream=None):
+        n = jac.numel()
+        ld = x.shape[1]
+        if x.dim() != 2 or x.shape[0] != self.dim:
+            raise ValueError(f"x must be [{self.dim}, ld]")
+        _check(lib().dmc_sample(self.h, seed, first, n, _dptr(x, "float32", "x"), ld, _dptr(jac, "float32", "jac"),
+                                _stream(stream)))
+
+    def grid(self):
+        import numpy as np
+        e = np.zeros((self.dim, self.n_bins + 1))
+        _check(lib().dmc_sampler_get_grid(self.h, e.ctypes.data_as(P)))
+        return e
+
+    def set_grid(self, edges, stream=None):
+        import numpy as np
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        _check(lib().dmc_sampler_set_grid(self.h, e.ctypes.data_as(P), _stream(stream)))
+
+    def refine(self, alpha: float = 0.5, stream=None):
+        _check(lib().dmc_sampler_refine(self.h, alpha, _stream(stream)))
+
+    def histogram(self, stream=None):
+        import numpy as np
+        h = np.zeros((self.dim, self.n_bins))
+        _check(lib().dmc_sampler_read_histogram(self.h, h.ctypes.data_as(P), _stream(stream)))
+        return h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dmc_sampler_destroy(self.h)
+            self.h = None
+
+
+def instances(params):
+    """params: iterable of (beta, mu, lambda, gamma) -> ctypes array of dmc_instance."""
+    params = list(params)
+    arr = (Instance * len(params))(*[Instance(*p) for p in params])
+    return arr
+
+
+def eval_batch(graph: Graph, inst, k_ext, x, jac, acc: Accumulator, f_out=None, imp_out=None, stream=None):
+    """dmc_eval_batch: inst is a list of (beta, mu, lambda, gamma); k_ext host floats."""
+    import numpy as np
+    arr = instances(inst)
+    k = np.ascontiguousarray(k_ext, dtype=np.float32)
+    n = jac.numel()
+    if x.dim() != 2:
+        raise ValueError("x must be [D, ld]")
+    _check(lib().dmc_eval_batch(graph.h, arr, len(arr), k.ctypes.data_as(P), len(k), _dptr(x, "float32", "x"),
+                                x.shape[1], _dptr(jac, "float32", "jac"), n, acc.h,
+                                _dptr(f_out, "float32", "f_out"), _dptr(imp_out, "float32", "imp_out"),
+                                _stream(stream)))
+
+
+def accumulate(acc: Accumulator, sampler: Sampler | None = None, imp=None, stream=None):
+    _check(lib().dmc_accumulate(acc.h, sampler.h if sampler is not None else None,
+                                _dptr(imp, "float32", "imp"), _stream(stream)))

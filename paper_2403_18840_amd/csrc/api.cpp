@@ -1,0 +1,574 @@
+// C ABI of the library (declared in include/dmc.h): handles, run-time compilation of the graph
+// kernels, launches, the FP64 estimate and the VEGAS grid refinement.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dmc.h"
+#include "graph.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dmc_status fail(dmc_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(DMC_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIP_ALLOC(expr)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation)                             \
+            return fail(DMC_E_NOMEM, std::string(#expr ": ") + hipGetErrorString(e_));               \
+        if (e_ != hipSuccess) return fail(DMC_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+hipStream_t S(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+int cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int max_blocks_per_cu = 1;
+    std::string src;
+};
+
+// the EvalArgs layout the generated kernel declares
+struct EvalArgs {
+    const float* x;
+    long long ld;
+    const float* jac;
+    long long n;
+    double* partial;
+    unsigned int* nonfinite;
+    float* f_out;
+    float* imp_out;
+    int n_k, s_total, pad0, pad1;
+    float mu, beta, bl, blmu, inv2beta, pad2;
+    float lam[8];
+    float scale[8];
+    float k[64];
+};
+
+}  // namespace
+
+struct dmc_graph {
+    dmc::Compiled c;
+    std::map<std::pair<int, int>, JitKernel> jit;  // (device, n_groups)
+    std::string exported;
+};
+
+struct dmc_accum {
+    int n_groups, n_k, n_roots, s_total;
+    double* totals = nullptr;                  // device [s_total][2]
+    unsigned long long* nonfin_tot = nullptr;  // device
+    double* partial = nullptr;                 // device [cap_blocks][s_total][2]
+    unsigned int* nonfin_part = nullptr;       // device [cap_blocks]
+    int cap_blocks = 0;
+    int pending_blocks = 0;
+    int64_t pending_n = 0;
+    int64_t n_samples = 0;
+    // instances of the last eval_batch: group and factor (gamma / gamma_group)^n
+    std::vector<int> inst_group;
+    std::vector<double> inst_factor;
+};
+
+struct dmc_sampler {
+    int kind, order, dim, n_bins;
+    double beta, qmax;
+    std::vector<double> edges;  // host [dim][n_bins + 1]
+    float* d_edges = nullptr;
+    double* d_hist = nullptr;               // [dim][n_bins]
+    unsigned long long* d_hist_u = nullptr;  // [dim][n_bins]
+    unsigned int* d_max = nullptr;
+    uint64_t last_seed = 0, last_first = 0;
+    int64_t last_n = -1;
+};
+
+extern "C" {
+
+const char* dmc_last_error(void) { return g_err.c_str(); }
+const char* dmc_version(void) { return "dmc-mi355x 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------------------ graph
+dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
+    if (!spec || !out) return fail(DMC_E_INVALID, "null argument");
+    if (spec->reserved != 0) return fail(DMC_E_INVALID, "reserved must be 0");
+    auto g = std::make_unique<dmc_graph>();
+    std::string err;
+    try {
+        if (!dmc::compile(spec->order, spec->deriv_mask, spec->diagram_index, g->c, err))
+            return fail(DMC_E_INVALID, err);
+        g->exported = dmc::export_text(g->c);
+    } catch (const std::bad_alloc&) {
+        return fail(DMC_E_NOMEM, "host allocation failed");
+    }
+    *out = g.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
+    if (!g || !o) return fail(DMC_E_INVALID, "null argument");
+    std::memset(o, 0, sizeof(*o));
+    o->order = g->c.order;
+    o->dim = g->c.dim;
+    o->n_diagrams = (int)g->c.diagrams.size();
+    o->n_root_classes = g->c.n_root_classes;
+    for (int i = 0; i < 4; ++i) {
+        o->ops_sample[i] = g->c.stats.sample[i];
+        o->ops_k[i] = g->c.stats.k[i];
+        o->ops_naive[i] = g->c.stats.naive[i];
+    }
+    return DMC_OK;
+}
+
+static dmc_status copy_text(const std::string& t, char* buf, size_t cap, size_t* len) {
+    if (len) *len = t.size();
+    if (!buf) return DMC_OK;
+    if (cap < t.size() + 1) return fail(DMC_E_INVALID, "buffer too small");
+    std::memcpy(buf, t.c_str(), t.size() + 1);
+    return DMC_OK;
+}
+
+dmc_status dmc_graph_export_diagrams(const dmc_graph* g, char* buf, size_t cap, size_t* len) {
+    if (!g) return fail(DMC_E_INVALID, "null graph");
+    return copy_text(g->exported, buf, cap, len);
+}
+
+dmc_status dmc_graph_source(const dmc_graph* g, int32_t n_groups, char* buf, size_t cap, size_t* len) {
+    if (!g || n_groups < 1 || n_groups > DMC_MAX_GROUPS) return fail(DMC_E_INVALID, "bad graph or n_groups");
+    return copy_text(dmc::emit_eval_source(g->c, n_groups, nullptr), buf, cap, len);
+}
+
+void dmc_graph_destroy(dmc_graph* g) {
+    if (!g) return;
+    for (auto& kv : g->jit)
+        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+    delete g;
+}
+
+static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto key = std::make_pair(dev, n_groups);
+    auto it = g->jit.find(key);
+    if (it != g->jit.end()) {
+        *out = &it->second;
+        return DMC_OK;
+    }
+    JitKernel jk;
+    jk.src = dmc::emit_eval_source(g->c, n_groups, nullptr);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, jk.src.c_str(), "dmc_eval.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(DMC_E_COMPILE, "hiprtcCreateProgram failed");
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(DMC_E_COMPILE, "graph kernel compilation failed: " + log);
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    HIP_TRY(hipModuleLoadData(&jk.mod, code.data()));
+    HIP_TRY(hipModuleGetFunction(&jk.fn, jk.mod, "dmc_eval"));
+    g->jit[key] = jk;
+    *out = &g->jit[key];
+    return DMC_OK;
+}
+
+// ------------------------------------------------------------------------------ accumulator
+dmc_status dmc_accum_create(int32_t n_groups, int32_t n_k, int32_t n_roots, dmc_accum** out) {
+    if (!out || n_groups < 1 || n_groups > DMC_MAX_GROUPS || n_k < 1 || n_k > DMC_MAX_K || n_roots < 1 ||
+        n_roots > 4)
+        return fail(DMC_E_INVALID, "accumulator shape out of range");
+    auto a = std::make_unique<dmc_accum>();
+    a->n_groups = n_groups;
+    a->n_k = n_k;
+    a->n_roots = n_roots;
+    a->s_total = n_k * 2 * n_groups * n_roots;
+    HIP_ALLOC(hipMalloc(&a->totals, sizeof(double) * 2 * a->s_total));
+    HIP_ALLOC(hipMalloc(&a->nonfin_tot, sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(a->totals, 0, sizeof(double) * 2 * a->s_total));
+    HIP_TRY(hipMemset(a->nonfin_tot, 0, sizeof(unsigned long long)));
+    *out = a.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_accum_reset(dmc_accum* a, void* stream) {
+    if (!a) return fail(DMC_E_INVALID, "null accumulator");
+    HIP_TRY(hipMemsetAsync(a->totals, 0, sizeof(double) * 2 * a->s_total, S(stream)));
+    HIP_TRY(hipMemsetAsync(a->nonfin_tot, 0, sizeof(unsigned long long), S(stream)));
+    a->n_samples = 0;
+    a->pending_blocks = 0;
+    a->pending_n = 0;
+    return DMC_OK;
+}
+
+void dmc_accum_destroy(dmc_accum* a) {
+    if (!a) return;
+    (void)hipFree(a->totals);
+    (void)hipFree(a->nonfin_tot);
+    (void)hipFree(a->partial);
+    (void)hipFree(a->nonfin_part);
+    delete a;
+}
+
+// ------------------------------------------------------------------------------ evaluation
+dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
+                          const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
+                          float* imp_out, void* stream) {
+    if (!g || !inst || !k_ext || !x || !jac || !acc) return fail(DMC_E_INVALID, "null argument");
+    if (n_inst < 1 || n_inst > DMC_MAX_INSTANCES) return fail(DMC_E_INVALID, "n_inst out of range");
+    if (n_k < 1 || n_k > DMC_MAX_K) return fail(DMC_E_INVALID, "n_k out of range");
+    if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    if (acc->pending_blocks) return fail(DMC_E_STATE, "dmc_accumulate must follow each dmc_eval_batch");
+    const double beta = inst[0].beta, mu = inst[0].mu;
+    if (!(beta > 0) || !(beta * std::fabs(mu) < 80.0)) return fail(DMC_E_INVALID, "need beta > 0, beta |mu| < 80");
+    std::vector<double> lam, gam;
+    std::vector<int> grp(n_inst);
+    std::vector<double> fac(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        if (inst[i].beta != beta || inst[i].mu != mu) return fail(DMC_E_INVALID, "instances must share beta and mu");
+        if (!(inst[i].lambda > 0) || !(inst[i].gamma > 0)) return fail(DMC_E_INVALID, "need lambda > 0, gamma > 0");
+        int gi = -1;
+        for (size_t j = 0; j < lam.size(); ++j)
+            if (lam[j] == inst[i].lambda) gi = (int)j;
+        if (gi < 0) {
+            if ((int)lam.size() == DMC_MAX_GROUPS) return fail(DMC_E_INVALID, "too many distinct lambda values");
+            gi = (int)lam.size();
+            lam.push_back(inst[i].lambda);
+            gam.push_back(inst[i].gamma);
+        }
+        grp[i] = gi;
+        fac[i] = std::pow(inst[i].gamma / gam[gi], g->c.order);
+    }
+    const int ng = (int)lam.size();
+    if (ng != acc->n_groups || n_k != acc->n_k || g->c.n_roots != acc->n_roots)
+        return fail(DMC_E_INVALID, "accumulator shape does not match graph, lambda groups and n_k");
+    JitKernel* jk = nullptr;
+    dmc_status st = get_kernel(g, ng, &jk);
+    if (st != DMC_OK) return st;
+
+    const int NR = g->c.n_roots;
+    const int SPK = 2 * ng * NR;
+    const int KC = SPK <= 16 ? 16 / SPK : 1;
+    const int M = (KC * SPK + 15) / 16;
+    const size_t smem = (size_t)4 * 16 * M * 64 * sizeof(float) + (size_t)4 * 2 * acc->s_total * sizeof(double);
+    if (smem > 160 * 1024) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
+    if (jk->max_blocks_per_cu <= 1) {
+        int nb = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jk->fn, 256, smem) == hipSuccess && nb > 0)
+            jk->max_blocks_per_cu = nb;
+    }
+    const int64_t ntiles = (n + 255) / 256;
+    const int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 4);
+    const int nb = (int)std::min<int64_t>(ntiles, cap);
+    if (nb > acc->cap_blocks) {
+        (void)hipFree(acc->partial);
+        (void)hipFree(acc->nonfin_part);
+        acc->partial = nullptr;
+        acc->nonfin_part = nullptr;
+        acc->cap_blocks = 0;
+        HIP_ALLOC(hipMalloc(&acc->partial, sizeof(double) * 2 * acc->s_total * (size_t)nb));
+        HIP_ALLOC(hipMalloc(&acc->nonfin_part, sizeof(unsigned int) * (size_t)nb));
+        acc->cap_blocks = nb;
+    }
+    EvalArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.x = x;
+    a.ld = ld;
+    a.jac = jac;
+    a.n = n;
+    a.partial = acc->partial;
+    a.nonfinite = acc->nonfin_part;
+    a.f_out = f_out;
+    a.imp_out = imp_out;
+    a.n_k = n_k;
+    a.s_total = acc->s_total;
+    a.mu = (float)mu;
+    a.beta = (float)beta;
+    a.bl = (float)(beta * M_LOG2E);
+    a.blmu = (float)(beta * M_LOG2E * mu);
+    a.inv2beta = (float)(0.5 / beta);
+    const int nord = g->c.order;
+    for (int gi = 0; gi < ng; ++gi) {
+        a.lam[gi] = (float)lam[gi];
+        // (8 pi gamma)^n (2 pi)^(-3n): the interaction strength and loop measure, applied once
+        a.scale[gi] = (float)(std::pow(8.0 * M_PI * gam[gi], nord) * std::pow(2.0 * M_PI, -3.0 * nord));
+    }
+    for (int j = 0; j < n_k; ++j) a.k[j] = k_ext[j];
+    void* params[] = {&a};
+    HIP_TRY(hipModuleLaunchKernel(jk->fn, nb, 1, 1, 256, 1, 1, (unsigned)smem, S(stream), params, nullptr));
+    acc->pending_blocks = nb;
+    acc->pending_n = n;
+    acc->inst_group = grp;
+    acc->inst_factor = fac;
+    return DMC_OK;
+}
+
+dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* s, const float* imp, void* stream) {
+    if (!acc) return fail(DMC_E_INVALID, "null accumulator");
+    if (!acc->pending_blocks) return fail(DMC_E_STATE, "no dmc_eval_batch to fold");
+    if (s && s->kind == DMC_SAMPLER_VEGAS) {
+        if (!imp) return fail(DMC_E_INVALID, "the VEGAS histogram needs the importance buffer");
+        if (s->last_n != acc->pending_n) return fail(DMC_E_STATE, "sampler's last batch does not match the evaluation");
+    }
+    HIP_TRY(dmc::launch_fold(acc->partial, acc->pending_blocks, 2 * acc->s_total, acc->totals, acc->nonfin_part,
+                             acc->nonfin_tot, S(stream)));
+    acc->n_samples += acc->pending_n;
+    acc->pending_blocks = 0;
+    if (s && s->kind == DMC_SAMPLER_VEGAS) {
+        dmc::HistArgs h;
+        h.imp = imp;
+        h.n = s->last_n;
+        h.seed = s->last_seed;
+        h.first = s->last_first;
+        h.dim = s->dim;
+        h.n_bins = s->n_bins;
+        h.maxbits = s->d_max;
+        h.hist_u64 = s->d_hist_u;
+        h.hist = s->d_hist;
+        HIP_TRY(dmc::launch_hist(h, cu_count(), S(stream)));
+    }
+    return DMC_OK;
+}
+
+dmc_status dmc_accum_read(dmc_accum* acc, double* sums, int64_t* n_samples, void* stream) {
+    if (!acc || !sums) return fail(DMC_E_INVALID, "null argument");
+    std::vector<double> t(2 * acc->s_total);
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(t.data(), acc->totals, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
+    // device slot order [k][group][root][comp] -> [group][root][k][comp]
+    const int NG = acc->n_groups, NR = acc->n_roots, K = acc->n_k;
+    for (int g = 0; g < NG; ++g)
+        for (int r = 0; r < NR; ++r)
+            for (int k = 0; k < K; ++k)
+                for (int c = 0; c < 2; ++c) {
+                    const int gs = k * (2 * NG * NR) + (g * NR + r) * 2 + c;
+                    const size_t o = ((((size_t)g * NR + r) * K + k) * 2 + c) * 2;
+                    sums[o] = t[2 * gs];
+                    sums[o + 1] = t[2 * gs + 1];
+                }
+    if (n_samples) *n_samples = acc->n_samples;
+    return DMC_OK;
+}
+
+dmc_status dmc_estimate(dmc_accum* acc, double* mean, double* stderr_, int64_t* n_samples, int64_t* n_nonfinite,
+                        void* stream) {
+    if (!acc || !mean || !stderr_) return fail(DMC_E_INVALID, "null argument");
+    if (acc->inst_group.empty()) return fail(DMC_E_STATE, "no evaluation yet");
+    const int NG = acc->n_groups, NR = acc->n_roots, K = acc->n_k;
+    std::vector<double> sums((size_t)NG * NR * K * 4);
+    dmc_status st = dmc_accum_read(acc, sums.data(), nullptr, stream);
+    if (st != DMC_OK) return st;
+    unsigned long long nf = 0;
+    HIP_TRY(hipMemcpy(&nf, acc->nonfin_tot, sizeof(nf), hipMemcpyDeviceToHost));
+    const double N = (double)acc->n_samples;
+    for (size_t i = 0; i < acc->inst_group.size(); ++i) {
+        const int g = acc->inst_group[i];
+        const double f = acc->inst_factor[i];
+        for (int r = 0; r < NR; ++r)
+            for (int k = 0; k < K; ++k)
+                for (int c = 0; c < 2; ++c) {
+                    const size_t o = ((((size_t)g * NR + r) * K + k) * 2 + c) * 2;
+                    const double m = sums[o] / N;
+                    const double var = N > 1 ? std::max(0.0, (sums[o + 1] / N - m * m)) / (N - 1) : 0.0;
+                    const size_t oi = (((size_t)i * NR + r) * K + k) * 2 + c;
+                    mean[oi] = f * m;
+                    stderr_[oi] = f * std::sqrt(var);
+                }
+    }
+    if (n_samples) *n_samples = acc->n_samples;
+    if (n_nonfinite) *n_nonfinite = (int64_t)nf;
+    return nf ? fail(DMC_E_NUMERIC, "non-finite sample weights were dropped") : DMC_OK;
+}
+
+// ------------------------------------------------------------------------------ sampler
+dmc_status dmc_sampler_create(int32_t kind, int32_t order, int32_t n_bins, double beta, double qmax,
+                              dmc_sampler** out) {
+    if (!out) return fail(DMC_E_INVALID, "null out");
+    if (kind != DMC_SAMPLER_UNIFORM && kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_INVALID, "unknown sampler kind");
+    if (order < 1 || order > DMC_MAX_ORDER) return fail(DMC_E_INVALID, "order out of range");
+    if (kind == DMC_SAMPLER_VEGAS && (n_bins < 2 || n_bins > 128)) return fail(DMC_E_INVALID, "n_bins in 2..128");
+    if (!(beta > 0) || !(qmax > 0)) return fail(DMC_E_INVALID, "need beta > 0 and qmax > 0");
+    auto s = std::make_unique<dmc_sampler>();
+    s->kind = kind;
+    s->order = order;
+    s->dim = 4 * order - 1;
+    s->n_bins = kind == DMC_SAMPLER_VEGAS ? n_bins : 1;
+    s->beta = beta;
+    s->qmax = qmax;
+    const int B = s->n_bins;
+    s->edges.resize((size_t)s->dim * (B + 1));
+    for (int d = 0; d < s->dim; ++d)
+        for (int b = 0; b <= B; ++b) s->edges[(size_t)d * (B + 1) + b] = (double)b / B;
+    const size_t nc = (size_t)s->dim * B;
+    HIP_ALLOC(hipMalloc(&s->d_edges, sizeof(float) * s->edges.size()));
+    HIP_ALLOC(hipMalloc(&s->d_hist, sizeof(double) * nc));
+    HIP_ALLOC(hipMalloc(&s->d_hist_u, sizeof(unsigned long long) * nc));
+    HIP_ALLOC(hipMalloc(&s->d_max, sizeof(unsigned int)));
+    std::vector<float> ef(s->edges.begin(), s->edges.end());
+    HIP_TRY(hipMemcpy(s->d_edges, ef.data(), sizeof(float) * ef.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(s->d_hist, 0, sizeof(double) * nc));
+    HIP_TRY(hipMemset(s->d_hist_u, 0, sizeof(unsigned long long) * nc));
+    *out = s.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_sample(dmc_sampler* s, uint64_t seed, uint64_t first_index, int64_t n, float* x, int64_t ld,
+                      float* jac, void* stream) {
+    if (!s || !x || !jac) return fail(DMC_E_INVALID, "null argument");
+    if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    dmc::SampleArgs a;
+    a.seed = seed;
+    a.first = first_index;
+    a.n = n;
+    a.ld = ld;
+    a.x = x;
+    a.jac = jac;
+    a.edges = s->d_edges;
+    a.kind = s->kind;
+    a.order = s->order;
+    a.dim = s->dim;
+    a.n_bins = s->n_bins;
+    a.beta = (float)s->beta;
+    a.qmax = (float)s->qmax;
+    a.jl = (float)(4.0 * M_PI * s->qmax);
+    a.jt = (float)std::pow(s->beta, s->order - 1);
+    HIP_TRY(dmc::launch_sample(a, cu_count(), S(stream)));
+    s->last_seed = seed;
+    s->last_first = first_index;
+    s->last_n = n;
+    return DMC_OK;
+}
+
+dmc_status dmc_sampler_get_grid(const dmc_sampler* s, double* edges) {
+    if (!s || !edges) return fail(DMC_E_INVALID, "null argument");
+    std::copy(s->edges.begin(), s->edges.end(), edges);
+    return DMC_OK;
+}
+
+dmc_status dmc_sampler_set_grid(dmc_sampler* s, const double* edges, void* stream) {
+    if (!s || !edges) return fail(DMC_E_INVALID, "null argument");
+    const int B = s->n_bins;
+    for (int d = 0; d < s->dim; ++d) {
+        const double* e = edges + (size_t)d * (B + 1);
+        if (e[0] != 0.0 || e[B] != 1.0) return fail(DMC_E_INVALID, "grid must start at 0 and end at 1");
+        for (int b = 0; b < B; ++b)
+            if (!(e[b + 1] > e[b])) return fail(DMC_E_INVALID, "grid edges must rise strictly");
+    }
+    s->edges.assign(edges, edges + s->edges.size());
+    std::vector<float> ef(s->edges.begin(), s->edges.end());
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(s->d_edges, ef.data(), sizeof(float) * ef.size(), hipMemcpyHostToDevice));
+    return DMC_OK;
+}
+
+dmc_status dmc_sampler_read_histogram(dmc_sampler* s, double* hist, void* stream) {
+    if (!s || !hist) return fail(DMC_E_INVALID, "null argument");
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(hist, s->d_hist, sizeof(double) * s->dim * s->n_bins, hipMemcpyDeviceToHost));
+    return DMC_OK;
+}
+
+// VEGAS refinement (Lepage 1978), FP64 on the host: smooth each dimension's histogram with its
+// neighbours, normalise, compress r -> ((1 - r) / ln(1/r))^alpha, then place the new edges so
+// that every new bin holds an equal share of the compressed weight (uniform within old bins).
+static void refine_dim(const double* e, const double* h, int B, double alpha, double* out) {
+    std::vector<double> sm(B), w(B);
+    sm[0] = (h[0] + h[1]) / 2;
+    sm[B - 1] = (h[B - 2] + h[B - 1]) / 2;
+    for (int b = 1; b < B - 1; ++b) sm[b] = (h[b - 1] + h[b] + h[b + 1]) / 3;
+    double tot = 0;
+    for (double v : sm) tot += v;
+    if (!(tot > 0) || !std::isfinite(tot)) {
+        std::copy(e, e + B + 1, out);
+        return;
+    }
+    double wsum = 0;
+    for (int b = 0; b < B; ++b) {
+        const double r = sm[b] / tot;
+        w[b] = r >= 1.0 ? 1.0 : (r > 0 ? std::pow((1.0 - r) / std::log(1.0 / r), alpha) : 0.0);
+        wsum += w[b];
+    }
+    const double per = wsum / B;
+    out[0] = 0.0;
+    out[B] = 1.0;
+    double acc = 0;
+    int ob = 0;
+    for (int j = 1; j < B; ++j) {
+        const double target = j * per;
+        while (ob < B && acc + w[ob] < target) acc += w[ob++];
+        out[j] = e[ob] + (target - acc) / w[ob] * (e[ob + 1] - e[ob]);
+    }
+}
+
+dmc_status dmc_sampler_refine(dmc_sampler* s, double alpha, void* stream) {
+    if (!s) return fail(DMC_E_INVALID, "null sampler");
+    if (s->kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_STATE, "only a VEGAS sampler has a grid");
+    if (!(alpha >= 0)) return fail(DMC_E_INVALID, "alpha must be >= 0");
+    const int B = s->n_bins;
+    std::vector<double> h((size_t)s->dim * B);
+    dmc_status st = dmc_sampler_read_histogram(s, h.data(), stream);
+    if (st != DMC_OK) return st;
+    std::vector<double> ne(s->edges.size());
+    for (int d = 0; d < s->dim; ++d)
+        refine_dim(&s->edges[(size_t)d * (B + 1)], &h[(size_t)d * B], B, alpha, &ne[(size_t)d * (B + 1)]);
+    // keep strictly rising edges (guard against empty histogram cells rounding to equal edges)
+    for (int d = 0; d < s->dim; ++d)
+        for (int b = 0; b < B; ++b) {
+            double& lo = ne[(size_t)d * (B + 1) + b];
+            double& hi = ne[(size_t)d * (B + 1) + b + 1];
+            if (!(hi > lo)) {
+                std::copy(&s->edges[(size_t)d * (B + 1)], &s->edges[(size_t)d * (B + 1)] + B + 1,
+                          &ne[(size_t)d * (B + 1)]);
+                break;
+            }
+        }
+    s->edges = ne;
+    std::vector<float> ef(ne.begin(), ne.end());
+    HIP_TRY(hipMemcpy(s->d_edges, ef.data(), sizeof(float) * ef.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(s->d_hist, 0, sizeof(double) * s->dim * B));
+    return DMC_OK;
+}
+
+void dmc_sampler_destroy(dmc_sampler* s) {
+    if (!s) return;
+    (void)hipFree(s->d_edges);
+    (void)hipFree(s->d_hist);
+    (void)hipFree(s->d_hist_u);
+    (void)hipFree(s->d_max);
+    delete s;
+}
+
+}  // extern "C"

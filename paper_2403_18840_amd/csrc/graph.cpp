@@ -1,0 +1,793 @@
+// Diagram front end and graph compiler.
+//
+// Front end (eq. sigma_integration, eq. ueg_action): the n-th order self-energy diagrams are
+// permutations sigma of 2n vertices (interaction line i joins vertices 2i and 2i+1; the
+// propagator leaving v enters sigma[v]; the external legs enter vertex 0 and leave the vertex
+// o with sigma[o] == 0).  Canonical forms are produced directly by an orderly generation: the
+// vertices are visited in label order and the propagator leaving the visited vertex either
+// enters an already-labelled vertex or opens the next interaction line, whose ends take the
+// next two labels.  Each connected diagram is produced exactly once, in the labelling in which
+// a breadth-first walk from the in-vertex discovers the vertices in label order.  Diagrams with
+// a bridge are dropped: an interaction-line bridge forces q = 0 (a Hartree tadpole, removed by
+// q != 0), a propagator bridge makes the self-energy one-particle reducible.
+//
+// Routing: propagators in order of their source vertex become chords (loop momenta q_0, q_1,
+// ...) whenever removing them keeps the internal graph connected; the spanning tree left over
+// carries the loop momenta back along tree paths and the external k from vertex 0 to the
+// out-vertex.
+//
+// IR and back end (Sec. V.A): leaves are deduplicated (a propagator depends on |p|^2 and the
+// ordered pair of interaction lines at its ends; an interaction depends on |p|^2), and every
+// root (one per out-vertex time line and lambda group) is the sum of products over its
+// diagrams.  That sum is factored greedily (repeatedly pulling out the factor common to most
+// terms, external-momentum-dependent factors first), with structural hashing of every product
+// and sum, so that the part of the graph that does not depend on k is computed once per sample
+// outside the loop over external momenta.
+#include "graph.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <set>
+#include <sstream>
+
+namespace dmc {
+
+namespace {
+
+struct Edge {
+    char kind;
+    int a, b;
+};
+
+bool connected(int nv, const std::vector<Edge>& es, int skip) {
+    std::vector<std::vector<int>> adj(nv);
+    for (int i = 0; i < (int)es.size(); ++i) {
+        if (i == skip) continue;
+        adj[es[i].a].push_back(es[i].b);
+        adj[es[i].b].push_back(es[i].a);
+    }
+    std::vector<char> seen(nv, 0);
+    std::vector<int> st{0};
+    seen[0] = 1;
+    int cnt = 1;
+    while (!st.empty()) {
+        int v = st.back();
+        st.pop_back();
+        for (int w : adj[v])
+            if (!seen[w]) {
+                seen[w] = 1;
+                ++cnt;
+                st.push_back(w);
+            }
+    }
+    return cnt == nv;
+}
+
+std::vector<Edge> internal_edges(const std::vector<int>& sigma, int& n_fermion) {
+    const int nv = (int)sigma.size();
+    std::vector<Edge> es;
+    for (int v = 0; v < nv; ++v)
+        if (sigma[v] != 0) es.push_back({'G', v, sigma[v]});
+    n_fermion = (int)es.size();
+    for (int i = 0; i < nv / 2; ++i) es.push_back({'V', 2 * i, 2 * i + 1});
+    return es;
+}
+
+bool bridgeless(const std::vector<int>& sigma) {
+    int nf;
+    auto es = internal_edges(sigma, nf);
+    for (int i = 0; i < (int)es.size(); ++i)
+        if (!connected((int)sigma.size(), es, i)) return false;
+    return true;
+}
+
+int count_cycles(const std::vector<int>& sigma) {
+    std::vector<char> seen(sigma.size(), 0);
+    int c = 0;
+    for (size_t s = 0; s < sigma.size(); ++s) {
+        if (seen[s]) continue;
+        ++c;
+        for (int v = (int)s; !seen[v]; v = sigma[v]) seen[v] = 1;
+    }
+    return c;
+}
+
+Diagram route(const std::vector<int>& sigma) {
+    const int nv = (int)sigma.size(), n = nv / 2;
+    Diagram d;
+    d.sigma = sigma;
+    d.order = n;
+    for (int v = 0; v < nv; ++v)
+        if (sigma[v] == 0) d.out_vertex = v;
+    d.n_fermion_loops = count_cycles(sigma) - 1;
+    d.weight = ((n + d.n_fermion_loops) % 2 ? -1.0 : 1.0) * std::ldexp(1.0, d.n_fermion_loops);
+
+    int nf;
+    std::vector<Edge> es = internal_edges(sigma, nf);
+    std::vector<char> in_tree(es.size(), 1);
+    std::vector<int> chord_of(es.size(), -1);
+    int n_ch = 0;
+    for (int i = 0; i < nf; ++i) {
+        std::vector<Edge> rest;
+        for (int j = 0; j < (int)es.size(); ++j)
+            if (in_tree[j] && j != i) rest.push_back(es[j]);
+        if (connected(nv, rest, -1)) {
+            in_tree[i] = 0;
+            chord_of[i] = n_ch++;
+        }
+    }
+    // tree adjacency
+    std::vector<std::vector<std::pair<int, int>>> adj(nv);  // (neighbour, edge index)
+    for (int j = 0; j < (int)es.size(); ++j)
+        if (in_tree[j]) {
+            adj[es[j].a].push_back({es[j].b, j});
+            adj[es[j].b].push_back({es[j].a, j});
+        }
+    std::vector<std::array<int, kMaxOrder + 1>> mom(es.size());
+    for (auto& m : mom) m.fill(0);
+    // add `coef` units of momentum component `comp` along the tree path from a to b
+    auto flow = [&](int a, int b, int comp) {
+        std::vector<int> prev_v(nv, -2), prev_e(nv, -1);
+        std::vector<int> st{a};
+        prev_v[a] = -1;
+        while (!st.empty()) {
+            int v = st.back();
+            st.pop_back();
+            for (auto [w, j] : adj[v])
+                if (prev_v[w] == -2) {
+                    prev_v[w] = v;
+                    prev_e[w] = j;
+                    st.push_back(w);
+                }
+        }
+        for (int v = b; v != a; v = prev_v[v]) {
+            int j = prev_e[v], u = prev_v[v];
+            mom[j][comp] += (es[j].a == u && es[j].b == v) ? 1 : -1;
+        }
+    };
+    for (int i = 0; i < (int)es.size(); ++i)
+        if (chord_of[i] >= 0) {
+            mom[i][chord_of[i]] = 1;
+            flow(es[i].b, es[i].a, chord_of[i]);
+        }
+    flow(0, d.out_vertex, n);
+    for (int i = 0; i < (int)es.size(); ++i) {
+        Line ln;
+        ln.kind = es[i].kind;
+        ln.src = es[i].a;
+        ln.dst = es[i].b;
+        ln.mom.fill(0);
+        for (int c = 0; c <= n; ++c) ln.mom[c] = mom[i][c];
+        d.lines.push_back(ln);
+    }
+    return d;
+}
+
+void generate(int n, int j, int labelled, std::vector<int>& sigma, std::vector<char>& used,
+              std::vector<Diagram>& out) {
+    const int nv = 2 * n;
+    if (j == nv) {
+        if (labelled == nv && bridgeless(sigma)) out.push_back(route(sigma));
+        return;
+    }
+    if (j >= labelled) return;  // the walk closed before reaching every line: disconnected
+    for (int w = 0; w < labelled; ++w) {
+        if (used[w]) continue;
+        used[w] = 1;
+        sigma[j] = w;
+        generate(n, j + 1, labelled, sigma, used, out);
+        used[w] = 0;
+    }
+    if (labelled < nv) {
+        const int w = labelled;  // opens a new interaction line (labels w, w + 1)
+        used[w] = 1;
+        sigma[j] = w;
+        generate(n, j + 1, labelled + 2, sigma, used, out);
+        used[w] = 0;
+    }
+}
+
+}  // namespace
+
+std::vector<Diagram> enumerate_sigma(int n) {
+    std::vector<Diagram> out;
+    std::vector<int> sigma(2 * n, -1);
+    std::vector<char> used(2 * n, 0);
+    generate(n, 0, 2, sigma, used, out);
+    return out;
+}
+
+// ----------------------------------------------------------------------------------------
+// Code emission
+// ----------------------------------------------------------------------------------------
+namespace {
+
+using Mom = std::array<int, kMaxOrder + 1>;
+
+Mom normalise(Mom m, int n) {
+    // p and -p give the same |p|^2: make the first nonzero coefficient positive
+    for (int c = 0; c <= n; ++c) {
+        if (m[c] > 0) break;
+        if (m[c] < 0) {
+            for (int e = 0; e <= n; ++e) m[e] = -m[e];
+            break;
+        }
+    }
+    return m;
+}
+
+std::string fstr(double v) {
+    std::ostringstream s;
+    s.precision(9);
+    s << std::scientific << v << "f";
+    return s.str();
+}
+
+struct Val {
+    std::string name;
+    bool kdep;
+};
+
+class Emitter {
+   public:
+    std::ostringstream pre, loop;
+    int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0};  // add mul fma trans
+
+    Val def(bool kdep, const std::string& expr, int opclass, int nops = 1) {
+        std::string nm = "v" + std::to_string(tmp_++);
+        (kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
+        if (opclass >= 0) (kdep ? cnt_loop : cnt_pre)[opclass] += nops;
+        return {nm, kdep};
+    }
+    Val hashed(const std::string& key, bool kdep, const std::string& expr, int opclass) {
+        auto it = cse_.find(key);
+        if (it != cse_.end()) return it->second;
+        Val v = def(kdep, expr, opclass);
+        cse_[key] = v;
+        return v;
+    }
+    Val mul(const Val& a, const Val& b) {
+        const std::string& x = std::min(a.name, b.name);
+        const std::string& y = std::max(a.name, b.name);
+        return hashed("*" + x + "," + y, a.kdep || b.kdep, x + " * " + y, 1);
+    }
+    Val fma(const Val& a, const Val& b, const Val& c) {
+        const std::string& x = std::min(a.name, b.name);
+        const std::string& y = std::max(a.name, b.name);
+        return hashed("f" + x + "," + y + "," + c.name, a.kdep || b.kdep || c.kdep,
+                      "__builtin_fmaf(" + x + ", " + y + ", " + c.name + ")", 2);
+    }
+    Val add(const Val& a, const Val& b) {
+        const std::string& x = std::min(a.name, b.name);
+        const std::string& y = std::max(a.name, b.name);
+        return hashed("+" + x + "," + y, a.kdep || b.kdep, x + " + " + y, 0);
+    }
+    Val scale(const Val& a, double c) {
+        if (c == 1.0) return a;
+        std::ostringstream k;
+        k << "c" << c << "*" << a.name;
+        return hashed(k.str(), a.kdep, fstr(c) + " * " + a.name, c == -1.0 ? -1 : 1);
+    }
+    Val constant(double c) { return {fstr(c), false}; }
+
+   private:
+    int tmp_ = 0;
+    std::map<std::string, Val> cse_;
+};
+
+struct Term {
+    double coef;
+    std::vector<int> f;  // factor ids into the `vals` table, sorted
+};
+
+struct Builder {
+    const Compiled& c;
+    int n, n_groups;
+    Emitter em;
+    std::vector<Val> vals;      // factor values
+    std::vector<char> val_k;    // k-dependence of each factor
+    // momentum, time-pair, energy caches
+    std::map<Mom, int> mom_id;
+    std::vector<Mom> moms;
+    std::map<int, std::array<std::string, 3>> mom_q;   // Qx Qy Qz
+    std::map<int, Val> mom_q2, mom_p2;
+    std::map<std::pair<int, int>, std::pair<std::string, std::string>> tpair;  // T2, pos
+    std::map<int, std::array<Val, 3>> energy;  // me = mu - p2, e = exp2(-bl eps), D
+    std::map<std::tuple<int, int, int>, int> gleaf;  // (mom, a, b) -> factor id
+    std::map<std::pair<int, int>, int> vleaf;        // (mom, group) -> factor id
+    int n_g = 0, n_v = 0;
+
+    Builder(const Compiled& cc, int ng) : c(cc), n(cc.order), n_groups(ng) {}
+
+    bool is_k(int m) const { return moms[m][n] != 0; }
+
+    int momentum(const Mom& raw) {
+        Mom m = normalise(raw, n);
+        auto it = mom_id.find(m);
+        if (it != mom_id.end()) return it->second;
+        int id = (int)moms.size();
+        moms.push_back(m);
+        mom_id[m] = id;
+        return id;
+    }
+
+    std::array<std::string, 3> Q(int m) {
+        auto it = mom_q.find(m);
+        if (it != mom_q.end()) return it->second;
+        std::array<std::string, 3> r;
+        const char* ax = "xyz";
+        for (int a = 0; a < 3; ++a) {
+            std::string e;
+            int nterms = 0;
+            for (int j = 0; j < n; ++j) {
+                int cf = moms[m][j];
+                if (!cf) continue;
+                std::string t = std::string("q") + std::to_string(j) + ax[a];
+                if (nterms == 0)
+                    e = (cf == 1 ? "" : cf == -1 ? "-" : std::to_string(cf) + ".0f * ") + t;
+                else
+                    e += (cf > 0 ? " + " : " - ") + (std::abs(cf) == 1 ? "" : std::to_string(std::abs(cf)) + ".0f * ") + t;
+                ++nterms;
+            }
+            if (nterms == 0) e = "0.0f";
+            if (nterms <= 1 && (e.empty() || e[0] != '-'))
+                r[a] = e;
+            else
+                r[a] = em.def(false, e, 0, std::max(1, nterms - 1)).name;
+        }
+        mom_q[m] = r;
+        return r;
+    }
+
+    Val q2(int m) {
+        auto it = mom_q2.find(m);
+        if (it != mom_q2.end()) return it->second;
+        auto q = Q(m);
+        Val v = em.def(false, "__builtin_fmaf(" + q[0] + ", " + q[0] + ", __builtin_fmaf(" + q[1] + ", " + q[1] + ", " +
+                                  q[2] + " * " + q[2] + "))",
+                       2, 2);
+        em.cnt_pre[1] += 1;
+        mom_q2[m] = v;
+        return v;
+    }
+
+    Val p2(int m) {
+        auto it = mom_p2.find(m);
+        if (it != mom_p2.end()) return it->second;
+        Val base = q2(m);
+        Val v = base;
+        if (is_k(m)) {
+            auto q = Q(m);
+            int ck = moms[m][n];
+            // |Q + ck k z|^2 = Q^2 + k (2 ck Qz + k)
+            Val t = em.def(true, "__builtin_fmaf(" + fstr(2.0 * ck) + ", " + q[2] + ", kk)", 2);
+            v = em.def(true, "__builtin_fmaf(kk, " + t.name + ", " + base.name + ")", 2);
+        }
+        mom_p2[m] = v;
+        return v;
+    }
+
+    // time pair: propagator from interaction line a to line b (a != b)
+    std::pair<std::string, std::string> T(int a, int b) {
+        auto key = std::make_pair(a, b);
+        auto it = tpair.find(key);
+        if (it != tpair.end()) return it->second;
+        std::string ta = a == 0 ? "0.0f" : "t" + std::to_string(a);
+        std::string tb = b == 0 ? "0.0f" : "t" + std::to_string(b);
+        std::string la = a == 0 ? "" : "tl" + std::to_string(a);
+        std::string lb = b == 0 ? "" : "tl" + std::to_string(b);
+        std::string pos = "ps" + std::to_string(a) + "_" + std::to_string(b);
+        em.pre << "    const bool " << pos << " = " << tb << " > " << ta << ";\n";
+        std::string dexpr = lb.empty() ? "-" + la : la.empty() ? lb : lb + " - " + la;
+        Val d = em.def(false, dexpr, 0, (la.empty() || lb.empty()) ? 0 : 1);
+        Val t2 = em.def(false, pos + " ? " + d.name + " : " + d.name + " + BL", 0, 2);  // add + select
+        em.cnt_pre[0] += 1;  // the compare
+        tpair[key] = {t2.name, pos};
+        return tpair[key];
+    }
+
+    std::array<Val, 3> E(int m) {
+        auto it = energy.find(m);
+        if (it != energy.end()) return it->second;
+        bool k = is_k(m);
+        Val p = p2(m);
+        Val arg = em.def(k, "__builtin_fmaf(" + p.name + ", -BL, BLMU)", 2);
+        Val e = em.def(k, "__builtin_amdgcn_exp2f(" + arg.name + ")", 3);
+        Val den = em.def(k, e.name + " + 1.0f", 0);
+        Val D = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3);
+        Val me = em.def(k, "MU - " + p.name, 0);
+        energy[m] = {me, e, D};
+        return energy[m];
+    }
+
+    int g_leaf(const Line& ln) {
+        int m = momentum(ln.mom);
+        int a = ln.src / 2, b = ln.dst / 2;
+        auto key = std::make_tuple(m, a, b);
+        auto it = gleaf.find(key);
+        if (it != gleaf.end()) return it->second;
+        bool k = is_k(m);
+        auto en = E(m);
+        Val v;
+        if (a == b) {
+            // equal time (0^-): nF(eps) = e^{-beta eps} / (1 + e^{-beta eps})
+            v = em.def(k, en[1].name + " * " + en[2].name, 1);
+        } else {
+            auto tp = T(a, b);
+            Val ex = em.def(k, "__builtin_amdgcn_exp2f(" + en[0].name + " * " + tp.first + ")", 3);
+            (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            Val g = em.def(k, ex.name + " * " + en[2].name, 1);
+            v = em.def(k, tp.second + " ? -" + g.name + " : " + g.name, 0);
+        }
+        int id = (int)vals.size();
+        vals.push_back(v);
+        val_k.push_back(k);
+        gleaf[key] = id;
+        ++n_g;
+        return id;
+    }
+
+    int v_leaf(const Line& ln, int grp) {
+        int m = momentum(ln.mom);
+        auto key = std::make_pair(m, grp);
+        auto it = vleaf.find(key);
+        if (it != vleaf.end()) return it->second;
+        bool k = is_k(m);
+        Val p = p2(m);
+        Val s = em.def(k, p.name + " + LAM" + std::to_string(grp), 0);
+        Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
+        int id = (int)vals.size();
+        vals.push_back(v);
+        val_k.push_back(k);
+        vleaf[key] = id;
+        ++n_v;
+        return id;
+    }
+
+    // greedy multivariate Horner factoring of sum_t coef_t prod f_t
+    Val horner(std::vector<Term> terms) {
+        if (terms.empty()) return em.constant(0.0);
+        if (terms.size() == 1) return product(terms[0]);
+        std::map<int, int> count;
+        for (auto& t : terms) {
+            std::set<int> s(t.f.begin(), t.f.end());
+            for (int f : s) count[f]++;
+        }
+        int best = -1, bc = 1;
+        bool bk = false;
+        for (auto [f, cnt] : count) {
+            bool k = val_k[f];
+            // external-momentum dependent factors first, then the most frequent
+            if (cnt >= 2 && (best < 0 || (k && !bk) || (k == bk && cnt > bc))) {
+                best = f;
+                bc = cnt;
+                bk = k;
+            }
+        }
+        if (best < 0) {
+            // no shared factor: plain sum, accumulated with fused multiply-adds
+            Val acc = product(terms[0]);
+            for (size_t i = 1; i < terms.size(); ++i) acc = accumulate(acc, terms[i]);
+            return acc;
+        }
+        std::vector<Term> A, B;
+        for (auto& t : terms) {
+            auto it = std::find(t.f.begin(), t.f.end(), best);
+            if (it != t.f.end()) {
+                Term u = t;
+                u.f.erase(u.f.begin() + (it - t.f.begin()));
+                A.push_back(u);
+            } else {
+                B.push_back(t);
+            }
+        }
+        Val ha = horner(A);
+        if (B.empty()) return em.mul(vals[best], ha);
+        Val hb = horner(B);
+        return em.fma(vals[best], ha, hb);
+    }
+
+    Val product(const Term& t) {
+        if (t.f.empty()) return em.constant(t.coef);
+        // multiply the k-independent factors first so that their product is hoisted
+        std::vector<int> f = t.f;
+        std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return val_k[a] < val_k[b]; });
+        Val p = vals[f[0]];
+        for (size_t i = 1; i < f.size(); ++i) p = em.mul(p, vals[f[i]]);
+        return em.scale(p, t.coef);
+    }
+
+    Val accumulate(const Val& acc, const Term& t) {
+        if (t.f.empty()) return em.add(acc, em.constant(t.coef));
+        std::vector<int> f = t.f;
+        std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return val_k[a] < val_k[b]; });
+        if (f.size() == 1) {
+            if (t.coef == 1.0) return em.add(acc, vals[f[0]]);
+            return em.fma(em.constant(t.coef), vals[f[0]], acc);
+        }
+        Val p = vals[f[0]];
+        for (size_t i = 1; i + 1 < f.size(); ++i) p = em.mul(p, vals[f[i]]);
+        p = em.scale(p, t.coef);
+        return em.fma(p, vals[f.back()], acc);
+    }
+};
+
+}  // namespace
+
+bool compile(int order, uint32_t deriv_mask, int diagram_index, Compiled& out, std::string& err) {
+    if (order < 1 || order > kMaxOrder) {
+        err = "order must be in 1..6";
+        return false;
+    }
+    if (deriv_mask & ~7u) {
+        err = "unknown derivative bits";
+        return false;
+    }
+    out = Compiled{};
+    out.order = order;
+    out.dim = 4 * order - 1;
+    out.deriv_mask = deriv_mask;
+    out.n_roots = 1 + __builtin_popcount(deriv_mask);
+    out.diagrams = enumerate_sigma(order);
+    if (diagram_index >= 0) {
+        if (diagram_index >= (int)out.diagrams.size()) {
+            err = "diagram_index out of range";
+            return false;
+        }
+        out.diagrams = {out.diagrams[diagram_index]};
+    }
+    std::set<int> cls;
+    for (auto& d : out.diagrams) cls.insert(d.ext_line());
+    out.n_root_classes = (int)cls.size();
+    CodeStats st;
+    emit_eval_source(out, 1, &st);
+    out.stats = st;
+    return true;
+}
+
+std::string export_text(const Compiled& c) {
+    std::ostringstream s;
+    const int n = c.order;
+    for (auto& d : c.diagrams) {
+        for (int v : d.sigma) s << v << " ";
+        s << "| w " << d.weight << " | ext " << d.ext_line();
+        for (char kind : {'G', 'V'}) {
+            s << " | " << kind;
+            for (auto& l : d.lines) {
+                if (l.kind != kind) continue;
+                s << " " << l.src << " " << l.dst;
+                for (int j = 0; j <= n; ++j) s << " " << l.mom[j];
+                s << " ;";
+            }
+        }
+        s << "\n";
+    }
+    return s.str();
+}
+
+}  // namespace dmc
+
+// ----------------------------------------------------------------------------------------
+// Evaluation kernel source.  One lane evaluates one sample; the k-independent part of the
+// graph is computed once per sample, then the lane loops over the external momenta.  Every
+// weight w = f J is staged (FP32) in the wave's slice of LDS; after each chunk of k values the
+// wave transposes the stage so that four lanes own each (k, group, Re/Im) slot, widen to FP64,
+// sum w and w^2 over the chunk's 64 samples in a fixed order and add into FP64 running totals in
+// LDS.  At the end the block folds its four waves in order and writes one FP64 partial per slot.
+// ----------------------------------------------------------------------------------------
+namespace dmc {
+
+std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) {
+    const int n = c.order;
+    Builder b(c, n_groups);
+    std::vector<int> cls;
+    for (auto& d : c.diagrams) cls.push_back(d.ext_line());
+    std::sort(cls.begin(), cls.end());
+    cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+
+    // roots[g][r]
+    std::vector<std::vector<Val>> roots(n_groups);
+    for (int g = 0; g < n_groups; ++g) {
+        for (int r : cls) {
+            std::vector<Term> terms;
+            for (auto& d : c.diagrams) {
+                if (d.ext_line() != r) continue;
+                Term t;
+                t.coef = d.weight;
+                for (auto& ln : d.lines) t.f.push_back(ln.kind == 'G' ? b.g_leaf(ln) : b.v_leaf(ln, g));
+                std::sort(t.f.begin(), t.f.end());
+                terms.push_back(t);
+            }
+            roots[g].push_back(b.horner(terms));
+        }
+    }
+    // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta)
+    std::ostringstream epi;
+    int64_t epi_ops[4] = {0, 0, 0, 0};
+    for (int g = 0; g < n_groups; ++g) {
+        std::string fr, fi;
+        for (size_t ri = 0; ri < cls.size(); ++ri) {
+            int r = cls[ri];
+            std::string rv = roots[g][ri].name;
+            std::string pc = "PC" + std::to_string(g) + "_" + std::to_string(r);
+            std::string ps = "PS" + std::to_string(g) + "_" + std::to_string(r);
+            if (fr.empty()) {
+                fr = rv + " * " + pc;
+                epi_ops[1]++;
+            } else {
+                fr = "__builtin_fmaf(" + rv + ", " + pc + ", " + fr + ")";
+                epi_ops[2]++;
+            }
+            if (r == 0) continue;
+            if (fi.empty()) {
+                fi = rv + " * " + ps;
+                epi_ops[1]++;
+            } else {
+                fi = "__builtin_fmaf(" + rv + ", " + ps + ", " + fi + ")";
+                epi_ops[2]++;
+            }
+        }
+        if (fi.empty()) fi = "0.0f";
+        epi << "        const float FR" << g << " = " << fr << ";\n";
+        epi << "        const float FI" << g << " = " << fi << ";\n";
+    }
+
+    const int NR = 1;
+    const int SPK = 2 * n_groups * NR;
+    const int KC = SPK <= 16 ? 16 / SPK : 1;
+    const int SCH = KC * SPK;
+    const int M = (SCH + 15) / 16;
+
+    std::ostringstream s;
+    s << "// generated: order " << n << ", " << c.diagrams.size() << " diagrams, " << n_groups
+      << " lambda group(s)\n";
+    s << "#define DIM " << c.dim << "\n#define NGRP " << n_groups << "\n#define NROOT " << NR << "\n#define SPK " << SPK
+      << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n";
+    s << R"K(
+struct EvalArgs {
+    const float* x; long long ld; const float* jac; long long n;
+    double* partial; unsigned int* nonfinite; float* f_out; float* imp_out;
+    int n_k; int s_total; int pad0; int pad1;
+    float mu, beta, bl, blmu, inv2beta, pad2;
+    float lam[8]; float scale[8];
+    float k[64];
+};
+
+extern "C" __global__ void __launch_bounds__(256) dmc_eval(const EvalArgs a) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float* stage = smem + wv * (16 * MST * 64);
+    double* tot = (double*)(smem + 4 * 16 * MST * 64) + wv * (2 * a.s_total);
+    for (int i = lane; i < 2 * a.s_total; i += 64) tot[i] = 0.0;
+    unsigned int nonfin = 0;
+    const float MU = a.mu, BL = a.bl, BLMU = a.blmu;
+    const float* __restrict__ X = a.x;
+    const long long ld = a.ld;
+)K";
+    for (int g = 0; g < n_groups; ++g) s << "    const float LAM" << g << " = a.lam[" << g << "];\n";
+    s << R"K(    const long long ntiles = (a.n + 255) >> 8;
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long s = tile * 256 + threadIdx.x;
+        const bool valid = s < a.n;
+        const long long si = valid ? s : a.n - 1;
+        const float J = valid ? a.jac[si] : 0.0f;
+)K";
+    const char* ax = "xyz";
+    for (int j = 0; j < n; ++j)
+        for (int e = 0; e < 3; ++e)
+            s << "        const float q" << j << ax[e] << " = X[" << (3 * j + e) << " * ld + si];\n";
+    for (int j = 1; j < n; ++j) {
+        s << "        const float t" << j << " = X[" << (3 * n + j - 1) << " * ld + si];\n";
+        s << "        const float tl" << j << " = t" << j << " * 1.44269504089f;\n";
+    }
+    for (int g = 0; g < n_groups; ++g)
+        for (int r : cls) {
+            if (r == 0) {
+                s << "        const float PC" << g << "_0 = a.scale[" << g << "];\n";
+            } else {
+                s << "        float sn" << g << "_" << r << ", cs" << g << "_" << r << ";\n";
+                s << "        sincospif(t" << r << " * (2.0f * a.inv2beta), &sn" << g << "_" << r << ", &cs" << g << "_" << r
+                  << ");\n";
+                s << "        const float PC" << g << "_" << r << " = a.scale[" << g << "] * cs" << g << "_" << r << ";\n";
+                s << "        const float PS" << g << "_" << r << " = a.scale[" << g << "] * sn" << g << "_" << r << ";\n";
+            }
+        }
+    s << b.em.pre.str();
+    s << R"K(        float imp = 0.0f;
+        for (int kb = 0; kb < a.n_k; kb += KC) {
+            for (int kq = 0; kq < KC; ++kq) {
+                const int ki = kb + kq;
+                const bool kv = ki < a.n_k;
+                const float kk = a.k[kv ? ki : 0];
+)K";
+    {
+        std::string body = b.em.loop.str();
+        std::istringstream in(body);
+        std::string line;
+        while (std::getline(in, line)) s << "            " << line << "\n";
+        std::string e = epi.str();
+        std::istringstream in2(e);
+        while (std::getline(in2, line)) s << "            " << line << "\n";
+    }
+    for (int g = 0; g < n_groups; ++g)
+        for (int comp = 0; comp < 2; ++comp) {
+            int slot = (g * NR + 0) * 2 + comp;
+            s << "                {\n";
+            s << "                    const float f = " << (comp ? "FI" : "FR") << g << ";\n";
+            s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
+            s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
+            s << "                    imp += __builtin_fabsf(w);\n";
+            s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
+            s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR) << ") * a.n_k + ki) * 2 + "
+              << comp << ") * a.n + s] = f;\n";
+            s << "                }\n";
+        }
+    s << R"K(            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int m = 0; m < MST; ++m) {
+                const int sl = (lane >> 2) + 16 * m;
+                const float4* src = (const float4*)(stage + sl * 64 + (lane & 3) * 16);
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 v = src[j];
+                    double d = (double)v.x; s1 += d; s2 = __builtin_fma(d, d, s2);
+                    d = (double)v.y; s1 += d; s2 = __builtin_fma(d, d, s2);
+                    d = (double)v.z; s1 += d; s2 = __builtin_fma(d, d, s2);
+                    d = (double)v.w; s1 += d; s2 = __builtin_fma(d, d, s2);
+                }
+                s1 += __shfl_xor(s1, 1); s2 += __shfl_xor(s2, 1);
+                s1 += __shfl_xor(s1, 2); s2 += __shfl_xor(s2, 2);
+                const int gs = (kb / KC) * SCH + sl;
+                if ((lane & 3) == 0 && sl < SCH && gs < a.s_total) { tot[2 * gs] += s1; tot[2 * gs + 1] += s2; }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (a.imp_out && valid) a.imp_out[s] = imp;
+    }
+    // fold the four waves in a fixed order into one FP64 partial per slot
+    for (int o = 32; o > 0; o >>= 1) nonfin += __shfl_xor(nonfin, o);
+    __shared__ unsigned int nf_w[4];
+    if (lane == 0) nf_w[wv] = nonfin;
+    __syncthreads();
+    const double* t0 = (const double*)(smem + 4 * 16 * MST * 64);
+    const int st2 = 2 * a.s_total;
+    for (int i = threadIdx.x; i < st2; i += 256)
+        a.partial[(long long)blockIdx.x * st2 + i] = ((t0[i] + t0[st2 + i]) + t0[2 * st2 + i]) + t0[3 * st2 + i];
+    if (threadIdx.x == 0) a.nonfinite[blockIdx.x] = nf_w[0] + nf_w[1] + nf_w[2] + nf_w[3];
+}
+)K";
+    if (stats) {
+        *stats = CodeStats{};
+        for (int i = 0; i < 4; ++i) {
+            stats->sample[i] = b.em.cnt_pre[i];
+            stats->k[i] = b.em.cnt_loop[i] + epi_ops[i];
+        }
+        // naive: every diagram as a plain product of its lines, every leaf evaluated per diagram
+        for (auto& d : c.diagrams) {
+            int ng = 0, nv = 0, neq = 0;
+            for (auto& l : d.lines) {
+                if (l.kind == 'G') {
+                    ++ng;
+                    if (l.src / 2 == l.dst / 2) ++neq;
+                } else
+                    ++nv;
+            }
+            // G: p^2 (3 fma-class) + energy (fma, exp2, add, rcp, sub) + leaf (mul, exp2, mul, select)
+            // V: p^2 + add + rcp; product chain: (lines - 1) mul + 1 fma into the sum
+            stats->naive[2] += (int64_t)(ng + nv) * 3 + ng;
+            stats->naive[3] += (int64_t)ng * 3 - neq + nv;
+            stats->naive[0] += (int64_t)ng * 3 + nv;
+            stats->naive[1] += (int64_t)ng * 2 + (ng + nv - 1);
+        }
+    }
+    return s.str();
+}
+
+}  // namespace dmc

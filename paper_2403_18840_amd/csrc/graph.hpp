@@ -1,0 +1,63 @@
+// Host-side diagram front end and graph compiler (Sec. II: diagrams as computational graphs;
+// Sec. V.A: front end, IR, back end).
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dmc {
+
+constexpr int kMaxOrder = 6;
+
+// A line of a routed diagram.  mom[j] (j < n) is the coefficient of loop momentum q_j and
+// mom[n] the coefficient of the external k along the reference direction src -> dst.
+struct Line {
+    char kind;  // 'G' propagator, 'V' interaction
+    int src, dst;
+    std::array<int, kMaxOrder + 1> mom{};
+};
+
+struct Diagram {
+    std::vector<int> sigma;  // propagator leaving vertex v enters sigma[v]
+    int order = 0;
+    int out_vertex = 0;      // sigma[out_vertex] == 0
+    int n_fermion_loops = 0; // F
+    double weight = 0;       // (-1)^(n+F) 2^F
+    std::vector<Line> lines; // propagators (by source vertex, external skipped), then interactions
+    int ext_line() const { return out_vertex / 2; }
+};
+
+// All connected, bridgeless (one-particle irreducible, tadpole free) self-energy diagrams of
+// order n in canonical labelling, routed.
+std::vector<Diagram> enumerate_sigma(int n);
+
+// ---- graph IR and code generation ----
+enum class Op : uint8_t { Leaf, Mul, Fma, Add, MulC };
+
+struct CodeStats {
+    int64_t sample[4] = {0, 0, 0, 0};  // add, mul, fma, trans per sample (k-independent)
+    int64_t k[4] = {0, 0, 0, 0};       // per (sample, k)
+    int64_t naive[4] = {0, 0, 0, 0};   // plain sum of products per (sample, k)
+};
+
+struct Compiled {
+    int order = 0, dim = 0, n_root_classes = 0;
+    int n_momenta = 0, n_g_leaves = 0, n_v_leaves = 0, n_groups = 0;
+    uint32_t deriv_mask = 0;
+    int n_roots = 1;
+    std::vector<Diagram> diagrams;
+    CodeStats stats;
+};
+
+// Builds the compiled description (diagram subset selection, IR statistics).
+// diagram_index < 0 keeps all diagrams.
+bool compile(int order, uint32_t deriv_mask, int diagram_index, Compiled& out, std::string& err);
+
+// Device source for the evaluation kernel specialised to `n_groups` lambda groups.
+std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);
+
+std::string export_text(const Compiled& c);
+
+}  // namespace dmc
