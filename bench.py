@@ -31,6 +31,21 @@ def flops(ops):
     return ops[0] + ops[1] + 2 * ops[2] + ops[3]
 
 
+def traffic_for(graph, n_groups=1):
+    """HBM bytes per launch from the committed counter runs, if the generated kernel is the one
+    that was measured (same source), else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "eval_o3_hbm_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    src = graph.source(n_groups)
+    if hashlib.sha1(src.encode()).hexdigest() != d.get("kernel_source_sha1"):
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma):
     """The oracle (numpy FP64, diagram by diagram) on a bounded sample of each order.  The rate is
     combined with the workload's mix (equal samples per order): value = sum_n N_diag(n) / sum_n t_n,
@@ -76,6 +91,8 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -89,6 +106,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     orders = [int(t) for t in args.orders.split(",")]
     N = 1 << args.log2_samples
     K = args.k
@@ -164,7 +188,8 @@ def main():
         },
         "roofline": {
             "bound": "alu", "kernel": f"dmc_eval (order {dom['n']})", "achieved": achieved,
-            "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+            "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+            "traffic": traffic_for(dom["g"]) if dom["n"] == 3 and N == (1 << 24) else None,
             "kernel_ms": kern_ms, "flop_per_launch": fl_launch,
         },
     }

@@ -200,7 +200,7 @@ static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     HIP_TRY(hipModuleLoadData(&jk.mod, code.data()));
-    HIP_TRY(hipModuleGetFunction(&jk.fn, jk.mod, "dmc_eval"));
+    HIP_TRY(hipModuleGetFunction(&jk.fn, jk.mod, dmc::kernel_name(g->c, n_groups).c_str()));
     g->jit[key] = jk;
     *out = &g->jit[key];
     return DMC_OK;

@@ -579,6 +579,11 @@ std::string export_text(const Compiled& c) {
 // ----------------------------------------------------------------------------------------
 namespace dmc {
 
+std::string kernel_name(const Compiled& c, int n_groups) {
+    return "dmc_eval_o" + std::to_string(c.order) + "_g" + std::to_string(n_groups) + "_r" + std::to_string(c.n_roots) +
+           (c.diagrams.size() == 1 ? "_single" : "");
+}
+
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) {
     const int n = c.order;
     Builder b(c, n_groups);
@@ -643,6 +648,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     std::ostringstream s;
     s << "// generated: order " << n << ", " << c.diagrams.size() << " diagrams, " << n_groups
       << " lambda group(s)\n";
+    s << "#define KERNEL_NAME " << kernel_name(c, n_groups) << "\n";
     s << "#define DIM " << c.dim << "\n#define NGRP " << n_groups << "\n#define NROOT " << NR << "\n#define SPK " << SPK
       << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n";
     s << R"K(
@@ -655,7 +661,7 @@ struct EvalArgs {
     float k[64];
 };
 
-extern "C" __global__ void __launch_bounds__(256) dmc_eval(const EvalArgs a) {
+extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float* stage = smem + wv * (16 * MST * 64);

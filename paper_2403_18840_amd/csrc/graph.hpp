@@ -60,4 +60,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);
 
 std::string export_text(const Compiled& c);
 
+// Symbol of the generated kernel: order, lambda groups, roots.
+std::string kernel_name(const Compiled& c, int n_groups);
+
 }  // namespace dmc

@@ -30,13 +30,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
-// 24-bit integer of draw d of sample i
-__device__ __forceinline__ uint32_t draw24(uint64_t seed, uint64_t i, int blk, int word) {
-    uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)blk, 0u};
-    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    return c[word] >> 8;
-}
-
 constexpr int kMaxDim = 4 * 6 - 1;
 
 // One thread per sample; the order is a template parameter so that the coordinates stay in
@@ -137,7 +130,10 @@ __global__ void __launch_bounds__(256) dmc_hist_max_kernel(const float* imp, int
         if (v > 0.0f && __builtin_isfinite(v)) m = max(m, __float_as_uint(v));
     }
     for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned int)__shfl_xor((int)m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, m);
+    __shared__ unsigned int wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(maxbits, max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
 __device__ __forceinline__ double hist_scale(unsigned int maxbits, int64_t n) {
