@@ -89,9 +89,9 @@ def abs_sum(x, n, k, beta, mu, lam, gamma, diagrams=None):
 
 
 # ----------------------------------------------------------------------------------------
-# Derivatives by forward-mode dual numbers: every line value carries its value and its
-# derivatives with respect to (mu, lambda, k); products follow the Leibniz rule.  This is an
-# independent route from the library's reverse sweep.
+# Derivatives by forward-mode dual numbers on the plain product of each diagram: every line
+# value carries its value and its derivatives with respect to (mu, lambda, k); products follow
+# the Leibniz rule.  Pinned by central differences and by the Fock closed forms.
 # ----------------------------------------------------------------------------------------
 
 def _G0_dual(eps, deps_dk, tau, beta):
@@ -103,8 +103,14 @@ def _G0_dual(eps, deps_dk, tau, beta):
     return g, -dge, dge * deps_dk
 
 
-def diagram_values_dual(x, n, k, beta, mu, lam, gamma, diagrams=None):
-    """Returns (value, d/dmu, d/dlambda, d/dk), each complex [Ndiag, N]."""
+def diagram_values_dual(x, n, k, beta, mu, lam, gamma, diagrams=None, absolute=False):
+    """Returns (value, d/dmu, d/dlambda, d/dk), each complex [Ndiag, N].
+
+    With absolute=True each derivative is replaced by the sum of the magnitudes of its terms
+    before any cancellation: |W| sum_l (tau'_l + beta nF_l) for mu (the two terms of
+    d ln G0 / d mu = tau' - beta nF, tau' the time shifted into (0, beta]), |W| sum_l 1/(p_l^2 + lam)
+    for lambda, and the same times |d|p_l|^2/dk| for k: the scale against which an FP32
+    evaluation is judged."""
     if diagrams is None:
         diagrams = dg.sigma_diagrams(n)
     q, taus = _unpack(x, n)
@@ -131,11 +137,22 @@ def diagram_values_dual(x, n, k, beta, mu, lam, gamma, diagrams=None):
                 flam = -f / (p2 + lam)
                 fk = flam * dp2_dk
                 fmu = np.zeros(N)
+            if absolute:
+                if ln.kind == "G":
+                    tp = np.where(tau > 0, tau, tau + beta)
+                    lmu = tp + beta * ph.nF(p2 - mu, beta)
+                    fmu = np.abs(f) * lmu
+                    fk = np.abs(f) * lmu * np.abs(dp2_dk)
+                else:
+                    flam = np.abs(f) / (p2 + lam)
+                    fk = flam * np.abs(dp2_dk)
+                f = np.abs(f)
+                v = np.abs(v)
             dmu = dmu * f + v * fmu
             dlam = dlam * f + v * flam
             dk = dk * f + v * fk
             v = v * f
-        phase = np.exp(1j * w0 * taus[:, d.ext_line])
+        phase = np.ones(N) if absolute else np.exp(1j * w0 * taus[:, d.ext_line])
         for o, val in zip(outs, (v, dmu, dlam, dk)):
             o[di] = val * phase
     return tuple(outs)

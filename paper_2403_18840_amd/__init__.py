@@ -271,3 +271,36 @@ def eval_batch(graph: Graph, inst, k_ext, x, jac, acc: Accumulator, f_out=None, 
 def accumulate(acc: Accumulator, sampler: Sampler | None = None, imp=None, stream=None):
     _check(lib().dmc_accumulate(acc.h, sampler.h if sampler is not None else None,
                                 _dptr(imp, "float32", "imp"), _stream(stream)))
+
+
+def sigma_function():
+    """torch.autograd.Function around eval_batch with derivative roots.
+
+    apply(mu, lam, k, graph, x, jac, beta, gamma) -> Sigma estimate [K, 2] (Re, Im) in float64,
+    where mu, lam are 0-dim float64 tensors and k a 1-D float64 tensor (host).  The graph must be
+    compiled with deriv_mask = D_MU | D_LAMBDA | D_K.  One device pass produces the value and the
+    three derivative estimates (the samples do not depend on the parameters); backward contracts
+    the saved derivatives with the incoming gradient."""
+    import torch
+
+    class SigmaFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, mu, lam, k, graph, x, jac, beta, gamma):
+            if graph.deriv_mask != (D_MU | D_LAMBDA | D_K):
+                raise ValueError("graph must carry all three derivative roots")
+            ks = k.detach().cpu().numpy().astype("float32")
+            acc = Accumulator(1, len(ks), 4)
+            eval_batch(graph, [(float(beta), float(mu), float(lam), float(gamma))], ks, x, jac, acc)
+            accumulate(acc)
+            m, e, ns, nf = acc.estimate(1)
+            import numpy as np
+            ri = torch.from_numpy(np.stack([m[0].real, m[0].imag], axis=-1))  # [4, K, 2]
+            ctx.save_for_backward(ri[1], ri[2], ri[3])
+            return ri[0].clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            dmu, dlam, dk = ctx.saved_tensors
+            return (g * dmu).sum(), (g * dlam).sum(), (g * dk).sum(-1), None, None, None, None, None
+
+    return SigmaFn

@@ -225,52 +225,110 @@ std::string fstr(double v) {
     return s.str();
 }
 
+// A value of the generated code and its first-order tangents along the active directions
+// (0: mu, 1: lambda, 2: k); an empty tangent name means structurally zero.
 struct Val {
     std::string name;
     bool kdep;
+    std::array<std::string, 3> d{};
 };
 
 class Emitter {
    public:
     std::ostringstream pre, loop;
     int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0};  // add mul fma trans
+    bool act[3] = {false, false, false};
 
     Val def(bool kdep, const std::string& expr, int opclass, int nops = 1) {
         std::string nm = "v" + std::to_string(tmp_++);
         (kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
         if (opclass >= 0) (kdep ? cnt_loop : cnt_pre)[opclass] += nops;
-        return {nm, kdep};
+        return {nm, kdep, {}};
     }
-    Val hashed(const std::string& key, bool kdep, const std::string& expr, int opclass) {
+    Val hashed(const std::string& key, bool kdep, const std::string& expr, int opclass,
+               const std::function<void(Val&)>& tangents) {
         auto it = cse_.find(key);
         if (it != cse_.end()) return it->second;
         Val v = def(kdep, expr, opclass);
+        tangents(v);
         cse_[key] = v;
         return v;
     }
     Val mul(const Val& a, const Val& b) {
-        const std::string& x = std::min(a.name, b.name);
-        const std::string& y = std::max(a.name, b.name);
-        return hashed("*" + x + "," + y, a.kdep || b.kdep, x + " * " + y, 1);
+        const Val& x = a.name < b.name ? a : b;
+        const Val& y = a.name < b.name ? b : a;
+        const bool kd = a.kdep || b.kdep;
+        return hashed("*" + x.name + "," + y.name, kd, x.name + " * " + y.name, 1, [&](Val& v) {
+            for (int i = 0; i < 3; ++i) {
+                if (!act[i]) continue;
+                const std::string &dx = x.d[i], &dy = y.d[i];
+                if (dx.empty() && dy.empty()) continue;
+                if (dy.empty())
+                    v.d[i] = def(kd, dx + " * " + y.name, 1).name;
+                else if (dx.empty())
+                    v.d[i] = def(kd, x.name + " * " + dy, 1).name;
+                else {
+                    v.d[i] = def(kd, "__builtin_fmaf(" + dx + ", " + y.name + ", " + x.name + " * " + dy + ")", 2).name;
+                    (kd ? cnt_loop : cnt_pre)[1] += 1;
+                }
+            }
+        });
     }
     Val fma(const Val& a, const Val& b, const Val& c) {
-        const std::string& x = std::min(a.name, b.name);
-        const std::string& y = std::max(a.name, b.name);
-        return hashed("f" + x + "," + y + "," + c.name, a.kdep || b.kdep || c.kdep,
-                      "__builtin_fmaf(" + x + ", " + y + ", " + c.name + ")", 2);
+        const Val& x = a.name < b.name ? a : b;
+        const Val& y = a.name < b.name ? b : a;
+        const bool kd = a.kdep || b.kdep || c.kdep;
+        return hashed("f" + x.name + "," + y.name + "," + c.name, kd,
+                      "__builtin_fmaf(" + x.name + ", " + y.name + ", " + c.name + ")", 2, [&](Val& v) {
+                          for (int i = 0; i < 3; ++i) {
+                              if (!act[i]) continue;
+                              std::string acc = c.d[i];
+                              int nf = 0;
+                              if (!y.d[i].empty()) {
+                                  acc = acc.empty() ? x.name + " * " + y.d[i]
+                                                    : "__builtin_fmaf(" + x.name + ", " + y.d[i] + ", " + acc + ")";
+                                  ++nf;
+                              }
+                              if (!x.d[i].empty()) {
+                                  acc = acc.empty() ? x.d[i] + " * " + y.name
+                                                    : "__builtin_fmaf(" + x.d[i] + ", " + y.name + ", " + acc + ")";
+                                  ++nf;
+                              }
+                              if (acc.empty()) continue;
+                              if (nf == 0) {
+                                  v.d[i] = acc;  // only the addend carries a tangent
+                              } else {
+                                  v.d[i] = def(kd, acc, 2, nf).name;
+                              }
+                          }
+                      });
     }
     Val add(const Val& a, const Val& b) {
-        const std::string& x = std::min(a.name, b.name);
-        const std::string& y = std::max(a.name, b.name);
-        return hashed("+" + x + "," + y, a.kdep || b.kdep, x + " + " + y, 0);
+        const Val& x = a.name < b.name ? a : b;
+        const Val& y = a.name < b.name ? b : a;
+        const bool kd = a.kdep || b.kdep;
+        return hashed("+" + x.name + "," + y.name, kd, x.name + " + " + y.name, 0, [&](Val& v) {
+            for (int i = 0; i < 3; ++i) {
+                if (!act[i]) continue;
+                if (x.d[i].empty())
+                    v.d[i] = y.d[i];
+                else if (y.d[i].empty())
+                    v.d[i] = x.d[i];
+                else
+                    v.d[i] = def(kd, x.d[i] + " + " + y.d[i], 0).name;
+            }
+        });
     }
     Val scale(const Val& a, double c) {
         if (c == 1.0) return a;
         std::ostringstream k;
         k << "c" << c << "*" << a.name;
-        return hashed(k.str(), a.kdep, fstr(c) + " * " + a.name, c == -1.0 ? -1 : 1);
+        return hashed(k.str(), a.kdep, fstr(c) + " * " + a.name, c == -1.0 ? -1 : 1, [&](Val& v) {
+            for (int i = 0; i < 3; ++i)
+                if (act[i] && !a.d[i].empty()) v.d[i] = def(a.kdep, fstr(c) + " * " + a.d[i], c == -1.0 ? -1 : 1).name;
+        });
     }
-    Val constant(double c) { return {fstr(c), false}; }
+    Val constant(double c) { return {fstr(c), false, {}}; }
 
    private:
     int tmp_ = 0;
@@ -299,7 +357,14 @@ struct Builder {
     std::map<std::pair<int, int>, int> vleaf;        // (mom, group) -> factor id
     int n_g = 0, n_v = 0;
 
-    Builder(const Compiled& cc, int ng) : c(cc), n(cc.order), n_groups(ng) {}
+    std::map<int, std::string> mom_dp2;   // d|p|^2/dk of k-dependent momenta
+    std::map<int, std::string> mom_bnf;   // beta nF(eps) per momentum
+
+    Builder(const Compiled& cc, int ng) : c(cc), n(cc.order), n_groups(ng) {
+        em.act[0] = cc.deriv_mask & 1u;
+        em.act[1] = cc.deriv_mask & 2u;
+        em.act[2] = cc.deriv_mask & 4u;
+    }
 
     bool is_k(int m) const { return moms[m][n] != 0; }
 
@@ -364,6 +429,7 @@ struct Builder {
             // |Q + ck k z|^2 = Q^2 + k (2 ck Qz + k)
             Val t = em.def(true, "__builtin_fmaf(" + fstr(2.0 * ck) + ", " + q[2] + ", kk)", 2);
             v = em.def(true, "__builtin_fmaf(kk, " + t.name + ", " + base.name + ")", 2);
+            if (em.act[2]) mom_dp2[m] = em.def(true, t.name + " + kk", 0).name;  // 2 ck Qz + 2k
         }
         mom_p2[m] = v;
         return v;
@@ -399,6 +465,10 @@ struct Builder {
         Val D = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3);
         Val me = em.def(k, "MU - " + p.name, 0);
         energy[m] = {me, e, D};
+        if (em.act[0] || em.act[2]) {
+            Val nf = em.def(k, e.name + " * " + D.name, 1);
+            mom_bnf[m] = em.def(k, nf.name + " * BETA", 1).name;
+        }
         return energy[m];
     }
 
@@ -411,15 +481,27 @@ struct Builder {
         bool k = is_k(m);
         auto en = E(m);
         Val v;
+        std::string tprime;  // tau' (the propagator's time shifted into (0, beta])
         if (a == b) {
             // equal time (0^-): nF(eps) = e^{-beta eps} / (1 + e^{-beta eps})
             v = em.def(k, en[1].name + " * " + en[2].name, 1);
+            tprime = "BETA";
         } else {
             auto tp = T(a, b);
             Val ex = em.def(k, "__builtin_amdgcn_exp2f(" + en[0].name + " * " + tp.first + ")", 3);
             (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
             Val g = em.def(k, ex.name + " * " + en[2].name, 1);
             v = em.def(k, tp.second + " ? -" + g.name + " : " + g.name, 0);
+            tprime = tp.first + " * 0.693147181f";
+        }
+        if (em.act[0] || (em.act[2] && k)) {
+            // d G0 / d mu = G0 (tau' - beta nF);  d G0 / dk = -(d G0 / d mu) d|p|^2/dk.  At equal
+            // time tau' = beta and tau' - beta nF = beta (1 - nF) = beta D, taken without cancellation.
+            Val lg = a == b ? em.def(k, "BETA * " + en[2].name, 1)
+                            : em.def(k, tprime + " - " + mom_bnf[m], 0, 2);
+            Val gm = em.def(k, v.name + " * " + lg.name, 1);
+            if (em.act[0]) v.d[0] = gm.name;
+            if (em.act[2] && k) v.d[2] = em.def(true, "-" + gm.name + " * " + mom_dp2[m], 1).name;
         }
         int id = (int)vals.size();
         vals.push_back(v);
@@ -438,6 +520,12 @@ struct Builder {
         Val p = p2(m);
         Val s = em.def(k, p.name + " + LAM" + std::to_string(grp), 0);
         Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
+        if (em.act[1] || (em.act[2] && k)) {
+            // d V / d lambda = -V^2 (times 8 pi gamma, applied at the end); d V / dk = -V^2 d|p|^2/dk
+            Val vl = em.def(k, "-" + v.name + " * " + v.name, 1);
+            if (em.act[1]) v.d[1] = vl.name;
+            if (em.act[2] && k) v.d[2] = em.def(true, vl.name + " * " + mom_dp2[m], 1).name;
+        }
         int id = (int)vals.size();
         vals.push_back(v);
         val_k.push_back(k);
@@ -608,38 +696,46 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
             roots[g].push_back(b.horner(terms));
         }
     }
-    // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta)
+    // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
+    // every derivative root (the phases and scale depend on none of mu, lambda, k)
+    std::vector<int> dirs;
+    for (int i = 0; i < 3; ++i)
+        if (b.em.act[i]) dirs.push_back(i);
+    const int NR = 1 + (int)dirs.size();
     std::ostringstream epi;
     int64_t epi_ops[4] = {0, 0, 0, 0};
     for (int g = 0; g < n_groups; ++g) {
-        std::string fr, fi;
-        for (size_t ri = 0; ri < cls.size(); ++ri) {
-            int r = cls[ri];
-            std::string rv = roots[g][ri].name;
-            std::string pc = "PC" + std::to_string(g) + "_" + std::to_string(r);
-            std::string ps = "PS" + std::to_string(g) + "_" + std::to_string(r);
-            if (fr.empty()) {
-                fr = rv + " * " + pc;
-                epi_ops[1]++;
-            } else {
-                fr = "__builtin_fmaf(" + rv + ", " + pc + ", " + fr + ")";
-                epi_ops[2]++;
+        for (int ro = 0; ro < NR; ++ro) {
+            std::string fr, fi;
+            for (size_t ri = 0; ri < cls.size(); ++ri) {
+                int r = cls[ri];
+                std::string rv = ro == 0 ? roots[g][ri].name : roots[g][ri].d[dirs[ro - 1]];
+                if (rv.empty()) continue;
+                std::string pc = "PC" + std::to_string(g) + "_" + std::to_string(r);
+                std::string ps = "PS" + std::to_string(g) + "_" + std::to_string(r);
+                if (fr.empty()) {
+                    fr = rv + " * " + pc;
+                    epi_ops[1]++;
+                } else {
+                    fr = "__builtin_fmaf(" + rv + ", " + pc + ", " + fr + ")";
+                    epi_ops[2]++;
+                }
+                if (r == 0) continue;
+                if (fi.empty()) {
+                    fi = rv + " * " + ps;
+                    epi_ops[1]++;
+                } else {
+                    fi = "__builtin_fmaf(" + rv + ", " + ps + ", " + fi + ")";
+                    epi_ops[2]++;
+                }
             }
-            if (r == 0) continue;
-            if (fi.empty()) {
-                fi = rv + " * " + ps;
-                epi_ops[1]++;
-            } else {
-                fi = "__builtin_fmaf(" + rv + ", " + ps + ", " + fi + ")";
-                epi_ops[2]++;
-            }
+            if (fr.empty()) fr = "0.0f";
+            if (fi.empty()) fi = "0.0f";
+            epi << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
+            epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
         }
-        if (fi.empty()) fi = "0.0f";
-        epi << "        const float FR" << g << " = " << fr << ";\n";
-        epi << "        const float FI" << g << " = " << fi << ";\n";
     }
 
-    const int NR = 1;
     const int SPK = 2 * n_groups * NR;
     const int KC = SPK <= 16 ? 16 / SPK : 1;
     const int SCH = KC * SPK;
@@ -668,7 +764,7 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
     double* tot = (double*)(smem + 4 * 16 * MST * 64) + wv * (2 * a.s_total);
     for (int i = lane; i < 2 * a.s_total; i += 64) tot[i] = 0.0;
     unsigned int nonfin = 0;
-    const float MU = a.mu, BL = a.bl, BLMU = a.blmu;
+    const float MU = a.mu, BL = a.bl, BLMU = a.blmu, BETA = a.beta;
     const float* __restrict__ X = a.x;
     const long long ld = a.ld;
 )K";
@@ -718,18 +814,19 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         while (std::getline(in2, line)) s << "            " << line << "\n";
     }
     for (int g = 0; g < n_groups; ++g)
-        for (int comp = 0; comp < 2; ++comp) {
-            int slot = (g * NR + 0) * 2 + comp;
-            s << "                {\n";
-            s << "                    const float f = " << (comp ? "FI" : "FR") << g << ";\n";
-            s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
-            s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
-            s << "                    imp += __builtin_fabsf(w);\n";
-            s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
-            s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR) << ") * a.n_k + ki) * 2 + "
-              << comp << ") * a.n + s] = f;\n";
-            s << "                }\n";
-        }
+        for (int ro = 0; ro < NR; ++ro)
+            for (int comp = 0; comp < 2; ++comp) {
+                int slot = (g * NR + ro) * 2 + comp;
+                s << "                {\n";
+                s << "                    const float f = " << (comp ? "FI" : "FR") << g << "_" << ro << ";\n";
+                s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
+                s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
+                if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
+                s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
+                s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
+                  << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
+                s << "                }\n";
+            }
     s << R"K(            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
