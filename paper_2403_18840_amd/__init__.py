@@ -304,3 +304,43 @@ def sigma_function():
             return (g * dmu).sum(), (g * dlam).sum(), (g * dk).sum(-1), None, None, None, None, None
 
     return SigmaFn
+
+
+def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int = 5, seed: int = 1,
+              kind: int = SAMPLER_VEGAS, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0, alpha: float = 0.5):
+    """Importance-sampling estimate of Sigma (and derivative roots) with the library's sampler.
+
+    `adapt` iterations refine the VEGAS grid (their samples are discarded); the next `iters`
+    iterations use the frozen grid and accumulate into one FP64 accumulator, whose mean over all
+    frozen samples is the estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K]."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    lams = []
+    for p in inst:
+        if p[2] not in lams:
+            lams.append(p[2])
+    K = len(k_ext)
+    D = dim(graph.order)
+    s = Sampler(kind, graph.order, n_bins, beta, qmax)
+    acc = Accumulator(len(lams), K, graph.n_roots)
+    X = torch.empty((D, n_samples), dtype=torch.float32, device=dev)
+    J = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    imp = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    ks = np.asarray(k_ext, dtype=np.float32)
+    it = 0
+    for a in range(adapt if kind == SAMPLER_VEGAS else 0):
+        acc.reset()
+        s.sample(seed, it * n_samples, X, J)
+        eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
+        accumulate(acc, s, imp)
+        s.refine(alpha)
+        it += 1
+    acc.reset()
+    for a in range(iters):
+        s.sample(seed, it * n_samples, X, J)
+        eval_batch(graph, inst, ks, X, J, acc)
+        accumulate(acc)
+        it += 1
+    m, e, ns, nf = acc.estimate(len(inst))
+    return m, e
