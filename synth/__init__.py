@@ -80,3 +80,38 @@ def histogram(D: int, B: int, seed: int) -> np.ndarray:
         c = g.random()
         h[d] = np.exp(-((xb - c) ** 2) / (2 * 0.05 ** 2)) + 0.01 + 0.01 * g.random(B)
     return h
+
+
+def flow_masks(D: int, n_layers: int, seed: int) -> np.ndarray:
+    """Coupling masks int8[n_layers][D] (1 = conditioning, 0 = transformed): a seeded permutation
+    of the dimensions, split in halves that alternate roles, a new permutation every two layers."""
+    g = rng(seed)
+    m = np.zeros((n_layers, D), dtype=np.int8)
+    perm = None
+    for l in range(n_layers):
+        if l % 2 == 0:
+            perm = g.permutation(D)
+        half = perm[: D // 2] if l % 2 == 0 else perm[D // 2:]
+        m[l, half] = 1
+    return m
+
+
+def flow_params(masks: np.ndarray, seed: int, last_scale: float = 0.0) -> np.ndarray:
+    """Initial flat FP32 parameters of the coupling networks (per layer W1t[128][16], W2t[128][128],
+    b2[128], W3t[32][128], b3[32]).  Hidden weights He-normal; the output layer is scaled by
+    `last_scale` (0 gives the identity flow)."""
+    g = rng(seed)
+    out = []
+    for m in masks:
+        dA = int(m.sum())
+        W1t = np.zeros((128, 16))
+        W1t[:, : dA + 1] = g.normal(size=(128, dA + 1)) * np.sqrt(2.0 / (dA + 1))
+        W2t = g.normal(size=(128, 128)) * np.sqrt(2.0 / 128)
+        b2 = np.zeros(128)
+        dB = m.size - dA
+        W3t = np.zeros((32, 128))
+        W3t[:dB] = g.normal(size=(dB, 128)) * last_scale / np.sqrt(128)
+        W3t[16:16 + dB] = g.normal(size=(dB, 128)) * last_scale / np.sqrt(128)
+        b3 = np.zeros(32)
+        out.append(np.concatenate([W1t.ravel(), W2t.ravel(), b2, W3t.ravel(), b3]))
+    return np.concatenate(out).astype(np.float32)
