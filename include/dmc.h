@@ -154,6 +154,37 @@ dmc_status dmc_estimate(dmc_accum* acc, double* mean, double* stderr_, int64_t* 
 /* Raw FP64 sums: host double[n_groups][n_roots][n_k][2][2] as (sum w, sum w^2). */
 dmc_status dmc_accum_read(dmc_accum* acc, double* sums, int64_t* n_samples, void* stream);
 
+/* ---- learned proposal: affine-coupling normalizing flow (Appendix A, eq. coupling_layer,
+ * eq. NFtransform) ----
+ * The flow acts on the VEGAS coordinates u' in (0,1)^D: Philox uniforms u -> z_0 = logit(u) ->
+ * n_layers affine couplings z_B <- z_B exp(s) + t, (s_hat, t) = MLP(z_A) with s = 2 tanh(s_hat) ->
+ * u' = sigmoid(z_K) -> the sampler's VEGAS grid -> physical map.  The MLP is in(16) -> 128 -> 128 ->
+ * 32 with ReLU; its matmuls run on BF16 MFMA with FP32 accumulation; FP32 master weights.
+ * masks: host int8[n_layers][dim], 1 = conditioning (at most 15 per layer), 0 = transformed (at
+ * most 16); both sets non-empty.  Parameters: host float[n_layers][22688], per layer
+ * W1t[128][16] (column d_A = first-layer bias), W2t[128][128], b2[128], W3t[32][128], b3[32];
+ * s_hat_b = output b, t_b = output 16 + b. */
+typedef struct dmc_flow dmc_flow;
+dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, dmc_flow** out);
+dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n_params);
+dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream);  /* also resets Adam state */
+dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream);
+/* n samples i = first .. first + n - 1 through the flow and the sampler's grid and physical map.
+ * x: device float[D][ld]; jac: device float[n] = J_phys J_VEGAS / q_flow(u');
+ * u_out (nullable): device float[D][ld], the flow outputs u'; lq_out (nullable): device float[n], log q. */
+dmc_status dmc_flow_sample(dmc_flow* f, const dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
+                           int64_t ld, float* jac, float* u_out, float* lq_out, void* stream);
+/* log q(u') by the inverse couplings; u: device float[D][ld]; lq: device float[n]. */
+dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream);
+/* One step of the weighted forward KL L = -sum_i w_i log q(u'_i) / sum_i w_i over n points:
+ * u' = u (device float[D][ld]) or, if u is NULL, the Philox uniforms (seed, first .. first+n-1);
+ * w: device float[n] >= 0.  lr > 0 applies one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) to the
+ * FP32 masters; grad_out (nullable): device float[n_params] receives dL/dtheta; loss (nullable, host)
+ * receives L and synchronises the stream. */
+dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t seed, uint64_t first, int64_t n,
+                               const float* w, double lr, float* grad_out, double* loss, void* stream);
+void dmc_flow_destroy(dmc_flow* f);
+
 #ifdef __cplusplus
 }
 #endif

@@ -141,8 +141,9 @@ def loss_and_grad(theta, masks, uprime, w):
     each layer's network from the stored states.  Per layer (inverse z_B <- (z_B - t) e^{-s}):
       G_B(in) = G_B(out) e^{-s},  G_t = -G_B(out) e^{-s},  G_s = -G_B(out) z_B(out) + w,
       G_shat = G_s S_MAX (1 - tanh^2), then back through the network; G_A(in) += dL/dz_A.
-    BF16 rounding of the gradient operands mirrors the forward: the output gradient, the hidden
-    gradients and the activations feeding each weight-gradient product are rounded."""
+    BF16 rounding of the gradient operands mirrors the forward: the output gradient and the hidden
+    gradients are rounded before every product they feed, and the bias gradients are the sums of
+    those rounded values (a convention shared with the library)."""
     L_ = len(masks)
     layers = unpack(theta, L_)
     w = np.asarray(w, dtype=np.float64)
@@ -182,12 +183,12 @@ def loss_and_grad(theta, masks, uprime, w):
         dOb = bf16(dO)
         g = {}
         g["W3t"] = dOb.T @ bf16(c["H2"])
-        g["b3"] = dO.sum(axis=0)
+        g["b3"] = dOb.sum(axis=0)
         dH2 = dOb @ bf16(p["W3t"])
         dpre2 = dH2 * (c["pre2"] > 0)
         dpre2b = bf16(dpre2)
         g["W2t"] = dpre2b.T @ bf16(c["H1"])
-        g["b2"] = dpre2.sum(axis=0)
+        g["b2"] = dpre2b.sum(axis=0)
         dH1 = dpre2b @ bf16(p["W2t"])
         dpre1 = dH1 * (c["pre1"] > 0)
         dpre1b = bf16(dpre1)

@@ -24,7 +24,8 @@ ABI_SYMBOLS = [
     "dmc_graph_source", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
-    "dmc_accum_read",
+    "dmc_accum_read", "dmc_flow_create", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
+    "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
 ]
 
 
@@ -93,6 +94,14 @@ def lib():
         "dmc_accumulate": (I32, [P, P, P, P]),
         "dmc_estimate": (I32, [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_accum_read": (I32, [P, P, ctypes.POINTER(I64), P]),
+        "dmc_flow_create": (I32, [I32, I32, P, ctypes.POINTER(P)]),
+        "dmc_flow_param_count": (I32, [P, ctypes.POINTER(I64)]),
+        "dmc_flow_set_params": (I32, [P, P, P]),
+        "dmc_flow_get_params": (I32, [P, P, P]),
+        "dmc_flow_sample": (I32, [P, P, U64, U64, I64, P, I64, P, P, P, P]),
+        "dmc_flow_log_density": (I32, [P, P, I64, I64, P, P]),
+        "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
+        "dmc_flow_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -344,3 +353,55 @@ def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int 
         it += 1
     m, e, ns, nf = acc.estimate(len(inst))
     return m, e
+
+
+class Flow:
+    """Affine-coupling flow on the VEGAS coordinates (dmc_flow_*)."""
+
+    def __init__(self, dim_: int, masks):
+        import numpy as np
+        m = np.ascontiguousarray(masks, dtype=np.int8)
+        self.h = P()
+        _check(lib().dmc_flow_create(dim_, m.shape[0], m.ctypes.data_as(P), ctypes.byref(self.h)))
+        self.dim, self.n_layers, self.masks = dim_, m.shape[0], m
+        n = I64()
+        _check(lib().dmc_flow_param_count(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def set_params(self, theta, stream=None):
+        import numpy as np
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(lib().dmc_flow_set_params(self.h, t.ctypes.data_as(P), _stream(stream)))
+
+    def params(self, stream=None):
+        import numpy as np
+        t = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().dmc_flow_get_params(self.h, t.ctypes.data_as(P), _stream(stream)))
+        return t
+
+    def sample(self, sampler: Sampler, seed: int, first: int, x, jac, u_out=None, lq_out=None, stream=None):
+        n = jac.numel()
+        _check(lib().dmc_flow_sample(self.h, sampler.h, seed, first, n, _dptr(x, "float32", "x"), x.shape[1],
+                                     _dptr(jac, "float32", "jac"), _dptr(u_out, "float32", "u_out"),
+                                     _dptr(lq_out, "float32", "lq_out"), _stream(stream)))
+
+    def log_density(self, u, lq, stream=None):
+        _check(lib().dmc_flow_log_density(self.h, _dptr(u, "float32", "u"), u.shape[1], lq.numel(),
+                                          _dptr(lq, "float32", "lq"), _stream(stream)))
+
+    def train_step(self, w, u=None, seed: int = 0, first: int = 0, lr: float = 0.0, grad_out=None,
+                   want_loss: bool = True, stream=None):
+        n = w.numel()
+        loss = F64()
+        _check(lib().dmc_flow_train_step(self.h, _dptr(u, "float32", "u"), u.shape[1] if u is not None else n,
+                                         seed, first, n, _dptr(w, "float32", "w"), lr,
+                                         _dptr(grad_out, "float32", "grad_out"),
+                                         ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dmc_flow_destroy(self.h)
+            self.h = None

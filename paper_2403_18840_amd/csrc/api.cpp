@@ -14,6 +14,7 @@
 
 #include "../../include/dmc.h"
 #include "graph.hpp"
+#include "flow.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -569,6 +570,279 @@ void dmc_sampler_destroy(dmc_sampler* s) {
     (void)hipFree(s->d_hist_u);
     (void)hipFree(s->d_max);
     delete s;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------ flow
+struct dmc_flow {
+    int dim = 0, n_layers = 0;
+    std::vector<int8_t> masks;
+    int* d_aidx = nullptr;
+    int* d_bidx = nullptr;
+    int* d_dA = nullptr;
+    float* master = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    __bf16* shadow = nullptr;
+    int64_t step = 0;
+    // training scratch
+    int64_t cap_n = 0;
+    int cap_part = 0;
+    float* states = nullptr;
+    float* G = nullptr;
+    float* loss_part = nullptr;
+    __bf16* acts = nullptr;
+    float* partial = nullptr;
+    double* sums = nullptr;
+};
+
+namespace {
+void free_train(dmc_flow* f) {
+    (void)hipFree(f->states);
+    (void)hipFree(f->G);
+    (void)hipFree(f->loss_part);
+    (void)hipFree(f->acts);
+    (void)hipFree(f->partial);
+    f->states = f->G = f->loss_part = f->partial = nullptr;
+    f->acts = nullptr;
+    f->cap_n = 0;
+    f->cap_part = 0;
+}
+constexpr int kActRows = dmc::FKIN + dmc::FH + dmc::FH + dmc::FNOUT + dmc::FH + dmc::FH;  // 560
+constexpr int kWgradChunk = 1024;
+}  // namespace
+
+extern "C" {
+
+dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, dmc_flow** out) {
+    if (!masks || !out) return fail(DMC_E_INVALID, "null argument");
+    if (dim != 3 && dim != 7 && dim != 11 && dim != 15 && dim != 19 && dim != 23)
+        return fail(DMC_E_INVALID, "dim must be 4n - 1 for an order n in 1..6");
+    if (n_layers < 1 || n_layers > 32) return fail(DMC_E_INVALID, "n_layers in 1..32");
+    std::vector<int> aidx(n_layers * 16, 0), bidx(n_layers * 16, 0), dA(n_layers);
+    for (int l = 0; l < n_layers; ++l) {
+        int na = 0, nb = 0;
+        for (int d = 0; d < dim; ++d) {
+            const int8_t mk = masks[l * dim + d];
+            if (mk == 1) {
+                if (na == 15) return fail(DMC_E_INVALID, "at most 15 conditioning dimensions per layer");
+                aidx[l * 16 + na++] = d;
+            } else if (mk == 0) {
+                if (nb == 16) return fail(DMC_E_INVALID, "at most 16 transformed dimensions per layer");
+                bidx[l * 16 + nb++] = d;
+            } else {
+                return fail(DMC_E_INVALID, "mask entries must be 0 or 1");
+            }
+        }
+        if (na == 0 || nb == 0) return fail(DMC_E_INVALID, "every layer needs both parts");
+        dA[l] = na;
+    }
+    auto f = std::make_unique<dmc_flow>();
+    f->dim = dim;
+    f->n_layers = n_layers;
+    f->masks.assign(masks, masks + (size_t)n_layers * dim);
+    const size_t P = (size_t)n_layers * dmc::LAYER_SIZE;
+    HIP_ALLOC(hipMalloc(&f->d_aidx, sizeof(int) * aidx.size()));
+    HIP_ALLOC(hipMalloc(&f->d_bidx, sizeof(int) * bidx.size()));
+    HIP_ALLOC(hipMalloc(&f->d_dA, sizeof(int) * dA.size()));
+    HIP_ALLOC(hipMalloc(&f->master, sizeof(float) * P));
+    HIP_ALLOC(hipMalloc(&f->m, sizeof(float) * P));
+    HIP_ALLOC(hipMalloc(&f->v, sizeof(float) * P));
+    HIP_ALLOC(hipMalloc(&f->shadow, sizeof(__bf16) * (size_t)n_layers * dmc::SHADOW_LAYER));
+    HIP_ALLOC(hipMalloc(&f->sums, sizeof(double) * 2));
+    HIP_TRY(hipMemcpy(f->d_aidx, aidx.data(), sizeof(int) * aidx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_dA, dA.data(), sizeof(int) * dA.size(), hipMemcpyHostToDevice));
+    // identity flow until parameters are set: all zero (the shadow's padding rows stay zero)
+    HIP_TRY(hipMemset(f->master, 0, sizeof(float) * P));
+    HIP_TRY(hipMemset(f->m, 0, sizeof(float) * P));
+    HIP_TRY(hipMemset(f->v, 0, sizeof(float) * P));
+    HIP_TRY(hipMemset(f->shadow, 0, sizeof(__bf16) * (size_t)n_layers * dmc::SHADOW_LAYER));
+    *out = f.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n) {
+    if (!f || !n) return fail(DMC_E_INVALID, "null argument");
+    *n = (int64_t)f->n_layers * dmc::LAYER_SIZE;
+    return DMC_OK;
+}
+
+dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream) {
+    if (!f || !theta) return fail(DMC_E_INVALID, "null argument");
+    const size_t P = (size_t)f->n_layers * dmc::LAYER_SIZE;
+    for (size_t i = 0; i < P; ++i)
+        if (!std::isfinite(theta[i])) return fail(DMC_E_INVALID, "parameters must be finite");
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(f->master, theta, sizeof(float) * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(f->m, 0, sizeof(float) * P));
+    HIP_TRY(hipMemset(f->v, 0, sizeof(float) * P));
+    f->step = 0;
+    HIP_TRY(dmc::launch_flow_shadow(f->master, f->shadow, f->n_layers, cu_count(), S(stream)));
+    return DMC_OK;
+}
+
+dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream) {
+    if (!f || !theta) return fail(DMC_E_INVALID, "null argument");
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(theta, f->master, sizeof(float) * (size_t)f->n_layers * dmc::LAYER_SIZE, hipMemcpyDeviceToHost));
+    return DMC_OK;
+}
+
+dmc_status dmc_flow_sample(dmc_flow* f, const dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
+                           int64_t ld, float* jac, float* u_out, float* lq_out, void* stream) {
+    if (!f || !s || !x || !jac) return fail(DMC_E_INVALID, "null argument");
+    if (s->dim != f->dim) return fail(DMC_E_INVALID, "sampler and flow dimensions differ");
+    if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    dmc::FlowSampleArgs a;
+    a.seed = seed;
+    a.first = first;
+    a.n = n;
+    a.ld = ld;
+    a.x = x;
+    a.jac = jac;
+    a.u_out = u_out;
+    a.lq_out = lq_out;
+    a.edges = s->d_edges;
+    a.master = f->master;
+    a.shadow = f->shadow;
+    a.aidx = f->d_aidx;
+    a.bidx = f->d_bidx;
+    a.dA = f->d_dA;
+    a.n_layers = f->n_layers;
+    a.n_bins = s->n_bins;
+    a.beta = (float)s->beta;
+    a.qmax = (float)s->qmax;
+    a.jl = (float)(4.0 * M_PI * s->qmax);
+    a.jt = (float)std::pow(s->beta, s->order - 1);
+    HIP_TRY(dmc::launch_flow_sample(a, f->dim, cu_count(), S(stream)));
+    return DMC_OK;
+}
+
+static dmc_status flow_scratch(dmc_flow* f, int64_t n, int nblk) {
+    if (n <= f->cap_n && nblk <= f->cap_part) return DMC_OK;
+    free_train(f);
+    const int64_t cn = std::max<int64_t>(n, 1024);
+    const int cp = std::max(nblk, (int)((cn + kWgradChunk - 1) / kWgradChunk));
+    HIP_ALLOC(hipMalloc(&f->states, sizeof(float) * (size_t)f->n_layers * f->dim * cn));
+    HIP_ALLOC(hipMalloc(&f->G, sizeof(float) * (size_t)f->dim * cn));
+    HIP_ALLOC(hipMalloc(&f->acts, sizeof(__bf16) * (size_t)kActRows * cn));
+    HIP_ALLOC(hipMalloc(&f->loss_part, sizeof(float) * (size_t)cp));
+    HIP_ALLOC(hipMalloc(&f->partial, sizeof(float) * (size_t)f->n_layers * cp * dmc::LAYER_SIZE));
+    f->cap_n = cn;
+    f->cap_part = cp;
+    return DMC_OK;
+}
+
+static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n) {
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.master = f->master;
+    a.shadow = f->shadow;
+    a.aidx = f->d_aidx;
+    a.bidx = f->d_bidx;
+    a.dA = f->d_dA;
+    a.n_layers = f->n_layers;
+    a.dim = f->dim;
+    a.states = f->states;
+    a.G = f->G;
+    a.loss_part = f->loss_part;
+    __bf16* p = f->acts;
+    a.act_x1 = p;
+    p += (size_t)dmc::FKIN * n;
+    a.act_h1 = p;
+    p += (size_t)dmc::FH * n;
+    a.act_h2 = p;
+    p += (size_t)dmc::FH * n;
+    a.act_do = p;
+    p += (size_t)dmc::FNOUT * n;
+    a.act_dp2 = p;
+    p += (size_t)dmc::FH * n;
+    a.act_dp1 = p;
+}
+
+dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream) {
+    if (!f || !u || !lq) return fail(DMC_E_INVALID, "null argument");
+    if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    const int nblk = dmc::flow_train_blocks(n, cu_count());
+    dmc_status st = flow_scratch(f, 1024, nblk);
+    if (st != DMC_OK) return st;
+    dmc::FlowTrainArgs a;
+    train_args(f, a, n);
+    a.u_in = u;
+    a.ld = ld;
+    a.states = nullptr;
+    a.G = nullptr;
+    a.w = nullptr;
+    a.lq_out = lq;
+    HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
+    return DMC_OK;
+}
+
+dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t seed, uint64_t first, int64_t n,
+                               const float* w, double lr, float* grad_out, double* loss, void* stream) {
+    if (!f || !w) return fail(DMC_E_INVALID, "null argument");
+    if (n < 1 || (u && ld < n)) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    if (!(lr >= 0)) return fail(DMC_E_INVALID, "lr must be >= 0");
+    const int ncu = cu_count();
+    const int nblk = dmc::flow_train_blocks(n, ncu);
+    const int wg_blocks = (int)((n + kWgradChunk - 1) / kWgradChunk);
+    dmc_status st = flow_scratch(f, n, std::max(nblk, wg_blocks));
+    if (st != DMC_OK) return st;
+    dmc::FlowTrainArgs a;
+    train_args(f, a, n);
+    a.u_in = u;
+    a.ld = u ? ld : n;
+    a.seed = seed;
+    a.first = first;
+    a.w = w;
+    HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
+    for (int l = 0; l < f->n_layers; ++l)
+        HIP_TRY(dmc::launch_flow_backward(a, nblk, l, kWgradChunk, wg_blocks,
+                                          f->partial + (size_t)l * f->cap_part * dmc::LAYER_SIZE, S(stream)));
+    HIP_TRY(dmc::launch_flow_sums(w, n, f->loss_part, nblk, f->sums, S(stream)));
+    dmc::FlowAdamArgs ad;
+    ad.partial = f->partial;
+    ad.nblk = wg_blocks;
+    ad.nblk_max = f->cap_part;
+    ad.n_layers = f->n_layers;
+    ad.apply = lr > 0;
+    ad.wsum = f->sums;
+    ad.master = f->master;
+    ad.m = f->m;
+    ad.v = f->v;
+    ad.shadow = f->shadow;
+    ad.grad_out = grad_out;
+    ad.lr = lr;
+    ad.b1 = 0.9;
+    ad.b2 = 0.999;
+    ad.eps = 1e-8;
+    if (lr > 0) ++f->step;
+    ad.b1t = std::pow(ad.b1, (double)std::max<int64_t>(f->step, 1));
+    ad.b2t = std::pow(ad.b2, (double)std::max<int64_t>(f->step, 1));
+    HIP_TRY(dmc::launch_flow_adam(ad, ncu, S(stream)));
+    if (loss) {
+        double h[2];
+        HIP_TRY(hipStreamSynchronize(S(stream)));
+        HIP_TRY(hipMemcpy(h, f->sums, sizeof(h), hipMemcpyDeviceToHost));
+        *loss = h[1];
+    }
+    return DMC_OK;
+}
+
+void dmc_flow_destroy(dmc_flow* f) {
+    if (!f) return;
+    free_train(f);
+    (void)hipFree(f->d_aidx);
+    (void)hipFree(f->d_bidx);
+    (void)hipFree(f->d_dA);
+    (void)hipFree(f->master);
+    (void)hipFree(f->m);
+    (void)hipFree(f->v);
+    (void)hipFree(f->shadow);
+    (void)hipFree(f->sums);
+    delete f;
 }
 
 }  // extern "C"

@@ -1,0 +1,113 @@
+// Layouts and launchers of the affine-coupling flow kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmc {
+
+constexpr int FH = 128;    // hidden width
+constexpr int FKIN = 16;   // first-layer input width: z_A (<= 12), the bias input, zero padding
+constexpr int FNOUT = 32;  // last-layer outputs: s_hat in 0..15, t in 16..31
+constexpr int ZMAX = 24;   // largest dimension + 1
+constexpr float FLOW_SMAX = 2.0f;
+
+// FP32 master parameters of one layer (the flat order of dmc_flow_set_params)
+constexpr int OFF_W1T = 0;                       // [128][16]; column d_A is the first-layer bias
+constexpr int OFF_W2T = OFF_W1T + FH * FKIN;     // [128][128]
+constexpr int OFF_B2 = OFF_W2T + FH * FH;        // [128]
+constexpr int OFF_W3T = OFF_B2 + FH;             // [32][128]
+constexpr int OFF_B3 = OFF_W3T + FNOUT * FH;     // [32]
+constexpr int LAYER_SIZE = OFF_B3 + FNOUT;       // 22688
+
+// BF16 shadow of one layer: forward operands (rows = outputs) and backward operands (rows = inputs)
+constexpr int SH_W1T = 0;                        // [128][16]
+constexpr int SH_W2T = SH_W1T + FH * FKIN;       // [128][128]
+constexpr int SH_W3T = SH_W2T + FH * FH;         // [32][128]
+constexpr int SH_W1 = SH_W3T + FNOUT * FH;       // [32][128]: rows 0..15 = W1t^T, rows 16..31 zero
+constexpr int SH_W2 = SH_W1 + 32 * FH;           // [128][128] = W2t^T
+constexpr int SH_W3 = SH_W2 + FH * FH;           // [128][32] = W3t^T
+constexpr int SHADOW_LAYER = SH_W3 + FH * FNOUT;
+
+__device__ __forceinline__ void write_shadow(__bf16* shadow, int l, int q, float th) {
+    __bf16* s = shadow + (size_t)l * SHADOW_LAYER;
+    const __bf16 b = (__bf16)th;
+    if (q < OFF_W2T) {
+        const int r = q / FKIN, k = q % FKIN;
+        s[SH_W1T + r * FKIN + k] = b;
+        s[SH_W1 + k * FH + r] = b;
+    } else if (q < OFF_B2) {
+        const int o = (q - OFF_W2T) / FH, i = (q - OFF_W2T) % FH;
+        s[SH_W2T + o * FH + i] = b;
+        s[SH_W2 + i * FH + o] = b;
+    } else if (q >= OFF_W3T && q < OFF_B3) {
+        const int o = (q - OFF_W3T) / FH, i = (q - OFF_W3T) % FH;
+        s[SH_W3T + o * FH + i] = b;
+        s[SH_W3 + i * FNOUT + o] = b;
+    }
+}
+
+struct FlowSampleArgs {
+    uint64_t seed, first;
+    int64_t n, ld;
+    float* x;
+    float* jac;
+    float* u_out;   // nullable [D][ld]: the flow output u' (VEGAS coordinates)
+    float* lq_out;  // nullable [n]: log q(u')
+    const float* edges;
+    const float* master;
+    const __bf16* shadow;
+    const int* aidx;  // [L][16]
+    const int* bidx;  // [L][16]
+    const int* dA;    // [L]
+    int n_layers, n_bins;
+    float beta, qmax, jl, jt;
+};
+
+struct FlowTrainArgs {
+    const float* u_in;  // nullable [D][ld]: training points u'; NULL = Philox uniforms (seed, first)
+    uint64_t seed, first;
+    int64_t n, ld;
+    const float* w;     // [n] importance weights
+    const float* master;
+    const __bf16* shadow;
+    const int* aidx;
+    const int* bidx;
+    const int* dA;
+    int n_layers, dim;
+    float* states;      // [L][D][n]
+    float* G;           // [D][n]
+    float* lq_out;      // nullable [n]
+    float* loss_part;   // [blocks]
+    __bf16* act_x1;     // [16][n]
+    __bf16* act_h1;     // [128][n]
+    __bf16* act_h2;     // [128][n]
+    __bf16* act_do;     // [32][n]
+    __bf16* act_dp2;    // [128][n]
+    __bf16* act_dp1;    // [128][n]
+};
+
+struct FlowAdamArgs {
+    const float* partial;  // [L][nblk_max][LAYER_SIZE]
+    int nblk, nblk_max, n_layers, apply;
+    const double* wsum;    // device: sum of w
+    float* master;
+    float* m;
+    float* v;
+    __bf16* shadow;
+    float* grad_out;       // nullable [P]
+    double lr, b1, b2, eps, b1t, b2t;  // b1t = b1^step, b2t = b2^step
+};
+
+int flow_sample_lds_bytes(int dim);
+hipError_t launch_flow_sample(const FlowSampleArgs& a, int dim, int n_cu, hipStream_t st);
+int flow_train_blocks(int64_t n, int n_cu);
+hipError_t launch_flow_inverse(const FlowTrainArgs& a, int nblk, hipStream_t st);
+hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int wg_chunk, int wg_blocks,
+                                float* partial_layer, hipStream_t st);
+hipError_t launch_flow_sums(const float* w, int64_t n, const float* loss_part, int nblk, double* out, hipStream_t st);
+hipError_t launch_flow_adam(const FlowAdamArgs& a, int n_cu, hipStream_t st);
+hipError_t launch_flow_shadow(const float* master, __bf16* shadow, int n_layers, int n_cu, hipStream_t st);
+
+}  // namespace dmc
