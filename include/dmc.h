@@ -157,7 +157,7 @@ dmc_status dmc_accum_read(dmc_accum* acc, double* sums, int64_t* n_samples, void
 /* ---- learned proposal: affine-coupling normalizing flow (Appendix A, eq. coupling_layer,
  * eq. NFtransform) ----
  * The flow acts on the VEGAS coordinates u' in (0,1)^D: Philox uniforms u -> z_0 = logit(u) ->
- * n_layers affine couplings z_B <- z_B exp(s) + t, (s_hat, t) = MLP(z_A) with s = 2 tanh(s_hat) ->
+ * n_layers affine couplings z_B <- z_B exp(s) + t, (s_hat, t) = MLP(sigmoid(z_A)) with s = 2 tanh(s_hat) ->
  * u' = sigmoid(z_K) -> the sampler's VEGAS grid -> physical map.  The MLP is in(16) -> 128 -> 128 ->
  * 32 with ReLU; its matmuls run on BF16 MFMA with FP32 accumulation; FP32 master weights.
  * masks: host int8[n_layers][dim], 1 = conditioning (at most 15 per layer), 0 = transformed (at
@@ -169,11 +169,16 @@ dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, d
 dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n_params);
 dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream);  /* also resets Adam state */
 dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream);
-/* n samples i = first .. first + n - 1 through the flow and the sampler's grid and physical map.
- * x: device float[D][ld]; jac: device float[n] = J_phys J_VEGAS / q_flow(u');
- * u_out (nullable): device float[D][ld], the flow outputs u'; lq_out (nullable): device float[n], log q. */
-dmc_status dmc_flow_sample(dmc_flow* f, const dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
-                           int64_t ld, float* jac, float* u_out, float* lq_out, void* stream);
+/* n samples i = first .. first + n - 1 from the mixture alpha q_flow + (1 - alpha) q_grid (a defensive
+ * mixture, in the spirit of the alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised): the first
+ * round((1 - alpha) n) samples are the VEGAS sampler's own points, the rest come through the flow; every
+ * sample is weighted by the mixture density (balance-heuristic multiple importance sampling, unbiased),
+ * so the weights stay within 1/(1 - alpha) of the grid's.  s must be a VEGAS sampler of the same dimension.
+ * x: device float[D][ld]; jac: device float[n] = J_phys J_VEGAS / (alpha q_flow(u') + 1 - alpha);
+ * u_out (nullable): device float[D][ld], the points u'; lq_out (nullable): device float[n], log q_flow(u').
+ * alpha in (0, 1]. */
+dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
+                           int64_t ld, float* jac, float* u_out, float* lq_out, double alpha, void* stream);
 /* log q(u') by the inverse couplings; u: device float[D][ld]; lq: device float[n]. */
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream);
 /* One step of the weighted forward KL L = -sum_i w_i log q(u'_i) / sum_i w_i over n points:

@@ -13,7 +13,9 @@ Conventions (shared with the library as data, each side with its own code):
   output: u' = sigmoid(z_K); the flow density of u' is
       log q(u') = sum_d log sig'(z_0,d) - sum_l sum_b s_{l,b} - sum_d log sig'(z_K,d),
   with log sig'(z) = -|z| - 2 log(1 + e^{-|z|}).
-  MLP per layer: X1 = [z_A, 1, 0...] (16 wide), H1 = relu(X1 W1t^T) (the bias of the first layer
+  MLP per layer: X1 = [sigmoid(z_A), 1, 0...] (16 wide: the conditioning variables enter in the
+  bounded coordinates u_A = sigmoid(z_A) so that the network never sees the logit tails),
+  H1 = relu(X1 W1t^T) (the bias of the first layer
   is W1t's column d_A), H2 = relu(H1 W2t^T + b2), O = H2 W3t^T + b3 (32 wide): s_hat_b = O[b],
   t_b = O[16 + b] for b < d_B.
   BF16: every matmul input (weights and activations) is rounded to bfloat16 (round to nearest
@@ -68,7 +70,7 @@ def split(mask):
 def mlp(p, zA, dB):
     N, dA = zA.shape
     X1 = np.zeros((N, KIN))
-    X1[:, :dA] = zA
+    X1[:, :dA] = sigmoid(zA)
     X1[:, dA] = 1.0
     pre1 = bf16(X1) @ bf16(p["W1t"]).T
     H1 = np.maximum(pre1, 0.0)
@@ -196,10 +198,20 @@ def loss_and_grad(theta, masks, uprime, w):
         dX1 = dpre1b @ bf16(p["W1t"])
         Gn = G.copy()
         Gn[:, B] = GB * e
-        Gn[:, A] += dX1[:, :dA]
+        sA = sigmoid(zin[:, A])
+        Gn[:, A] += dX1[:, :dA] * sA * (1.0 - sA)
         G = Gn
         grads.append(np.concatenate([g["W1t"].ravel(), g["W2t"].ravel(), g["b2"], g["W3t"].ravel(), g["b3"]]))
     return loss, np.concatenate(grads)
+
+
+def mixture_weight(jac_grid, lq, alpha):
+    """Weight of a point drawn from the defensive mixture alpha q + (1 - alpha) u, with u the
+    uniform density of the VEGAS cube: the point's grid weight divided by the mixture density (the
+    balance heuristic of multiple importance sampling, Veach and Guibas 1995; the mixture mirrors
+    the alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised).  Unbiased for any split of the
+    samples in the proportions alpha : 1 - alpha, and never above jac_grid / (1 - alpha)."""
+    return np.asarray(jac_grid, dtype=np.float64) / (alpha * np.exp(np.asarray(lq, dtype=np.float64)) + (1.0 - alpha))
 
 
 def adam_step(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -98,7 +98,7 @@ def lib():
         "dmc_flow_param_count": (I32, [P, ctypes.POINTER(I64)]),
         "dmc_flow_set_params": (I32, [P, P, P]),
         "dmc_flow_get_params": (I32, [P, P, P]),
-        "dmc_flow_sample": (I32, [P, P, U64, U64, I64, P, I64, P, P, P, P]),
+        "dmc_flow_sample": (I32, [P, P, U64, U64, I64, P, I64, P, P, P, F64, P]),
         "dmc_flow_log_density": (I32, [P, P, I64, I64, P, P]),
         "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
         "dmc_flow_destroy": (None, [P]),
@@ -315,42 +315,116 @@ def sigma_function():
     return SigmaFn
 
 
-def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int = 5, seed: int = 1,
-              kind: int = SAMPLER_VEGAS, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0, alpha: float = 0.5):
-    """Importance-sampling estimate of Sigma (and derivative roots) with the library's sampler.
-
-    `adapt` iterations refine the VEGAS grid (their samples are discarded); the next `iters`
-    iterations use the frozen grid and accumulate into one FP64 accumulator, whose mean over all
-    frozen samples is the estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K]."""
-    import numpy as np
-    import torch
-    dev = torch.device("cuda", torch.cuda.current_device())
+def _n_groups(inst):
     lams = []
     for p in inst:
         if p[2] not in lams:
             lams.append(p[2])
-    K = len(k_ext)
+    return len(lams)
+
+
+def adapt_grid(graph: Graph, inst, k_ext, sampler: Sampler, n_samples: int, iters: int, seed: int = 1,
+               first: int = 0, alpha: float = 0.5):
+    """`iters` VEGAS refinements of the sampler's grid on batches of `n_samples` points (the samples
+    are discarded).  Returns the next unused sample index."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
     D = dim(graph.order)
-    s = Sampler(kind, graph.order, n_bins, beta, qmax)
-    acc = Accumulator(len(lams), K, graph.n_roots)
+    acc = Accumulator(_n_groups(inst), len(k_ext), graph.n_roots)
     X = torch.empty((D, n_samples), dtype=torch.float32, device=dev)
     J = torch.empty(n_samples, dtype=torch.float32, device=dev)
     imp = torch.empty(n_samples, dtype=torch.float32, device=dev)
     ks = np.asarray(k_ext, dtype=np.float32)
-    it = 0
-    for a in range(adapt if kind == SAMPLER_VEGAS else 0):
+    for _ in range(iters):
         acc.reset()
-        s.sample(seed, it * n_samples, X, J)
+        sampler.sample(seed, first, X, J)
         eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
-        accumulate(acc, s, imp)
-        s.refine(alpha)
-        it += 1
-    acc.reset()
-    for a in range(iters):
-        s.sample(seed, it * n_samples, X, J)
+        accumulate(acc, sampler, imp)
+        sampler.refine(alpha)
+        first += n_samples
+    return first
+
+
+def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs: int = 8, steps: int = 16,
+               minibatch: int = 1 << 16, lr: float = 1e-3, alpha: float = 0.9, seed: int = 3):
+    """Fit `flow` (on the VEGAS coordinates of `sampler`, whose grid stays frozen) to the absolute
+    integrand by the weighted forward KL of Appendix A, with Adam on the device.
+
+    Every step draws `minibatch` new points, evaluates the graph on them (the training weight of a
+    point is its importance value, sum |f| J over the proposal density) and takes one step.  The
+    first epoch draws from the grid alone; later epochs from the mixture alpha q + (1 - alpha) of
+    the current flow, so the training points follow the flow as it sharpens.  Returns the loss of
+    the last step of every epoch."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    D = dim(graph.order)
+    if flow.dim != D:
+        raise ValueError("flow dimension does not match the graph's order")
+    ks = np.asarray(k_ext, dtype=np.float32)
+    acc = Accumulator(_n_groups(inst), len(ks), graph.n_roots)
+    X = torch.empty((D, minibatch), dtype=torch.float32, device=dev)
+    J = torch.empty(minibatch, dtype=torch.float32, device=dev)
+    U = torch.empty((D, minibatch), dtype=torch.float32, device=dev)
+    imp = torch.empty(minibatch, dtype=torch.float32, device=dev)
+    losses = []
+    step = 0
+    for ep in range(epochs):
+        loss = None
+        for b in range(steps):
+            first = step * minibatch
+            last = b == steps - 1
+            if ep == 0:
+                sampler.sample(seed, first, X, J)
+                eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
+                loss = flow.train_step(imp, seed=seed, first=first, lr=lr, want_loss=last)
+            else:
+                flow.sample(sampler, seed, first, X, J, u_out=U, alpha=alpha)
+                eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
+                loss = flow.train_step(imp, u=U, lr=lr, want_loss=last)
+            acc.reset()
+            step += 1
+        losses.append(loss)
+    return losses
+
+
+def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int = 5, seed: int = 1,
+              kind: int = SAMPLER_VEGAS, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0, alpha: float = 0.5,
+              flow: "Flow | None" = None, flow_alpha: float = 0.9, train: dict | None = None):
+    """Importance-sampling estimate of Sigma (and derivative roots) with the library's sampler.
+
+    `adapt` iterations refine the VEGAS grid (their samples are discarded).  With a `flow`, it is
+    then trained on the frozen grid (`train`: keyword arguments of train_flow; None skips training)
+    and the estimate draws from the mixture flow_alpha q + (1 - flow_alpha).  The next `iters`
+    iterations accumulate into one FP64 accumulator, whose mean over all estimation samples is the
+    estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K]."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ks = np.asarray(k_ext, dtype=np.float32)
+    D = dim(graph.order)
+    s = Sampler(kind, graph.order, n_bins, beta, qmax)
+    first = 0
+    if kind == SAMPLER_VEGAS:
+        first = adapt_grid(graph, inst, ks, s, n_samples, adapt, seed=seed, alpha=alpha)
+    if flow is not None:
+        if kind != SAMPLER_VEGAS:
+            raise ValueError("the flow maps onto a VEGAS grid")
+        if train is not None:
+            train_flow(graph, inst, ks, s, flow, **dict({"seed": seed + 1}, **train))
+    acc = Accumulator(_n_groups(inst), len(ks), graph.n_roots)
+    X = torch.empty((D, n_samples), dtype=torch.float32, device=dev)
+    J = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    est_seed = seed + 2 if flow is not None else seed
+    for _ in range(iters):
+        if flow is not None:
+            flow.sample(s, est_seed, first, X, J, alpha=flow_alpha)
+        else:
+            s.sample(seed, first, X, J)
         eval_batch(graph, inst, ks, X, J, acc)
         accumulate(acc)
-        it += 1
+        first += n_samples
     m, e, ns, nf = acc.estimate(len(inst))
     return m, e
 
@@ -381,11 +455,12 @@ class Flow:
         _check(lib().dmc_flow_get_params(self.h, t.ctypes.data_as(P), _stream(stream)))
         return t
 
-    def sample(self, sampler: Sampler, seed: int, first: int, x, jac, u_out=None, lq_out=None, stream=None):
+    def sample(self, sampler: Sampler, seed: int, first: int, x, jac, u_out=None, lq_out=None, alpha: float = 1.0,
+               stream=None):
         n = jac.numel()
         _check(lib().dmc_flow_sample(self.h, sampler.h, seed, first, n, _dptr(x, "float32", "x"), x.shape[1],
                                      _dptr(jac, "float32", "jac"), _dptr(u_out, "float32", "u_out"),
-                                     _dptr(lq_out, "float32", "lq_out"), _stream(stream)))
+                                     _dptr(lq_out, "float32", "lq_out"), alpha, _stream(stream)))
 
     def log_density(self, u, lq, stream=None):
         _check(lib().dmc_flow_log_density(self.h, _dptr(u, "float32", "u"), u.shape[1], lq.numel(),

@@ -591,20 +591,24 @@ struct dmc_flow {
     int cap_part = 0;
     float* states = nullptr;
     float* G = nullptr;
+    float* weff = nullptr;
     float* loss_part = nullptr;
     __bf16* acts = nullptr;
     float* partial = nullptr;
     double* sums = nullptr;
+    float* mix_lq = nullptr;
+    int64_t mix_cap = 0;
 };
 
 namespace {
 void free_train(dmc_flow* f) {
     (void)hipFree(f->states);
     (void)hipFree(f->G);
+    (void)hipFree(f->weff);
     (void)hipFree(f->loss_part);
     (void)hipFree(f->acts);
     (void)hipFree(f->partial);
-    f->states = f->G = f->loss_part = f->partial = nullptr;
+    f->states = f->G = f->weff = f->loss_part = f->partial = nullptr;
     f->acts = nullptr;
     f->cap_n = 0;
     f->cap_part = 0;
@@ -612,6 +616,8 @@ void free_train(dmc_flow* f) {
 constexpr int kActRows = dmc::FKIN + dmc::FH + dmc::FH + dmc::FNOUT + dmc::FH + dmc::FH;  // 560
 constexpr int kWgradChunk = 1024;
 }  // namespace
+
+static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n);
 
 extern "C" {
 
@@ -650,7 +656,7 @@ dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, d
     HIP_ALLOC(hipMalloc(&f->m, sizeof(float) * P));
     HIP_ALLOC(hipMalloc(&f->v, sizeof(float) * P));
     HIP_ALLOC(hipMalloc(&f->shadow, sizeof(__bf16) * (size_t)n_layers * dmc::SHADOW_LAYER));
-    HIP_ALLOC(hipMalloc(&f->sums, sizeof(double) * 2));
+    HIP_ALLOC(hipMalloc(&f->sums, sizeof(double) * 4));
     HIP_TRY(hipMemcpy(f->d_aidx, aidx.data(), sizeof(int) * aidx.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(f->d_bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(f->d_dA, dA.data(), sizeof(int) * dA.size(), hipMemcpyHostToDevice));
@@ -690,33 +696,73 @@ dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream) {
     return DMC_OK;
 }
 
-dmc_status dmc_flow_sample(dmc_flow* f, const dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
-                           int64_t ld, float* jac, float* u_out, float* lq_out, void* stream) {
+dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
+                           int64_t ld, float* jac, float* u_out, float* lq_out, double alpha, void* stream) {
     if (!f || !s || !x || !jac) return fail(DMC_E_INVALID, "null argument");
-    if (s->dim != f->dim) return fail(DMC_E_INVALID, "sampler and flow dimensions differ");
+    if (s->dim != f->dim || s->kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_INVALID, "need a VEGAS sampler of the flow's dimension");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
-    dmc::FlowSampleArgs a;
-    a.seed = seed;
-    a.first = first;
-    a.n = n;
-    a.ld = ld;
-    a.x = x;
-    a.jac = jac;
-    a.u_out = u_out;
-    a.lq_out = lq_out;
-    a.edges = s->d_edges;
-    a.master = f->master;
-    a.shadow = f->shadow;
-    a.aidx = f->d_aidx;
-    a.bidx = f->d_bidx;
-    a.dA = f->d_dA;
-    a.n_layers = f->n_layers;
-    a.n_bins = s->n_bins;
-    a.beta = (float)s->beta;
-    a.qmax = (float)s->qmax;
-    a.jl = (float)(4.0 * M_PI * s->qmax);
-    a.jt = (float)std::pow(s->beta, s->order - 1);
-    HIP_TRY(dmc::launch_flow_sample(a, f->dim, cu_count(), S(stream)));
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in (0, 1]");
+    // balance-heuristic mixture: the first n_g samples come from the grid alone, the rest from the flow
+    const int64_t n_g = alpha < 1.0 ? (int64_t)std::llround((1.0 - alpha) * (double)n) : 0;
+    const int64_t n_f = n - n_g;
+    if (n_g > 0) {
+        dmc_status st = dmc_sample(s, seed, first, n_g, x, ld, jac, stream);
+        if (st != DMC_OK) return st;
+        float* lq = lq_out;
+        if (!lq) {
+            if (!f->mix_lq || f->mix_cap < n_g) {
+                (void)hipFree(f->mix_lq);
+                f->mix_lq = nullptr;
+                f->mix_cap = 0;
+                HIP_ALLOC(hipMalloc(&f->mix_lq, sizeof(float) * (size_t)n_g));
+                f->mix_cap = n_g;
+            }
+            lq = f->mix_lq;
+        }
+        // the inverse pass alone: density of the grid's points under the flow, nothing stored
+        const int nblk = dmc::flow_train_blocks(n_g, cu_count());
+        dmc::FlowTrainArgs a;
+        train_args(f, a, n_g);
+        a.u_in = nullptr;
+        a.seed = seed;
+        a.first = first;
+        a.ld = ld;
+        a.states = nullptr;
+        a.G = nullptr;
+        a.weff = nullptr;
+        a.w = nullptr;
+        a.loss_part = nullptr;
+        a.lq_out = lq;
+        a.u_out = u_out;
+        HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
+        HIP_TRY(dmc::launch_flow_mix(jac, lq, n_g, (float)alpha, S(stream)));
+    }
+    if (n_f > 0) {
+        dmc::FlowSampleArgs a;
+        a.seed = seed;
+        a.first = first + (uint64_t)n_g;
+        a.n = n_f;
+        a.ld = ld;
+        a.x = x + n_g;
+        a.jac = jac + n_g;
+        a.u_out = u_out ? u_out + n_g : nullptr;
+        a.lq_out = lq_out ? lq_out + n_g : nullptr;
+        a.edges = s->d_edges;
+        a.master = f->master;
+        a.shadow = f->shadow;
+        a.aidx = f->d_aidx;
+        a.bidx = f->d_bidx;
+        a.dA = f->d_dA;
+        a.n_layers = f->n_layers;
+        a.n_bins = s->n_bins;
+        a.beta = (float)s->beta;
+        a.qmax = (float)s->qmax;
+        a.jl = (float)(4.0 * M_PI * s->qmax);
+        a.jt = (float)std::pow(s->beta, s->order - 1);
+        a.alpha = (float)alpha;
+        HIP_TRY(dmc::launch_flow_sample(a, f->dim, cu_count(), S(stream)));
+    }
+    s->last_n = -1;  // the grid histogram does not apply to mixture samples
     return DMC_OK;
 }
 
@@ -727,6 +773,7 @@ static dmc_status flow_scratch(dmc_flow* f, int64_t n, int nblk) {
     const int cp = std::max(nblk, (int)((cn + kWgradChunk - 1) / kWgradChunk));
     HIP_ALLOC(hipMalloc(&f->states, sizeof(float) * (size_t)f->n_layers * f->dim * cn));
     HIP_ALLOC(hipMalloc(&f->G, sizeof(float) * (size_t)f->dim * cn));
+    HIP_ALLOC(hipMalloc(&f->weff, sizeof(float) * (size_t)cn));
     HIP_ALLOC(hipMalloc(&f->acts, sizeof(__bf16) * (size_t)kActRows * cn));
     HIP_ALLOC(hipMalloc(&f->loss_part, sizeof(float) * (size_t)cp));
     HIP_ALLOC(hipMalloc(&f->partial, sizeof(float) * (size_t)f->n_layers * cp * dmc::LAYER_SIZE));
@@ -747,7 +794,9 @@ static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n) {
     a.dim = f->dim;
     a.states = f->states;
     a.G = f->G;
+    a.weff = f->weff;
     a.loss_part = f->loss_part;
+    if (!f->acts) return;  // density-only passes before any training scratch exists
     __bf16* p = f->acts;
     a.act_x1 = p;
     p += (size_t)dmc::FKIN * n;
@@ -766,15 +815,15 @@ dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t
     if (!f || !u || !lq) return fail(DMC_E_INVALID, "null argument");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
     const int nblk = dmc::flow_train_blocks(n, cu_count());
-    dmc_status st = flow_scratch(f, 1024, nblk);
-    if (st != DMC_OK) return st;
     dmc::FlowTrainArgs a;
     train_args(f, a, n);
     a.u_in = u;
     a.ld = ld;
     a.states = nullptr;
     a.G = nullptr;
+    a.weff = nullptr;
     a.w = nullptr;
+    a.loss_part = nullptr;
     a.lq_out = lq;
     HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
     return DMC_OK;
@@ -797,18 +846,19 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
     a.seed = seed;
     a.first = first;
     a.w = w;
+    a.inv_wsum = f->sums + 2;
+    HIP_TRY(dmc::launch_flow_sums(w, n, f->sums, S(stream)));
     HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
     for (int l = 0; l < f->n_layers; ++l)
         HIP_TRY(dmc::launch_flow_backward(a, nblk, l, kWgradChunk, wg_blocks,
                                           f->partial + (size_t)l * f->cap_part * dmc::LAYER_SIZE, S(stream)));
-    HIP_TRY(dmc::launch_flow_sums(w, n, f->loss_part, nblk, f->sums, S(stream)));
+    HIP_TRY(dmc::launch_flow_loss(f->loss_part, nblk, f->sums, S(stream)));
     dmc::FlowAdamArgs ad;
     ad.partial = f->partial;
     ad.nblk = wg_blocks;
     ad.nblk_max = f->cap_part;
     ad.n_layers = f->n_layers;
     ad.apply = lr > 0;
-    ad.wsum = f->sums;
     ad.master = f->master;
     ad.m = f->m;
     ad.v = f->v;
@@ -823,10 +873,11 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
     ad.b2t = std::pow(ad.b2, (double)std::max<int64_t>(f->step, 1));
     HIP_TRY(dmc::launch_flow_adam(ad, ncu, S(stream)));
     if (loss) {
-        double h[2];
+        double h[4];
         HIP_TRY(hipStreamSynchronize(S(stream)));
         HIP_TRY(hipMemcpy(h, f->sums, sizeof(h), hipMemcpyDeviceToHost));
         *loss = h[1];
+        if (!std::isfinite(h[0]) || !(h[0] > 0)) return fail(DMC_E_NUMERIC, "weights sum to zero or are not finite");
     }
     return DMC_OK;
 }
@@ -842,6 +893,7 @@ void dmc_flow_destroy(dmc_flow* f) {
     (void)hipFree(f->v);
     (void)hipFree(f->shadow);
     (void)hipFree(f->sums);
+    (void)hipFree(f->mix_lq);
     delete f;
 }
 

@@ -1,7 +1,7 @@
 // Affine-coupling normalizing flow on gfx950 BF16 MFMA (Appendix A: coupling layers, eq.
 // coupling_layer; density by eq. NFtransform; forward-KL training).
 //
-// Network per coupling layer: X1 = [z_A, 1, 0..] (16) -> relu(X1 W1t^T) (128) -> relu(. W2t^T + b2)
+// Network per coupling layer: X1 = [sigmoid(z_A), 1, 0..] (16) -> relu(X1 W1t^T) (128) -> relu(. W2t^T + b2)
 // (128) -> . W3t^T + b3 (32): s = S_MAX tanh(O[b]), t = O[16 + b] for the d_B transformed dims.
 // All matmuls run as v_mfma_f32_32x32x16_bf16 in the transposed form H^T = W^T X^T: the A operand
 // is a weight tile (rows = outputs, 8 consecutive K per lane), the B operand an activation tile
@@ -150,10 +150,10 @@ __device__ void wave_mlp_lds(char* sm, char* wb, int dA) {
     float* ob = (float*)(wb + WaveLds<D>::h);
     const float* zr = (const float*)(wb + WaveLds<D>::z) + lane * WaveLds<D>::ZS;
 
-    // X1 row of this lane's sample: z_A, then the constant 1 that carries the first-layer bias
+    // X1 row of this lane's sample: sigmoid(z_A), then the constant 1 that carries the first-layer bias
 #pragma unroll
     for (int k = 0; k < FKIN; ++k) {
-        const float v = k < dA ? zr[ix[k]] : (k == dA ? 1.0f : 0.0f);
+        const float v = k < dA ? 1.0f / (1.0f + expf(-zr[ix[k]])) : (k == dA ? 1.0f : 0.0f);
         x1[lane * XS + k] = (__bf16)v;
     }
     wave_sync();
@@ -319,7 +319,9 @@ __global__ void __launch_bounds__(256) dmc_flow_sample_kernel(FlowSampleArgs a) 
             }
 #pragma unroll
             for (int j = 1; j < N; ++j) a.x[(int64_t)(3 * N + j - 1) * a.ld + s] = a.beta * y[3 * N + j - 1];
-            a.jac[s] = J * a.jt * expf(-lq);
+            // weight against the mixture density alpha q_flow + (1 - alpha): bounded by the grid's
+            // own Jacobian / (1 - alpha) in the flow's tails
+            a.jac[s] = J * a.jt / __builtin_fmaf(a.alpha, expf(lq), 1.0f - a.alpha);
             if (a.lq_out) a.lq_out[s] = lq;
         }
     }
@@ -352,7 +354,7 @@ __device__ void tile_mlp_global(const __bf16* wl, const float* ml, char* wb, con
     if (lane < 32) {
 #pragma unroll
         for (int k = 0; k < FKIN; ++k) {
-            const float v = (k < dA && have_row) ? zrow[aidx[k]] : (k == dA ? 1.0f : 0.0f);
+            const float v = (k < dA && have_row) ? 1.0f / (1.0f + expf(-zrow[aidx[k]])) : (k == dA ? 1.0f : 0.0f);
             x1[lane * XS + k] = (__bf16)v;
         }
     }
@@ -435,6 +437,9 @@ __global__ void __launch_bounds__(256) dmc_flow_inverse_kernel(FlowTrainArgs a) 
                     philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
                     up = ((float)(c[d & 3] >> 8) + 0.5f) * 0x1p-24f;
                 }
+                // outputs that rounded to 0 or 1 in FP32 are taken at the nearest interior point
+                up = fminf(fmaxf(up, 0x1p-25f), 0x1.fffffep-1f);  // 1 - 2^-24, the largest float below 1
+                if (valid && a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
                 const float z = logf(up) - log1pf(-up);
                 zr[d] = z;
                 lq -= log_sig_prime(z);
@@ -459,17 +464,18 @@ __global__ void __launch_bounds__(256) dmc_flow_inverse_kernel(FlowTrainArgs a) 
             wave_sync();
         }
         if (lane < 32) {
-            const float w = valid && a.w ? a.w[s] : 0.0f;
-            for (int d = 0; d < D; ++d) {
-                const float z = zr[d];
-                lq += log_sig_prime(z);
-                if (valid && a.G) {
-                    const float sg = 1.0f / (1.0f + expf(-z));
-                    a.G[(int64_t)d * a.n + s] = -w * (1.0f - 2.0f * sg);
+            for (int d = 0; d < D; ++d) lq += log_sig_prime(zr[d]);
+            // a sample whose density is not finite is dropped from the loss and the gradient
+            float w = valid && a.w ? (float)((double)a.w[s] * a.inv_wsum[0]) : 0.0f;
+            if (!__builtin_isfinite(lq) || !__builtin_isfinite(w)) w = 0.0f;
+            if (valid && a.weff) a.weff[s] = w;
+            if (valid && a.G)
+                for (int d = 0; d < D; ++d) {
+                    const float sg = 1.0f / (1.0f + expf(-zr[d]));
+                    a.G[(int64_t)d * a.n + s] = w != 0.0f ? -w * (1.0f - 2.0f * sg) : 0.0f;
                 }
-            }
             if (valid && a.lq_out) a.lq_out[s] = lq;
-            if (valid) loss -= w * lq;
+            if (valid && w != 0.0f) loss -= w * lq;
         }
         wave_sync();
     }
@@ -515,7 +521,7 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
             const float* orow = ob + col * OS;
             float* grow = dxb + col * OS;
             for (int o = 0; o < FNOUT; ++o) grow[o] = 0.0f;
-            const float w = valid ? a.w[s] : 0.0f;
+            const float w = valid ? a.weff[s] : 0.0f;
             for (int b = 0; b < dB; ++b) {
                 const int zi = bidx[b];
                 const float th = tanhf(orow[b]);
@@ -616,7 +622,8 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
         if (valid && lane < 32)
             for (int k = 0; k < dA; ++k) {
                 const int zi = aidx[k];
-                a.G[(int64_t)zi * a.n + s] += dxb[col * OS + k];
+                const float sg = 1.0f / (1.0f + expf(-zr[zi]));
+                a.G[(int64_t)zi * a.n + s] += dxb[col * OS + k] * sg * (1.0f - sg);
             }
         wave_sync();
     }
@@ -702,16 +709,14 @@ __global__ void __launch_bounds__(256) dmc_flow_wgrad_kernel(FlowTrainArgs a, in
 // partial losses and sum(w) (thread 0 of block 0).
 __global__ void __launch_bounds__(256) dmc_flow_adam_kernel(FlowAdamArgs a) {
     const int64_t P = (int64_t)a.n_layers * LAYER_SIZE;
-    const double inv_w = a.wsum[0] > 0.0 ? 1.0 / a.wsum[0] : 0.0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(p / LAYER_SIZE);
         const int q = (int)(p % LAYER_SIZE);
         double g = 0.0;
         const float* src = a.partial + (size_t)l * a.nblk_max * LAYER_SIZE + q;
         for (int b = 0; b < a.nblk; ++b) g += (double)src[(size_t)b * LAYER_SIZE];
-        g *= inv_w;
         if (a.grad_out) a.grad_out[p] = (float)g;
-        if (!a.apply) continue;
+        if (!a.apply || !isfinite(g)) continue;
         float th = a.master[p];
         float m = a.m[p] = (float)(a.b1 * a.m[p] + (1.0 - a.b1) * g);
         float v = a.v[p] = (float)(a.b2 * a.v[p] + (1.0 - a.b2) * g * g);
@@ -722,15 +727,21 @@ __global__ void __launch_bounds__(256) dmc_flow_adam_kernel(FlowAdamArgs a) {
     }
 }
 
+// samples drawn from the grid alone: J <- J / (alpha q_flow + 1 - alpha)
+__global__ void dmc_flow_mix_kernel(float* jac, const float* lq, int64_t n, float alpha) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        jac[i] = jac[i] / __builtin_fmaf(alpha, expf(lq[i]), 1.0f - alpha);
+}
+
 __global__ void __launch_bounds__(256) dmc_flow_shadow_kernel(const float* master, __bf16* shadow, int n_layers) {
     const int64_t P = (int64_t)n_layers * LAYER_SIZE;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
         write_shadow(shadow, (int)(p / LAYER_SIZE), (int)(p % LAYER_SIZE), master[p]);
 }
 
-// sum of w and of the block losses in a fixed order (one block)
-__global__ void __launch_bounds__(256) dmc_flow_sums_kernel(const float* w, int64_t n, const float* loss_part,
-                                                           int nblk, double* out) {
+// sum of w in a fixed order (one block): out[0] = sum, out[2] = 1 / sum (0 if the sum is not
+// positive and finite); the normalised loss is folded by dmc_flow_loss_kernel after the pass
+__global__ void __launch_bounds__(256) dmc_flow_sums_kernel(const float* w, int64_t n, double* out) {
     __shared__ double red[256];
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) acc += (double)w[i];
@@ -742,9 +753,15 @@ __global__ void __launch_bounds__(256) dmc_flow_sums_kernel(const float* w, int6
     }
     if (threadIdx.x == 0) {
         out[0] = red[0];
+        out[2] = (red[0] > 0.0 && red[0] < 1e300) ? 1.0 / red[0] : 0.0;
+    }
+}
+
+__global__ void dmc_flow_loss_kernel(const float* loss_part, int nblk, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
         double L = 0.0;
         for (int b = 0; b < nblk; ++b) L += (double)loss_part[b];
-        out[1] = red[0] > 0 ? L / red[0] : 0.0;
+        out[1] = L;
     }
 }
 
@@ -811,13 +828,25 @@ hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int
     return hipGetLastError();
 }
 
-hipError_t launch_flow_sums(const float* w, int64_t n, const float* loss_part, int nblk, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_flow_sums_kernel, dim3(1), dim3(256), 0, st, w, n, loss_part, nblk, out);
+hipError_t launch_flow_sums(const float* w, int64_t n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_flow_sums_kernel, dim3(1), dim3(256), 0, st, w, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_loss(const float* loss_part, int nblk, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_flow_loss_kernel, dim3(1), dim3(64), 0, st, loss_part, nblk, out);
     return hipGetLastError();
 }
 
 hipError_t launch_flow_adam(const FlowAdamArgs& a, int n_cu, hipStream_t st) {
     hipLaunchKernelGGL(dmc_flow_adam_kernel, dim3(n_cu * 4), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_mix(float* jac, const float* lq, int64_t n, float alpha, hipStream_t st) {
+    const int64_t want = (n + 255) / 256;
+    hipLaunchKernelGGL(dmc_flow_mix_kernel, dim3((unsigned)(want < 4096 ? want : 4096)), dim3(256), 0, st, jac, lq, n,
+                       alpha);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct FlowSampleArgs {
     const int* dA;    // [L]
     int n_layers, n_bins;
     float beta, qmax, jl, jt;
+    float alpha;  // share of the flow in the sampling mixture alpha q_flow + (1 - alpha)
 };
 
 struct FlowTrainArgs {
@@ -70,6 +71,7 @@ struct FlowTrainArgs {
     uint64_t seed, first;
     int64_t n, ld;
     const float* w;     // [n] importance weights
+    const double* inv_wsum;  // device: 1 / sum(w) (the weights enter normalised)
     const float* master;
     const __bf16* shadow;
     const int* aidx;
@@ -78,7 +80,9 @@ struct FlowTrainArgs {
     int n_layers, dim;
     float* states;      // [L][D][n]
     float* G;           // [D][n]
+    float* weff;        // [n]: w / sum(w), or 0 for a sample whose density is not finite
     float* lq_out;      // nullable [n]
+    float* u_out;       // nullable [D][ld]: the points u' used (Philox uniforms when u_in is NULL)
     float* loss_part;   // [blocks]
     __bf16* act_x1;     // [16][n]
     __bf16* act_h1;     // [128][n]
@@ -91,7 +95,6 @@ struct FlowTrainArgs {
 struct FlowAdamArgs {
     const float* partial;  // [L][nblk_max][LAYER_SIZE]
     int nblk, nblk_max, n_layers, apply;
-    const double* wsum;    // device: sum of w
     float* master;
     float* m;
     float* v;
@@ -106,8 +109,10 @@ int flow_train_blocks(int64_t n, int n_cu);
 hipError_t launch_flow_inverse(const FlowTrainArgs& a, int nblk, hipStream_t st);
 hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int wg_chunk, int wg_blocks,
                                 float* partial_layer, hipStream_t st);
-hipError_t launch_flow_sums(const float* w, int64_t n, const float* loss_part, int nblk, double* out, hipStream_t st);
+hipError_t launch_flow_sums(const float* w, int64_t n, double* out, hipStream_t st);
+hipError_t launch_flow_loss(const float* loss_part, int nblk, double* out, hipStream_t st);
 hipError_t launch_flow_adam(const FlowAdamArgs& a, int n_cu, hipStream_t st);
+hipError_t launch_flow_mix(float* jac, const float* lq, int64_t n, float alpha, hipStream_t st);
 hipError_t launch_flow_shadow(const float* master, __bf16* shadow, int n_layers, int n_cu, hipStream_t st);
 
 }  // namespace dmc

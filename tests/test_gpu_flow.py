@@ -139,3 +139,65 @@ def test_training_lowers_the_loss_and_adam_matches_oracle_step():
         losses.append(f.train_step(W, seed=33, first=0, lr=3e-3))
     print(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < losses[0] - 1.0
+
+
+@pytest.mark.parametrize("alpha,N", [(0.6, 1000), (0.9, 4099)])
+def test_mixture_samples_match_oracle(alpha, N):
+    torch, dev = torch_dev()
+    D, n = 11, 3
+    f, m, th = _flow(D, scale=0.03, seed=2)
+    seed, first = 0x51A3, 1 << 33
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    grid = synth.vegas_grid(D, 50, seed=4).astype(np.float64)
+    s.set_grid(grid)
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    Uo = torch.empty((D, N), dtype=torch.float32, device=dev)
+    LQ = torch.empty(N, dtype=torch.float32, device=dev)
+    f.sample(s, seed, first, X, J, u_out=Uo, lq_out=LQ, alpha=alpha)
+    n_g = int(np.floor((1 - alpha) * N + 0.5))
+    X2 = torch.empty((D, n_g), dtype=torch.float32, device=dev)
+    J2 = torch.empty(n_g, dtype=torch.float32, device=dev)
+    s.sample(seed, first, X2, J2)
+    torch.cuda.synchronize()
+    xg, jg = X.cpu().numpy().T.astype(np.float64), J.cpu().numpy().astype(np.float64)
+    ug, lqg = Uo.cpu().numpy().T.astype(np.float64), LQ.cpu().numpy().astype(np.float64)
+    # the grid's share: the sampler's own points, weighted by the mixture at the flow's density there
+    assert np.array_equal(xg[:n_g], X2.cpu().numpy().T)
+    u, _ = osp.uniforms(seed, first, n_g, D)
+    assert np.max(np.abs(ug[:n_g] - u)) < 1e-7
+    lq_ref = ofl.log_q(th, m, u)
+    assert np.median(np.abs(lqg[:n_g] - lq_ref)) < 1e-4 and np.max(np.abs(lqg[:n_g] - lq_ref)) < 5e-3
+    jv = J2.cpu().numpy().astype(np.float64)
+    assert np.allclose(jg[:n_g], ofl.mixture_weight(jv, lqg[:n_g], alpha), rtol=2e-6)
+    # the flow's share: counters first + n_g onwards through the flow
+    uf, _ = osp.uniforms(seed, first + n_g, N - n_g, D)
+    up, lq, _ = ofl.sample(th, m, uf)
+    assert np.max(np.abs(ug[n_g:] - up)) < 2e-3
+    assert np.median(np.abs(lqg[n_g:] - lq)) < 1e-4 and np.max(np.abs(lqg[n_g:] - lq)) < 5e-3
+    y, JV, _ = osp.vegas_map_float(ug[n_g:].astype(np.float32), grid.astype(np.float32).astype(np.float64))
+    xr, Jp = ig.physical_map(y, n, BETA, 6.0)
+    assert np.allclose(xg[n_g:], xr, rtol=0, atol=6.0 * 1e-5)
+    assert np.allclose(jg[n_g:], ofl.mixture_weight(JV * Jp, lqg[n_g:], alpha), rtol=1e-4)
+    # bounded weights: never above the grid's own weight / (1 - alpha)
+    assert np.all(jg[:n_g] <= jv / (1 - alpha) * (1 + 1e-5))
+
+
+def test_trained_flow_integral_unbiased_and_lower_variance():
+    from oracle import physics as ph
+    torch, dev = torch_dev()
+    n, D = 2, 7
+    inst = [(BETA, 1.0, 1.0, ph.coupling(1.0))]
+    ks = np.linspace(0.0, 2.0, 8).astype(np.float32)
+    g = dmc.Graph(n)
+    mv, ev = dmc.integrate(g, inst, ks, 1 << 20, iters=4, adapt=6, seed=21)
+    masks = synth.flow_masks(D, L, 5)
+    f = dmc.Flow(D, masks)
+    f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+    mf, ef = dmc.integrate(g, inst, ks, 1 << 20, iters=4, adapt=6, seed=21, flow=f, flow_alpha=0.9,
+                           train=dict(epochs=5, steps=16, minibatch=1 << 16, lr=1e-3))
+    z = (mv[0, 0].real - mf[0, 0].real) / np.hypot(ev[0, 0].real, ef[0, 0].real)
+    ratio = (ev[0, 0].real / ef[0, 0].real) ** 2
+    print("z", np.round(z, 2), "variance ratio", np.round(ratio, 2))
+    assert np.all(np.abs(z) < 4.5)
+    assert np.mean(ratio) > 2.0

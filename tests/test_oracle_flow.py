@@ -97,7 +97,7 @@ def _torch_loss(th, m, up, w):
     for l in reversed(range(len(m))):
         A = np.nonzero(m[l] == 1)[0]; B = np.nonzero(m[l] == 0)[0]
         W1t, W2t, b2, W3t, b3 = lay[l]
-        X1 = torch.cat([z[:, A], torch.ones(z.shape[0], 1, dtype=torch.float64),
+        X1 = torch.cat([torch.sigmoid(z[:, A]), torch.ones(z.shape[0], 1, dtype=torch.float64),
                         torch.zeros(z.shape[0], 16 - len(A) - 1, dtype=torch.float64)], dim=1)
         H1 = torch.relu(X1 @ W1t.T)
         H2 = torch.relu(H1 @ W2t.T + b2)
@@ -142,3 +142,25 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert r[0] == 1.0 and r[1] == 1.0 and r[3] == 1.0078125
     assert r[2] == 1.0078125
     assert abs(r[4] - (-3.140625)) < 1e-12
+
+
+def test_mixture_estimate_unbiased_and_bounded():
+    # integral of prod_d 3 u_d^2 over the cube is 1: points from the grid (uniform) and from a
+    # strongly non-uniform flow, in the proportions 1 - alpha : alpha, weighted by the mixture
+    with smooth():
+        m, th = _setup(scale=0.4, seed=4)
+        rng = np.random.default_rng(9)
+        alpha, N = 0.7, 1 << 15
+        n_g = int(round((1 - alpha) * N))
+        ug = rng.uniform(size=(n_g, D))
+        uf, lqf, _ = fl.sample(th, m, rng.uniform(size=(N - n_g, D)))
+        u = np.concatenate([ug, uf])
+        lq = np.concatenate([fl.log_q(th, m, ug), lqf])
+        w = fl.mixture_weight(np.ones(N), lq, alpha)
+        assert w.max() <= 1.0 / (1.0 - alpha) * (1 + 1e-12)
+        assert np.exp(lq).std() > 0.3          # the flow is far from the uniform density
+        est = np.prod(3 * u ** 2, axis=1) * w
+        assert abs(est.mean() - 1.0) < 4 * est.std() / np.sqrt(N)
+        # alpha = 1 is plain flow importance sampling; alpha -> 0 the grid alone
+        assert np.allclose(fl.mixture_weight(2.0, lq, 1.0), 2.0 * np.exp(-lq))
+        assert np.allclose(fl.mixture_weight(2.0, lq, 0.0), 2.0)
