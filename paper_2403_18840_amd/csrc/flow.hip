@@ -66,6 +66,14 @@ __device__ __forceinline__ float log_sig_prime(float z) {
     return -a - 2.0f * log1pf(expf(-a));
 }
 
+// logit of the 24-bit uniform u = (m + 1/2) 2^-24, m = w >> 8: log(m + 1/2) - log(2^24 - 1 - m + 1/2).
+// Both operands are exact in FP32 wherever their logarithm is sensitive to rounding (below 2^23),
+// so the result is finite for every word (u itself rounds to 1 in FP32 at m = 2^24 - 1).
+__device__ __forceinline__ float philox_logit(uint32_t w) {
+    const uint32_t m = w >> 8;
+    return logf((float)m + 0.5f) - logf((float)(0xFFFFFFu - m) + 0.5f);
+}
+
 // ---------------------------------------------------------------- LDS geometry
 // Row strides padded by 8 BF16 (16 B) so that 16 lanes reading 16 B each hit distinct banks.
 constexpr int W1S = FKIN + 8;   // 24
@@ -266,8 +274,7 @@ __global__ void __launch_bounds__(256) dmc_flow_sample_kernel(FlowSampleArgs a) 
             for (int w = 0; w < 4; ++w) {
                 const int d = 4 * b4 + w;
                 if (d < D) {
-                    const float u = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
-                    const float z = logf(u) - log1pf(-u);
+                    const float z = philox_logit(c[w]);
                     zr[d] = z;
                     lq += log_sig_prime(z);
                 }
@@ -428,19 +435,20 @@ __global__ void __launch_bounds__(256) dmc_flow_inverse_kernel(FlowTrainArgs a) 
         float lq = 0.0f;
         if (lane < 32) {
             for (int d = 0; d < D; ++d) {
-                float up;
+                float up, z;
                 if (a.u_in) {
                     up = valid ? a.u_in[(int64_t)d * a.ld + s] : 0.5f;
+                    // outputs that rounded to 0 or 1 in FP32 are taken at the nearest interior point
+                    up = fminf(fmaxf(up, 0x1p-25f), 0x1.fffffep-1f);  // 1 - 2^-24, the largest float below 1
+                    z = logf(up) - log1pf(-up);
                 } else {
                     const uint64_t idx = a.first + (uint64_t)(valid ? s : 0);
                     uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)(d >> 2), 0u};
                     philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
                     up = ((float)(c[d & 3] >> 8) + 0.5f) * 0x1p-24f;
+                    z = philox_logit(c[d & 3]);
                 }
-                // outputs that rounded to 0 or 1 in FP32 are taken at the nearest interior point
-                up = fminf(fmaxf(up, 0x1p-25f), 0x1.fffffep-1f);  // 1 - 2^-24, the largest float below 1
                 if (valid && a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
-                const float z = logf(up) - log1pf(-up);
                 zr[d] = z;
                 lq -= log_sig_prime(z);
             }

@@ -201,3 +201,29 @@ def test_trained_flow_integral_unbiased_and_lower_variance():
     print("z", np.round(z, 2), "variance ratio", np.round(ratio, 2))
     assert np.all(np.abs(z) < 4.5)
     assert np.mean(ratio) > 2.0
+
+
+@pytest.mark.parametrize("first", [414480 - 3, 414480 - 12, 2655605 - 12])
+def test_extreme_base_words_stay_finite(first):
+    # Philox(seed 0x2403) gives the 24-bit word 2^24 - 1 at sample 414480 (dimension 1) and the
+    # word 0 at sample 2655605 (dimension 11): u = 1 - 2^-25 rounds to 1 in FP32, but the logit
+    # of the base point must stay finite and equal the oracle's; with alpha = 1/2 of 16 samples the
+    # first offset puts the sample in the grid's share, the other two in the flow's share
+    torch, dev = torch_dev()
+    D, n, N, seed = 15, 4, 16, 0x2403
+    _, mw = osp.uniforms(seed, first, N, D)
+    assert np.any(mw == 0xFFFFFF) or np.any(mw == 0)
+    f, m, th = _flow(D, scale=0.03, seed=3)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    s.set_grid(synth.vegas_grid(D, 50, seed=1).astype(np.float64))
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    LQ = torch.empty(N, dtype=torch.float32, device=dev)
+    f.sample(s, seed, first, X, J, lq_out=LQ, alpha=0.5)
+    torch.cuda.synchronize()
+    lqg = LQ.cpu().numpy().astype(np.float64)
+    assert torch.isfinite(X).all() and torch.isfinite(J).all() and np.isfinite(lqg).all()
+    u, _ = osp.uniforms(seed, first, N, D)
+    lq_grid = ofl.log_q(th, m, u[:8])
+    _, lq_flow, _ = ofl.sample(th, m, u[8:])
+    assert np.max(np.abs(lqg - np.concatenate([lq_grid, lq_flow]))) < 5e-3
