@@ -720,7 +720,7 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
             lq = f->mix_lq;
         }
         // the inverse pass alone: density of the grid's points under the flow, nothing stored
-        const int nblk = dmc::flow_train_blocks(n_g, cu_count());
+        const int nblk = dmc::flow_inverse_blocks(n_g, cu_count());
         dmc::FlowTrainArgs a;
         train_args(f, a, n_g);
         a.u_in = nullptr;
@@ -766,6 +766,9 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
     return DMC_OK;
 }
 
+// activation rows hold whole 16-sample slices (two aligned 16-byte loads per MFMA operand)
+static int64_t act_stride(int64_t n) { return (n + 15) & ~(int64_t)15; }
+
 static dmc_status flow_scratch(dmc_flow* f, int64_t n, int nblk) {
     if (n <= f->cap_n && nblk <= f->cap_part) return DMC_OK;
     free_train(f);
@@ -774,7 +777,7 @@ static dmc_status flow_scratch(dmc_flow* f, int64_t n, int nblk) {
     HIP_ALLOC(hipMalloc(&f->states, sizeof(float) * (size_t)f->n_layers * f->dim * cn));
     HIP_ALLOC(hipMalloc(&f->G, sizeof(float) * (size_t)f->dim * cn));
     HIP_ALLOC(hipMalloc(&f->weff, sizeof(float) * (size_t)cn));
-    HIP_ALLOC(hipMalloc(&f->acts, sizeof(__bf16) * (size_t)kActRows * cn));
+    HIP_ALLOC(hipMalloc(&f->acts, sizeof(__bf16) * (size_t)kActRows * act_stride(cn)));
     HIP_ALLOC(hipMalloc(&f->loss_part, sizeof(float) * (size_t)cp));
     HIP_ALLOC(hipMalloc(&f->partial, sizeof(float) * (size_t)f->n_layers * cp * dmc::LAYER_SIZE));
     f->cap_n = cn;
@@ -796,25 +799,26 @@ static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n) {
     a.G = f->G;
     a.weff = f->weff;
     a.loss_part = f->loss_part;
+    a.lda = act_stride(n);
     if (!f->acts) return;  // density-only passes before any training scratch exists
     __bf16* p = f->acts;
     a.act_x1 = p;
-    p += (size_t)dmc::FKIN * n;
+    p += (size_t)dmc::FKIN * a.lda;
     a.act_h1 = p;
-    p += (size_t)dmc::FH * n;
+    p += (size_t)dmc::FH * a.lda;
     a.act_h2 = p;
-    p += (size_t)dmc::FH * n;
+    p += (size_t)dmc::FH * a.lda;
     a.act_do = p;
-    p += (size_t)dmc::FNOUT * n;
+    p += (size_t)dmc::FNOUT * a.lda;
     a.act_dp2 = p;
-    p += (size_t)dmc::FH * n;
+    p += (size_t)dmc::FH * a.lda;
     a.act_dp1 = p;
 }
 
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream) {
     if (!f || !u || !lq) return fail(DMC_E_INVALID, "null argument");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
-    const int nblk = dmc::flow_train_blocks(n, cu_count());
+    const int nblk = dmc::flow_inverse_blocks(n, cu_count());
     dmc::FlowTrainArgs a;
     train_args(f, a, n);
     a.u_in = u;
@@ -836,8 +840,9 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
     if (!(lr >= 0)) return fail(DMC_E_INVALID, "lr must be >= 0");
     const int ncu = cu_count();
     const int nblk = dmc::flow_train_blocks(n, ncu);
+    const int nblk_inv = dmc::flow_inverse_blocks(n, ncu);
     const int wg_blocks = (int)((n + kWgradChunk - 1) / kWgradChunk);
-    dmc_status st = flow_scratch(f, n, std::max(nblk, wg_blocks));
+    dmc_status st = flow_scratch(f, n, std::max(std::max(nblk, nblk_inv), wg_blocks));
     if (st != DMC_OK) return st;
     dmc::FlowTrainArgs a;
     train_args(f, a, n);
@@ -848,11 +853,11 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
     a.w = w;
     a.inv_wsum = f->sums + 2;
     HIP_TRY(dmc::launch_flow_sums(w, n, f->sums, S(stream)));
-    HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
+    HIP_TRY(dmc::launch_flow_inverse(a, nblk_inv, S(stream)));
     for (int l = 0; l < f->n_layers; ++l)
         HIP_TRY(dmc::launch_flow_backward(a, nblk, l, kWgradChunk, wg_blocks,
                                           f->partial + (size_t)l * f->cap_part * dmc::LAYER_SIZE, S(stream)));
-    HIP_TRY(dmc::launch_flow_loss(f->loss_part, nblk, f->sums, S(stream)));
+    HIP_TRY(dmc::launch_flow_loss(f->loss_part, nblk_inv, f->sums, S(stream)));
     dmc::FlowAdamArgs ad;
     ad.partial = f->partial;
     ad.nblk = wg_blocks;

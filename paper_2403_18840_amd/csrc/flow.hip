@@ -32,6 +32,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -60,10 +64,21 @@ __device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) 
     }
 }
 
+// Hardware exp2 / log2 / reciprocal (about 1 ulp).  The flow uses them on both sides of every
+// density (the map and its log-determinant share each computed s), so their rounding changes the
+// density at the 1e-7 level only.
+constexpr float LOG2E = 1.44269504088896341f, LN2 = 0.693147180559945309f;
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * LOG2E); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * LN2; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsigmoid(float z) { return frcp(1.0f + fexp(-z)); }
+// tanh x = 1 - 2 / (1 + e^{2x}): saturates to +-1 without overflow; absolute error ~1e-7
+__device__ __forceinline__ float ftanh(float x) { return 1.0f - 2.0f * frcp(1.0f + fexp(2.0f * x)); }
+
 // log sigma'(z) = -|z| - 2 log(1 + e^{-|z|})
 __device__ __forceinline__ float log_sig_prime(float z) {
     const float a = fabsf(z);
-    return -a - 2.0f * log1pf(expf(-a));
+    return -a - 2.0f * flog(1.0f + fexp(-a));
 }
 
 // logit of the 24-bit uniform u = (m + 1/2) 2^-24, m = w >> 8: log(m + 1/2) - log(2^24 - 1 - m + 1/2).
@@ -71,7 +86,7 @@ __device__ __forceinline__ float log_sig_prime(float z) {
 // so the result is finite for every word (u itself rounds to 1 in FP32 at m = 2^24 - 1).
 __device__ __forceinline__ float philox_logit(uint32_t w) {
     const uint32_t m = w >> 8;
-    return logf((float)m + 0.5f) - logf((float)(0xFFFFFFu - m) + 0.5f);
+    return flog((float)m + 0.5f) - flog((float)(0xFFFFFFu - m) + 0.5f);
 }
 
 // ---------------------------------------------------------------- LDS geometry
@@ -82,218 +97,258 @@ constexpr int XS = FKIN + 8;    // 24
 constexpr int HS = FH + 8;      // 136
 constexpr int OS = FNOUT + 4;   // 36 floats
 
-struct FwdLds {
-    static constexpr int w1t = 0;                           // bf16 [128][W1S]
-    static constexpr int w2t = w1t + FH * W1S * 2;          // bf16 [128][W2S]
-    static constexpr int w3t = w2t + FH * W2S * 2;          // bf16 [32][W2S]
-    static constexpr int b2 = w3t + FNOUT * W2S * 2;        // f32 [128]
-    static constexpr int b3 = b2 + FH * 4;                  // f32 [32]
-    static constexpr int idx = b3 + FNOUT * 4;              // int [32]: a list (16), b list (16)
-    static constexpr int waves = idx + 32 * 4;              // per-wave regions
+// One coupling layer in LDS: the 44 weight fragments (lane-contiguous, so every fragment read is
+// one linear 1 KiB sweep without bank conflicts) and the biases: the 45 chunks of the shadow.
+struct LayerLds {
+    static constexpr int frag = 0;                  // bf16 [44][64][8]
+    static constexpr int b2 = NFRAG * 1024;         // f32 [128]
+    static constexpr int b3 = b2 + FH * 4;          // f32 [32]
+    static constexpr int bytes = NCHUNK * 1024;     // 46080
 };
 
+// The sampler and the inverse pass: 512-thread blocks (8 waves, two per SIMD), one per CU.
+// Two layer buffers: while the waves multiply with layer l, the next layer streams from L2
+// straight into the other buffer (global_load_lds, 1 KiB per wave instruction), so the only
+// synchronisation per layer is one barrier.  Per wave: the coupling states of its 64 samples
+// (two 32-sample tiles), rows of D + 2 floats (an odd stride for odd D spreads the lanes' rows
+// over the banks).
+constexpr int PASS_WAVES = 8;
+constexpr int PASS_THREADS = 64 * PASS_WAVES;
 template <int D>
-struct WaveLds {
-    static constexpr int ZS = D + 2;                        // odd row stride of the state rows
-    static constexpr int x1 = 0;                            // bf16 [64][XS]
-    static constexpr int h = x1 + 64 * XS * 2;              // bf16 [64][HS]; f32 [64][OS] aliases it
-    static constexpr int z = h + 64 * HS * 2;               // f32 [64][ZS]
-    static constexpr int bytes = z + 64 * ZS * 4;
+struct PassLds {
+    static constexpr int ZS = D + 2;
+    static constexpr int buf0 = 0;
+    static constexpr int buf1 = LayerLds::bytes;
+    static constexpr int z = 2 * LayerLds::bytes;   // f32 [8 waves][64][ZS]
+    static constexpr int bytes = z + PASS_WAVES * 64 * ZS * 4;
 };
 
-template <int D>
-constexpr int flow_fwd_lds_bytes() {
-    return FwdLds::waves + 4 * WaveLds<D>::bytes;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Start copying layer l's 45 chunks into an LDS buffer: wave w copies chunks w, w + 8, ...
+__device__ __forceinline__ void prefetch_layer(char* buf, const __bf16* shadow, int l) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const char* src = (const char*)(shadow + (size_t)l * SHADOW_LAYER + SH_FRAG);
+    for (int c = wv; c < NCHUNK; c += PASS_WAVES)
+        __builtin_amdgcn_global_load_lds((const void*)(src + c * 1024 + lane * 16), (lds_ptr)(buf + c * 1024), 16, 0, 0);
 }
 
-// stage the forward weights of one layer (global bf16 shadow, unpadded rows) into padded LDS rows
-__device__ void stage_fwd(char* sm, const __bf16* shadow, const float* master, const int* aidx, const int* bidx,
-                          int layer) {
-    const __bf16* wl = shadow + (size_t)layer * SHADOW_LAYER;
-    const float* ml = master + (size_t)layer * LAYER_SIZE;
-    __bf16* w1t = (__bf16*)(sm + FwdLds::w1t);
-    __bf16* w2t = (__bf16*)(sm + FwdLds::w2t);
-    __bf16* w3t = (__bf16*)(sm + FwdLds::w3t);
-    // 16-byte chunks: W1t 128 rows x 2, W2t 128 x 16, W3t 32 x 16
-    for (int c = threadIdx.x; c < FH * 2 + FH * 16 + FNOUT * 16; c += blockDim.x) {
-        if (c < FH * 2) {
-            const int r = c >> 1, k = (c & 1) * 8;
-            *(uint4*)(w1t + r * W1S + k) = *(const uint4*)(wl + SH_W1T + r * FKIN + k);
-        } else if (c < FH * 2 + FH * 16) {
-            const int cc = c - FH * 2, r = cc >> 4, k = (cc & 15) * 8;
-            *(uint4*)(w2t + r * W2S + k) = *(const uint4*)(wl + SH_W2T + r * FH + k);
-        } else {
-            const int cc = c - FH * 2 - FH * 16, r = cc >> 4, k = (cc & 15) * 8;
-            *(uint4*)(w3t + r * W2S + k) = *(const uint4*)(wl + SH_W3T + r * FH + k);
-        }
-    }
-    float* b2 = (float*)(sm + FwdLds::b2);
-    float* b3 = (float*)(sm + FwdLds::b3);
-    int* ix = (int*)(sm + FwdLds::idx);
-    for (int i = threadIdx.x; i < FH + FNOUT + 32; i += blockDim.x) {
-        if (i < FH)
-            b2[i] = ml[OFF_B2 + i];
-        else if (i < FH + FNOUT)
-            b3[i - FH] = ml[OFF_B3 + i - FH];
-        else {
-            const int j = i - FH - FNOUT;
-            ix[j] = j < 16 ? aidx[layer * 16 + j] : bidx[layer * 16 + j - 16];
-        }
-    }
+// every copy this wave started has landed in LDS (and all its other memory operations are done)
+__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ bf16x8 lds_frag(const char* sm, int f, int lane) {
+    return *(const bf16x8*)(sm + LayerLds::frag + f * 1024 + lane * 16);
 }
 
-// The network of one coupling layer for the wave's 64 samples (two 32-sample tiles).  On return
-// the wave's O buffer (f32 [64][OS], aliasing H) holds s_hat (columns 0..15) and t (16..31).
-template <int D>
-__device__ void wave_mlp_lds(char* sm, char* wb, int dA) {
-    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
-    const __bf16* w1t = (const __bf16*)(sm + FwdLds::w1t);
-    const __bf16* w2t = (const __bf16*)(sm + FwdLds::w2t);
-    const __bf16* w3t = (const __bf16*)(sm + FwdLds::w3t);
-    const float* b2 = (const float*)(sm + FwdLds::b2);
-    const float* b3 = (const float*)(sm + FwdLds::b3);
-    const int* ix = (const int*)(sm + FwdLds::idx);
-    __bf16* x1 = (__bf16*)(wb + WaveLds<D>::x1);
-    __bf16* hb = (__bf16*)(wb + WaveLds<D>::h);
-    float* ob = (float*)(wb + WaveLds<D>::h);
-    const float* zr = (const float*)(wb + WaveLds<D>::z) + lane * WaveLds<D>::ZS;
+// BF16 rounding and ReLU of accumulator registers 8p .. 8p + 7: the B operand of one K-slice.
+// ReLU acts on the rounded values as a packed signed 16-bit max against 0 (a BF16 with the sign
+// bit set is a negative 16-bit integer, and the non-negative ones order like integers), which
+// equals rounding after the ReLU: RNE keeps the sign, and -0 becomes +0.
+__device__ __forceinline__ unsigned relu_pair(float a, float b) {
+    const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);  // one packed RNE conversion
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), (i16x2){}));
+}
+__device__ __forceinline__ bf16x8 relu_slice(const f32x16& c, int p) {
+    const u32x4 r = {relu_pair(c[8 * p], c[8 * p + 1]), relu_pair(c[8 * p + 2], c[8 * p + 3]),
+                     relu_pair(c[8 * p + 4], c[8 * p + 5]), relu_pair(c[8 * p + 6], c[8 * p + 7])};
+    return __builtin_bit_cast(bf16x8, r);
+}
 
-    // X1 row of this lane's sample: sigmoid(z_A), then the constant 1 that carries the first-layer bias
+// bias in accumulator layout: register 4g + q of lane l holds row 8g + 4(l/32) + q
+__device__ __forceinline__ f32x16 bias_acc(const float* b, int h) {
+    f32x16 c;
 #pragma unroll
-    for (int k = 0; k < FKIN; ++k) {
-        const float v = k < dA ? 1.0f / (1.0f + expf(-zr[ix[k]])) : (k == dA ? 1.0f : 0.0f);
-        x1[lane * XS + k] = (__bf16)v;
+    for (int g = 0; g < 4; ++g) {
+        const f32x4 v = *(const f32x4*)(b + 8 * g + 4 * h);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[4 * g + q] = v[q];
     }
-    wave_sync();
-    // layer 1: 4 output tiles x 2 sample tiles, K = 16
-    bf16x8 bx[2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) bx[nt] = *(const bf16x8*)(x1 + (32 * nt + col) * XS + 8 * h);
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-        const bf16x8 aw = *(const bf16x8*)(w1t + (32 * ot + col) * W1S + 8 * h);
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            f32x16 c = {};
-            c = mfma(aw, bx[nt], c);
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                bf16x4 v;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (__bf16)fmaxf(c[4 * g + q], 0.0f);
-                *(bf16x4*)(hb + (32 * nt + col) * HS + 32 * ot + 8 * g + 4 * h) = v;
-            }
-        }
-    }
-    wave_sync();
-    // layer 2: K = 128 in 8 steps of 16; accumulators start at the bias
-    f32x16 acc[2][4];
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float bv = b2[32 * ot + 8 * (r >> 2) + 4 * h + (r & 3)];
-            acc[0][ot][r] = bv;
-            acc[1][ot][r] = bv;
-        }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        bf16x8 bb[2];
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) bb[nt] = *(const bf16x8*)(hb + (32 * nt + col) * HS + 16 * s + 8 * h);
+    return c;
+}
+
+// The network of the staged layer for two 32-sample tiles, all activations in registers:
+// x1[tile] (B operands, K = 16 inputs) -> o[tile] (s_hat in registers 0..7, t in 8..15; see
+// coupling_b for the unit each register holds).  The code issues the products of one output
+// tile before rounding the previous tile's results, so the rounding overlaps the matrix core.
+__device__ __forceinline__ void mlp_regs(const char* sm, const bf16x8 (&x1)[2], f32x16 (&o)[2]) {
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    bf16x8 h1[8][2];
+    {
+        f32x16 c[2][2];
 #pragma unroll
         for (int ot = 0; ot < 4; ++ot) {
-            const bf16x8 aw = *(const bf16x8*)(w2t + (32 * ot + col) * W2S + 16 * s + 8 * h);
-            acc[0][ot] = mfma(aw, bb[0], acc[0][ot]);
-            acc[1][ot] = mfma(aw, bb[1], acc[1][ot]);
+            const bf16x8 aw = lds_frag(sm, ot, lane);
+            c[ot & 1][0] = mfma(aw, x1[0], (f32x16){});
+            c[ot & 1][1] = mfma(aw, x1[1], (f32x16){});
+            if (ot > 0)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    h1[2 * ot - 2][nt] = relu_slice(c[(ot - 1) & 1][nt], 0);
+                    h1[2 * ot - 1][nt] = relu_slice(c[(ot - 1) & 1][nt], 1);
+                }
         }
-    }
-    wave_sync();
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                bf16x4 v;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (__bf16)fmaxf(acc[nt][ot][4 * g + q], 0.0f);
-                *(bf16x4*)(hb + (32 * nt + col) * HS + 32 * ot + 8 * g + 4 * h) = v;
-            }
-    wave_sync();
-    // layer 3: 32 outputs, K = 128
-    f32x16 o3[2];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const float bv = b3[8 * (r >> 2) + 4 * h + (r & 3)];
-        o3[0][r] = bv;
-        o3[1][r] = bv;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const bf16x8 aw = *(const bf16x8*)(w3t + col * W2S + 16 * s + 8 * h);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            const bf16x8 bb = *(const bf16x8*)(hb + (32 * nt + col) * HS + 16 * s + 8 * h);
-            o3[nt] = mfma(aw, bb, o3[nt]);
+            h1[6][nt] = relu_slice(c[1][nt], 0);
+            h1[7][nt] = relu_slice(c[1][nt], 1);
         }
     }
-    wave_sync();
+    bf16x8 h2[8][2];
+    const float* b2 = (const float*)(sm + LayerLds::b2);
+    {
+        f32x16 acc[2][2];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+        for (int ot = 0; ot < 4; ++ot) {
+            const f32x16 bias = bias_acc(b2 + 32 * ot, h);
+            f32x16* a2 = acc[ot & 1];
+            {
+                const bf16x8 aw = lds_frag(sm, 4 + 8 * ot, lane);
+                a2[0] = mfma(aw, h1[0][0], bias);
+                a2[1] = mfma(aw, h1[0][1], bias);
+            }
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            f32x4 v;
+            for (int sg = 1; sg < 8; ++sg) {
+                const bf16x8 aw = lds_frag(sm, 4 + 8 * ot + sg, lane);
+                a2[0] = mfma(aw, h1[sg][0], a2[0]);
+                a2[1] = mfma(aw, h1[sg][1], a2[1]);
+                if (sg == 2 && ot > 0)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = o3[nt][4 * g + q];
-            *(f32x4*)(ob + (32 * nt + col) * OS + 8 * g + 4 * h) = v;
+                    for (int nt = 0; nt < 2; ++nt) {
+                        h2[2 * ot - 2][nt] = relu_slice(acc[(ot - 1) & 1][nt], 0);
+                        h2[2 * ot - 1][nt] = relu_slice(acc[(ot - 1) & 1][nt], 1);
+                    }
+            }
         }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            h2[6][nt] = relu_slice(acc[1][nt], 0);
+            h2[7][nt] = relu_slice(acc[1][nt], 1);
+        }
+    }
+    const f32x16 b3 = bias_acc((const float*)(sm + LayerLds::b3), h);
+    {
+        const bf16x8 aw = lds_frag(sm, 36, lane);
+        o[0] = mfma(aw, h2[0][0], b3);
+        o[1] = mfma(aw, h2[0][1], b3);
+    }
+#pragma unroll
+    for (int sg = 1; sg < 8; ++sg) {
+        const bf16x8 aw = lds_frag(sm, 36 + sg, lane);
+        o[0] = mfma(aw, h2[sg][0], o[0]);
+        o[1] = mfma(aw, h2[sg][1], o[1]);
+    }
+}
+
+// transformed unit whose (s_hat, t) sit in output registers (r, r + 8) of a lane in half h
+__device__ __forceinline__ int coupling_b(int r, int h) { return r < 4 ? 4 * h + r : 4 + 4 * h + r; }
+
+// X1 of one tile as the B operand: lane half h supplies inputs 8h .. 8h + 7 of its sample.
+// ia: the layer's conditioning list in global memory (uniform: read through the scalar cache).
+__device__ __forceinline__ bf16x8 x1_operand(const float* zr, const int* ia, int dA, int h) {
+    bf16x8 v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int k = 8 * h + t;
+        const int zi = h ? ia[8 + t] : ia[t];
+        const float x = k < dA ? fsigmoid(zr[zi]) : (k == dA ? 1.0f : 0.0f);
+        v[t] = (__bf16)x;
+    }
+    return v;
+}
+
+// transformed-list entry of output register r (r < 8) in lane half h (ib: the layer's list)
+__device__ __forceinline__ int coupling_z(const int* ib, int r, int h) {
+    return r < 4 ? (h ? ib[4 + r] : ib[r]) : (h ? ib[8 + r] : ib[4 + r]);
+}
+
+// One coupling layer for the wave's two tiles, with the layer's weights in buf: the network
+// (registers only), then the affine update of the transformed units this lane half owns and
+// its share of the log-determinant.  Forward: z_B <- z_B e^s + t; inverse: z_B <- (z_B - t) e^-s.
+// With s = 2 tanh(x) = 2 - 4 r, r = 1 / (1 + e^{2x}): e^{+-s} = 2^{+-(2 - 4r) log2 e}.
+template <int D, bool INVERSE>
+__device__ __forceinline__ void coupling_layer(const char* buf, float* zw, const int* ia, const int* ib, int dA,
+                                               float (&lqp)[2]) {
+    constexpr int ZS = D + 2;
+    const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
+    const int dB = D - dA;
+    bf16x8 x1[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) x1[nt] = x1_operand(zw + (32 * nt + j) * ZS, ia, dA, h);
+    f32x16 o[2];
+    mlp_regs(buf, x1, o);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        float* zr = zw + (32 * nt + j) * ZS;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (coupling_b(r, h) < dB) {
+                const float rr = frcp(1.0f + __builtin_amdgcn_exp2f(o[nt][r] * (2.0f * LOG2E)));
+                const float sv = __builtin_fmaf(-2.0f * FLOW_SMAX, rr, FLOW_SMAX);
+                const int zi = coupling_z(ib, r, h);
+                if (INVERSE)
+                    zr[zi] = (zr[zi] - o[nt][r + 8]) * __builtin_amdgcn_exp2f(-sv * LOG2E);
+                else
+                    zr[zi] = __builtin_fmaf(zr[zi], __builtin_amdgcn_exp2f(sv * LOG2E), o[nt][r + 8]);
+                lqp[nt] -= sv;
+            }
+        }
+    }
     wave_sync();
 }
 
+// Forward sampling.  A wave owns 64 samples (tiles 0 and 1 of 32; lanes l and l + 32 share
+// sample l % 32 of a tile: during the layers half h computes the Philox blocks, inputs and
+// transformed units of its share, and at the end half h finishes tile h's samples).
 template <int D>
-__global__ void __launch_bounds__(256) dmc_flow_sample_kernel(FlowSampleArgs a) {
+__global__ void __launch_bounds__(PASS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+dmc_flow_sample_kernel(FlowSampleArgs a) {
     extern __shared__ __attribute__((aligned(16))) char sm[];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    char* wb = sm + FwdLds::waves + wv * WaveLds<D>::bytes;
-    float* zr = (float*)(wb + WaveLds<D>::z) + lane * WaveLds<D>::ZS;
-    const float* orow = (const float*)(wb + WaveLds<D>::h) + lane * OS;
-    const int* ix = (const int*)(sm + FwdLds::idx);
+    constexpr int ZS = PassLds<D>::ZS;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, j = lane & 31;
+    float* zw = (float*)(sm + PassLds<D>::z) + wv * 64 * ZS;
     constexpr int N = (D + 1) / 4;  // loop momenta
-    const int64_t nbatch = (a.n + 255) / 256;
+    const int64_t nbatch = (a.n + PASS_THREADS - 1) / PASS_THREADS;
+    const int L = a.n_layers;
+    int g = 0;  // layers done by this block: layer buffer g & 1
+    prefetch_layer(sm + PassLds<D>::buf0, a.shadow, 0);
     for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
-        const int64_t s = bt * 256 + threadIdx.x;
-        const bool valid = s < a.n;
-        const uint64_t idx = a.first + (uint64_t)(valid ? s : 0);
-        float lq = 0.0f;
+        const int64_t base = bt * PASS_THREADS + wv * 64;
+        float lqp[2];
 #pragma unroll
-        for (int b4 = 0; b4 * 4 < D; ++b4) {
-            uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)b4, 0u};
-            philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        for (int nt = 0; nt < 2; ++nt) {
+            const int64_t s = base + 32 * nt + j;
+            const uint64_t idx = a.first + (uint64_t)(s < a.n ? s : 0);
+            float* zr = zw + (32 * nt + j) * ZS;
+            lqp[nt] = 0.0f;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int d = 4 * b4 + w;
-                if (d < D) {
-                    const float z = philox_logit(c[w]);
-                    zr[d] = z;
-                    lq += log_sig_prime(z);
+            for (int b4 = 0; b4 * 4 < D; ++b4) {
+                if ((b4 & 1) != h) continue;
+                uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)b4, 0u};
+                philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int d = 4 * b4 + w;
+                    if (d < D) {
+                        const float z = philox_logit(c[w]);
+                        zr[d] = z;
+                        lqp[nt] += log_sig_prime(z);
+                    }
                 }
             }
         }
-        for (int l = 0; l < a.n_layers; ++l) {
-            __syncthreads();
-            stage_fwd(sm, a.shadow, a.master, a.aidx, a.bidx, l);
-            __syncthreads();
-            const int dA = a.dA[l], dB = D - dA;
-            wave_mlp_lds<D>(sm, wb, dA);
-            for (int b = 0; b < dB; ++b) {
-                const float sv = FLOW_SMAX * tanhf(orow[b]);
-                const int zi = ix[16 + b];
-                zr[zi] = zr[zi] * expf(sv) + orow[16 + b];
-                lq -= sv;
-            }
+        for (int l = 0; l < L; ++l, ++g) {
+            wait_copies();
+            __syncthreads();  // layer l is in buffer g & 1; every wave is done with the other buffer
+            if (l + 1 < L || bt + gridDim.x < nbatch)
+                prefetch_layer(sm + ((g + 1) & 1 ? PassLds<D>::buf1 : PassLds<D>::buf0), a.shadow, l + 1 < L ? l + 1 : 0);
+            coupling_layer<D, false>(sm + (g & 1 ? PassLds<D>::buf1 : PassLds<D>::buf0), zw, a.aidx + l * 16,
+                                     a.bidx + l * 16, a.dA[l], lqp);
         }
-        if (valid) {
+        // tile h's sample: its log q is this lane's share plus the other half's
+        const int64_t s = base + 32 * h + j;
+        float lq = lqp[h] + __shfl_xor(lqp[1 - h], 32);
+        if (s < a.n) {
+            const float* zr = zw + (32 * h + j) * ZS;
             // u' = sigmoid(z_K); VEGAS map with the bin taken in FP32; physical map
             float J = 1.0f;
             float y[D];
@@ -301,7 +356,7 @@ __global__ void __launch_bounds__(256) dmc_flow_sample_kernel(FlowSampleArgs a) 
             for (int d = 0; d < D; ++d) {
                 const float z = zr[d];
                 lq -= log_sig_prime(z);
-                const float up = 1.0f / (1.0f + expf(-z));
+                const float up = fsigmoid(z);
                 if (a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
                 const float ub = up * (float)a.n_bins;
                 // clamp before the conversion: a non-finite output must not index outside the grid
@@ -325,12 +380,112 @@ __global__ void __launch_bounds__(256) dmc_flow_sample_kernel(FlowSampleArgs a) 
                 J *= a.jl * r * r;
             }
 #pragma unroll
-            for (int j = 1; j < N; ++j) a.x[(int64_t)(3 * N + j - 1) * a.ld + s] = a.beta * y[3 * N + j - 1];
+            for (int jt = 1; jt < N; ++jt) a.x[(int64_t)(3 * N + jt - 1) * a.ld + s] = a.beta * y[3 * N + jt - 1];
             // weight against the mixture density alpha q_flow + (1 - alpha): bounded by the grid's
             // own Jacobian / (1 - alpha) in the flow's tails
-            a.jac[s] = J * a.jt / __builtin_fmaf(a.alpha, expf(lq), 1.0f - a.alpha);
+            a.jac[s] = J * a.jt / __builtin_fmaf(a.alpha, fexp(lq), 1.0f - a.alpha);
             if (a.lq_out) a.lq_out[s] = lq;
         }
+    }
+    wait_copies();  // no copy into LDS outlives the block
+}
+
+// Inverse pass u' -> z_0, same geometry as the sampler.  Stores (when asked) every state
+// states[l][d][n] = z^(l) (the output of inverse layer l), log q, the effective weights
+// w / sum(w), G[d][n] = d(-w lq)/dz_0 and the block's partial loss.
+template <int D>
+__global__ void __launch_bounds__(PASS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+dmc_flow_inverse_kernel(FlowTrainArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char sm[];
+    constexpr int ZS = PassLds<D>::ZS;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, j = lane & 31;
+    float* zw = (float*)(sm + PassLds<D>::z) + wv * 64 * ZS;
+    float loss = 0.0f;
+    const int64_t nbatch = (a.n + PASS_THREADS - 1) / PASS_THREADS;
+    const int L = a.n_layers;
+    int g = 0;
+    prefetch_layer(sm + PassLds<D>::buf0, a.shadow, L - 1);
+    for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+        const int64_t base = bt * PASS_THREADS + wv * 64;
+        float lqp[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int64_t s = base + 32 * nt + j;
+            const bool valid = s < a.n;
+            float* zr = zw + (32 * nt + j) * ZS;
+            lqp[nt] = 0.0f;
+            if (a.u_in) {
+                for (int d = h; d < D; d += 2) {
+                    float up = valid ? a.u_in[(int64_t)d * a.ld + s] : 0.5f;
+                    // outputs that rounded to 0 or 1 in FP32 are taken at the nearest interior point
+                    up = fminf(fmaxf(up, 0x1p-25f), 0x1.fffffep-1f);  // 1 - 2^-24, the largest float below 1
+                    const float z = flog(up) - flog(1.0f - up);
+                    zr[d] = z;
+                    lqp[nt] -= log_sig_prime(z);
+                }
+            } else {
+                const uint64_t idx = a.first + (uint64_t)(valid ? s : 0);
+#pragma unroll
+                for (int b4 = 0; b4 * 4 < D; ++b4) {
+                    if ((b4 & 1) != h) continue;
+                    uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)b4, 0u};
+                    philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const int d = 4 * b4 + w;
+                        if (d < D) {
+                            if (valid && a.u_out) a.u_out[(int64_t)d * a.ld + s] = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
+                            const float z = philox_logit(c[w]);
+                            zr[d] = z;
+                            lqp[nt] -= log_sig_prime(z);
+                        }
+                    }
+                }
+            }
+        }
+        for (int l = L - 1; l >= 0; --l, ++g) {
+            wait_copies();
+            __syncthreads();
+            if (l > 0 || bt + gridDim.x < nbatch)
+                prefetch_layer(sm + ((g + 1) & 1 ? PassLds<D>::buf1 : PassLds<D>::buf0), a.shadow, l > 0 ? l - 1 : L - 1);
+            coupling_layer<D, true>(sm + (g & 1 ? PassLds<D>::buf1 : PassLds<D>::buf0), zw, a.aidx + l * 16,
+                                    a.bidx + l * 16, a.dA[l], lqp);
+            if (a.states)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int64_t s = base + 32 * nt + j;
+                    if (s < a.n)
+                        for (int d = h; d < D; d += 2)
+                            a.states[((int64_t)l * D + d) * a.n + s] = zw[(32 * nt + j) * ZS + d];
+                }
+        }
+        const int64_t s = base + 32 * h + j;
+        const bool valid = s < a.n;
+        float lq = lqp[h] + __shfl_xor(lqp[1 - h], 32);
+        const float* zr = zw + (32 * h + j) * ZS;
+        for (int d = 0; d < D; ++d) lq += log_sig_prime(zr[d]);
+        // a sample whose density is not finite is dropped from the loss and the gradient
+        float w = valid && a.w ? (float)((double)a.w[s] * a.inv_wsum[0]) : 0.0f;
+        if (!__builtin_isfinite(lq) || !__builtin_isfinite(w)) w = 0.0f;
+        if (valid && a.weff) a.weff[s] = w;
+        if (valid && a.G)
+            for (int d = 0; d < D; ++d) {
+                const float sg = fsigmoid(zr[d]);
+                a.G[(int64_t)d * a.n + s] = w != 0.0f ? -w * (1.0f - 2.0f * sg) : 0.0f;
+            }
+        if (valid && a.lq_out) a.lq_out[s] = lq;
+        if (valid && w != 0.0f) loss -= w * lq;
+    }
+    wait_copies();
+    // deterministic block loss: wave sums, then waves in order
+    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o);
+    __shared__ float wl_[PASS_WAVES];
+    if (lane == 0) wl_[wv] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0 && a.loss_part) {
+        float t = 0.0f;
+        for (int w = 0; w < PASS_WAVES; ++w) t += wl_[w];
+        a.loss_part[blockIdx.x] = t;
     }
 }
 
@@ -361,7 +516,7 @@ __device__ void tile_mlp_global(const __bf16* wl, const float* ml, char* wb, con
     if (lane < 32) {
 #pragma unroll
         for (int k = 0; k < FKIN; ++k) {
-            const float v = (k < dA && have_row) ? 1.0f / (1.0f + expf(-zrow[aidx[k]])) : (k == dA ? 1.0f : 0.0f);
+            const float v = (k < dA && have_row) ? fsigmoid(zrow[aidx[k]]) : (k == dA ? 1.0f : 0.0f);
             x1[lane * XS + k] = (__bf16)v;
         }
     }
@@ -417,84 +572,6 @@ __device__ void tile_mlp_global(const __bf16* wl, const float* ml, char* wb, con
     wave_sync();
 }
 
-// Inverse pass u' -> z_0 for one sample per lane of the wave's first 32 lanes (tile of 32).
-// states[l][d][n]: z^(l) (the output of inverse layer l); lq[n]; G[d][n] = d(-w lq)/dz_0 (unnormalised);
-// partial loss per block.
-__global__ void __launch_bounds__(256) dmc_flow_inverse_kernel(FlowTrainArgs a) {
-    extern __shared__ __attribute__((aligned(16))) char sm[];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    char* wb = sm + wv * TrainWave::bytes;
-    float* zs = (float*)(sm + 4 * TrainWave::bytes) + wv * 32 * ZMAX;
-    const int D = a.dim;
-    float loss = 0.0f;
-    const int64_t ntile = (a.n + 31) / 32;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + wv; t < ntile; t += (int64_t)gridDim.x * 4) {
-        const int64_t s = t * 32 + (lane & 31);
-        const bool valid = lane < 32 && s < a.n;
-        float* zr = zs + (lane & 31) * ZMAX;
-        float lq = 0.0f;
-        if (lane < 32) {
-            for (int d = 0; d < D; ++d) {
-                float up, z;
-                if (a.u_in) {
-                    up = valid ? a.u_in[(int64_t)d * a.ld + s] : 0.5f;
-                    // outputs that rounded to 0 or 1 in FP32 are taken at the nearest interior point
-                    up = fminf(fmaxf(up, 0x1p-25f), 0x1.fffffep-1f);  // 1 - 2^-24, the largest float below 1
-                    z = logf(up) - log1pf(-up);
-                } else {
-                    const uint64_t idx = a.first + (uint64_t)(valid ? s : 0);
-                    uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)(d >> 2), 0u};
-                    philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-                    up = ((float)(c[d & 3] >> 8) + 0.5f) * 0x1p-24f;
-                    z = philox_logit(c[d & 3]);
-                }
-                if (valid && a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
-                zr[d] = z;
-                lq -= log_sig_prime(z);
-            }
-        }
-        wave_sync();
-        for (int l = a.n_layers - 1; l >= 0; --l) {
-            const int dA = a.dA[l];
-            tile_mlp_global(a.shadow + (size_t)l * SHADOW_LAYER, a.master + (size_t)l * LAYER_SIZE, wb, zr,
-                            a.aidx + l * 16, dA, lane < 32);
-            const float* orow = (const float*)(wb + TrainWave::o) + (lane & 31) * OS;
-            if (lane < 32) {
-                for (int b = 0; b < D - dA; ++b) {
-                    const float sv = FLOW_SMAX * tanhf(orow[b]);
-                    const int zi = a.bidx[l * 16 + b];
-                    zr[zi] = (zr[zi] - orow[16 + b]) * expf(-sv);
-                    lq -= sv;
-                }
-                if (valid && a.states)
-                    for (int d = 0; d < D; ++d) a.states[((int64_t)l * D + d) * a.n + s] = zr[d];
-            }
-            wave_sync();
-        }
-        if (lane < 32) {
-            for (int d = 0; d < D; ++d) lq += log_sig_prime(zr[d]);
-            // a sample whose density is not finite is dropped from the loss and the gradient
-            float w = valid && a.w ? (float)((double)a.w[s] * a.inv_wsum[0]) : 0.0f;
-            if (!__builtin_isfinite(lq) || !__builtin_isfinite(w)) w = 0.0f;
-            if (valid && a.weff) a.weff[s] = w;
-            if (valid && a.G)
-                for (int d = 0; d < D; ++d) {
-                    const float sg = 1.0f / (1.0f + expf(-zr[d]));
-                    a.G[(int64_t)d * a.n + s] = w != 0.0f ? -w * (1.0f - 2.0f * sg) : 0.0f;
-                }
-            if (valid && a.lq_out) a.lq_out[s] = lq;
-            if (valid && w != 0.0f) loss -= w * lq;
-        }
-        wave_sync();
-    }
-    // deterministic block loss: wave sums, then waves in order
-    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o);
-    __shared__ float wl_[4];
-    if (lane == 0) wl_[wv] = loss;
-    __syncthreads();
-    if (threadIdx.x == 0 && a.loss_part) a.loss_part[blockIdx.x] = ((wl_[0] + wl_[1]) + wl_[2]) + wl_[3];
-}
-
 // One layer of the reverse sweep (layer l, visited in order 0..L-1).
 __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int l) {
     extern __shared__ __attribute__((aligned(16))) char sm[];
@@ -532,9 +609,9 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
             const float w = valid ? a.weff[s] : 0.0f;
             for (int b = 0; b < dB; ++b) {
                 const int zi = bidx[b];
-                const float th = tanhf(orow[b]);
+                const float th = ftanh(orow[b]);
                 const float sv = FLOW_SMAX * th;
-                const float e = expf(-sv);
+                const float e = fexp(-sv);
                 const float gB = valid ? a.G[(int64_t)zi * a.n + s] : 0.0f;
                 const float zBo = zr[zi];  // z_B(l), the inverse layer's output
                 grow[b] = (-gB * zBo + w) * FLOW_SMAX * (1.0f - th * th);
@@ -551,13 +628,13 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
         // activations and output gradient to global (feature-major, sample-contiguous) for the
         // weight-gradient products
         if (valid && lane < 32) {
-            for (int k = 0; k < FKIN; ++k) a.act_x1[(int64_t)k * a.n + s] = x1[col * XS + k];
-            for (int o = 0; o < FNOUT; ++o) a.act_do[(int64_t)o * a.n + s] = dob[col * XS2 + o];
+            for (int k = 0; k < FKIN; ++k) a.act_x1[(int64_t)k * a.lda + s] = x1[col * XS + k];
+            for (int o = 0; o < FNOUT; ++o) a.act_do[(int64_t)o * a.lda + s] = dob[col * XS2 + o];
         }
         for (int k = h; k < FH; k += 2)
             if (valid) {
-                a.act_h1[(int64_t)k * a.n + s] = h1[col * HS + k];
-                a.act_h2[(int64_t)k * a.n + s] = h2[col * HS + k];
+                a.act_h1[(int64_t)k * a.lda + s] = h1[col * HS + k];
+                a.act_h2[(int64_t)k * a.lda + s] = h2[col * HS + k];
             }
         // dH2^T = W3 dO^T (A = W3 [hidden][out], K = 32 out in 2 steps); mask by H2 > 0 -> dpre2
         f32x16 d2[4];
@@ -585,7 +662,7 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
             }
         wave_sync();
         for (int k = h; k < FH; k += 2)
-            if (valid) a.act_dp2[(int64_t)k * a.n + s] = dp[col * HS + k];
+            if (valid) a.act_dp2[(int64_t)k * a.lda + s] = dp[col * HS + k];
         // dH1^T = W2 dpre2^T (A = W2 [in hidden][out hidden]); mask by H1 > 0 -> dpre1
         f32x16 d1[4];
 #pragma unroll
@@ -613,7 +690,7 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
             }
         wave_sync();
         for (int k = h; k < FH; k += 2)
-            if (valid) a.act_dp1[(int64_t)k * a.n + s] = dp[col * HS + k];
+            if (valid) a.act_dp1[(int64_t)k * a.lda + s] = dp[col * HS + k];
         // dX1^T = W1 dpre1^T (A = W1 [32 rows: 16 inputs + zero pad][128])
         f32x16 dx = {};
 #pragma unroll
@@ -630,86 +707,113 @@ __global__ void __launch_bounds__(256) dmc_flow_bwd_kernel(FlowTrainArgs a, int 
         if (valid && lane < 32)
             for (int k = 0; k < dA; ++k) {
                 const int zi = aidx[k];
-                const float sg = 1.0f / (1.0f + expf(-zr[zi]));
+                const float sg = fsigmoid(zr[zi]);
                 a.G[(int64_t)zi * a.n + s] += dxb[col * OS + k] * sg * (1.0f - sg);
             }
         wave_sync();
     }
 }
 
-// Weight gradients of one layer, split over sample chunks: block b sums samples
-// [b * chunk, (b + 1) * chunk) in a fixed order and writes partial[b][LAYER_SIZE].
-//   W1t[h][k] = sum_s dpre1[h][s] X1[k][s]   (16 x 128 -> 4 tiles of rows, 1 tile of columns)
-//   W2t[o][i] = sum_s dpre2[o][s] H1[i][s]   (16 tiles)
-//   W3t[o][i] = sum_s dO[o][s]    H2[i][s]   (4 tiles)
-//   b2[o] = sum_s dpre2[o][s],  b3[o] = sum_s dO[o][s]
+// Weight gradients of one layer, split over sample chunks: block (c, g) sums the samples of chunk
+// c, [c * chunk, (c + 1) * chunk), in a fixed order into partial[c][LAYER_SIZE]; group g picks the
+// output: g = 0..3 the W2t row block g (wave w: column block w), g = 4 W1t (wave w: row block w),
+// g = 5 W3t (wave w: column block w), g = 6 the biases.  The four waves of a W2t block read the
+// same dpre2 rows at the same time, so those loads are served once from the CU's cache.
+//   W1t[h][k] = sum_s dpre1[h][s] X1[k][s]
+//   W2t[o][i] = sum_s dpre2[o][s] H1[i][s]
+//   W3t[o][i] = sum_s dO[o][s]    H2[i][s]
+//   b2[o] = sum_s dpre2[o][s],  b3[o] = sum_s dO[o][s]   (FP32, in sample order)
+// Activation rows have stride lda (a multiple of 16 samples): every 16-sample slice of a row is one
+// aligned pair of 16-byte loads; slices past the chunk end are masked to zero.
+__device__ __forceinline__ bf16x8 masked_slice(const __bf16* row, int64_t k, int64_t s1, bool ok) {
+    bf16x8 v = {};
+    if (ok) {
+        v = *(const bf16x8*)(row + k);
+        if (k + 8 > s1)
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (k + t >= s1) v[t] = (__bf16)0.0f;
+    }
+    return v;
+}
+
 __global__ void __launch_bounds__(256) dmc_flow_wgrad_kernel(FlowTrainArgs a, int chunk, float* partial) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+    const int g = blockIdx.y;
     const int64_t s0 = (int64_t)blockIdx.x * chunk;
     const int64_t s1 = min(s0 + (int64_t)chunk, a.n);
     float* out = partial + (size_t)blockIdx.x * LAYER_SIZE;
-    // 24 output tiles: 0..15 W2t (row tile rt, column tile ct), 16..19 W1t (rows), 20..23 W3t (cols)
-    for (int tile = wv; tile < 24; tile += 4) {
-        const __bf16* Ab;
-        const __bf16* Bb;
-        int rows_base, cols_base, ncols;
-        float* dst;
-        int ld_dst;
-        if (tile < 16) {
-            Ab = a.act_dp2 + (int64_t)(32 * (tile >> 2)) * a.n;
-            Bb = a.act_h1 + (int64_t)(32 * (tile & 3)) * a.n;
-            rows_base = 32 * (tile >> 2);
-            cols_base = 32 * (tile & 3);
-            ncols = 32;
-            dst = out + OFF_W2T;
-            ld_dst = FH;
-        } else if (tile < 20) {
-            Ab = a.act_dp1 + (int64_t)(32 * (tile - 16)) * a.n;
-            Bb = a.act_x1;
-            rows_base = 32 * (tile - 16);
-            cols_base = 0;
-            ncols = FKIN;
-            dst = out + OFF_W1T;
-            ld_dst = FKIN;
-        } else {
-            Ab = a.act_do;
-            Bb = a.act_h2 + (int64_t)(32 * (tile - 20)) * a.n;
-            rows_base = 0;
-            cols_base = 32 * (tile - 20);
-            ncols = 32;
-            dst = out + OFF_W3T;
-            ld_dst = FH;
-        }
-        f32x16 c = {};
-        const bool bok = col < ncols;
-        for (int64_t k0 = s0; k0 < s1; k0 += 16) {
-            bf16x8 av, bv;
+    if (g == 6) {
+        // bias gradients: sums of the rounded output gradients in sample order
+        const int r = threadIdx.x;
+        if (r < FH + FNOUT) {
+            const __bf16* src = r < FH ? a.act_dp2 + (int64_t)r * a.lda : a.act_do + (int64_t)(r - FH) * a.lda;
+            float acc = 0.0f;
+            for (int64_t k = s0; k < s1; k += 8) {
+                const bf16x8 v = masked_slice(src, k, s1, true);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int64_t k = k0 + 8 * h + t;
-                const bool in = k < s1;
-                av[t] = in ? Ab[(int64_t)col * a.n + k] : (__bf16)0.0f;
-                bv[t] = (in && bok) ? Bb[(int64_t)col * a.n + k] : (__bf16)0.0f;
+                for (int t = 0; t < 8; ++t) acc += (float)v[t];
             }
-            c = mfma(av, bv, c);
+            if (r < FH)
+                out[OFF_B2 + r] = acc;
+            else
+                out[OFF_B3 + r - FH] = acc;
         }
-        if (bok)
+        return;
+    }
+    const __bf16* Ab;
+    const __bf16* Bb;
+    int rows_base, cols_base, ncols, ld_dst;
+    float* dst;
+    if (g < 4) {
+        Ab = a.act_dp2 + (int64_t)(32 * g) * a.lda;
+        Bb = a.act_h1 + (int64_t)(32 * wv) * a.lda;
+        rows_base = 32 * g;
+        cols_base = 32 * wv;
+        ncols = 32;
+        dst = out + OFF_W2T;
+        ld_dst = FH;
+    } else if (g == 4) {
+        Ab = a.act_dp1 + (int64_t)(32 * wv) * a.lda;
+        Bb = a.act_x1;
+        rows_base = 32 * wv;
+        cols_base = 0;
+        ncols = FKIN;
+        dst = out + OFF_W1T;
+        ld_dst = FKIN;
+    } else {
+        Ab = a.act_do;
+        Bb = a.act_h2 + (int64_t)(32 * wv) * a.lda;
+        rows_base = 0;
+        cols_base = 32 * wv;
+        ncols = 32;
+        dst = out + OFF_W3T;
+        ld_dst = FH;
+    }
+    const bool bok = col < ncols;
+    const __bf16* Ar = Ab + (int64_t)col * a.lda;
+    const __bf16* Br = Bb + (int64_t)(bok ? col : 0) * a.lda;
+    f32x16 c0 = {}, c1 = {};
+    for (int64_t k0 = s0; k0 < s1; k0 += 64) {
+        bf16x8 av[4], bv[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = rows_base + 8 * (r >> 2) + 4 * h + (r & 3);
-                dst[row * ld_dst + cols_base + col] = c[r];
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + 16 * u + 8 * h;
+            const bool in = k0 + 16 * u < s1;
+            av[u] = masked_slice(Ar, k, s1, in);
+            bv[u] = masked_slice(Br, k, s1, in && bok);
+        }
+        c0 = mfma(av[0], bv[0], c0);
+        c1 = mfma(av[1], bv[1], c1);
+        c0 = mfma(av[2], bv[2], c0);
+        c1 = mfma(av[3], bv[3], c1);
     }
-    // bias gradients: sums of the rounded output gradients in sample order
-    for (int r = threadIdx.x; r < FH + FNOUT; r += blockDim.x) {
-        const __bf16* src = r < FH ? a.act_dp2 + (int64_t)r * a.n : a.act_do + (int64_t)(r - FH) * a.n;
-        float acc = 0.0f;
-        for (int64_t k = s0; k < s1; ++k) acc += (float)src[k];
-        if (r < FH)
-            out[OFF_B2 + r] = acc;
-        else
-            out[OFF_B3 + r - FH] = acc;
-    }
+    if (bok)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = rows_base + 8 * (r >> 2) + 4 * h + (r & 3);
+            dst[row * ld_dst + cols_base + col] = c0[r] + c1[r];
+        }
 }
 
 // Fold the per-block partial gradients (fixed order, FP64), scale by 1/sum(w), Adam on the FP32
@@ -738,7 +842,7 @@ __global__ void __launch_bounds__(256) dmc_flow_adam_kernel(FlowAdamArgs a) {
 // samples drawn from the grid alone: J <- J / (alpha q_flow + 1 - alpha)
 __global__ void dmc_flow_mix_kernel(float* jac, const float* lq, int64_t n, float alpha) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        jac[i] = jac[i] / __builtin_fmaf(alpha, expf(lq[i]), 1.0f - alpha);
+        jac[i] = jac[i] / __builtin_fmaf(alpha, fexp(lq[i]), 1.0f - alpha);
 }
 
 __global__ void __launch_bounds__(256) dmc_flow_shadow_kernel(const float* master, __bf16* shadow, int n_layers) {
@@ -749,13 +853,13 @@ __global__ void __launch_bounds__(256) dmc_flow_shadow_kernel(const float* maste
 
 // sum of w in a fixed order (one block): out[0] = sum, out[2] = 1 / sum (0 if the sum is not
 // positive and finite); the normalised loss is folded by dmc_flow_loss_kernel after the pass
-__global__ void __launch_bounds__(256) dmc_flow_sums_kernel(const float* w, int64_t n, double* out) {
-    __shared__ double red[256];
+__global__ void __launch_bounds__(1024) dmc_flow_sums_kernel(const float* w, int64_t n, double* out) {
+    __shared__ double red[1024];
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) acc += (double)w[i];
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += (double)w[i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -774,26 +878,30 @@ __global__ void dmc_flow_loss_kernel(const float* loss_part, int nblk, double* o
 }
 
 // ---------------------------------------------------------------- launchers
+// Sampler and inverse: one 512-thread block per CU (grid-stride over batches of 512 samples)
+static int pass_blocks(int64_t n, int n_cu) {
+    const int64_t want = (n + PASS_THREADS - 1) / PASS_THREADS;
+    return (int)(want < (int64_t)n_cu ? want : (int64_t)n_cu);
+}
+
 template <int D>
 static hipError_t launch_sample_d(const FlowSampleArgs& a, int n_cu, hipStream_t st) {
-    const int smem = flow_fwd_lds_bytes<D>();
+    constexpr int smem = PassLds<D>::bytes;
     hipError_t e = hipFuncSetAttribute((const void*)dmc_flow_sample_kernel<D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, smem);
     if (e != hipSuccess) return e;
-    const int64_t want = (a.n + 255) / 256;
-    const int grid = (int)(want < (int64_t)n_cu ? want : (int64_t)n_cu);
-    hipLaunchKernelGGL(dmc_flow_sample_kernel<D>, dim3(grid), dim3(256), smem, st, a);
+    hipLaunchKernelGGL(dmc_flow_sample_kernel<D>, dim3(pass_blocks(a.n, n_cu)), dim3(PASS_THREADS), smem, st, a);
     return hipGetLastError();
 }
 
 int flow_sample_lds_bytes(int dim) {
     switch (dim) {
-        case 3: return flow_fwd_lds_bytes<3>();
-        case 7: return flow_fwd_lds_bytes<7>();
-        case 11: return flow_fwd_lds_bytes<11>();
-        case 15: return flow_fwd_lds_bytes<15>();
-        case 19: return flow_fwd_lds_bytes<19>();
-        case 23: return flow_fwd_lds_bytes<23>();
+        case 3: return PassLds<3>::bytes;
+        case 7: return PassLds<7>::bytes;
+        case 11: return PassLds<11>::bytes;
+        case 15: return PassLds<15>::bytes;
+        case 19: return PassLds<19>::bytes;
+        case 23: return PassLds<23>::bytes;
     }
     return -1;
 }
@@ -818,12 +926,28 @@ int flow_train_blocks(int64_t n, int n_cu) {
     return (int)(want < (int64_t)n_cu * 2 ? want : (int64_t)n_cu * 2);
 }
 
-hipError_t launch_flow_inverse(const FlowTrainArgs& a, int nblk, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void*)dmc_flow_inverse_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, TRAIN_LDS);
+int flow_inverse_blocks(int64_t n, int n_cu) { return pass_blocks(n, n_cu); }
+
+template <int D>
+static hipError_t launch_inverse_d(const FlowTrainArgs& a, int nblk, hipStream_t st) {
+    constexpr int smem = PassLds<D>::bytes;
+    hipError_t e = hipFuncSetAttribute((const void*)dmc_flow_inverse_kernel<D>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dmc_flow_inverse_kernel, dim3(nblk), dim3(256), TRAIN_LDS, st, a);
+    hipLaunchKernelGGL(dmc_flow_inverse_kernel<D>, dim3(nblk), dim3(PASS_THREADS), smem, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_flow_inverse(const FlowTrainArgs& a, int nblk, hipStream_t st) {
+    switch (a.dim) {
+        case 3: return launch_inverse_d<3>(a, nblk, st);
+        case 7: return launch_inverse_d<7>(a, nblk, st);
+        case 11: return launch_inverse_d<11>(a, nblk, st);
+        case 15: return launch_inverse_d<15>(a, nblk, st);
+        case 19: return launch_inverse_d<19>(a, nblk, st);
+        case 23: return launch_inverse_d<23>(a, nblk, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int wg_chunk, int wg_blocks,
@@ -832,12 +956,12 @@ hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int
                                        TRAIN_LDS);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dmc_flow_bwd_kernel, dim3(nblk), dim3(256), TRAIN_LDS, st, a, layer);
-    hipLaunchKernelGGL(dmc_flow_wgrad_kernel, dim3(wg_blocks), dim3(256), 0, st, a, wg_chunk, partial_layer);
+    hipLaunchKernelGGL(dmc_flow_wgrad_kernel, dim3(wg_blocks, 7), dim3(256), 0, st, a, wg_chunk, partial_layer);
     return hipGetLastError();
 }
 
 hipError_t launch_flow_sums(const float* w, int64_t n, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_flow_sums_kernel, dim3(1), dim3(256), 0, st, w, n, out);
+    hipLaunchKernelGGL(dmc_flow_sums_kernel, dim3(1), dim3(1024), 0, st, w, n, out);
     return hipGetLastError();
 }
 

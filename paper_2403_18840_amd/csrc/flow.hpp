@@ -28,7 +28,29 @@ constexpr int SH_W3T = SH_W2T + FH * FH;         // [32][128]
 constexpr int SH_W1 = SH_W3T + FNOUT * FH;       // [32][128]: rows 0..15 = W1t^T, rows 16..31 zero
 constexpr int SH_W2 = SH_W1 + 32 * FH;           // [128][128] = W2t^T
 constexpr int SH_W3 = SH_W2 + FH * FH;           // [128][32] = W3t^T
-constexpr int SHADOW_LAYER = SH_W3 + FH * FNOUT;
+// Forward weights in MFMA fragment order (44 fragments of 64 lanes x 8 BF16; fragment f, lane l,
+// element t at SH_FRAG + 512 f + 8 l + t): the A operands of the 32x32x16 products, laid out so
+// that the ReLU'd accumulator registers of one layer are the B operands of the next.
+//   f = ot (0..3):            W1t[32 ot + l%32][8 (l/32) + t]
+//   f = 4 + 8 ot + sg:        W2t[32 ot + l%32][rho(sg, l/32, t)]
+//   f = 36 + sg:              W3t[l%32][rho(sg, l/32, t)]
+// with rho(sg, h, t) = 32 (sg/2) + 16 (sg%2) + 8 (t/4) + 4 h + t%4, the hidden unit that the
+// accumulator register 8 (sg%2) + t of output tile sg/2 holds in lane half h.
+constexpr int NFRAG = 44;
+constexpr int SH_FRAG = SH_W3 + FH * FNOUT;
+// the FP32 biases b2 [128] and b3 [32] as raw words right after the fragments (1 KiB with padding):
+// fragments and biases of a layer form 45 contiguous 1 KiB chunks
+constexpr int SH_BIAS = SH_FRAG + NFRAG * 512;
+constexpr int NCHUNK = NFRAG + 1;
+constexpr int SHADOW_LAYER = SH_BIAS + 512;
+
+// slot of hidden input c within a fragment row: (sg, h, t) with rho(sg, h, t) = c
+__device__ __forceinline__ int frag_slot(int sg_base, int row, int c) {
+    const int sg = 2 * (c >> 5) + ((c & 31) >> 4);
+    const int h = (c & 7) >> 2;
+    const int t = 4 * ((c & 15) >> 3) + (c & 3);
+    return SH_FRAG + (sg_base + sg) * 512 + (32 * h + row) * 8 + t;
+}
 
 __device__ __forceinline__ void write_shadow(__bf16* shadow, int l, int q, float th) {
     __bf16* s = shadow + (size_t)l * SHADOW_LAYER;
@@ -37,14 +59,21 @@ __device__ __forceinline__ void write_shadow(__bf16* shadow, int l, int q, float
         const int r = q / FKIN, k = q % FKIN;
         s[SH_W1T + r * FKIN + k] = b;
         s[SH_W1 + k * FH + r] = b;
+        s[SH_FRAG + (r >> 5) * 512 + (32 * (k >> 3) + (r & 31)) * 8 + (k & 7)] = b;
     } else if (q < OFF_B2) {
         const int o = (q - OFF_W2T) / FH, i = (q - OFF_W2T) % FH;
         s[SH_W2T + o * FH + i] = b;
         s[SH_W2 + i * FH + o] = b;
+        s[frag_slot(4 + 8 * (o >> 5), o & 31, i)] = b;
     } else if (q >= OFF_W3T && q < OFF_B3) {
         const int o = (q - OFF_W3T) / FH, i = (q - OFF_W3T) % FH;
         s[SH_W3T + o * FH + i] = b;
         s[SH_W3 + i * FNOUT + o] = b;
+        s[frag_slot(36, o, i)] = b;
+    } else if (q < OFF_W3T) {
+        ((float*)(s + SH_BIAS))[q - OFF_B2] = th;
+    } else {
+        ((float*)(s + SH_BIAS))[FH + q - OFF_B3] = th;
     }
 }
 
@@ -70,6 +99,7 @@ struct FlowTrainArgs {
     const float* u_in;  // nullable [D][ld]: training points u'; NULL = Philox uniforms (seed, first)
     uint64_t seed, first;
     int64_t n, ld;
+    int64_t lda;        // row stride of the activation buffers: n rounded up to a multiple of 16
     const float* w;     // [n] importance weights
     const double* inv_wsum;  // device: 1 / sum(w) (the weights enter normalised)
     const float* master;
@@ -105,7 +135,8 @@ struct FlowAdamArgs {
 
 int flow_sample_lds_bytes(int dim);
 hipError_t launch_flow_sample(const FlowSampleArgs& a, int dim, int n_cu, hipStream_t st);
-int flow_train_blocks(int64_t n, int n_cu);
+int flow_train_blocks(int64_t n, int n_cu);    // grid of the backward sweep (128 samples per block pass)
+int flow_inverse_blocks(int64_t n, int n_cu);  // grid of the inverse pass (one 512-thread block per CU at most)
 hipError_t launch_flow_inverse(const FlowTrainArgs& a, int nblk, hipStream_t st);
 hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int wg_chunk, int wg_blocks,
                                 float* partial_layer, hipStream_t st);
