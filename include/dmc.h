@@ -169,16 +169,23 @@ dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, d
 dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n_params);
 dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream);  /* also resets Adam state */
 dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream);
-/* n samples i = first .. first + n - 1 from the mixture alpha q_flow + (1 - alpha) q_grid (a defensive
- * mixture, in the spirit of the alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised): the first
- * round((1 - alpha) n) samples are the VEGAS sampler's own points, the rest come through the flow; every
- * sample is weighted by the mixture density (balance-heuristic multiple importance sampling, unbiased),
- * so the weights stay within 1/(1 - alpha) of the grid's.  s must be a VEGAS sampler of the same dimension.
- * x: device float[D][ld]; jac: device float[n] = J_phys J_VEGAS / (alpha q_flow(u') + 1 - alpha);
+/* n samples i = first .. first + n - 1 from the defensive mixture
+ *     a_f q_flow + a_g q_grid + a_u q_uniform,   a_f = mix_flow, a_u = mix_uniform, a_g = 1 - a_f - a_u,
+ * (in the spirit of the alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised): samples
+ * [0, n_u) are uniform points y (the uniform sampler's Philox draw, counters first ..), samples
+ * [n_u, n_u + n_g) are the VEGAS sampler's own points (counters first + n_u ..), the rest go through
+ * the flow (counters first + n_u + n_g ..), with n_u = round(a_u n), n_g = round(a_g n).  Every sample
+ * is weighted by the mixture density at its point (balance-heuristic multiple importance sampling,
+ * unbiased): jac = J_phys J_V(u') / (a_f q_flow(u') + a_g + a_u J_V(u')), with u' the point's grid
+ * coordinates (u' = G^-1(y) for the uniform share) and J_V the grid's Jacobian there, so every weight
+ * is within 1/a_g of the grid sampler's and within 1/a_u of the uniform sampler's.
+ * s must be a VEGAS sampler of the flow's dimension.  x: device float[D][ld]; jac: device float[n];
  * u_out (nullable): device float[D][ld], the points u'; lq_out (nullable): device float[n], log q_flow(u').
- * alpha in (0, 1]. */
+ * mix_flow in (0, 1], mix_uniform in [0, 1), mix_flow + mix_uniform <= 1.  The library keeps a
+ * scratch buffer of 2 (n_u + n_g) (+ D n_u without u_out) floats per flow between calls. */
 dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
-                           int64_t ld, float* jac, float* u_out, float* lq_out, double alpha, void* stream);
+                           int64_t ld, float* jac, float* u_out, float* lq_out, double mix_flow, double mix_uniform,
+                           void* stream);
 /* log q(u') by the inverse couplings; u: device float[D][ld]; lq: device float[n]. */
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream);
 /* One step of the weighted forward KL L = -sum_i w_i log q(u'_i) / sum_i w_i over n points:

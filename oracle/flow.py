@@ -205,13 +205,18 @@ def loss_and_grad(theta, masks, uprime, w):
     return loss, np.concatenate(grads)
 
 
-def mixture_weight(jac_grid, lq, alpha):
-    """Weight of a point drawn from the defensive mixture alpha q + (1 - alpha) u, with u the
-    uniform density of the VEGAS cube: the point's grid weight divided by the mixture density (the
-    balance heuristic of multiple importance sampling, Veach and Guibas 1995; the mixture mirrors
-    the alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised).  Unbiased for any split of the
-    samples in the proportions alpha : 1 - alpha, and never above jac_grid / (1 - alpha)."""
-    return np.asarray(jac_grid, dtype=np.float64) / (alpha * np.exp(np.asarray(lq, dtype=np.float64)) + (1.0 - alpha))
+def mixture_weight(jac, lq, alpha, uniform=0.0, jv=None):
+    """Weight of a point drawn from the defensive mixture alpha q + (1 - alpha - uniform) g + uniform u,
+    where g is the VEGAS grid's density (1 / J_V in the cube of its outputs) and u the uniform density
+    of that cube: jac (the point's physical Jacobian times J_V at its grid coordinates) divided by the
+    mixture density in grid coordinates, alpha q + (1 - alpha - uniform) + uniform J_V.  This is the
+    balance heuristic of multiple importance sampling (Veach and Guibas 1995); the mixture mirrors the
+    alpha-mixed target of eq. target_distr_nf_mcmc_qft_revised.  Unbiased for any split of the samples
+    in the proportions of the shares, never above jac / (1 - alpha - uniform) nor above
+    (jac / J_V) / uniform."""
+    lq = np.asarray(lq, dtype=np.float64)
+    jv = np.zeros_like(lq) if jv is None else np.asarray(jv, dtype=np.float64)
+    return np.asarray(jac, dtype=np.float64) / (alpha * np.exp(lq) + ((1.0 - alpha - uniform) + uniform * jv))
 
 
 def adam_step(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

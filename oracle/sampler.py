@@ -101,6 +101,24 @@ def vegas_map_float(u, edges):
     return y, J, b
 
 
+def vegas_inverse(y, edges):
+    """Inverse of the VEGAS map: for points y[N, D] in the unit cube, the bin b with
+    e_b <= y < e_{b+1} (clamped to the grid), the grid coordinate u' = (b + (y - e_b) / (e_{b+1} - e_b)) / B
+    and the Jacobian J_V = prod_d B (e_{b+1} - e_b) of the forward map at u'."""
+    edges = np.asarray(edges, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    D, B1 = edges.shape
+    B = B1 - 1
+    u = np.empty(y.shape)
+    J = np.ones(y.shape[0])
+    for d in range(D):
+        b = np.clip(np.searchsorted(edges[d], y[:, d], side="right") - 1, 0, B - 1)
+        lo, hi = edges[d, b], edges[d, b + 1]
+        u[:, d] = (b + np.minimum((y[:, d] - lo) / (hi - lo), 1.0)) / B
+        J *= B * (hi - lo)
+    return u, J
+
+
 def refine_grid(edges, hist, alpha=0.5):
     """One VEGAS grid refinement (Lepage 1978), FP64.
 

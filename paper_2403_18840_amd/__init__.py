@@ -98,7 +98,7 @@ def lib():
         "dmc_flow_param_count": (I32, [P, ctypes.POINTER(I64)]),
         "dmc_flow_set_params": (I32, [P, P, P]),
         "dmc_flow_get_params": (I32, [P, P, P]),
-        "dmc_flow_sample": (I32, [P, P, U64, U64, I64, P, I64, P, P, P, F64, P]),
+        "dmc_flow_sample": (I32, [P, P, U64, U64, I64, P, I64, P, P, P, F64, F64, P]),
         "dmc_flow_log_density": (I32, [P, P, I64, I64, P, P]),
         "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
         "dmc_flow_destroy": (None, [P]),
@@ -347,15 +347,16 @@ def adapt_grid(graph: Graph, inst, k_ext, sampler: Sampler, n_samples: int, iter
 
 
 def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs: int = 8, steps: int = 16,
-               minibatch: int = 1 << 16, lr: float = 1e-3, alpha: float = 0.9, seed: int = 3):
+               minibatch: int = 1 << 17, lr: float = 1e-3, alpha: float = 0.85, uniform: float = 0.05, seed: int = 3):
     """Fit `flow` (on the VEGAS coordinates of `sampler`, whose grid stays frozen) to the absolute
     integrand by the weighted forward KL of Appendix A, with Adam on the device.
 
     Every step draws `minibatch` new points, evaluates the graph on them (the training weight of a
     point is its importance value, sum |f| J over the proposal density) and takes one step.  The
-    first epoch draws from the grid alone; later epochs from the mixture alpha q + (1 - alpha) of
-    the current flow, so the training points follow the flow as it sharpens.  Returns the loss of
-    the last step of every epoch."""
+    first epoch draws from the grid alone; later epochs from the mixture alpha q_flow + uniform
+    q_uniform + (rest) q_grid of the current flow, so the training points follow the flow as it
+    sharpens.  k_ext selects the external momenta whose |Sigma| integrand the flow learns (the figure
+    of merit's).  Returns the loss of the last step of every epoch."""
     import numpy as np
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -380,7 +381,7 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
                 eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
                 loss = flow.train_step(imp, seed=seed, first=first, lr=lr, want_loss=last)
             else:
-                flow.sample(sampler, seed, first, X, J, u_out=U, alpha=alpha)
+                flow.sample(sampler, seed, first, X, J, u_out=U, alpha=alpha, uniform=uniform)
                 eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
                 loss = flow.train_step(imp, u=U, lr=lr, want_loss=last)
             acc.reset()
@@ -391,12 +392,14 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
 
 def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int = 5, seed: int = 1,
               kind: int = SAMPLER_VEGAS, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0, alpha: float = 0.5,
-              flow: "Flow | None" = None, flow_alpha: float = 0.9, train: dict | None = None):
+              flow: "Flow | None" = None, flow_alpha: float = 0.85, flow_uniform: float = 0.05,
+              train: dict | None = None, train_k=None):
     """Importance-sampling estimate of Sigma (and derivative roots) with the library's sampler.
 
     `adapt` iterations refine the VEGAS grid (their samples are discarded).  With a `flow`, it is
-    then trained on the frozen grid (`train`: keyword arguments of train_flow; None skips training)
-    and the estimate draws from the mixture flow_alpha q + (1 - flow_alpha).  The next `iters`
+    then trained on the frozen grid (`train`: keyword arguments of train_flow, on the external
+    momenta train_k, default all; None skips training) and the estimate draws from the mixture
+    flow_alpha q_flow + flow_uniform q_uniform + (rest) q_grid.  The next `iters`
     iterations accumulate into one FP64 accumulator, whose mean over all estimation samples is the
     estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K]."""
     import numpy as np
@@ -412,14 +415,16 @@ def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int 
         if kind != SAMPLER_VEGAS:
             raise ValueError("the flow maps onto a VEGAS grid")
         if train is not None:
-            train_flow(graph, inst, ks, s, flow, **dict({"seed": seed + 1}, **train))
+            kt = ks if train_k is None else np.asarray(train_k, dtype=np.float32)
+            opts = dict({"seed": seed + 1, "alpha": flow_alpha, "uniform": flow_uniform}, **train)
+            train_flow(graph, inst, kt, s, flow, **opts)
     acc = Accumulator(_n_groups(inst), len(ks), graph.n_roots)
     X = torch.empty((D, n_samples), dtype=torch.float32, device=dev)
     J = torch.empty(n_samples, dtype=torch.float32, device=dev)
     est_seed = seed + 2 if flow is not None else seed
     for _ in range(iters):
         if flow is not None:
-            flow.sample(s, est_seed, first, X, J, alpha=flow_alpha)
+            flow.sample(s, est_seed, first, X, J, alpha=flow_alpha, uniform=flow_uniform)
         else:
             s.sample(seed, first, X, J)
         eval_batch(graph, inst, ks, X, J, acc)
@@ -456,11 +461,12 @@ class Flow:
         return t
 
     def sample(self, sampler: Sampler, seed: int, first: int, x, jac, u_out=None, lq_out=None, alpha: float = 1.0,
-               stream=None):
+               uniform: float = 0.0, stream=None):
+        """Mixture alpha q_flow + (1 - alpha - uniform) q_grid + uniform q_uniform (dmc_flow_sample)."""
         n = jac.numel()
         _check(lib().dmc_flow_sample(self.h, sampler.h, seed, first, n, _dptr(x, "float32", "x"), x.shape[1],
                                      _dptr(jac, "float32", "jac"), _dptr(u_out, "float32", "u_out"),
-                                     _dptr(lq_out, "float32", "lq_out"), alpha, _stream(stream)))
+                                     _dptr(lq_out, "float32", "lq_out"), alpha, uniform, _stream(stream)))
 
     def log_density(self, u, lq, stream=None):
         _check(lib().dmc_flow_log_density(self.h, _dptr(u, "float32", "u"), u.shape[1], lq.numel(),

@@ -596,7 +596,7 @@ struct dmc_flow {
     __bf16* acts = nullptr;
     float* partial = nullptr;
     double* sums = nullptr;
-    float* mix_lq = nullptr;
+    float* mix_buf = nullptr;  // mixture scratch: log q, J_V, u' of the uniform share
     int64_t mix_cap = 0;
 };
 
@@ -697,56 +697,99 @@ dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream) {
 }
 
 dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t first, int64_t n, float* x,
-                           int64_t ld, float* jac, float* u_out, float* lq_out, double alpha, void* stream) {
+                           int64_t ld, float* jac, float* u_out, float* lq_out, double mix_flow, double mix_uniform,
+                           void* stream) {
     if (!f || !s || !x || !jac) return fail(DMC_E_INVALID, "null argument");
     if (s->dim != f->dim || s->kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_INVALID, "need a VEGAS sampler of the flow's dimension");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
-    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in (0, 1]");
-    // balance-heuristic mixture: the first n_g samples come from the grid alone, the rest from the flow
-    const int64_t n_g = alpha < 1.0 ? (int64_t)std::llround((1.0 - alpha) * (double)n) : 0;
-    const int64_t n_f = n - n_g;
+    if (!(mix_flow > 0.0 && mix_flow <= 1.0) || !(mix_uniform >= 0.0 && mix_uniform < 1.0) ||
+        mix_flow + mix_uniform > 1.0 + 1e-12)
+        return fail(DMC_E_INVALID, "mixture shares: flow in (0, 1], uniform in [0, 1), flow + uniform <= 1");
+    const double mix_grid = std::max(0.0, 1.0 - mix_flow - mix_uniform);
+    // balance-heuristic mixture: samples [0, n_u) uniform, [n_u, n_u + n_g) from the grid, the rest through the flow
+    const int64_t n_u = std::min<int64_t>(n, (int64_t)std::llround(mix_uniform * (double)n));
+    const int64_t n_g = std::min<int64_t>(n - n_u, (int64_t)std::llround(mix_grid * (double)n));
+    const int64_t n_f = n - n_u - n_g;
+    const int D = f->dim;
+    const float af = (float)mix_flow, ag = (float)mix_grid, au = (float)mix_uniform;
+    // scratch: log q and J_V of the uniform and grid shares, u' of the uniform share if u_out is NULL
+    const int64_t need = 2 * (n_u + n_g) + (u_out ? 0 : (int64_t)D * n_u);
+    if (need > 0 && f->mix_cap < need) {
+        (void)hipFree(f->mix_buf);
+        f->mix_buf = nullptr;
+        f->mix_cap = 0;
+        HIP_ALLOC(hipMalloc(&f->mix_buf, sizeof(float) * (size_t)need));
+        f->mix_cap = need;
+    }
+    float* lq_s = f->mix_buf;
+    float* jv_s = lq_s + (n_u + n_g);
+    float* up_s = jv_s + (n_u + n_g);
+    const int ncu = cu_count();
+    if (n_u > 0) {
+        dmc::FlowUniformArgs ua;
+        ua.seed = seed;
+        ua.first = first;
+        ua.n = n_u;
+        ua.ld = ld;
+        ua.ldu = u_out ? ld : n_u;
+        ua.x = x;
+        ua.jac = jac;
+        ua.u_out = u_out ? u_out : up_s;
+        ua.jv_out = jv_s;
+        ua.edges = s->d_edges;
+        ua.n_bins = s->n_bins;
+        ua.dim = D;
+        ua.beta = (float)s->beta;
+        ua.qmax = (float)s->qmax;
+        ua.jl = (float)(4.0 * M_PI * s->qmax);
+        ua.jt = (float)std::pow(s->beta, s->order - 1);
+        HIP_TRY(dmc::launch_flow_uniform(ua, ncu, S(stream)));
+        dmc::FlowTrainArgs a;
+        train_args(f, a, n_u);
+        a.u_in = u_out ? u_out : up_s;
+        a.ld = u_out ? ld : n_u;
+        a.states = nullptr;
+        a.G = nullptr;
+        a.weff = nullptr;
+        a.w = nullptr;
+        a.loss_part = nullptr;
+        a.lq_out = lq_out ? lq_out : lq_s;
+        HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_u, ncu), S(stream)));
+        HIP_TRY(dmc::launch_flow_mix(jac, a.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
+    }
     if (n_g > 0) {
-        dmc_status st = dmc_sample(s, seed, first, n_g, x, ld, jac, stream);
+        dmc_status st = dmc_sample(s, seed, first + (uint64_t)n_u, n_g, x + n_u, ld, jac + n_u, stream);
         if (st != DMC_OK) return st;
-        float* lq = lq_out;
-        if (!lq) {
-            if (!f->mix_lq || f->mix_cap < n_g) {
-                (void)hipFree(f->mix_lq);
-                f->mix_lq = nullptr;
-                f->mix_cap = 0;
-                HIP_ALLOC(hipMalloc(&f->mix_lq, sizeof(float) * (size_t)n_g));
-                f->mix_cap = n_g;
-            }
-            lq = f->mix_lq;
-        }
-        // the inverse pass alone: density of the grid's points under the flow, nothing stored
-        const int nblk = dmc::flow_inverse_blocks(n_g, cu_count());
         dmc::FlowTrainArgs a;
         train_args(f, a, n_g);
         a.u_in = nullptr;
         a.seed = seed;
-        a.first = first;
+        a.first = first + (uint64_t)n_u;
         a.ld = ld;
         a.states = nullptr;
         a.G = nullptr;
         a.weff = nullptr;
         a.w = nullptr;
         a.loss_part = nullptr;
-        a.lq_out = lq;
-        a.u_out = u_out;
-        HIP_TRY(dmc::launch_flow_inverse(a, nblk, S(stream)));
-        HIP_TRY(dmc::launch_flow_mix(jac, lq, n_g, (float)alpha, S(stream)));
+        a.lq_out = lq_out ? lq_out + n_u : lq_s + n_u;
+        a.u_out = u_out ? u_out + n_u : nullptr;
+        a.edges = s->d_edges;
+        a.n_bins = s->n_bins;
+        a.jv_out = jv_s + n_u;
+        HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_g, ncu), S(stream)));
+        HIP_TRY(dmc::launch_flow_mix(jac + n_u, a.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
     }
     if (n_f > 0) {
+        const int64_t o = n_u + n_g;
         dmc::FlowSampleArgs a;
         a.seed = seed;
-        a.first = first + (uint64_t)n_g;
+        a.first = first + (uint64_t)o;
         a.n = n_f;
         a.ld = ld;
-        a.x = x + n_g;
-        a.jac = jac + n_g;
-        a.u_out = u_out ? u_out + n_g : nullptr;
-        a.lq_out = lq_out ? lq_out + n_g : nullptr;
+        a.x = x + o;
+        a.jac = jac + o;
+        a.u_out = u_out ? u_out + o : nullptr;
+        a.lq_out = lq_out ? lq_out + o : nullptr;
         a.edges = s->d_edges;
         a.master = f->master;
         a.shadow = f->shadow;
@@ -759,8 +802,10 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
         a.qmax = (float)s->qmax;
         a.jl = (float)(4.0 * M_PI * s->qmax);
         a.jt = (float)std::pow(s->beta, s->order - 1);
-        a.alpha = (float)alpha;
-        HIP_TRY(dmc::launch_flow_sample(a, f->dim, cu_count(), S(stream)));
+        a.mix_f = af;
+        a.mix_g = ag;
+        a.mix_u = au;
+        HIP_TRY(dmc::launch_flow_sample(a, D, ncu, S(stream)));
     }
     s->last_n = -1;  // the grid histogram does not apply to mixture samples
     return DMC_OK;
@@ -898,7 +943,7 @@ void dmc_flow_destroy(dmc_flow* f) {
     (void)hipFree(f->v);
     (void)hipFree(f->shadow);
     (void)hipFree(f->sums);
-    (void)hipFree(f->mix_lq);
+    (void)hipFree(f->mix_buf);
     delete f;
 }
 

@@ -350,7 +350,7 @@ dmc_flow_sample_kernel(FlowSampleArgs a) {
         if (s < a.n) {
             const float* zr = zw + (32 * h + j) * ZS;
             // u' = sigmoid(z_K); VEGAS map with the bin taken in FP32; physical map
-            float J = 1.0f;
+            float J = 1.0f, jv = 1.0f;
             float y[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -365,7 +365,7 @@ dmc_flow_sample_kernel(FlowSampleArgs a) {
                 const float lo = a.edges[d * (a.n_bins + 1) + bin];
                 const float hi = a.edges[d * (a.n_bins + 1) + bin + 1];
                 y[d] = __builtin_fmaf(fr, hi - lo, lo);
-                J *= (float)a.n_bins * (hi - lo);
+                jv *= (float)a.n_bins * (hi - lo);
             }
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -381,9 +381,9 @@ dmc_flow_sample_kernel(FlowSampleArgs a) {
             }
 #pragma unroll
             for (int jt = 1; jt < N; ++jt) a.x[(int64_t)(3 * N + jt - 1) * a.ld + s] = a.beta * y[3 * N + jt - 1];
-            // weight against the mixture density alpha q_flow + (1 - alpha): bounded by the grid's
-            // own Jacobian / (1 - alpha) in the flow's tails
-            a.jac[s] = J * a.jt / __builtin_fmaf(a.alpha, fexp(lq), 1.0f - a.alpha);
+            // weight against the mixture density: within 1/a_g of the grid's own weight and within
+            // 1/a_u of the uniform sampler's in the flow's tails
+            a.jac[s] = J * jv * a.jt / __builtin_fmaf(a.mix_f, fexp(lq), __builtin_fmaf(a.mix_u, jv, a.mix_g));
             if (a.lq_out) a.lq_out[s] = lq;
         }
     }
@@ -407,7 +407,7 @@ dmc_flow_inverse_kernel(FlowTrainArgs a) {
     prefetch_layer(sm + PassLds<D>::buf0, a.shadow, L - 1);
     for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
         const int64_t base = bt * PASS_THREADS + wv * 64;
-        float lqp[2];
+        float lqp[2], jvp[2] = {1.0f, 1.0f};
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             const int64_t s = base + 32 * nt + j;
@@ -435,6 +435,12 @@ dmc_flow_inverse_kernel(FlowTrainArgs a) {
                         const int d = 4 * b4 + w;
                         if (d < D) {
                             if (valid && a.u_out) a.u_out[(int64_t)d * a.ld + s] = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
+                            if (a.jv_out) {
+                                // the sampler's bin: (2m + 1) B >> 25 in integers
+                                const uint32_t bin = (uint32_t)(((2ull * (c[w] >> 8) + 1ull) * (uint64_t)a.n_bins) >> 25);
+                                const float* e = a.edges + d * (a.n_bins + 1) + bin;
+                                jvp[nt] *= (float)a.n_bins * (e[1] - e[0]);
+                            }
                             const float z = philox_logit(c[w]);
                             zr[d] = z;
                             lqp[nt] -= log_sig_prime(z);
@@ -462,6 +468,8 @@ dmc_flow_inverse_kernel(FlowTrainArgs a) {
         const int64_t s = base + 32 * h + j;
         const bool valid = s < a.n;
         float lq = lqp[h] + __shfl_xor(lqp[1 - h], 32);
+        const float jv = jvp[h] * __shfl_xor(jvp[1 - h], 32);
+        if (valid && a.jv_out) a.jv_out[s] = jv;
         const float* zr = zw + (32 * h + j) * ZS;
         for (int d = 0; d < D; ++d) lq += log_sig_prime(zr[d]);
         // a sample whose density is not finite is dropped from the loss and the gradient
@@ -840,9 +848,59 @@ __global__ void __launch_bounds__(256) dmc_flow_adam_kernel(FlowAdamArgs a) {
 }
 
 // samples drawn from the grid alone: J <- J / (alpha q_flow + 1 - alpha)
-__global__ void dmc_flow_mix_kernel(float* jac, const float* lq, int64_t n, float alpha) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        jac[i] = jac[i] / __builtin_fmaf(alpha, fexp(lq[i]), 1.0f - alpha);
+// balance-heuristic weight of points drawn from one share of the mixture
+__global__ void dmc_flow_mix_kernel(float* jac, const float* lq, const float* jv, int64_t n, float a_f, float a_g,
+                                    float a_u, int scale_jv) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = jv[i];
+        const float den = __builtin_fmaf(a_f, fexp(lq[i]), __builtin_fmaf(a_u, v, a_g));
+        jac[i] = (scale_jv ? jac[i] * v : jac[i]) / den;
+    }
+}
+
+// The uniform share: Philox y (24-bit uniform), physical map, u' = G^-1(y) by a binary search of
+// the grid edges (the bin b with e_b <= y < e_{b+1}, clamped to the grid), J_V = prod_d B (e_{b+1} - e_b).
+__global__ void __launch_bounds__(256) dmc_flow_uniform_kernel(FlowUniformArgs a) {
+    const int D = a.dim, B = a.n_bins, N = (D + 1) / 4;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t idx = a.first + (uint64_t)s;
+        float jv = 1.0f, jp = a.jt;
+        float y[ZMAX];
+        for (int b4 = 0; b4 * 4 < D; ++b4) {
+            uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)b4, 0u};
+            philox(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+            for (int w = 0; w < 4 && 4 * b4 + w < D; ++w) y[4 * b4 + w] = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
+        }
+        for (int d = 0; d < D; ++d) {
+            const float* e = a.edges + d * (B + 1);
+            int lo = 0, hi = B;  // invariant: e[lo] <= y, answer in [lo, hi)
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (e[mid] <= y[d])
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const float w = e[lo + 1] - e[lo];
+            const float fr = w > 0.0f ? fminf((y[d] - e[lo]) / w, 1.0f) : 0.0f;
+            a.u_out[(int64_t)d * a.ldu + s] = ((float)lo + fr) / (float)B;
+            jv *= (float)B * w;
+        }
+        for (int q = 0; q < N; ++q) {
+            const float r = a.qmax * y[3 * q];
+            const float ct = __builtin_fmaf(2.0f, y[3 * q + 1], -1.0f);
+            const float st = __builtin_sqrtf(__builtin_fmaxf(0.0f, __builtin_fmaf(-ct, ct, 1.0f)));
+            float sp, cp;
+            sincospif(2.0f * y[3 * q + 2], &sp, &cp);
+            a.x[(int64_t)(3 * q) * a.ld + s] = r * st * cp;
+            a.x[(int64_t)(3 * q + 1) * a.ld + s] = r * st * sp;
+            a.x[(int64_t)(3 * q + 2) * a.ld + s] = r * ct;
+            jp *= a.jl * r * r;
+        }
+        for (int j = 1; j < N; ++j) a.x[(int64_t)(3 * N + j - 1) * a.ld + s] = a.beta * y[3 * N + j - 1];
+        a.jac[s] = jp;
+        a.jv_out[s] = jv;
+    }
 }
 
 __global__ void __launch_bounds__(256) dmc_flow_shadow_kernel(const float* master, __bf16* shadow, int n_layers) {
@@ -975,10 +1033,18 @@ hipError_t launch_flow_adam(const FlowAdamArgs& a, int n_cu, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_flow_mix(float* jac, const float* lq, int64_t n, float alpha, hipStream_t st) {
+hipError_t launch_flow_mix(float* jac, const float* lq, const float* jv, int64_t n, float a_f, float a_g, float a_u,
+                           bool scale_jv, hipStream_t st) {
     const int64_t want = (n + 255) / 256;
-    hipLaunchKernelGGL(dmc_flow_mix_kernel, dim3((unsigned)(want < 4096 ? want : 4096)), dim3(256), 0, st, jac, lq, n,
-                       alpha);
+    hipLaunchKernelGGL(dmc_flow_mix_kernel, dim3((unsigned)(want < 4096 ? want : 4096)), dim3(256), 0, st, jac, lq, jv,
+                       n, a_f, a_g, a_u, scale_jv ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_uniform(const FlowUniformArgs& a, int n_cu, hipStream_t st) {
+    const int64_t want = (a.n + 255) / 256;
+    const int64_t cap = (int64_t)n_cu * 8;
+    hipLaunchKernelGGL(dmc_flow_uniform_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -92,7 +92,23 @@ struct FlowSampleArgs {
     const int* dA;    // [L]
     int n_layers, n_bins;
     float beta, qmax, jl, jt;
-    float alpha;  // share of the flow in the sampling mixture alpha q_flow + (1 - alpha)
+    // shares of the sampling mixture a_f q_flow + a_g (grid) + a_u (uniform): the weight of a point is
+    // J_phys J_V / (a_f q_flow(u') + a_g + a_u J_V), J_V the grid's Jacobian at u'
+    float mix_f, mix_g, mix_u;
+};
+
+// The uniform share of the mixture: y = Philox uniforms (as the uniform sampler draws them),
+// physical map, and the grid coordinates u' = G^-1(y) with the grid's Jacobian J_V(u').
+struct FlowUniformArgs {
+    uint64_t seed, first;
+    int64_t n, ld, ldu;
+    float* x;        // [D][ld]
+    float* jac;      // [n]: J_phys
+    float* u_out;    // [D][ldu]: u'
+    float* jv_out;   // [n]: J_V(u')
+    const float* edges;
+    int n_bins, dim;
+    float beta, qmax, jl, jt;
 };
 
 struct FlowTrainArgs {
@@ -113,6 +129,9 @@ struct FlowTrainArgs {
     float* weff;        // [n]: w / sum(w), or 0 for a sample whose density is not finite
     float* lq_out;      // nullable [n]
     float* u_out;       // nullable [D][ld]: the points u' used (Philox uniforms when u_in is NULL)
+    const float* edges; // with jv_out: the VEGAS grid [D][n_bins + 1]
+    int n_bins;
+    float* jv_out;      // nullable [n]: J_V at the Philox points (bin by the sampler's integer rule)
     float* loss_part;   // [blocks]
     __bf16* act_x1;     // [16][n]
     __bf16* act_h1;     // [128][n]
@@ -143,7 +162,10 @@ hipError_t launch_flow_backward(const FlowTrainArgs& a, int nblk, int layer, int
 hipError_t launch_flow_sums(const float* w, int64_t n, double* out, hipStream_t st);
 hipError_t launch_flow_loss(const float* loss_part, int nblk, double* out, hipStream_t st);
 hipError_t launch_flow_adam(const FlowAdamArgs& a, int n_cu, hipStream_t st);
-hipError_t launch_flow_mix(float* jac, const float* lq, int64_t n, float alpha, hipStream_t st);
+// jac[i] <- jac[i] (jv[i] if scale_jv) / (a_f exp(lq[i]) + a_g + a_u jv[i])
+hipError_t launch_flow_mix(float* jac, const float* lq, const float* jv, int64_t n, float a_f, float a_g, float a_u,
+                           bool scale_jv, hipStream_t st);
+hipError_t launch_flow_uniform(const FlowUniformArgs& a, int n_cu, hipStream_t st);
 hipError_t launch_flow_shadow(const float* master, __bf16* shadow, int n_layers, int n_cu, hipStream_t st);
 
 }  // namespace dmc

@@ -227,3 +227,59 @@ def test_extreme_base_words_stay_finite(first):
     lq_grid = ofl.log_q(th, m, u[:8])
     _, lq_flow, _ = ofl.sample(th, m, u[8:])
     assert np.max(np.abs(lqg - np.concatenate([lq_grid, lq_flow]))) < 5e-3
+
+
+def test_three_way_mixture_matches_oracle():
+    torch, dev = torch_dev()
+    D, n, N = 11, 3, 3001
+    a_f, a_u = 0.7, 0.2
+    f, m, th = _flow(D, scale=0.03, seed=2)
+    seed, first = 0x7717, 5 << 20
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    grid = synth.vegas_grid(D, 50, seed=6).astype(np.float64)
+    s.set_grid(grid)
+    g32 = grid.astype(np.float32).astype(np.float64)
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    Uo = torch.empty((D, N), dtype=torch.float32, device=dev)
+    LQ = torch.empty(N, dtype=torch.float32, device=dev)
+    f.sample(s, seed, first, X, J, u_out=Uo, lq_out=LQ, alpha=a_f, uniform=a_u)
+    n_u = int(np.floor(a_u * N + 0.5))
+    n_g = int(np.floor((1 - a_f - a_u) * N + 0.5))
+    X2 = torch.empty((D, n_g), dtype=torch.float32, device=dev)
+    J2 = torch.empty(n_g, dtype=torch.float32, device=dev)
+    s.sample(seed, first + n_u, X2, J2)
+    torch.cuda.synchronize()
+    xg, jg = X.cpu().numpy().T.astype(np.float64), J.cpu().numpy().astype(np.float64)
+    ug, lqg = Uo.cpu().numpy().T.astype(np.float64), LQ.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(jg)) and np.all(jg >= 0)
+    # uniform share: y = the uniform sampler's points, u' = G^-1(y), weight by the mixture
+    y, _ = osp.uniforms(seed, first, n_u, D)
+    y32 = y.astype(np.float32).astype(np.float64)
+    xr, Jp = ig.physical_map(y32, n, BETA, 6.0)
+    assert np.allclose(xg[:n_u], xr, rtol=0, atol=6.0 * 1e-5)
+    ur, jv_u = osp.vegas_inverse(y32, g32)
+    assert np.max(np.abs(ug[:n_u] - ur)) < 2e-6
+    lq_u = ofl.log_q(th, m, ug[:n_u])
+    assert np.median(np.abs(lqg[:n_u] - lq_u)) < 1e-4 and np.max(np.abs(lqg[:n_u] - lq_u)) < 5e-3
+    assert np.allclose(jg[:n_u], ofl.mixture_weight(Jp * jv_u, lqg[:n_u], a_f, a_u, jv_u), rtol=1e-4)
+    assert np.all(jg[:n_u] <= Jp / a_u * (1 + 1e-4))
+    # grid share: the sampler's own points and Jacobians, weighted by the mixture
+    sl = slice(n_u, n_u + n_g)
+    assert np.array_equal(xg[sl], X2.cpu().numpy().T)
+    u, mw = osp.uniforms(seed, first + n_u, n_g, D)
+    _, jv_g, _ = osp.vegas_map_int(mw, g32)
+    jgrid = J2.cpu().numpy().astype(np.float64)
+    lq_ref = ofl.log_q(th, m, u)
+    assert np.median(np.abs(lqg[sl] - lq_ref)) < 1e-4 and np.max(np.abs(lqg[sl] - lq_ref)) < 5e-3
+    assert np.allclose(jg[sl], ofl.mixture_weight(jgrid, lqg[sl], a_f, a_u, jv_g), rtol=1e-4)
+    # flow share
+    fs = slice(n_u + n_g, N)
+    uf, _ = osp.uniforms(seed, first + n_u + n_g, N - n_u - n_g, D)
+    up, lq, _ = ofl.sample(th, m, uf)
+    assert np.max(np.abs(ug[fs] - up)) < 2e-3
+    assert np.median(np.abs(lqg[fs] - lq)) < 1e-4 and np.max(np.abs(lqg[fs] - lq)) < 5e-3
+    yv, JV, _ = osp.vegas_map_float(ug[fs].astype(np.float32), g32)
+    xr, Jp = ig.physical_map(yv, n, BETA, 6.0)
+    assert np.allclose(xg[fs], xr, rtol=0, atol=6.0 * 1e-5)
+    assert np.allclose(jg[fs], ofl.mixture_weight(JV * Jp, lqg[fs], a_f, a_u, JV), rtol=1e-4)

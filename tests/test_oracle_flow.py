@@ -164,3 +164,46 @@ def test_mixture_estimate_unbiased_and_bounded():
         # alpha = 1 is plain flow importance sampling; alpha -> 0 the grid alone
         assert np.allclose(fl.mixture_weight(2.0, lq, 1.0), 2.0 * np.exp(-lq))
         assert np.allclose(fl.mixture_weight(2.0, lq, 0.0), 2.0)
+
+
+def test_three_way_mixture_unbiased_and_bounded():
+    # integral of prod_d 3 y_d^2 over the cube (= 1) with a non-uniform VEGAS grid G: points from the
+    # uniform density, from the grid (y = G(u'), u' uniform) and from the flow on the grid, in the
+    # proportions a_u : a_g : a_f, weighted by the mixture density in grid coordinates
+    import synth as sy
+    from oracle import sampler as sp
+    with smooth():
+        m, th = _setup(scale=0.4, seed=4)
+        edges = sy.vegas_grid(D, 50, seed=3).astype(np.float64)
+        rng = np.random.default_rng(11)
+        a_f, a_u, N = 0.6, 0.15, 1 << 15
+        n_u, n_g = int(round(a_u * N)), int(round((1 - a_f - a_u) * N))
+        y_u = rng.uniform(size=(n_u, D))
+        u_u, jv_u = sp.vegas_inverse(y_u, edges)
+        u_g = rng.uniform(size=(n_g, D))
+        y_g, jv_g, _ = sp.vegas_map_float(u_g.astype(np.float32), edges)
+        u_f, lq_f, _ = fl.sample(th, m, rng.uniform(size=(N - n_u - n_g, D)))
+        y_f, jv_f, _ = sp.vegas_map_float(u_f.astype(np.float32), edges)
+        u_g32 = u_g.astype(np.float32).astype(np.float64)
+        lq = np.concatenate([fl.log_q(th, m, u_u), fl.log_q(th, m, u_g32), lq_f])
+        jv = np.concatenate([jv_u, jv_g, jv_f])
+        y = np.concatenate([y_u, y_g, y_f])
+        w = fl.mixture_weight(jv, lq, a_f, a_u, jv)
+        assert w.max() <= 1.0 / a_u * (1 + 1e-12)                          # bounded by the uniform share
+        assert np.all(w <= jv / (1 - a_f - a_u) * (1 + 1e-12))              # and by the grid share
+        est = np.prod(3 * y ** 2, axis=1) * w
+        assert abs(est.mean() - 1.0) < 4 * est.std() / np.sqrt(N)
+        # a wrong share in the denominator (the flow's alone) biases the same samples
+        bad = np.prod(3 * y ** 2, axis=1) * jv * np.exp(-lq)
+        assert abs(bad.mean() - 1.0) > 4 * est.std() / np.sqrt(N)
+
+
+def test_vegas_inverse_round_trip():
+    import synth as sy
+    from oracle import sampler as sp
+    edges = sy.vegas_grid(7, 50, seed=9).astype(np.float64)
+    u = np.random.default_rng(2).uniform(size=(5000, 7))
+    y, J, _ = sp.vegas_map_float(u.astype(np.float32), edges)
+    u2, J2 = sp.vegas_inverse(y, edges)
+    assert np.allclose(u2, u.astype(np.float32), atol=1e-6)
+    assert np.allclose(J2, J, rtol=1e-9)
