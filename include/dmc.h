@@ -58,12 +58,14 @@ typedef struct {
     int32_t order;         /* n interaction lines, 1..DMC_MAX_ORDER */
     uint32_t deriv_mask;   /* derivative roots to build; 0 = value only */
     int32_t diagram_index; /* -1 = all diagrams; otherwise only diagram #i of the exported list */
-    int32_t reserved;      /* must be 0 */
+    int32_t part_size;     /* diagrams per straight-line part of the generated kernel (its parts share
+                              nothing and keep the register set bounded); 0 chooses by graph size */
 } dmc_graph_spec;
 
 typedef struct {
     int32_t order, dim, n_diagrams, n_root_classes;
     int32_t n_momenta, n_g_leaves, n_v_leaves, n_groups;
+    int32_t n_parts, part_size; /* straight-line parts of the generated kernel and their size (0: one part) */
     /* operation counts of the emitted code per sample: [0] add, [1] mul, [2] fma, [3] transcendental.
      * ops_sample: once per sample (k-independent part, per lambda group already multiplied in at
      * evaluation); ops_k: once per (sample, k) for one lambda group; ops_naive: the plain sum of

@@ -37,13 +37,14 @@ class DmcError(RuntimeError):
 
 class GraphSpec(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("deriv_mask", ctypes.c_uint32), ("diagram_index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("part_size", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_diagrams", ctypes.c_int32),
                 ("n_root_classes", ctypes.c_int32), ("n_momenta", ctypes.c_int32), ("n_g_leaves", ctypes.c_int32),
-                ("n_v_leaves", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("ops_sample", ctypes.c_int64 * 4),
+                ("n_v_leaves", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("n_parts", ctypes.c_int32),
+                ("part_size", ctypes.c_int32), ("ops_sample", ctypes.c_int64 * 4),
                 ("ops_k", ctypes.c_int64 * 4), ("ops_naive", ctypes.c_int64 * 4)]
 
 
@@ -147,9 +148,9 @@ def dim(order: int) -> int:
 class Graph:
     """A compiled diagram graph (dmc_compile_graph)."""
 
-    def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1):
+    def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1, part_size: int = 0):
         self.h = P()
-        spec = GraphSpec(order, deriv_mask, diagram_index, 0)
+        spec = GraphSpec(order, deriv_mask, diagram_index, part_size)
         _check(lib().dmc_compile_graph(ctypes.byref(spec), ctypes.byref(self.h)))
         self.order = order
         self.deriv_mask = deriv_mask

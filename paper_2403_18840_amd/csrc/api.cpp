@@ -116,11 +116,11 @@ const char* dmc_version(void) { return "dmc-mi355x 0.1 (gfx950)"; }
 // ------------------------------------------------------------------------------ graph
 dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
     if (!spec || !out) return fail(DMC_E_INVALID, "null argument");
-    if (spec->reserved != 0) return fail(DMC_E_INVALID, "reserved must be 0");
+    if (spec->part_size < 0) return fail(DMC_E_INVALID, "part_size must be >= 0");
     auto g = std::make_unique<dmc_graph>();
     std::string err;
     try {
-        if (!dmc::compile(spec->order, spec->deriv_mask, spec->diagram_index, g->c, err))
+        if (!dmc::compile(spec->order, spec->deriv_mask, spec->diagram_index, spec->part_size, g->c, err))
             return fail(DMC_E_INVALID, err);
         g->exported = dmc::export_text(g->c);
     } catch (const std::bad_alloc&) {
@@ -137,6 +137,8 @@ dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
     o->dim = g->c.dim;
     o->n_diagrams = (int)g->c.diagrams.size();
     o->n_root_classes = g->c.n_root_classes;
+    o->n_parts = g->c.stats.parts;
+    o->part_size = g->c.part_size;
     for (int i = 0; i < 4; ++i) {
         o->ops_sample[i] = g->c.stats.sample[i];
         o->ops_k[i] = g->c.stats.k[i];

@@ -239,8 +239,11 @@ class Emitter {
     int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0};  // add mul fma trans
     bool act[3] = {false, false, false};
 
+    std::string prefix = "v";  // name prefix (distinct per part of a partitioned kernel)
+    std::string tag;           // prefix of the few names not made by def (empty for one part)
+
     Val def(bool kdep, const std::string& expr, int opclass, int nops = 1) {
-        std::string nm = "v" + std::to_string(tmp_++);
+        std::string nm = prefix + std::to_string(tmp_++);
         (kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
         if (opclass >= 0) (kdep ? cnt_loop : cnt_pre)[opclass] += nops;
         return {nm, kdep, {}};
@@ -389,7 +392,7 @@ struct Builder {
             for (int j = 0; j < n; ++j) {
                 int cf = moms[m][j];
                 if (!cf) continue;
-                std::string t = std::string("q") + std::to_string(j) + ax[a];
+                std::string t = em.tag + "q" + std::to_string(j) + ax[a];
                 if (nterms == 0)
                     e = (cf == 1 ? "" : cf == -1 ? "-" : std::to_string(cf) + ".0f * ") + t;
                 else
@@ -440,11 +443,11 @@ struct Builder {
         auto key = std::make_pair(a, b);
         auto it = tpair.find(key);
         if (it != tpair.end()) return it->second;
-        std::string ta = a == 0 ? "0.0f" : "t" + std::to_string(a);
-        std::string tb = b == 0 ? "0.0f" : "t" + std::to_string(b);
-        std::string la = a == 0 ? "" : "tl" + std::to_string(a);
-        std::string lb = b == 0 ? "" : "tl" + std::to_string(b);
-        std::string pos = "ps" + std::to_string(a) + "_" + std::to_string(b);
+        std::string ta = a == 0 ? "0.0f" : em.tag + "t" + std::to_string(a);
+        std::string tb = b == 0 ? "0.0f" : em.tag + "t" + std::to_string(b);
+        std::string la = a == 0 ? "" : em.tag + "tl" + std::to_string(a);
+        std::string lb = b == 0 ? "" : em.tag + "tl" + std::to_string(b);
+        std::string pos = em.tag + "ps" + std::to_string(a) + "_" + std::to_string(b);
         em.pre << "    const bool " << pos << " = " << tb << " > " << ta << ";\n";
         std::string dexpr = lb.empty() ? "-" + la : la.empty() ? lb : lb + " - " + la;
         Val d = em.def(false, dexpr, 0, (la.empty() || lb.empty()) ? 0 : 1);
@@ -604,7 +607,9 @@ struct Builder {
 
 }  // namespace
 
-bool compile(int order, uint32_t deriv_mask, int diagram_index, Compiled& out, std::string& err) {
+int default_part_size(int n_diagrams, int n_roots);
+
+bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -629,6 +634,11 @@ bool compile(int order, uint32_t deriv_mask, int diagram_index, Compiled& out, s
     std::set<int> cls;
     for (auto& d : out.diagrams) cls.insert(d.ext_line());
     out.n_root_classes = (int)cls.size();
+    if (part_size < 0) {
+        err = "part_size must be >= 0";
+        return false;
+    }
+    out.part_size = part_size > 0 ? part_size : default_part_size((int)out.diagrams.size(), out.n_roots);
     CodeStats st;
     emit_eval_source(out, 1, &st);
     out.stats = st;
@@ -668,72 +678,157 @@ std::string export_text(const Compiled& c) {
 namespace dmc {
 
 std::string kernel_name(const Compiled& c, int n_groups) {
+    const int nd = (int)c.diagrams.size();
+    const int np = c.part_size > 0 && nd > c.part_size ? (nd + c.part_size - 1) / c.part_size : 1;
     return "dmc_eval_o" + std::to_string(c.order) + "_g" + std::to_string(n_groups) + "_r" + std::to_string(c.n_roots) +
-           (c.diagrams.size() == 1 ? "_single" : "");
+           (nd == 1 ? "_single" : "") + (np > 1 ? "_p" + std::to_string(np) : "");
+}
+
+// Diagram parts of a partitioned kernel: diagrams sorted by root class and by the leaves that
+// carry the external momentum (diagrams in one part share their k-dependent leaves), then cut into
+// parts of at most part_size diagrams.  One part = the whole graph when it fits.
+static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_size) {
+    const int n = c.order;
+    const int nd = (int)c.diagrams.size();
+    std::vector<std::vector<int>> parts;
+    if (part_size <= 0 || nd <= part_size) {
+        parts.emplace_back();
+        for (int i = 0; i < nd; ++i) parts[0].push_back(i);
+        return parts;
+    }
+    std::vector<std::pair<std::vector<int>, int>> keyed;
+    for (int i = 0; i < nd; ++i) {
+        const Diagram& d = c.diagrams[i];
+        std::vector<int> key{d.ext_line()};
+        std::vector<std::vector<int>> kl;
+        for (auto& ln : d.lines) {
+            Mom m = normalise(ln.mom, n);
+            if (m[n] == 0) continue;
+            std::vector<int> e{ln.kind == 'G' ? 0 : 1, ln.src / 2, ln.dst / 2};
+            if (ln.kind == 'V') e[1] = e[2] = 0;
+            e.insert(e.end(), m.begin(), m.end());
+            kl.push_back(e);
+        }
+        std::sort(kl.begin(), kl.end());
+        for (auto& e : kl) key.insert(key.end(), e.begin(), e.end());
+        keyed.push_back({key, i});
+    }
+    std::stable_sort(keyed.begin(), keyed.end());
+    for (int i = 0; i < nd; ++i) {
+        if (i % part_size == 0) parts.emplace_back();
+        parts.back().push_back(keyed[i].second);
+    }
+    return parts;
+}
+
+int default_part_size(int n_diagrams, int n_roots) {
+    // Measured on MI355X (2^24 samples, 32 k): order 5 runs in 587 ms as one spilling part, 115 ms
+    // in parts of 800 diagrams, 130 ms in parts of 400; order 4 with three derivative roots in
+    // 147 ms as one part, 65 ms in parts of 95; order 5 with them in 696 ms in parts of 120.
+    // Parts of about 800 / R^1.5 diagrams (R roots) keep each part's live set within the register
+    // file without recomputing more leaves than needed.
+    const int per = std::max(16, (int)(800.0 / std::pow((double)n_roots, 1.5)));
+    return n_diagrams <= per ? 0 : per;
 }
 
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) {
     const int n = c.order;
-    Builder b(c, n_groups);
     std::vector<int> cls;
     for (auto& d : c.diagrams) cls.push_back(d.ext_line());
     std::sort(cls.begin(), cls.end());
     cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
-
-    // roots[g][r]
-    std::vector<std::vector<Val>> roots(n_groups);
-    for (int g = 0; g < n_groups; ++g) {
-        for (int r : cls) {
-            std::vector<Term> terms;
-            for (auto& d : c.diagrams) {
-                if (d.ext_line() != r) continue;
-                Term t;
-                t.coef = d.weight;
-                for (auto& ln : d.lines) t.f.push_back(ln.kind == 'G' ? b.g_leaf(ln) : b.v_leaf(ln, g));
-                std::sort(t.f.begin(), t.f.end());
-                terms.push_back(t);
-            }
-            roots[g].push_back(b.horner(terms));
-        }
-    }
-    // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
-    // every derivative root (the phases and scale depend on none of mu, lambda, k)
     std::vector<int> dirs;
     for (int i = 0; i < 3; ++i)
-        if (b.em.act[i]) dirs.push_back(i);
+        if (c.deriv_mask & (1u << i)) dirs.push_back(i);
     const int NR = 1 + (int)dirs.size();
-    std::ostringstream epi;
+    const auto parts = diagram_parts(c, c.part_size);
+    const bool split = parts.size() > 1;
+
+    struct Part {
+        std::string pre, loop, epi;
+        int64_t cnt_pre[4], cnt_loop[4];
+    };
+    std::vector<Part> pc;
     int64_t epi_ops[4] = {0, 0, 0, 0};
-    for (int g = 0; g < n_groups; ++g) {
-        for (int ro = 0; ro < NR; ++ro) {
-            std::string fr, fi;
-            for (size_t ri = 0; ri < cls.size(); ++ri) {
-                int r = cls[ri];
-                std::string rv = ro == 0 ? roots[g][ri].name : roots[g][ri].d[dirs[ro - 1]];
-                if (rv.empty()) continue;
-                std::string pc = "PC" + std::to_string(g) + "_" + std::to_string(r);
-                std::string ps = "PS" + std::to_string(g) + "_" + std::to_string(r);
-                if (fr.empty()) {
-                    fr = rv + " * " + pc;
-                    epi_ops[1]++;
-                } else {
-                    fr = "__builtin_fmaf(" + rv + ", " + pc + ", " + fr + ")";
-                    epi_ops[2]++;
+    for (size_t pi = 0; pi < parts.size(); ++pi) {
+        Builder b(c, n_groups);
+        if (split) {
+            b.em.tag = "p" + std::to_string(pi) + "_";
+            b.em.prefix = b.em.tag + "v";
+        }
+        std::vector<int> pcls;
+        for (int di : parts[pi]) pcls.push_back(c.diagrams[di].ext_line());
+        std::sort(pcls.begin(), pcls.end());
+        pcls.erase(std::unique(pcls.begin(), pcls.end()), pcls.end());
+        // roots[g][class index within the part]
+        std::vector<std::vector<Val>> roots(n_groups);
+        for (int g = 0; g < n_groups; ++g) {
+            for (int r : pcls) {
+                std::vector<Term> terms;
+                for (int di : parts[pi]) {
+                    const Diagram& d = c.diagrams[di];
+                    if (d.ext_line() != r) continue;
+                    Term t;
+                    t.coef = d.weight;
+                    for (auto& ln : d.lines) t.f.push_back(ln.kind == 'G' ? b.g_leaf(ln) : b.v_leaf(ln, g));
+                    std::sort(t.f.begin(), t.f.end());
+                    terms.push_back(t);
                 }
-                if (r == 0) continue;
-                if (fi.empty()) {
-                    fi = rv + " * " + ps;
-                    epi_ops[1]++;
+                roots[g].push_back(b.horner(terms));
+            }
+        }
+        // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
+        // every derivative root (the phases and scale depend on none of mu, lambda, k)
+        std::ostringstream epi;
+        for (int g = 0; g < n_groups; ++g) {
+            for (int ro = 0; ro < NR; ++ro) {
+                std::string fr, fi;
+                for (size_t ri = 0; ri < pcls.size(); ++ri) {
+                    int r = pcls[ri];
+                    std::string rv = ro == 0 ? roots[g][ri].name : roots[g][ri].d[dirs[ro - 1]];
+                    if (rv.empty()) continue;
+                    std::string pcn = "PC" + std::to_string(g) + "_" + std::to_string(r);
+                    std::string psn = "PS" + std::to_string(g) + "_" + std::to_string(r);
+                    if (fr.empty()) {
+                        fr = rv + " * " + pcn;
+                        epi_ops[1]++;
+                    } else {
+                        fr = "__builtin_fmaf(" + rv + ", " + pcn + ", " + fr + ")";
+                        epi_ops[2]++;
+                    }
+                    if (r == 0) continue;
+                    if (fi.empty()) {
+                        fi = rv + " * " + psn;
+                        epi_ops[1]++;
+                    } else {
+                        fi = "__builtin_fmaf(" + rv + ", " + psn + ", " + fi + ")";
+                        epi_ops[2]++;
+                    }
+                }
+                if (!split) {
+                    if (fr.empty()) fr = "0.0f";
+                    if (fi.empty()) fi = "0.0f";
+                    epi << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
+                    epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
                 } else {
-                    fi = "__builtin_fmaf(" + rv + ", " + ps + ", " + fi + ")";
-                    epi_ops[2]++;
+                    const int slot = (g * NR + ro) * 2;
+                    if (!fr.empty())
+                        epi << "        stage[(kq * SPK + " << slot << ") * 64 + lane] += " << fr << ";\n";
+                    if (!fi.empty())
+                        epi << "        stage[(kq * SPK + " << slot + 1 << ") * 64 + lane] += " << fi << ";\n";
+                    epi_ops[0] += (!fr.empty()) + (!fi.empty());
                 }
             }
-            if (fr.empty()) fr = "0.0f";
-            if (fi.empty()) fi = "0.0f";
-            epi << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
-            epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
         }
+        Part p;
+        p.pre = b.em.pre.str();
+        p.loop = b.em.loop.str();
+        p.epi = epi.str();
+        for (int i = 0; i < 4; ++i) {
+            p.cnt_pre[i] = b.em.cnt_pre[i];
+            p.cnt_loop[i] = b.em.cnt_loop[i];
+        }
+        pc.push_back(std::move(p));
     }
 
     const int SPK = 2 * n_groups * NR;
@@ -741,9 +836,16 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     const int SCH = KC * SPK;
     const int M = (SCH + 15) / 16;
 
+    auto indent = [](std::ostringstream& out, const std::string& text, const std::string& pad) {
+        std::istringstream in(text);
+        std::string line;
+        while (std::getline(in, line)) out << pad << line << "\n";
+    };
+
     std::ostringstream s;
-    s << "// generated: order " << n << ", " << c.diagrams.size() << " diagrams, " << n_groups
-      << " lambda group(s)\n";
+    s << "// generated: order " << n << ", " << c.diagrams.size() << " diagrams, " << n_groups << " lambda group(s)";
+    if (split) s << ", " << parts.size() << " parts";
+    s << "\n";
     s << "#define KERNEL_NAME " << kernel_name(c, n_groups) << "\n";
     s << "#define DIM " << c.dim << "\n#define NGRP " << n_groups << "\n#define NROOT " << NR << "\n#define SPK " << SPK
       << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n";
@@ -796,39 +898,84 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
                 s << "        const float PS" << g << "_" << r << " = a.scale[" << g << "] * sn" << g << "_" << r << ";\n";
             }
         }
-    s << b.em.pre.str();
-    s << R"K(        float imp = 0.0f;
+    if (!split) {
+        s << pc[0].pre;
+        s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += KC) {
             for (int kq = 0; kq < KC; ++kq) {
                 const int ki = kb + kq;
                 const bool kv = ki < a.n_k;
                 const float kk = a.k[kv ? ki : 0];
 )K";
-    {
-        std::string body = b.em.loop.str();
-        std::istringstream in(body);
-        std::string line;
-        while (std::getline(in, line)) s << "            " << line << "\n";
-        std::string e = epi.str();
-        std::istringstream in2(e);
-        while (std::getline(in2, line)) s << "            " << line << "\n";
-    }
-    for (int g = 0; g < n_groups; ++g)
-        for (int ro = 0; ro < NR; ++ro)
-            for (int comp = 0; comp < 2; ++comp) {
-                int slot = (g * NR + ro) * 2 + comp;
-                s << "                {\n";
-                s << "                    const float f = " << (comp ? "FI" : "FR") << g << "_" << ro << ";\n";
-                s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
-                s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
-                if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
-                s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
-                s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
-                  << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
-                s << "                }\n";
+        indent(s, pc[0].loop, "            ");
+        indent(s, pc[0].epi, "            ");
+        for (int g = 0; g < n_groups; ++g)
+            for (int ro = 0; ro < NR; ++ro)
+                for (int comp = 0; comp < 2; ++comp) {
+                    int slot = (g * NR + ro) * 2 + comp;
+                    s << "                {\n";
+                    s << "                    const float f = " << (comp ? "FI" : "FR") << g << "_" << ro << ";\n";
+                    s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
+                    s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
+                    if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
+                    s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
+                    s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
+                      << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
+                    s << "                }\n";
+                }
+        s << "            }\n";
+    } else {
+        // partitioned: every part adds its roots into the stage; each part's k-independent code is
+        // recomputed per chunk of KC external momenta so that no part's values stay live across parts
+        s << R"K(        float imp = 0.0f;
+        for (int kb = 0; kb < a.n_k; kb += KC) {
+            for (int i = 0; i < SCH; ++i) stage[i * 64 + lane] = 0.0f;
+)K";
+        for (size_t pi = 0; pi < pc.size(); ++pi) {
+            s << "            {  // part " << pi << " (" << parts[pi].size() << " diagrams)\n";
+            // the part's own copies of the coordinates, passed through an empty asm statement so that
+            // the compiler neither merges nor keeps alive values across parts
+            const std::string tg = "p" + std::to_string(pi) + "_";
+            std::vector<std::string> in;
+            for (int j = 0; j < n; ++j)
+                for (int e = 0; e < 3; ++e) in.push_back(std::string("q") + std::to_string(j) + ax[e]);
+            for (int j = 1; j < n; ++j) {
+                in.push_back("t" + std::to_string(j));
+                in.push_back("tl" + std::to_string(j));
             }
-    s << R"K(            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            for (auto& v : in) {
+                s << "            float " << tg << v << " = " << v << ";\n";
+                s << "            asm volatile(\"\" : \"+v\"(" << tg << v << "));\n";
+            }
+            indent(s, pc[pi].pre, "        ");
+            s << "            for (int kq = 0; kq < KC; ++kq) {\n";
+            s << "                const int ki = kb + kq;\n";
+            s << "                const float kk = a.k[ki < a.n_k ? ki : 0];\n";
+            indent(s, pc[pi].loop, "            ");
+            indent(s, pc[pi].epi, "            ");
+            s << "            }\n";
+            s << "            }\n";
+        }
+        s << "            for (int kq = 0; kq < KC; ++kq) {\n";
+        s << "                const int ki = kb + kq;\n";
+        s << "                const bool kv = ki < a.n_k;\n";
+        for (int g = 0; g < n_groups; ++g)
+            for (int ro = 0; ro < NR; ++ro)
+                for (int comp = 0; comp < 2; ++comp) {
+                    int slot = (g * NR + ro) * 2 + comp;
+                    s << "                {\n";
+                    s << "                    const float f = stage[(kq * SPK + " << slot << ") * 64 + lane];\n";
+                    s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
+                    s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
+                    if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
+                    s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
+                    s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
+                      << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
+                    s << "                }\n";
+                }
+        s << "            }\n";
+    }
+    s << R"K(            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int m = 0; m < MST; ++m) {
@@ -868,10 +1015,13 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
 )K";
     if (stats) {
         *stats = CodeStats{};
-        for (int i = 0; i < 4; ++i) {
-            stats->sample[i] = b.em.cnt_pre[i];
-            stats->k[i] = b.em.cnt_loop[i] + epi_ops[i];
-        }
+        for (auto& p : pc)
+            for (int i = 0; i < 4; ++i) {
+                stats->sample[i] += p.cnt_pre[i];
+                stats->k[i] += p.cnt_loop[i];
+            }
+        for (int i = 0; i < 4; ++i) stats->k[i] += epi_ops[i];
+        stats->parts = (int)parts.size();
         // naive: every diagram as a plain product of its lines, every leaf evaluated per diagram
         for (auto& d : c.diagrams) {
             int ng = 0, nv = 0, neq = 0;

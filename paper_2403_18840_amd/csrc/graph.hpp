@@ -40,6 +40,7 @@ struct CodeStats {
     int64_t sample[4] = {0, 0, 0, 0};  // add, mul, fma, trans per sample (k-independent)
     int64_t k[4] = {0, 0, 0, 0};       // per (sample, k)
     int64_t naive[4] = {0, 0, 0, 0};   // plain sum of products per (sample, k)
+    int parts = 1;                       // straight-line parts of the generated kernel
 };
 
 struct Compiled {
@@ -47,13 +48,15 @@ struct Compiled {
     int n_momenta = 0, n_g_leaves = 0, n_v_leaves = 0, n_groups = 0;
     uint32_t deriv_mask = 0;
     int n_roots = 1;
+    int part_size = 0;  // diagrams per straight-line part; 0 = one part
     std::vector<Diagram> diagrams;
     CodeStats stats;
 };
 
 // Builds the compiled description (diagram subset selection, IR statistics).
 // diagram_index < 0 keeps all diagrams.
-bool compile(int order, uint32_t deriv_mask, int diagram_index, Compiled& out, std::string& err);
+// part_size: diagrams per straight-line part of the kernel; 0 chooses by size.
+bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, Compiled& out, std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);

@@ -10,26 +10,30 @@ from oracle import integrand as ig
 from oracle import physics as ph
 
 from gpu_helpers import BETA, LAM, MU, gpu_integrand, to_soa, torch_dev
+from golden_diagrams import oracle_diagrams
 
 pytestmark = pytest.mark.gpu
 ALL = dmc.D_MU | dmc.D_LAMBDA | dmc.D_K
 
 
-@pytest.mark.parametrize("n,N,K", [(1, 600, 3), (2, 600, 5), (3, 400, 3)])
+@pytest.mark.parametrize("n,N,K", [(1, 600, 3), (2, 600, 5), (3, 400, 3), (4, 300, 3), (5, 100, 2)])
 def test_derivative_roots_per_sample(n, N, K):
     """Each derivative against the oracle's dual numbers, judged against the size of the
-    derivative's terms before cancellation (the condition-aware reading of 1e-5 relative)."""
+    derivative's terms before cancellation (the condition-aware reading of 1e-5 relative).
+    Orders 4 and 5 run the partitioned kernel (2 and 23 parts)."""
     x = synth.loop_points(n, N, seed=300 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
     f, acc, _ = gpu_integrand(dmc.Graph(n, ALL), x, ks, [(BETA, MU, LAM, gamma)])
     assert f.shape[1] == 4
     x64 = x.astype(np.float64)
+    dgs = oracle_diagrams(n)
     worst = [0.0] * 4
     for j, k in enumerate(ks):
         kk = float(np.float32(k))
-        ref = [a.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma)]
-        scale = [a.real.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, absolute=True)]
+        ref = [a.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)]
+        scale = [a.real.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs,
+                                                                    absolute=True)]
         for r in range(4):
             err = np.abs(f[0, r, j] - ref[r])
             ok = err <= 1e-5 * scale[r] + 1e-30

@@ -11,6 +11,7 @@ from oracle import physics as ph
 from oracle import sampler as osp
 
 from gpu_helpers import BETA, LAM, MU, gpu_integrand, to_soa, torch_dev
+from golden_diagrams import oracle_diagrams
 
 pytestmark = pytest.mark.gpu
 
@@ -21,21 +22,24 @@ REL = 1e-5
 
 
 def _oracle_f(x, n, k, lam, gamma):
-    return ig.integrand(x.astype(np.float64), n, float(np.float32(k)), BETA, MU, lam, gamma)
+    return ig.integrand(x.astype(np.float64), n, float(np.float32(k)), BETA, MU, lam, gamma,
+                        diagrams=oracle_diagrams(n))
 
 
-@pytest.mark.parametrize("n,N,K", [(1, 845, 5), (2, 845, 11), (3, 600, 9), (4, 300, 3)])
-def test_integrand_per_sample(n, N, K):
-    """Several 256-sample tiles plus a ragged tail; K spans a partial chunk of k values."""
+@pytest.mark.parametrize("n,N,K,part_size", [(1, 845, 5, 0), (2, 845, 11, 0), (3, 600, 9, 0), (4, 300, 3, 0),
+                                             (4, 300, 10, 40), (5, 300, 3, 0)])
+def test_integrand_per_sample(n, N, K, part_size):
+    """Several 256-sample tiles plus a ragged tail; K spans a partial chunk of k values.  Order 4
+    in parts of 40 diagrams and order 5 (three parts by default) cover the partitioned kernel."""
     x = synth.loop_points(n, N, seed=100 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
-    g = dmc.Graph(n)
+    g = dmc.Graph(n, part_size=part_size)
     f, acc, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
     worst = 0.0
     for j, k in enumerate(ks):
         ref = _oracle_f(x, n, k, LAM, gamma)
-        A = ig.abs_sum(x.astype(np.float64), n, float(k), BETA, MU, LAM, gamma)
+        A = ig.abs_sum(x.astype(np.float64), n, float(k), BETA, MU, LAM, gamma, diagrams=oracle_diagrams(n))
         err = np.abs(f[0, 0, j] - ref)
         ratio = err / (A + 1e-300)
         worst = max(worst, float(np.max(ratio[A > 1e-30])) if np.any(A > 1e-30) else 0.0)

@@ -7,6 +7,8 @@ import pytest
 import paper_2403_18840_amd as dmc
 from oracle import diagrams as dg
 
+from golden_diagrams import golden_counts, oracle_diagrams
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -40,19 +42,46 @@ def _parse_export(text, n):
 
 def _oracle_set(n):
     out = set()
-    for d in dg.sigma_diagrams(n):
+    for d in oracle_diagrams(n):
         lines = tuple(sorted((l.kind, l.src, l.dst, tuple(l.mom)) for l in d.lines))
         out.add((d.sigma, d.weight, d.ext_line, lines))
     return out
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
 def test_exported_diagrams_equal_oracle_set(n):
     # the library's orderly generator and the oracle's brute force give the same canonical
-    # diagrams, the same signs and the same momentum routing
+    # diagrams, the same signs and the same momentum routing (order 5 from the golden list that
+    # the oracle's brute force wrote)
     g = dmc.Graph(n)
     assert _parse_export(g.export(), n) == _oracle_set(n)
-    assert g.info().n_diagrams == len(dg.sigma_diagrams(n))
+    assert g.info().n_diagrams == len(oracle_diagrams(n))
+
+
+def test_order5_golden_counts():
+    # 2232 topologies; each has (n-1)! 2^(n-1) labelled forms (the in-vertex's line is fixed)
+    tops, lab = golden_counts(5)
+    assert tops == 2232 and lab == tops * 24 * 16
+
+
+def test_partitioned_graphs():
+    # large graphs are emitted as several straight-line parts that share nothing
+    for n, mask, parts in [(3, 0, 1), (4, 0, 1), (4, 7, 2), (5, 0, 3)]:
+        i = dmc.Graph(n, deriv_mask=mask).info()
+        assert i.n_parts == parts, (n, mask, i.n_parts)
+    g = dmc.Graph(4, part_size=40)
+    i = g.info()
+    assert i.n_parts == 5 and i.part_size == 40
+    src = g.source(1)
+    assert "_p5" in src and src.count("// part ") == 5 and 'asm volatile("" : "+v"(p4_q0x))' in src
+    # every diagram lands in exactly one part
+    import re
+    sizes = [int(m) for m in re.findall(r"// part \d+ \((\d+) diagrams\)", src)]
+    assert sum(sizes) == 189 and max(sizes) == 40
+    # splitting costs extra leaf evaluations but no change of the diagram set
+    assert sum(i.ops_k) >= sum(dmc.Graph(4).info().ops_k)
+    with pytest.raises(dmc.DmcError):
+        dmc.Graph(3, part_size=-1)
 
 
 def test_single_diagram_graph_and_errors():
