@@ -607,7 +607,7 @@ struct Builder {
 
 }  // namespace
 
-int default_part_size(int n_diagrams, int n_roots);
+int default_part_size(int order, int n_diagrams, int n_roots);
 
 bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
@@ -638,7 +638,7 @@ bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, C
         err = "part_size must be >= 0";
         return false;
     }
-    out.part_size = part_size > 0 ? part_size : default_part_size((int)out.diagrams.size(), out.n_roots);
+    out.part_size = part_size > 0 ? part_size : default_part_size(order, (int)out.diagrams.size(), out.n_roots);
     CodeStats st;
     emit_eval_source(out, 1, &st);
     out.stats = st;
@@ -721,13 +721,15 @@ static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_s
     return parts;
 }
 
-int default_part_size(int n_diagrams, int n_roots) {
+int default_part_size(int order, int n_diagrams, int n_roots) {
     // Measured on MI355X (2^24 samples, 32 k): order 5 runs in 587 ms as one spilling part, 115 ms
     // in parts of 800 diagrams, 130 ms in parts of 400; order 4 with three derivative roots in
     // 147 ms as one part, 65 ms in parts of 95; order 5 with them in 696 ms in parts of 120.
     // Parts of about 800 / R^1.5 diagrams (R roots) keep each part's live set within the register
-    // file without recomputing more leaves than needed.
-    const int per = std::max(16, (int)(800.0 / std::pow((double)n_roots, 1.5)));
+    // file without recomputing more leaves than needed; order-6 diagrams have more lines (parts of
+    // 800 spill 300 registers, parts of 400 none).
+    const double base = order >= 6 ? 400.0 : 800.0;
+    const int per = std::max(16, (int)(base / std::pow((double)n_roots, 1.5)));
     return n_diagrams <= per ? 0 : per;
 }
 

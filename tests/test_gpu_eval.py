@@ -27,10 +27,11 @@ def _oracle_f(x, n, k, lam, gamma):
 
 
 @pytest.mark.parametrize("n,N,K,part_size", [(1, 845, 5, 0), (2, 845, 11, 0), (3, 600, 9, 0), (4, 300, 3, 0),
-                                             (4, 300, 10, 40), (5, 300, 3, 0)])
+                                             (4, 300, 10, 40), (5, 300, 3, 0), (6, 40, 2, 0)])
 def test_integrand_per_sample(n, N, K, part_size):
     """Several 256-sample tiles plus a ragged tail; K spans a partial chunk of k values.  Order 4
-    in parts of 40 diagrams and order 5 (three parts by default) cover the partitioned kernel."""
+    in parts of 40 diagrams, order 5 (3 parts) and order 6 (31130 diagrams in 78 parts; about
+    two minutes of run-time compilation) cover the partitioned kernel."""
     x = synth.loop_points(n, N, seed=100 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)

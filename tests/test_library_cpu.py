@@ -1,4 +1,5 @@
 """Host-side checks of the C ABI library (no GPU): symbols, diagram export, errors, op counts."""
+import math
 import os
 import re
 
@@ -7,7 +8,8 @@ import pytest
 import paper_2403_18840_amd as dmc
 from oracle import diagrams as dg
 
-from golden_diagrams import golden_counts, oracle_diagrams
+from golden_diagrams import golden_counts, golden_topologies, oracle_diagrams
+from oracle import build as ob
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -48,7 +50,7 @@ def _oracle_set(n):
     return out
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
 def test_exported_diagrams_equal_oracle_set(n):
     # the library's orderly generator and the oracle's brute force give the same canonical
     # diagrams, the same signs and the same momentum routing (order 5 from the golden list that
@@ -58,15 +60,27 @@ def test_exported_diagrams_equal_oracle_set(n):
     assert g.info().n_diagrams == len(oracle_diagrams(n))
 
 
-def test_order5_golden_counts():
-    # 2232 topologies; each has (n-1)! 2^(n-1) labelled forms (the in-vertex's line is fixed)
-    tops, lab = golden_counts(5)
-    assert tops == 2232 and lab == tops * 24 * 16
+@pytest.mark.parametrize("n,tops_expected", [(5, 2232), (6, 31130)])
+def test_golden_counts(n, tops_expected):
+    # each topology has (n-1)! 2^(n-1) labelled forms (the in-vertex's line is fixed)
+    tops, lab = golden_counts(n)
+    assert tops == tops_expected and lab == tops * math.factorial(n - 1) * 2 ** (n - 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_c_enumerator_matches_python_brute_force(n):
+    # the C version of the oracle's brute force (used at order 6) against the Python one
+    assert ob.enumerate_topologies(n) == dg.enumerate_topologies(n)
+
+
+def test_c_enumerator_matches_order5_golden():
+    tops, lab = ob.enumerate_topologies(5)
+    assert tops == golden_topologies(5) and lab == golden_counts(5)[1]
 
 
 def test_partitioned_graphs():
     # large graphs are emitted as several straight-line parts that share nothing
-    for n, mask, parts in [(3, 0, 1), (4, 0, 1), (4, 7, 2), (5, 0, 3)]:
+    for n, mask, parts in [(3, 0, 1), (4, 0, 1), (4, 7, 2), (5, 0, 3), (6, 0, 78)]:
         i = dmc.Graph(n, deriv_mask=mask).info()
         assert i.n_parts == parts, (n, mask, i.n_parts)
     g = dmc.Graph(4, part_size=40)
