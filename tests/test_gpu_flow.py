@@ -22,7 +22,7 @@ def _flow(D, scale=0.03, seed=1):
     return f, m, th.astype(np.float64)
 
 
-@pytest.mark.parametrize("D", [7, 15])
+@pytest.mark.parametrize("D", [3, 7, 15, 23])
 def test_log_density_matches_oracle(D):
     torch, dev = torch_dev()
     f, m, th = _flow(D)
@@ -41,7 +41,7 @@ def test_log_density_matches_oracle(D):
     assert np.median(err) < 1e-4 and err.max() < 5e-3
 
 
-@pytest.mark.parametrize("D,n", [(7, 2), (15, 4)])
+@pytest.mark.parametrize("D,n", [(3, 1), (7, 2), (15, 4), (23, 6)])
 def test_flow_samples_match_oracle(D, n):
     torch, dev = torch_dev()
     f, m, th = _flow(D)
@@ -95,7 +95,7 @@ def test_identity_flow_reproduces_vegas_sampler():
     assert torch.allclose(J1, J2, rtol=1e-4)
 
 
-@pytest.mark.parametrize("D,N", [(7, 2048), (15, 3000)])
+@pytest.mark.parametrize("D,N", [(3, 1000), (7, 2048), (15, 3000), (23, 1500)])
 def test_gradient_matches_oracle(D, N):
     torch, dev = torch_dev()
     f, m, th = _flow(D, scale=0.03, seed=7)
