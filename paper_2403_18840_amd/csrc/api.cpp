@@ -286,7 +286,10 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     const int SPK = 2 * ng * NR;
     const int KC = SPK <= 16 ? 16 / SPK : 1;
     const int M = (KC * SPK + 15) / 16;
-    const size_t smem = (size_t)4 * 16 * M * 64 * sizeof(float) + (size_t)4 * 2 * acc->s_total * sizeof(double);
+    // stage, FP64 totals, and for a kernel in parts the lanes' inputs (3n + 2(n - 1) rows per wave)
+    const int nin = g->c.stats.parts > 1 ? 3 * g->c.order + 2 * (g->c.order - 1) : 0;
+    const size_t smem = (size_t)4 * 16 * M * 64 * sizeof(float) + (size_t)4 * 2 * acc->s_total * sizeof(double) +
+                        (size_t)4 * nin * 64 * sizeof(float);
     if (smem > 160 * 1024) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
     if (jk->max_blocks_per_cu <= 1) {
         int nb = 0;

@@ -747,6 +747,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     const bool split = parts.size() > 1;
 
     struct Part {
+        std::vector<int> cls;
         std::string pre, loop, epi;
         int64_t cnt_pre[4], cnt_loop[4];
     };
@@ -814,15 +815,14 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                     epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
                 } else {
                     const int slot = (g * NR + ro) * 2;
-                    if (!fr.empty())
-                        epi << "        stage[(kq * SPK + " << slot << ") * 64 + lane] += " << fr << ";\n";
-                    if (!fi.empty())
-                        epi << "        stage[(kq * SPK + " << slot + 1 << ") * 64 + lane] += " << fi << ";\n";
+                    if (!fr.empty()) epi << "        st[(kq * SPK + " << slot << ") * 64] += " << fr << ";\n";
+                    if (!fi.empty()) epi << "        st[(kq * SPK + " << slot + 1 << ") * 64] += " << fi << ";\n";
                     epi_ops[0] += (!fr.empty()) + (!fi.empty());
                 }
             }
         }
         Part p;
+        p.cls = pcls;
         p.pre = b.em.pre.str();
         p.loop = b.em.loop.str();
         p.epi = epi.str();
@@ -860,7 +860,50 @@ struct EvalArgs {
     float lam[8]; float scale[8];
     float k[64];
 };
-
+)K";
+    const char* ax = "xyz";
+    // inputs of a part, one LDS row of 64 lanes each: q (3n), t (n - 1), t log2(e) (n - 1)
+    std::vector<std::string> ins;
+    for (int j = 0; j < n; ++j)
+        for (int e = 0; e < 3; ++e) ins.push_back(std::string("q") + std::to_string(j) + ax[e]);
+    for (int j = 1; j < n; ++j) ins.push_back("t" + std::to_string(j));
+    for (int j = 1; j < n; ++j) ins.push_back("tl" + std::to_string(j));
+    if (split) {
+        // every part is a function of its own (never inlined): the compiler allocates registers and
+        // schedules each part alone, so compile time and register use grow with the part, not
+        // with the whole graph.  in: this lane's inputs (stride 64); st: this lane's stage column.
+        for (size_t pi = 0; pi < pc.size(); ++pi) {
+            const std::string tg = "p" + std::to_string(pi) + "_";
+            s << "\n// part " << pi << " (" << parts[pi].size() << " diagrams)\n";
+            s << "__device__ __attribute__((noinline)) void dmc_part_" << pi
+              << "(const EvalArgs* __restrict__ ap, const float* __restrict__ in, float* __restrict__ st, const int kb) {\n";
+            s << "    const float MU = ap->mu, BL = ap->bl, BLMU = ap->blmu, BETA = ap->beta;\n";
+            s << "    (void)MU; (void)BL; (void)BLMU; (void)BETA;\n";
+            for (int g = 0; g < n_groups; ++g) s << "    const float LAM" << g << " = ap->lam[" << g << "];\n";
+            for (size_t i = 0; i < ins.size(); ++i)
+                s << "    const float " << tg << ins[i] << " = in[" << i * 64 << "];\n";
+            for (int g = 0; g < n_groups; ++g)
+                for (int r : pc[pi].cls) {
+                    if (r == 0) {
+                        s << "    const float PC" << g << "_0 = ap->scale[" << g << "];\n";
+                    } else {
+                        s << "    float sn" << g << "_" << r << ", cs" << g << "_" << r << ";\n";
+                        s << "    sincospif(" << tg << "t" << r << " * (2.0f * ap->inv2beta), &sn" << g << "_" << r << ", &cs"
+                          << g << "_" << r << ");\n";
+                        s << "    const float PC" << g << "_" << r << " = ap->scale[" << g << "] * cs" << g << "_" << r << ";\n";
+                        s << "    const float PS" << g << "_" << r << " = ap->scale[" << g << "] * sn" << g << "_" << r << ";\n";
+                    }
+                }
+            s << pc[pi].pre;
+            s << "    for (int kq = 0; kq < KC; ++kq) {\n";
+            s << "        const int ki = kb + kq;\n";
+            s << "        const float kk = ap->k[ki < ap->n_k ? ki : 0];\n";
+            indent(s, pc[pi].loop, "    ");
+            indent(s, pc[pi].epi, "");
+            s << "    }\n}\n";
+        }
+    }
+    s << R"K(
 extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -880,7 +923,6 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         const long long si = valid ? s : a.n - 1;
         const float J = valid ? a.jac[si] : 0.0f;
 )K";
-    const char* ax = "xyz";
     for (int j = 0; j < n; ++j)
         for (int e = 0; e < 3; ++e)
             s << "        const float q" << j << ax[e] << " = X[" << (3 * j + e) << " * ld + si];\n";
@@ -888,7 +930,7 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         s << "        const float t" << j << " = X[" << (3 * n + j - 1) << " * ld + si];\n";
         s << "        const float tl" << j << " = t" << j << " * 1.44269504089f;\n";
     }
-    for (int g = 0; g < n_groups; ++g)
+    for (int g = 0; g < n_groups && !split; ++g)
         for (int r : cls) {
             if (r == 0) {
                 s << "        const float PC" << g << "_0 = a.scale[" << g << "];\n";
@@ -929,35 +971,15 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
     } else {
         // partitioned: every part adds its roots into the stage; each part's k-independent code is
         // recomputed per chunk of KC external momenta so that no part's values stay live across parts
+        s << "        float* cin = (float*)((double*)(smem + 4 * 16 * MST * 64) + 4 * 2 * a.s_total) + wv * "
+          << ins.size() * 64 << " + lane;\n";
+        for (size_t i = 0; i < ins.size(); ++i) s << "        cin[" << i * 64 << "] = " << ins[i] << ";\n";
         s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += KC) {
             for (int i = 0; i < SCH; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
-        for (size_t pi = 0; pi < pc.size(); ++pi) {
-            s << "            {  // part " << pi << " (" << parts[pi].size() << " diagrams)\n";
-            // the part's own copies of the coordinates, passed through an empty asm statement so that
-            // the compiler neither merges nor keeps alive values across parts
-            const std::string tg = "p" + std::to_string(pi) + "_";
-            std::vector<std::string> in;
-            for (int j = 0; j < n; ++j)
-                for (int e = 0; e < 3; ++e) in.push_back(std::string("q") + std::to_string(j) + ax[e]);
-            for (int j = 1; j < n; ++j) {
-                in.push_back("t" + std::to_string(j));
-                in.push_back("tl" + std::to_string(j));
-            }
-            for (auto& v : in) {
-                s << "            float " << tg << v << " = " << v << ";\n";
-                s << "            asm volatile(\"\" : \"+v\"(" << tg << v << "));\n";
-            }
-            indent(s, pc[pi].pre, "        ");
-            s << "            for (int kq = 0; kq < KC; ++kq) {\n";
-            s << "                const int ki = kb + kq;\n";
-            s << "                const float kk = a.k[ki < a.n_k ? ki : 0];\n";
-            indent(s, pc[pi].loop, "            ");
-            indent(s, pc[pi].epi, "            ");
-            s << "            }\n";
-            s << "            }\n";
-        }
+        for (size_t pi = 0; pi < pc.size(); ++pi)
+            s << "            dmc_part_" << pi << "(&a, cin, stage + lane, kb);\n";
         s << "            for (int kq = 0; kq < KC; ++kq) {\n";
         s << "                const int ki = kb + kq;\n";
         s << "                const bool kv = ki < a.n_k;\n";
