@@ -66,13 +66,18 @@ typedef struct {
     int32_t order, dim, n_diagrams, n_root_classes;
     int32_t n_momenta, n_g_leaves, n_v_leaves, n_groups;
     int32_t n_parts, part_size; /* straight-line parts of the generated kernel and their size (0: one part) */
-    /* operation counts of the emitted code per sample: [0] add, [1] mul, [2] fma, [3] transcendental.
+    /* operation counts of the graph per sample: [0] add, [1] mul, [2] fma, [3] transcendental.
      * ops_sample: once per sample (k-independent part, per lambda group already multiplied in at
-     * evaluation); ops_k: once per (sample, k) for one lambda group; ops_naive: the plain sum of
-     * products over diagrams per (sample, k) before hoisting and common-subexpression elimination. */
+     * evaluation); ops_k: once per (sample, k) for one lambda group (the algorithmic counts: the
+     * graph as one straight-line part); ops_naive: the plain sum of products over diagrams per
+     * (sample, k) before hoisting and common-subexpression elimination. */
     int64_t ops_sample[4];
     int64_t ops_k[4];
     int64_t ops_naive[4];
+    /* as executed by a kernel in parts (each part evaluates the leaves it uses; k-independent code
+     * once per chunk of external momenta is not counted here): ops_*_exec >= ops_* */
+    int64_t ops_sample_exec[4];
+    int64_t ops_k_exec[4];
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that

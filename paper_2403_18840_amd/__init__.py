@@ -45,7 +45,8 @@ class GraphInfo(ctypes.Structure):
                 ("n_root_classes", ctypes.c_int32), ("n_momenta", ctypes.c_int32), ("n_g_leaves", ctypes.c_int32),
                 ("n_v_leaves", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("n_parts", ctypes.c_int32),
                 ("part_size", ctypes.c_int32), ("ops_sample", ctypes.c_int64 * 4),
-                ("ops_k", ctypes.c_int64 * 4), ("ops_naive", ctypes.c_int64 * 4)]
+                ("ops_k", ctypes.c_int64 * 4), ("ops_naive", ctypes.c_int64 * 4),
+                ("ops_sample_exec", ctypes.c_int64 * 4), ("ops_k_exec", ctypes.c_int64 * 4)]
 
 
 class Instance(ctypes.Structure):

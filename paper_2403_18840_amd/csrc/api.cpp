@@ -143,6 +143,8 @@ dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
         o->ops_sample[i] = g->c.stats.sample[i];
         o->ops_k[i] = g->c.stats.k[i];
         o->ops_naive[i] = g->c.stats.naive[i];
+        o->ops_sample_exec[i] = g->c.stats.sample_exec[i];
+        o->ops_k_exec[i] = g->c.stats.k_exec[i];
     }
     return DMC_OK;
 }

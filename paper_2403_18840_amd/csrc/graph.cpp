@@ -641,6 +641,21 @@ bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, C
     out.part_size = part_size > 0 ? part_size : default_part_size(order, (int)out.diagrams.size(), out.n_roots);
     CodeStats st;
     emit_eval_source(out, 1, &st);
+    for (int i = 0; i < 4; ++i) {
+        st.sample_exec[i] = st.sample[i];
+        st.k_exec[i] = st.k[i];
+    }
+    if (st.parts > 1) {
+        // algorithmic counts: the same graph emitted as one part (no leaf evaluated twice)
+        Compiled whole = out;
+        whole.part_size = 0;
+        CodeStats one;
+        emit_eval_source(whole, 1, &one);
+        for (int i = 0; i < 4; ++i) {
+            st.sample[i] = one.sample[i];
+            st.k[i] = one.k[i];
+        }
+    }
     out.stats = st;
     return true;
 }

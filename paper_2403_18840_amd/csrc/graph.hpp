@@ -41,6 +41,8 @@ struct CodeStats {
     int64_t k[4] = {0, 0, 0, 0};       // per (sample, k)
     int64_t naive[4] = {0, 0, 0, 0};   // plain sum of products per (sample, k)
     int parts = 1;                       // straight-line parts of the generated kernel
+    int64_t sample_exec[4] = {0, 0, 0, 0};  // as executed by a kernel in parts (leaves recomputed
+    int64_t k_exec[4] = {0, 0, 0, 0};       // per part); equal to sample / k for one part
 };
 
 struct Compiled {

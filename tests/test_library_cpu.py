@@ -93,8 +93,9 @@ def test_partitioned_graphs():
     import re
     sizes = [int(m) for m in re.findall(r"// part \d+ \((\d+) diagrams\)", src)]
     assert sum(sizes) == 189 and max(sizes) == 40
-    # splitting costs extra leaf evaluations but no change of the diagram set
-    assert sum(i.ops_k) >= sum(dmc.Graph(4).info().ops_k)
+    # splitting costs extra leaf evaluations (executed counts) but not algorithmic ones
+    assert list(i.ops_k) == list(dmc.Graph(4).info().ops_k)
+    assert sum(i.ops_k_exec) > sum(i.ops_k) and i.ops_k_exec[3] > i.ops_k[3]
     with pytest.raises(dmc.DmcError):
         dmc.Graph(3, part_size=-1)
 
