@@ -92,3 +92,25 @@ def test_autograd_function_backward_and_finite_differences():
     fd_k0 = (val(MU, LAM, [kk[0] + h, kk[1]]) - val(MU, LAM, [kk[0] - h, kk[1]])) / (2 * h)
     for got, fd in [(mu.grad.item(), fd_mu), (lam.grad.item(), fd_lam), (k.grad[0].item(), fd_k0)]:
         assert abs(got - fd) <= 5e-3 * max(abs(fd), 1e-6), (got, fd)
+
+
+def test_k_derivative_order6_per_sample():
+    """d Sigma / dk at order 6 (31130 diagrams; a kernel of 221 parts, about a minute of run-time
+    compilation) against the oracle's dual numbers at k near k_F."""
+    n, N = 6, 24
+    x = synth.loop_points(n, N, seed=306)
+    ks = np.array([0.0, 1.0], dtype=np.float32)
+    gamma = ph.coupling(1.0)
+    f, acc, _ = gpu_integrand(dmc.Graph(n, dmc.D_K), x, ks, [(BETA, MU, LAM, gamma)])
+    assert f.shape[1] == 2
+    x64 = x.astype(np.float64)
+    dgs = oracle_diagrams(n)
+    for j, k in enumerate(ks):
+        kk = float(np.float32(k))
+        vals = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
+        scales = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs, absolute=True)
+        for r, src in [(0, 0), (1, 3)]:
+            ref = vals[src].sum(axis=0)
+            scale = scales[src].real.sum(axis=0)
+            err = np.abs(f[0, r, j] - ref)
+            assert np.all(err <= 1e-5 * scale + 1e-30), f"root {r} k={k}: worst {np.max(err / (scale + 1e-300))}"
