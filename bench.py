@@ -12,7 +12,7 @@ second), with the roofline of the dominant kernel (the order-3 graph evaluation)
 HIP events on its stream, and the CPU oracle timed on a bounded sample of the same workload.
 
 After the timed steps (outside them), `flow_vs_vegas` compares the learned proposal with VEGAS at
-order 4 (D = 15): the error of Re Sigma(k_F, i omega_0) (scatter of 16 independent batch means) and
+order 4 (D = 15): the error of Re Sigma(k_F, i omega_0) (scatter of 64 independent batch means of 2^22) and
 wall time for the same number of samples from the adapted grid and from the trained 8-layer
 affine-coupling flow (defensive mixture 0.85 flow + 0.10 grid + 0.05 uniform), the efficiency
 (sigma_V^2 T_V) / (sigma_F^2 T_F) with and without adaptation and training time, and the flow
@@ -96,8 +96,10 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     samples drawn from the adapted VEGAS grid alone and from the trained flow's defensive mixture
     (0.85 flow + 0.10 grid + 0.05 uniform), each with its wall time (GPU-synchronised).  sigma is the
     scatter of the batch means / sqrt(batches): at this order the weights are heavy-tailed and the
-    in-run sample sigma understates the error (both are reported).  Efficiency =
-    (sigma_V^2 T_V) / (sigma_F^2 T_F), without and with adaptation + training time."""
+    in-run sample sigma understates the error (both are reported), and a few batches can dominate
+    the scatter, so the robust spread (1.4826 x the median absolute deviation of the batch means)
+    is reported beside it.  Efficiency = (sigma_V^2 T_V) / (sigma_F^2 T_F), without and with
+    adaptation + training time."""
     import numpy as np
     import torch
 
@@ -136,7 +138,9 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
             sig.append(e[0, 0, jf].real)
             nonfin += nf
         means = np.array(means)
+        mad = 1.4826 * float(np.median(np.abs(means - np.median(means))))
         return {"re": float(means.mean()), "sigma": float(means.std(ddof=1) / math.sqrt(batches)),
+                "sigma_mad": mad / math.sqrt(batches),
                 "sigma_in_run": float(math.sqrt(np.mean(np.square(sig)) / batches)), "nonfinite": int(nonfin)}
 
     vg, t_v = timed(lambda: run(lambda b: s.sample(seed + 1, b * N, X, J)))
@@ -170,6 +174,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
                      "flop_per_launch": flop},
         "z": float((vg["re"] - fl["re"]) / math.hypot(ev, ef)),
         "variance_ratio": float((ev / ef) ** 2),
+        "variance_ratio_mad": float((vg["sigma_mad"] / fl["sigma_mad"]) ** 2),
         "efficiency_steady": float((ev ** 2 * t_v) / (ef ** 2 * t_f)),
         "efficiency_total": float((ev ** 2 * (t_adapt + t_v)) / (ef ** 2 * (t_adapt + t_train + t_f))),
     }
@@ -187,7 +192,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--flow-order", type=int, default=4,
                     help="order of the learned-proposal comparison (0 skips it)")
-    ap.add_argument("--flow-batches", type=int, default=16)
+    ap.add_argument("--flow-batches", type=int, default=64)
+    ap.add_argument("--flow-log2-samples", type=int, default=22)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -298,7 +304,8 @@ def main():
                        "re_err": float(last[1][0, 0, j].real), "im": float(last[0][0, 0, j].imag),
                        "im_err": float(last[1][0, 0, j].imag)}
     if args.flow_order:
-        out["flow_vs_vegas"] = flow_vs_vegas(args.flow_order, K, N, args.flow_batches, beta, mu, lam, inst[0][3])
+        out["flow_vs_vegas"] = flow_vs_vegas(args.flow_order, K, 1 << args.flow_log2_samples, args.flow_batches, beta, mu,
+                                             lam, inst[0][3])
     print(json.dumps(out), flush=True)
 
 
