@@ -94,7 +94,10 @@ const char* dmc_version(void);
  * with no zero-momentum interaction line (Hartree tadpoles vanish by q != 0 in eq. ueg_action),
  * weight (-1)^(n+F) 2^F, routes their momenta, builds the leaf-deduplicated graph, hoists the
  * k- and lambda-independent part and removes repeated products.  Host only; the device code is
- * compiled lazily at the first evaluation.  *out is library-owned: free with dmc_graph_destroy. */
+ * compiled lazily at the first evaluation (hiprtc, for gfx950) and its code object is kept in an
+ * on-disk cache keyed by source and compiler: directory $DMC_KERNEL_CACHE (set and empty: no
+ * cache), else $XDG_CACHE_HOME/dmc-kernels, else $HOME/.cache/dmc-kernels.  Large graphs are
+ * emitted in parts (spec.part_size).  *out is library-owned: free with dmc_graph_destroy. */
 dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out);
 dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* out);
 /* Text export of the diagram list, one diagram per line:

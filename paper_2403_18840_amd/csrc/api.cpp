@@ -2,10 +2,14 @@
 // kernels, launches, the FP64 estimate and the VEGAS grid refinement.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -174,6 +178,52 @@ void dmc_graph_destroy(dmc_graph* g) {
     delete g;
 }
 
+// On-disk cache of compiled graph kernels: an order-6 graph takes tens of seconds of run-time
+// compilation.  Directory: $DMC_KERNEL_CACHE (empty: no cache), else $XDG_CACHE_HOME/dmc-kernels,
+// else $HOME/.cache/dmc-kernels.  Key: 64-bit FNV-1a of compiler version, options and source.
+static std::string cache_dir() {
+    const char* e = std::getenv("DMC_KERNEL_CACHE");
+    if (e) return std::string(e);
+    if (const char* x = std::getenv("XDG_CACHE_HOME"); x && *x) return std::string(x) + "/dmc-kernels";
+    if (const char* h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/dmc-kernels";
+    return std::string();
+}
+
+static uint64_t fnv1a(const std::string& t, uint64_t h = 1469598103934665603ull) {
+    for (unsigned char c : t) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static bool read_file(const std::string& path, std::vector<char>& out) {
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    std::fseek(f, 0, SEEK_END);
+    const long sz = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    out.resize(sz > 0 ? (size_t)sz : 0);
+    const bool ok = sz > 0 && std::fread(out.data(), 1, out.size(), f) == out.size();
+    std::fclose(f);
+    return ok;
+}
+
+static void write_file_atomic(const std::string& dir, const std::string& name, const std::vector<char>& data) {
+    std::error_code ec;
+    std::filesystem::create_directories(dir, ec);
+    if (ec) return;
+    const std::string tmp = dir + "/" + name + ".tmp" + std::to_string((long long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
+    std::fclose(f);
+    if (ok)
+        std::filesystem::rename(tmp, dir + "/" + name, ec);
+    else
+        std::filesystem::remove(tmp, ec);
+}
+
 static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -185,11 +235,27 @@ static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
     }
     JitKernel jk;
     jk.src = dmc::emit_eval_source(g->c, n_groups, nullptr);
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    int vmaj = 0, vmin = 0;
+    hiprtcVersion(&vmaj, &vmin);
+    std::string tag = "hiprtc " + std::to_string(vmaj) + "." + std::to_string(vmin);
+    for (const char* o : opts) tag += std::string(" ") + o;
+    char hex[17];
+    std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)fnv1a(jk.src, fnv1a(tag)));
+    const std::string cdir = cache_dir(), cname = std::string(hex) + ".co";
+    std::vector<char> cached;
+    if (!cdir.empty() && read_file(cdir + "/" + cname, cached) &&
+        hipModuleLoadData(&jk.mod, cached.data()) == hipSuccess) {
+        HIP_TRY(hipModuleGetFunction(&jk.fn, jk.mod, dmc::kernel_name(g->c, n_groups).c_str()));
+        g->jit[key] = jk;
+        *out = &g->jit[key];
+        return DMC_OK;
+    }
+    (void)hipGetLastError();  // a stale cache entry that failed to load is recompiled
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, jk.src.c_str(), "dmc_eval.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return fail(DMC_E_COMPILE, "hiprtcCreateProgram failed");
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
     hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
@@ -205,6 +271,7 @@ static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     HIP_TRY(hipModuleLoadData(&jk.mod, code.data()));
+    if (!cdir.empty()) write_file_atomic(cdir, cname, code);
     HIP_TRY(hipModuleGetFunction(&jk.fn, jk.mod, dmc::kernel_name(g->c, n_groups).c_str()));
     g->jit[key] = jk;
     *out = &g->jit[key];
