@@ -207,6 +207,39 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
                                const float* w, double lr, float* grad_out, double* loss, void* stream);
 void dmc_flow_destroy(dmc_flow* f);
 
+/* ---- Markov-chain estimator (Sec. IV, eq. target_distr_nf_mcmc_qft_revised and
+ * eq. nf_mcmc_estimator_qft_final_revised) ----
+ * n independent chains, one per sample lane, with independent proposals: every step the caller draws
+ * n proposals from a sampler (dmc_sample or dmc_flow_sample, jac = 1/q at each proposal) and
+ * evaluates them with dmc_eval_batch capturing f_out ([G][R][K][2][ld], ld = the chain count or more).
+ * The target is pi = alpha q + (1 - alpha) p, p = |f| summed over root 0's slots (every lambda group,
+ * external momentum, Re and Im); a chain moves to its proposal x' with probability
+ * min(1, pi(x') q(x) / (pi(x) q(x'))), decided in FP64 as u pi(x) q(x') < pi(x') q(x) with u the 24-bit
+ * Philox uniform of key `seed`, counter (chain, step) (first word).  The first step takes every valid
+ * proposal; a proposal whose q or pi is not finite and positive is never taken, and a chain without a
+ * valid state takes its next valid proposal.  A measured step adds, over the chains, f/pi per slot and
+ * q/pi, with their squares, to FP64 sums in a fixed order: I = sum f/pi / sum q/pi.  At alpha = 1 every
+ * proposal is taken and the estimate is the plain importance-sampling one.  The sums are kept per chain
+ * batch: batch b holds chains [b n / B, (b + 1) n / B) (integer division), so the B batches are
+ * independent estimates whose scatter gives the error whatever the chains' autocorrelation time.
+ * Handles are library-owned; DMC_E_INVALID for n < 1, n_batches outside [1, min(n,
+ * DMC_MAX_CHAIN_BATCHES)] or an observable shape outside the accumulator's limits. */
+#define DMC_MAX_CHAIN_BATCHES 4096
+typedef struct dmc_chains dmc_chains;
+dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
+                             dmc_chains** out);
+/* One step of every chain; measure != 0 accumulates the chains' states after the step. */
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, double alpha,
+                           uint64_t seed, int32_t measure, void* stream);
+/* sums: host double[n_batches][S + 1][2], S = n_groups n_roots n_k 2 slots in the f_out order, per batch:
+ * [b][s][0] = sum f_s/pi, [b][s][1] = sum (f_s/pi)^2; row S: sum q/pi and its squares.  n_measured: chain
+ * states added (all batches);
+ * n_accepted: proposals taken since the last reset.  Synchronises `stream`. */
+dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream);
+/* Zero the sums and the accepted count (the chain states are kept). */
+dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
+void dmc_chains_destroy(dmc_chains* c);
+
 #ifdef __cplusplus
 }
 #endif

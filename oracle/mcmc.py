@@ -1,0 +1,92 @@
+"""Oracle Markov-chain estimator with independent proposals (test infrastructure; only tests/, the
+smoke check and the bench's CPU leg use it).
+
+Follows Sec. IV: the target pi = alpha q + (1 - alpha) p with p = |f| (eq.
+target_distr_nf_mcmc_qft_revised), the Metropolis-Hastings acceptance
+min(1, pi(x') Q(x | x') / (pi(x) Q(x' | x))), which for independent proposals Q(x' | x) = q(x')
+reads min(1, pi(x') q(x) / (pi(x) q(x'))), and the ratio estimator
+I = sum_i f(x_i)/pi(x_i) / sum_i q(x_i)/pi(x_i) over the chain states x_i (eq.
+nf_mcmc_estimator_qft_final_revised).
+
+Conventions shared with the library (data, each side with its own code): p sums |f| over the
+root-0 observable slots in slot order, in FP64; the test is u pi(x) q(x') < pi(x') q(x) in FP64
+with u = ((w >> 8) + 1/2) 2^-24, w the first Philox4x32-10 word of key `seed`, counter
+(chain mod 2^32, chain div 2^32, step mod 2^32, step div 2^32); a proposal whose q or pi is not
+finite and positive is never taken, a chain without a valid state takes its next valid proposal,
+and the first step takes every valid proposal.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import sampler as osp
+
+MASK = 0xFFFFFFFF
+
+
+def uniforms(seed: int, step: int, n: int):
+    c = np.arange(n, dtype=np.uint64)
+    ctr = np.stack([c & np.uint64(MASK), c >> np.uint64(32),
+                    np.full(n, step & MASK, dtype=np.uint64), np.full(n, step >> 32, dtype=np.uint64)], axis=-1)
+    key = np.broadcast_to(np.array([seed & MASK, (seed >> 32) & MASK], dtype=np.uint64), (n, 2))
+    w = osp.philox4x32_10(ctr, key)[:, 0]
+    return ((w >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+
+
+def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots):
+    """One Metropolis-Hastings step of every chain.  state: dict f [S][n] (float32 values), q, pi
+    [n] float64, or None before the first step.  f_prop [S][n] float32, jac_prop [n] float32.
+    Returns (new state, taken [n] bool)."""
+    f_prop = np.asarray(f_prop, dtype=np.float32)
+    n = f_prop.shape[1]
+    p = np.zeros(n)
+    for s in root0_slots:
+        p = p + np.abs(f_prop[s].astype(np.float64))
+    jp = np.asarray(jac_prop, dtype=np.float32).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        qp = 1.0 / jp
+        pip = alpha * qp + (1.0 - alpha) * p
+        vp = (jp > 0) & np.isfinite(qp) & np.isfinite(pip) & (pip > 0)
+        if state is None:
+            pis = np.zeros(n)
+            qs = np.zeros(n)
+        else:
+            pis, qs = state["pi"], state["q"]
+        vs = (pis > 0) & np.isfinite(pis)
+        u = uniforms(seed, step_index, n)
+        test = u * pis * qp < pip * qs
+    take = vp & (~vs | test)
+    if state is None:
+        new = {"f": np.zeros_like(f_prop), "q": np.zeros(n), "pi": np.zeros(n)}
+    else:
+        new = {k: v.copy() for k, v in state.items()}
+    new["f"][:, take] = f_prop[:, take]
+    new["q"][take] = qp[take]
+    new["pi"][take] = pip[take]
+    return new, take
+
+
+def batch_bounds(n: int, n_batches: int):
+    """Chain batch b holds chains [b n // B, (b + 1) n // B)."""
+    return [(b * n // n_batches, (b + 1) * n // n_batches) for b in range(n_batches)]
+
+
+def measure(state, n_batches: int = 1):
+    """Per chain batch and slot, the sum over the batch's chains of f/pi and of (f/pi)^2, and the same
+    for q/pi: [n_batches][S + 1][2] (a chain without a valid state adds zero)."""
+    pi = state["pi"]
+    ok = pi > 0
+    rows = [state["f"][s].astype(np.float64) for s in range(state["f"].shape[0])] + [state["q"]]
+    out = np.zeros((n_batches, len(rows), 2))
+    for b, (c0, c1) in enumerate(batch_bounds(len(pi), n_batches)):
+        for i, r in enumerate(rows):
+            v = np.where(ok[c0:c1], r[c0:c1] / np.where(ok[c0:c1], pi[c0:c1], 1.0), 0.0)
+            out[b, i, 0] = np.sum(v)
+            out[b, i, 1] = np.sum(v * v)
+    return out
+
+
+def ratio_estimate(sums):
+    """I_s = sum f_s/pi / sum q/pi, over the last two axes [S + 1][2] (any leading batch axes)."""
+    sums = np.asarray(sums, dtype=np.float64)
+    return sums[..., :-1, 0] / sums[..., -1:, 0]

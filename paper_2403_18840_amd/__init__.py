@@ -7,6 +7,7 @@ fail loudly if the library is not built.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,6 +27,7 @@ ABI_SYMBOLS = [
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
+    "dmc_chains_create", "dmc_chains_step", "dmc_chains_read", "dmc_chains_reset", "dmc_chains_destroy",
 ]
 
 
@@ -104,6 +106,11 @@ def lib():
         "dmc_flow_log_density": (I32, [P, P, I64, I64, P, P]),
         "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
         "dmc_flow_destroy": (None, [P]),
+        "dmc_chains_create": (I32, [I64, I32, I32, I32, I32, ctypes.POINTER(P)]),
+        "dmc_chains_step": (I32, [P, P, I64, P, F64, U64, I32, P]),
+        "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
+        "dmc_chains_reset": (I32, [P, P]),
+        "dmc_chains_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -488,3 +495,101 @@ class Flow:
         if getattr(self, "h", None) and _lib is not None:
             _lib.dmc_flow_destroy(self.h)
             self.h = None
+
+
+class Chains:
+    """Independent-proposal Markov chains, one per sample lane (dmc_chains_*), their sums kept per chain
+    batch (batch b: chains [b n // n_batches, (b + 1) n // n_batches))."""
+
+    def __init__(self, n: int, n_groups: int, n_k: int, n_roots: int = 1, n_batches: int = 1):
+        self.h = P()
+        _check(lib().dmc_chains_create(n, n_batches, n_groups, n_k, n_roots, ctypes.byref(self.h)))
+        self.n, self.n_groups, self.n_k, self.n_roots, self.n_batches = n, n_groups, n_k, n_roots, n_batches
+        self.S = n_groups * n_roots * n_k * 2
+
+    def step(self, f_prop, jac_prop, alpha: float, seed: int, measure: bool = True, stream=None):
+        """f_prop: the f_out capture of eval_batch at the proposals (flat [G][R][K][2][ld]); jac_prop: 1/q."""
+        ld = f_prop.numel() // self.S
+        _check(lib().dmc_chains_step(self.h, _dptr(f_prop, "float32", "f_prop"), ld,
+                                     _dptr(jac_prop, "float32", "jac_prop"), alpha, seed, 1 if measure else 0,
+                                     _stream(stream)))
+
+    def read(self, stream=None):
+        """(sums [n_batches][S + 1][2] float64, states measured, proposals accepted)."""
+        import numpy as np
+        sums = np.zeros((self.n_batches, self.S + 1, 2), dtype=np.float64)
+        nm, na = I64(), I64()
+        _check(lib().dmc_chains_read(self.h, sums.ctypes.data_as(P), ctypes.byref(nm), ctypes.byref(na),
+                                     _stream(stream)))
+        return sums, nm.value, na.value
+
+    def reset(self, stream=None):
+        _check(lib().dmc_chains_reset(self.h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dmc_chains_destroy(self.h)
+            self.h = None
+
+
+def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, steps: int, thermal: int = 200,
+                   alpha: float = 0.5, seed: int = 1, n_batches: int = 32, flow: "Flow | None" = None,
+                   flow_alpha: float = 0.85, flow_uniform: float = 0.05):
+    """Markov-chain estimate (eq. nf_mcmc_estimator_qft_final_revised) with independent proposals from
+    `sampler` (its grid frozen) or, with `flow`, from the flow's mixture.  The first `thermal` steps
+    are discarded: chains start from the proposal density, and an independence sampler whose
+    proposal is far from |f| needs many steps to reach the target.  Every later step is measured;
+    the estimate is the ratio of the sums over all chains, and the error is the scatter of the
+    `n_batches` independent chain-batch estimates.
+    Returns (mean, stderr) complex [n_inst][n_roots][K], the acceptance rate of the measured steps,
+    and the plain importance-sampling estimate of the same proposals (mean, stderr)."""
+    import numpy as np
+    import torch
+    if steps < 1:
+        raise ValueError("steps must be at least 1")
+    if n_batches < 2:
+        raise ValueError("n_batches must be at least 2 for an error estimate")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ks = np.asarray(k_ext, dtype=np.float32)
+    K = len(ks)
+    G = _n_groups(inst)
+    R = graph.n_roots
+    D = dim(graph.order)
+    ch = Chains(n_chains, G, K, R, n_batches)
+    acc = Accumulator(G, K, R)
+    X = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+    J = torch.empty(n_chains, dtype=torch.float32, device=dev)
+    F = torch.empty(G * R * K * 2 * n_chains, dtype=torch.float32, device=dev)
+    for t in range(thermal + steps):
+        if flow is not None:
+            flow.sample(sampler, seed, t * n_chains, X, J, alpha=flow_alpha, uniform=flow_uniform)
+        else:
+            sampler.sample(seed, t * n_chains, X, J)
+        eval_batch(graph, inst, ks, X, J, acc, f_out=F)
+        accumulate(acc)
+        ch.step(F, J, alpha, seed + 0x5EED, measure=t >= thermal)
+        if t + 1 == thermal:
+            ch.reset()  # the acceptance rate counts the measured steps only
+    sums, _, accepted = ch.read()
+    S = G * R * K * 2
+    # per-batch and overall ratio estimates, per instance (r_s copies scale by (gamma / gamma_group)^n
+    # like eval)
+    lam_of = []
+    for p in inst:
+        if p[2] not in lam_of:
+            lam_of.append(p[2])
+    num = sums[:, :S, 0].reshape(n_batches, G, R, K, 2)
+    est = (num[..., 0] + 1j * num[..., 1]) / sums[:, S, 0].reshape(n_batches, 1, 1, 1)
+    tot = num.sum(axis=0)
+    mean_g = (tot[..., 0] + 1j * tot[..., 1]) / sums[:, S, 0].sum()
+    err_g = (est.real.std(axis=0, ddof=1) + 1j * est.imag.std(axis=0, ddof=1)) / math.sqrt(n_batches)
+    out_m = np.empty((len(inst), R, K), dtype=complex)
+    out_e = np.empty((len(inst), R, K), dtype=complex)
+    for i, p in enumerate(inst):
+        g = lam_of.index(p[2])
+        gam0 = next(q[3] for q in inst if q[2] == p[2])
+        fac = (p[3] / gam0) ** graph.order
+        out_m[i] = mean_g[g] * fac
+        out_e[i] = err_g[g] * fac
+    mi, ei, _, _ = acc.estimate(len(inst))
+    return out_m, out_e, accepted / (n_chains * steps), (mi, ei)

@@ -20,6 +20,7 @@
 #include "graph.hpp"
 #include "flow.hpp"
 #include "kernels.hpp"
+#include "mcmc.hpp"
 
 namespace {
 
@@ -1019,6 +1020,133 @@ void dmc_flow_destroy(dmc_flow* f) {
     (void)hipFree(f->sums);
     (void)hipFree(f->mix_buf);
     delete f;
+}
+
+
+// ------------------------------------------------------------------------------ Markov chains
+}  // extern "C"
+
+struct dmc_chains {
+    int64_t n = 0;
+    int n_batches = 0, n_groups = 0, n_k = 0, n_roots = 0, S = 0;
+    float* f_state = nullptr;     // device [S][n]
+    double* q_state = nullptr;    // device [n]
+    double* pi_state = nullptr;   // device [n]
+    double* partial = nullptr;    // device [nblk][n_batches][S + 1][2]
+    double* totals = nullptr;     // device [n_batches][S + 1][2]
+    unsigned int* zeros = nullptr;              // device [nblk] (the fold's count column, unused)
+    unsigned long long* nonfin = nullptr;       // device, the fold's count (unused)
+    unsigned long long* n_acc = nullptr;        // device: accepted proposals since the last reset
+    int nblk = 0, chunk = 0;      // accumulate blocks per batch, chains per block
+    int64_t steps = 0, measured = 0;
+    size_t totals_len() const { return (size_t)n_batches * (S + 1) * 2; }
+};
+
+extern "C" {
+
+dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
+                             dmc_chains** out) {
+    if (!out || n < 1 || n_groups < 1 || n_groups > DMC_MAX_GROUPS || n_k < 1 || n_k > DMC_MAX_K || n_roots < 1 ||
+        n_roots > 4)
+        return fail(DMC_E_INVALID, "chain count or observable shape out of range");
+    if (n_batches < 1 || n_batches > DMC_MAX_CHAIN_BATCHES || n_batches > n)
+        return fail(DMC_E_INVALID, "n_batches must be in [1, min(n, DMC_MAX_CHAIN_BATCHES)]");
+    auto c = std::make_unique<dmc_chains>();
+    c->n = n;
+    c->n_batches = n_batches;
+    c->n_groups = n_groups;
+    c->n_k = n_k;
+    c->n_roots = n_roots;
+    c->S = n_groups * n_roots * n_k * 2;
+    c->nblk = dmc::mcmc_acc_blocks((n + n_batches - 1) / n_batches, &c->chunk);
+    HIP_ALLOC(hipMalloc(&c->f_state, sizeof(float) * (size_t)c->S * n));
+    HIP_ALLOC(hipMalloc(&c->q_state, sizeof(double) * (size_t)n));
+    HIP_ALLOC(hipMalloc(&c->pi_state, sizeof(double) * (size_t)n));
+    HIP_ALLOC(hipMalloc(&c->partial, sizeof(double) * (size_t)c->nblk * c->totals_len()));
+    HIP_ALLOC(hipMalloc(&c->totals, sizeof(double) * c->totals_len()));
+    HIP_ALLOC(hipMalloc(&c->zeros, sizeof(unsigned int) * (size_t)c->nblk));
+    HIP_ALLOC(hipMalloc(&c->nonfin, sizeof(unsigned long long)));
+    HIP_ALLOC(hipMalloc(&c->n_acc, sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(c->totals, 0, sizeof(double) * c->totals_len()));
+    HIP_TRY(hipMemset(c->zeros, 0, sizeof(unsigned int) * (size_t)c->nblk));
+    HIP_TRY(hipMemset(c->nonfin, 0, sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(c->n_acc, 0, sizeof(unsigned long long)));
+    *out = c.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, double alpha,
+                           uint64_t seed, int32_t measure, void* stream) {
+    if (!c || !f_prop || !jac_prop) return fail(DMC_E_INVALID, "null argument");
+    if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
+    dmc::McmcArgs a;
+    a.n = c->n;
+    a.S = c->S;
+    a.R = c->n_roots;
+    a.K = c->n_k;
+    a.G = c->n_groups;
+    a.f_prop = f_prop;
+    a.ld_prop = ld;
+    a.jac_prop = jac_prop;
+    a.f_state = c->f_state;
+    a.q_state = c->q_state;
+    a.pi_state = c->pi_state;
+    a.alpha = alpha;
+    a.seed = seed;
+    a.step = (uint64_t)c->steps;
+    a.first = c->steps == 0;
+    a.n_acc = c->n_acc;
+    HIP_TRY(dmc::launch_mcmc_accept(a, cu_count(), S(stream)));
+    ++c->steps;
+    if (measure) {
+        dmc::McmcAccArgs m;
+        m.n = c->n;
+        m.S = c->S;
+        m.n_batches = c->n_batches;
+        m.f_state = c->f_state;
+        m.q_state = c->q_state;
+        m.pi_state = c->pi_state;
+        m.partial = c->partial;
+        m.chunk = c->chunk;
+        HIP_TRY(dmc::launch_mcmc_accumulate(m, c->nblk, S(stream)));
+        HIP_TRY(dmc::launch_fold(c->partial, c->nblk, (int)c->totals_len(), c->totals, c->zeros, c->nonfin,
+                                 S(stream)));
+        c->measured += c->n;
+    }
+    return DMC_OK;
+}
+
+dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream) {
+    if (!c || !sums) return fail(DMC_E_INVALID, "null argument");
+    unsigned long long acc = 0;
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipMemcpy(sums, c->totals, sizeof(double) * c->totals_len(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&acc, c->n_acc, sizeof(acc), hipMemcpyDeviceToHost));
+    if (n_measured) *n_measured = c->measured;
+    if (n_accepted) *n_accepted = (int64_t)acc;
+    return DMC_OK;
+}
+
+dmc_status dmc_chains_reset(dmc_chains* c, void* stream) {
+    if (!c) return fail(DMC_E_INVALID, "null argument");
+    HIP_TRY(hipMemsetAsync(c->totals, 0, sizeof(double) * c->totals_len(), S(stream)));
+    HIP_TRY(hipMemsetAsync(c->n_acc, 0, sizeof(unsigned long long), S(stream)));
+    c->measured = 0;
+    return DMC_OK;
+}
+
+void dmc_chains_destroy(dmc_chains* c) {
+    if (!c) return;
+    (void)hipFree(c->f_state);
+    (void)hipFree(c->q_state);
+    (void)hipFree(c->pi_state);
+    (void)hipFree(c->partial);
+    (void)hipFree(c->totals);
+    (void)hipFree(c->zeros);
+    (void)hipFree(c->nonfin);
+    (void)hipFree(c->n_acc);
+    delete c;
 }
 
 }  // extern "C"

@@ -115,3 +115,17 @@ def flow_params(masks: np.ndarray, seed: int, last_scale: float = 0.0) -> np.nda
         b3 = np.zeros(32)
         out.append(np.concatenate([W1t.ravel(), W2t.ravel(), b2, W3t.ravel(), b3]))
     return np.concatenate(out).astype(np.float32)
+
+
+def chain_proposals(S: int, n: int, seed: int, bad: bool = True):
+    """Integrand values f[S][n] float32 (signed, log-uniform magnitudes over six decades) and proposal
+    Jacobians jac[n] float32 (log-uniform in [1e-3, 1e3]) for the Markov-chain step; with `bad`, a few
+    chains carry a NaN value, an infinite value or a zero Jacobian."""
+    g = rng(seed)
+    f = (np.sign(g.random((S, n)) - 0.5) * 10.0 ** (6 * g.random((S, n)) - 6)).astype(np.float32)
+    jac = (10.0 ** (6 * g.random(n) - 3)).astype(np.float32)
+    if bad and n >= 8:
+        f[0, 3] = np.nan
+        f[S - 1, 5] = np.inf
+        jac[6] = 0.0
+    return f, jac

@@ -1,0 +1,77 @@
+"""GPU Markov chains (independent proposals) against the oracle chain and the importance-sampling limit."""
+import numpy as np
+import pytest
+
+import paper_2403_18840_amd as dmc
+import synth
+from oracle import mcmc
+from oracle import physics as ph
+
+from gpu_helpers import BETA, LAM, MU, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("alpha,n,batches",
+                         [(0.3, 1000, 3), (0.9, 2049, 5), (0.0, 777, 1), (0.5, 9001, 2), (0.7, 20000, 13)])
+def test_chain_steps_match_oracle(alpha, n, batches):
+    torch, dev = torch_dev()
+    G, R, K = 2, 2, 3
+    S = G * R * K * 2
+    root0 = [s for g in range(G) for s in range(g * R * K * 2, (g * R + 1) * K * 2)]
+    seed = 0xC4A1
+    ch = dmc.Chains(n, G, K, R, batches)
+    state = None
+    ref = np.zeros((batches, S + 1, 2))
+    taken = 0
+    for t in range(4):
+        f, jac = synth.chain_proposals(S, n, seed=40 + t, bad=(t < 2))
+        ch.step(torch.from_numpy(f.ravel()).to(dev), torch.from_numpy(jac).to(dev), alpha, seed, measure=True)
+        state, take = mcmc.step(state, f, jac, alpha, seed, t, root0)
+        taken += int(take.sum())
+        ref += mcmc.measure(state, batches)
+        sums, nm, na = ch.read()
+        assert na == taken, f"step {t}: accepted {na} vs oracle {taken}"
+        assert nm == n * (t + 1)
+        # FP64 sums in another order: equal to a few ulps of the sum of magnitudes; a slot that holds
+        # an infinite value (a taken proposal may carry one outside root 0) is infinite on both sides
+        fin = np.isfinite(ref)
+        scale = np.abs(np.where(fin, ref, 0.0)).sum(axis=-1)[..., None]
+        with np.errstate(invalid="ignore"):
+            close = np.abs(sums - ref) <= 1e-12 * scale + 1e-300
+        assert np.all(np.where(fin, close, sums == ref)), f"step {t}"
+    assert 0 < taken < 4 * n or alpha == 1.0
+
+
+def test_alpha_one_equals_importance_sampling():
+    torch, dev = torch_dev()
+    n = 2
+    g = dmc.Graph(n)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    s.set_grid(synth.vegas_grid(dmc.dim(n), 50, seed=3).astype(np.float64))
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    ks = synth.k_grid(5)
+    m, e, rate, (mi, ei) = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=4, thermal=0, alpha=1.0, seed=9,
+                                              n_batches=4)
+    assert rate == 1.0
+    # same proposals, every one taken: sum (f J) / n in FP64 from FP32 f and J on both paths
+    assert np.allclose(m, mi, rtol=2e-6, atol=1e-7 * np.abs(mi).max())
+
+
+def test_chain_estimate_agrees_with_importance_sampling():
+    torch, dev = torch_dev()
+    n = 2
+    g = dmc.Graph(n)
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    ks = synth.k_grid(6)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    dmc.adapt_grid(g, inst, ks, s, 1 << 20, 5, seed=2)
+    # chains start from the proposal density; with an adapted grid the chain average settles within
+    # a few hundred steps (shorter runs read |Sigma| low, the bias of an unthermalised independence
+    # sampler), so 400 steps are discarded.  The error is the scatter of 32 independent chain batches.
+    m, e, rate, (mi, ei) = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=800, thermal=400, alpha=0.3, seed=7,
+                                              n_batches=32)
+    assert 0.05 < rate < 1.0
+    z = (m[0, 0].real - mi[0, 0].real) / np.hypot(e[0, 0].real, ei[0, 0].real)
+    print("acceptance", rate, "z", z)
+    assert np.all(np.abs(z) < 4.5), z

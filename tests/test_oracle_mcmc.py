@@ -1,0 +1,90 @@
+"""Pins of the oracle Markov-chain estimator: the importance-sampling limit alpha = 1, a closed-form
+sign-changing integral, and the stationary distribution of the chain."""
+import numpy as np
+
+from oracle import mcmc
+
+
+def _toy(alpha, n=4096, steps=60, thermal=10, seed=5, batches=16):
+    # integral over (0, 1) of f(x) = cos(6 x) (= sin(6) / 6, sign-changing), uniform proposals q = 1;
+    # per chain batch, the ratio estimate over all measured steps (batches are independent)
+    rng = np.random.default_rng(seed)
+    state = None
+    cur = np.zeros((batches, 2, 2))
+    xs = np.zeros(n)
+    for t in range(thermal + steps):
+        xp = rng.uniform(size=n)
+        f = np.cos(6 * xp).astype(np.float32)[None, :]
+        state, take = mcmc.step(state, f, np.ones(n, dtype=np.float32), alpha, seed, t, [0])
+        xs = np.where(take, xp, xs)
+        if t >= thermal:
+            cur += mcmc.measure(state, batches)
+    sizes = np.array([c1 - c0 for c0, c1 in mcmc.batch_bounds(n, batches)])
+    return mcmc.ratio_estimate(cur)[:, 0], xs, cur[:, 0, 0] / (sizes * steps)
+
+
+def test_alpha_one_is_importance_sampling():
+    # pi = q: every proposal is taken and the estimate is the plain mean of f / q
+    rng = np.random.default_rng(1)
+    n = 1000
+    f = rng.normal(size=(4, n)).astype(np.float32)
+    jac = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    state, take = mcmc.step(None, f, jac, 1.0, 3, 0, [0, 1])
+    state, take = mcmc.step(state, f[::-1].copy(), jac, 1.0, 3, 1, [0, 1])
+    assert take.all()
+    est = mcmc.ratio_estimate(mcmc.measure(state)[0])
+    ref = (f[::-1].astype(np.float64) * jac.astype(np.float64)).mean(axis=1)
+    assert np.allclose(est, ref, rtol=1e-12)
+
+
+def test_sign_changing_integral_and_target():
+    exact = np.sin(6.0) / 6.0
+    for alpha in [0.2, 0.6]:
+        blocks, xs, _ = _toy(alpha)
+        m, e = blocks.mean(), blocks.std(ddof=1) / np.sqrt(len(blocks))
+        assert abs(m - exact) < 5 * e, (alpha, m, e, exact)
+        # the chain samples pi = alpha + (1 - alpha) |cos 6x|, normalised over (0, 1)
+        edges = np.linspace(0, 1, 21)
+        h, _ = np.histogram(xs, edges)
+        xm = np.linspace(0, 1, 20001)
+        dens = alpha + (1 - alpha) * np.abs(np.cos(6 * xm))
+        cdf = np.concatenate([[0], np.cumsum((dens[1:] + dens[:-1]) / 2 * np.diff(xm))])
+        cdf /= cdf[-1]
+        expect = np.diff(np.interp(edges, xm, cdf)) * len(xs)
+        chi2 = np.sum((h - expect) ** 2 / expect)
+        assert chi2 < 60, (alpha, chi2)   # 19 degrees of freedom (chains are independent)
+    # the plain mean of f / pi over the chain states is I / Z_pi, not the integral: the ratio with
+    # the mean of q / pi is what removes the unknown normalisation of pi
+    blocks, _, naive = _toy(0.2)
+    z_pi = 0.2 + 0.8 * np.mean(np.abs(np.cos(6 * np.linspace(0, 1, 200001))))
+    assert abs(naive.mean() - exact / z_pi) < 5 * naive.std(ddof=1) / np.sqrt(len(naive))
+    assert abs(naive.mean() - exact) > 10 * naive.std(ddof=1) / np.sqrt(len(naive))
+
+
+def test_batches_partition_the_chains():
+    rng = np.random.default_rng(4)
+    n = 1001
+    f = rng.normal(size=(3, n)).astype(np.float32)
+    jac = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    state, _ = mcmc.step(None, f, jac, 0.4, 3, 0, [0, 1])
+    bounds = mcmc.batch_bounds(n, 7)
+    assert bounds[0][0] == 0 and bounds[-1][1] == n
+    assert all(a[1] == b[0] for a, b in zip(bounds, bounds[1:]))
+    assert {c1 - c0 for c0, c1 in bounds} <= {n // 7, n // 7 + 1}
+    per = mcmc.measure(state, 7)
+    whole = mcmc.measure(state)[0]
+    assert np.allclose(per.sum(axis=0), whole, rtol=1e-12)
+    c0, c1 = bounds[3]
+    v = f[1, c0:c1].astype(np.float64) / state["pi"][c0:c1]
+    assert np.isclose(per[3, 1, 0], v.sum(), rtol=1e-12) and np.isclose(per[3, 1, 1], (v * v).sum(), rtol=1e-12)
+
+
+def test_invalid_proposals_are_never_taken():
+    f = np.array([[1.0, 2.0, np.nan, 1.0]], dtype=np.float32)
+    jac = np.array([1.0, 0.0, 1.0, 1.0], dtype=np.float32)
+    state, take = mcmc.step(None, f, jac, 0.5, 1, 0, [0])
+    assert list(take) == [True, False, False, True]
+    assert list(state["pi"] > 0) == [True, False, False, True]
+    # a chain without a valid state takes its next valid proposal
+    state, take = mcmc.step(state, np.ones((1, 4), dtype=np.float32), np.ones(4, dtype=np.float32), 0.5, 1, 1, [0])
+    assert take[1] and take[2]
