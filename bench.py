@@ -16,7 +16,9 @@ order 4 (D = 15): the error of Re Sigma(k_F, i omega_0) (scatter of 64 independe
 wall time for the same number of samples from the adapted grid and from the trained 8-layer
 affine-coupling flow (defensive mixture 0.85 flow + 0.10 grid + 0.05 uniform), the efficiency
 (sigma_V^2 T_V) / (sigma_F^2 T_F) with and without adaptation and training time, and the flow
-sampler's matrix-core roofline.
+sampler's matrix-core roofline.  Then `mcmc_vs_vegas` compares, at order 2 by default, plain VEGAS
+importance sampling with VEGAS-MCMC and NF-MCMC (independent proposals from the frozen grid or the
+trained flow, target alpha q + (1 - alpha)|f|) over a sweep of alpha, at equal evaluation counts.
 """
 from __future__ import annotations
 
@@ -180,6 +182,104 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     }
 
 
+def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, thermal=2000, n_batches=64,
+                  alphas=(0.05, 0.2, 0.5, 0.8), seed=0x2403188400000005, flow=True, ref_factor=16):
+    """Markov-chain estimators against plain VEGAS importance sampling at one order (the comparison
+    of Sec. IV): Re Sigma(k_F, i omega_0) alone (K = 1, so p = |Re f| + |Im f| at k_F).  VEGAS IS:
+    ref_factor x n_batches batches of n_chains * steps / n_batches samples from the adapted grid; the
+    scatter of the batch means gives sigma at the chains' evaluation count (sigma_b / sqrt(n_batches))
+    and the reference for the z of each chain estimate (sigma_b / sqrt(ref_factor n_batches)).  VEGAS-MCMC (the frozen grid as independent proposal) and, with `flow`,
+    NF-MCMC (the trained flow's defensive mixture as proposal), for each mixing parameter alpha:
+    n_chains chains, `thermal` steps discarded, `steps` measured, sigma from n_batches independent
+    chain batches.  Equal evaluation counts: the efficiency relative to VEGAS is
+    sigma_VEGAS^2 / sigma^2 per evaluation and sigma_VEGAS^2 T_VEGAS / (sigma^2 T) per wall second
+    (the thermalisation steps count in T)."""
+    import numpy as np
+    import torch
+
+    import paper_2403_18840_amd as dmc
+    import synth
+
+    dev = torch.device("cuda:0")
+    ks = np.array([1.0], dtype=np.float32)
+    inst = [(beta, mu, lam, gamma)]
+    D = dmc.dim(order)
+    g = dmc.Graph(order)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, order, n_bins=50, beta=beta, qmax=6.0)
+    n_eval = n_chains * steps
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def log(msg):
+        print(f"[mcmc order {order}] {msg}", file=sys.stderr, flush=True)
+
+    _, t_adapt = timed(lambda: dmc.adapt_grid(g, inst, ks, s, 1 << 22, 6, seed=seed))
+    nb = n_eval // n_batches
+    X = torch.empty((D, nb), dtype=torch.float32, device=dev)
+    J = torch.empty(nb, dtype=torch.float32, device=dev)
+
+    def vegas_is():
+        means = []
+        for b in range(n_batches * ref_factor):
+            acc = dmc.Accumulator(1, 1, 1)
+            s.sample(seed + 1, b * nb, X, J)
+            dmc.eval_batch(g, inst, ks, X, J, acc)
+            dmc.accumulate(acc)
+            m, _, _, _ = acc.estimate(1)
+            means.append(m[0, 0, 0].real)
+        means = np.array(means)
+        sb = float(means.std(ddof=1))
+        return float(means.mean()), sb / math.sqrt(n_batches), sb / math.sqrt(n_batches * ref_factor)
+
+    (v_re, v_sig, v_ref), t_ref = timed(vegas_is)
+    t_v = t_ref / ref_factor
+    log(f"VEGAS IS {v_re:.6g} +- {v_ref:.3g} ({ref_factor} x {n_eval} evaluations, {t_ref:.2f} s); "
+        f"sigma at {n_eval}: {v_sig:.3g}")
+    out = {"order": order, "k": 1.0, "evaluations": n_eval, "n_chains": n_chains, "steps": steps,
+           "thermal": thermal, "n_batches": n_batches, "adapt_seconds": t_adapt,
+           "vegas": {"re": v_re, "sigma_ref": v_ref, "ref_factor": ref_factor, "sigma": v_sig, "seconds": t_v}}
+
+    def chains(label, fl):
+        rows = []
+        for a in alphas:
+            r, t = timed(lambda: dmc.mcmc_integrate(g, inst, ks, s, n_chains, steps, thermal=thermal, alpha=a,
+                                                    seed=seed + 7, n_batches=n_batches, flow=fl))
+            re, sig = float(r.mean[0, 0, 0].real), float(r.err[0, 0, 0].real)
+            zh = float(r.halves[2][0, 0, 0].real)
+            rows.append({"alpha": a, "re": re, "sigma": sig, "acceptance": r.acceptance, "seconds": t,
+                         "efficiency_per_eval": (v_sig / sig) ** 2,
+                         "efficiency_per_second": (v_sig ** 2 * t_v) / (sig ** 2 * t),
+                         "z_vs_vegas": (re - v_re) / math.hypot(sig, v_ref), "z_halves": zh,
+                         "proposal_is": {"re": float(r.is_mean[0, 0, 0].real), "sigma": float(r.is_err[0, 0, 0].real)}})
+            log(f"{label} alpha {a}: {re:.6g} +- {sig:.3g} (z vs VEGAS {rows[-1]['z_vs_vegas']:+.2f}, halves {zh:+.2f}), "
+                f"acceptance {r.acceptance:.3f}, efficiency/eval {(v_sig / sig) ** 2:.2f} ({t:.2f} s)")
+        # best alpha among the runs that agree with VEGAS and show no trend between their halves
+        ok = [r for r in rows if abs(r["z_vs_vegas"]) < 3 and abs(r["z_halves"]) < 3]
+        best = max(ok, key=lambda r: r["efficiency_per_eval"]) if ok else None
+        return {"alphas": rows, "best_alpha": best and best["alpha"],
+                "best_efficiency_per_eval": best and best["efficiency_per_eval"],
+                "best_efficiency_per_second": best and best["efficiency_per_second"]}
+
+    out["vegas_mcmc"] = chains("VEGAS-MCMC", None)
+    if flow:
+        masks = synth.flow_masks(D, 8, 5)
+        f = dmc.Flow(D, masks)
+        f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+        epochs, tsteps, mb = 4, 64, 1 << 17
+        losses, t_train = timed(lambda: dmc.train_flow(g, inst, ks, s, f, epochs=epochs, steps=tsteps, minibatch=mb,
+                                                        lr=1e-3, seed=seed + 2))
+        log(f"flow trained ({t_train:.1f} s), losses {[round(float(x), 3) for x in losses]}")
+        out["nf_mcmc"] = chains("NF-MCMC", f)
+        out["nf_mcmc"]["training"] = {"samples": epochs * tsteps * mb, "seconds": t_train,
+                                      "loss": [float(x) for x in losses], "mixture": {"flow": 0.85, "uniform": 0.05}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +294,12 @@ def main():
                     help="order of the learned-proposal comparison (0 skips it)")
     ap.add_argument("--flow-batches", type=int, default=64)
     ap.add_argument("--flow-log2-samples", type=int, default=22)
+    ap.add_argument("--mcmc-orders", default="2",
+                    help="orders of the Markov-chain vs VEGAS comparison, comma-separated (empty skips it)")
+    ap.add_argument("--mcmc-log2-chains", type=int, default=16)
+    ap.add_argument("--mcmc-steps", type=int, default=1024)
+    ap.add_argument("--mcmc-thermal", type=int, default=2000)
+    ap.add_argument("--mcmc-no-flow", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -306,6 +412,11 @@ def main():
     if args.flow_order:
         out["flow_vs_vegas"] = flow_vs_vegas(args.flow_order, K, 1 << args.flow_log2_samples, args.flow_batches, beta, mu,
                                              lam, inst[0][3])
+    if args.mcmc_orders:
+        out["mcmc_vs_vegas"] = [mcmc_vs_vegas(int(n), beta, mu, lam, inst[0][3], n_chains=1 << args.mcmc_log2_chains,
+                                              steps=args.mcmc_steps, thermal=args.mcmc_thermal,
+                                              flow=not args.mcmc_no_flow)
+                                for n in args.mcmc_orders.split(",")]
     print(json.dumps(out), flush=True)
 
 

@@ -228,9 +228,13 @@ void dmc_flow_destroy(dmc_flow* f);
 typedef struct dmc_chains dmc_chains;
 dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
                              dmc_chains** out);
-/* One step of every chain; measure != 0 accumulates the chains' states after the step. */
-dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, double alpha,
-                           uint64_t seed, int32_t measure, void* stream);
+/* One step of every chain: chain c takes proposal (c + offset) mod n (columns of f_prop, entries of
+ * jac_prop), 0 <= offset < n.  Draw offset uniformly and afresh every step: a sampler that lays its
+ * proposals out by index (dmc_flow_sample puts each mixture component's share in one index range)
+ * then still hands every chain a draw from its full density q, which the acceptance test assumes.
+ * measure != 0 accumulates the chains' states after the step. */
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, int64_t offset,
+                           double alpha, uint64_t seed, int32_t measure, void* stream);
 /* sums: host double[n_batches][S + 1][2], S = n_groups n_roots n_k 2 slots in the f_out order, per batch:
  * [b][s][0] = sum f_s/pi, [b][s][1] = sum (f_s/pi)^2; row S: sum q/pi and its squares.  n_measured: chain
  * states added (all batches);

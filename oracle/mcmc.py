@@ -33,12 +33,16 @@ def uniforms(seed: int, step: int, n: int):
     return ((w >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
 
 
-def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots):
+def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots, offset=0):
     """One Metropolis-Hastings step of every chain.  state: dict f [S][n] (float32 values), q, pi
-    [n] float64, or None before the first step.  f_prop [S][n] float32, jac_prop [n] float32.
+    [n] float64, or None before the first step.  f_prop [S][n] float32, jac_prop [n] float32; chain c
+    proposes column (c + offset) mod n (a uniform offset per step makes every chain's proposal a
+    draw from the whole proposal density when the sampler orders its draws by mixture component).
     Returns (new state, taken [n] bool)."""
-    f_prop = np.asarray(f_prop, dtype=np.float32)
-    n = f_prop.shape[1]
+    n = np.asarray(f_prop).shape[1]
+    cols = (np.arange(n) + offset) % n
+    f_prop = np.asarray(f_prop, dtype=np.float32)[:, cols]
+    jac_prop = np.asarray(jac_prop)[cols]
     p = np.zeros(n)
     for s in root0_slots:
         p = p + np.abs(f_prop[s].astype(np.float64))

@@ -7,6 +7,7 @@ fail loudly if the library is not built.
 from __future__ import annotations
 
 import ctypes
+from typing import NamedTuple
 import math
 import os
 
@@ -107,7 +108,7 @@ def lib():
         "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
         "dmc_flow_destroy": (None, [P]),
         "dmc_chains_create": (I32, [I64, I32, I32, I32, I32, ctypes.POINTER(P)]),
-        "dmc_chains_step": (I32, [P, P, I64, P, F64, U64, I32, P]),
+        "dmc_chains_step": (I32, [P, P, I64, P, I64, F64, U64, I32, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
         "dmc_chains_destroy": (None, [P]),
@@ -507,12 +508,17 @@ class Chains:
         self.n, self.n_groups, self.n_k, self.n_roots, self.n_batches = n, n_groups, n_k, n_roots, n_batches
         self.S = n_groups * n_roots * n_k * 2
 
-    def step(self, f_prop, jac_prop, alpha: float, seed: int, measure: bool = True, stream=None):
-        """f_prop: the f_out capture of eval_batch at the proposals (flat [G][R][K][2][ld]); jac_prop: 1/q."""
+    def step(self, f_prop, jac_prop, alpha: float, seed: int, offset: int = 0, measure: bool = True, stream=None):
+        """f_prop: the f_out capture of eval_batch at the proposals (flat [G][R][K][2][ld]); jac_prop: 1/q;
+        chain c takes proposal (c + offset) mod n."""
         ld = f_prop.numel() // self.S
+        if f_prop.numel() != ld * self.S or ld < self.n:
+            raise ValueError(f"f_prop must hold [{self.S}][ld >= {self.n}] values, got {f_prop.numel()}")
+        if jac_prop.numel() < self.n:
+            raise ValueError(f"jac_prop must hold at least {self.n} values")
         _check(lib().dmc_chains_step(self.h, _dptr(f_prop, "float32", "f_prop"), ld,
-                                     _dptr(jac_prop, "float32", "jac_prop"), alpha, seed, 1 if measure else 0,
-                                     _stream(stream)))
+                                     _dptr(jac_prop, "float32", "jac_prop"), offset, alpha, seed,
+                                     1 if measure else 0, _stream(stream)))
 
     def read(self, stream=None):
         """(sums [n_batches][S + 1][2] float64, states measured, proposals accepted)."""
@@ -532,21 +538,34 @@ class Chains:
             self.h = None
 
 
+class McmcResult(NamedTuple):
+    """mean, err: complex [n_inst][n_roots][K] (ratio estimate over all measured steps and chains; error
+    from the scatter of the independent chain batches).  acceptance: over the measured steps.
+    is_mean, is_err: plain importance sampling over every proposal (thermalisation included).
+    halves: ((mean, err) of the first half of the measured steps, the same of the second half, z of
+    their difference per entry): chains still relaxing from the proposal density show as a trend
+    between the halves, which the batch error does not see."""
+    mean: object
+    err: object
+    acceptance: float
+    is_mean: object
+    is_err: object
+    halves: tuple
+
+
 def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, steps: int, thermal: int = 200,
                    alpha: float = 0.5, seed: int = 1, n_batches: int = 32, flow: "Flow | None" = None,
-                   flow_alpha: float = 0.85, flow_uniform: float = 0.05):
+                   flow_alpha: float = 0.85, flow_uniform: float = 0.05) -> McmcResult:
     """Markov-chain estimate (eq. nf_mcmc_estimator_qft_final_revised) with independent proposals from
-    `sampler` (its grid frozen) or, with `flow`, from the flow's mixture.  The first `thermal` steps
-    are discarded: chains start from the proposal density, and an independence sampler whose
-    proposal is far from |f| needs many steps to reach the target.  Every later step is measured;
-    the estimate is the ratio of the sums over all chains, and the error is the scatter of the
-    `n_batches` independent chain-batch estimates.
-    Returns (mean, stderr) complex [n_inst][n_roots][K], the acceptance rate of the measured steps,
-    and the plain importance-sampling estimate of the same proposals (mean, stderr)."""
+    `sampler` (its grid frozen) or, with `flow`, from the flow's mixture.  Every step draws n_chains
+    proposals and hands chain c proposal (c + r) mod n_chains with r uniform and fresh (the
+    mixture orders its draws by component).  The first `thermal` steps are discarded: chains start
+    from the proposal density, and an independence sampler whose proposal is far from |f| needs many
+    steps to reach the target.  Every later step is measured."""
     import numpy as np
     import torch
-    if steps < 1:
-        raise ValueError("steps must be at least 1")
+    if steps < 2:
+        raise ValueError("steps must be at least 2")
     if n_batches < 2:
         raise ValueError("n_batches must be at least 2 for an error estimate")
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -560,6 +579,8 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
     X = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
     J = torch.empty(n_chains, dtype=torch.float32, device=dev)
     F = torch.empty(G * R * K * 2 * n_chains, dtype=torch.float32, device=dev)
+    offsets = np.random.default_rng([seed, 0x0FF5E7]).integers(0, n_chains, size=thermal + steps)
+    half = None
     for t in range(thermal + steps):
         if flow is not None:
             flow.sample(sampler, seed, t * n_chains, X, J, alpha=flow_alpha, uniform=flow_uniform)
@@ -567,29 +588,42 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
             sampler.sample(seed, t * n_chains, X, J)
         eval_batch(graph, inst, ks, X, J, acc, f_out=F)
         accumulate(acc)
-        ch.step(F, J, alpha, seed + 0x5EED, measure=t >= thermal)
+        ch.step(F, J, alpha, seed + 0x5EED, offset=int(offsets[t]), measure=t >= thermal)
         if t + 1 == thermal:
             ch.reset()  # the acceptance rate counts the measured steps only
+        if t + 1 == thermal + steps // 2:
+            half = ch.read()[0]
     sums, _, accepted = ch.read()
     S = G * R * K * 2
-    # per-batch and overall ratio estimates, per instance (r_s copies scale by (gamma / gamma_group)^n
-    # like eval)
     lam_of = []
     for p in inst:
         if p[2] not in lam_of:
             lam_of.append(p[2])
-    num = sums[:, :S, 0].reshape(n_batches, G, R, K, 2)
-    est = (num[..., 0] + 1j * num[..., 1]) / sums[:, S, 0].reshape(n_batches, 1, 1, 1)
-    tot = num.sum(axis=0)
-    mean_g = (tot[..., 0] + 1j * tot[..., 1]) / sums[:, S, 0].sum()
-    err_g = (est.real.std(axis=0, ddof=1) + 1j * est.imag.std(axis=0, ddof=1)) / math.sqrt(n_batches)
-    out_m = np.empty((len(inst), R, K), dtype=complex)
-    out_e = np.empty((len(inst), R, K), dtype=complex)
-    for i, p in enumerate(inst):
-        g = lam_of.index(p[2])
-        gam0 = next(q[3] for q in inst if q[2] == p[2])
-        fac = (p[3] / gam0) ** graph.order
-        out_m[i] = mean_g[g] * fac
-        out_e[i] = err_g[g] * fac
+
+    def ratio(sm):
+        # per-batch and overall ratio estimates, per instance (r_s copies scale by (gamma / gamma_group)^n
+        # like eval)
+        num = sm[:, :S, 0].reshape(n_batches, G, R, K, 2)
+        est = (num[..., 0] + 1j * num[..., 1]) / sm[:, S, 0].reshape(n_batches, 1, 1, 1)
+        tot = num.sum(axis=0)
+        mean_g = (tot[..., 0] + 1j * tot[..., 1]) / sm[:, S, 0].sum()
+        err_g = (est.real.std(axis=0, ddof=1) + 1j * est.imag.std(axis=0, ddof=1)) / math.sqrt(n_batches)
+        out_m = np.empty((len(inst), R, K), dtype=complex)
+        out_e = np.empty((len(inst), R, K), dtype=complex)
+        for i, p in enumerate(inst):
+            g = lam_of.index(p[2])
+            gam0 = next(q[3] for q in inst if q[2] == p[2])
+            fac = (p[3] / gam0) ** graph.order
+            out_m[i] = mean_g[g] * fac
+            out_e[i] = err_g[g] * fac
+        return out_m, out_e
+
+    m, e = ratio(sums)
+    m1, e1 = ratio(half)
+    m2, e2 = ratio(sums - half)
+    z = np.empty_like(m)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        z.real = (m1.real - m2.real) / np.hypot(e1.real, e2.real)
+        z.imag = (m1.imag - m2.imag) / np.hypot(e1.imag, e2.imag)
     mi, ei, _, _ = acc.estimate(len(inst))
-    return out_m, out_e, accepted / (n_chains * steps), (mi, ei)
+    return McmcResult(m, e, accepted / (n_chains * steps), mi, ei, ((m1, e1), (m2, e2), z))

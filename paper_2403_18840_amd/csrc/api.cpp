@@ -1075,10 +1075,11 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
     return DMC_OK;
 }
 
-dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, double alpha,
-                           uint64_t seed, int32_t measure, void* stream) {
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, int64_t offset,
+                           double alpha, uint64_t seed, int32_t measure, void* stream) {
     if (!c || !f_prop || !jac_prop) return fail(DMC_E_INVALID, "null argument");
     if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (offset < 0 || offset >= c->n) return fail(DMC_E_INVALID, "offset must be in [0, n)");
     if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
     dmc::McmcArgs a;
     a.n = c->n;
@@ -1089,6 +1090,7 @@ dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const
     a.f_prop = f_prop;
     a.ld_prop = ld;
     a.jac_prop = jac_prop;
+    a.offset = offset;
     a.f_state = c->f_state;
     a.q_state = c->q_state;
     a.pi_state = c->pi_state;

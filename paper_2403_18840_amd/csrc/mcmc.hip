@@ -2,6 +2,9 @@
 // and eq. nf_mcmc_estimator_qft_final_revised), one chain per sample lane.
 //
 // The proposal density q is the sampler's (VEGAS or flow mixture): jac = 1/q at every proposal.
+// A sampler may lay its proposals out by index (the defensive mixture puts each component's share
+// in one index range), so chain c takes proposal (c + offset) mod n with a fresh uniform offset per
+// step: each chain's proposal is then a draw from q itself, whatever the layout.
 // The target is pi = alpha q + (1 - alpha) p with p = |f| summed over the root-0 observables
 // (every lambda group, external momentum, Re and Im).  A chain's state needs no coordinates (the
 // next proposal does not depend on it): only the integrand values f, q and pi at its point.
@@ -40,12 +43,13 @@ __device__ __forceinline__ void philox_round10(uint32_t c[4], uint32_t k0, uint3
 __global__ void __launch_bounds__(256) dmc_mcmc_accept_kernel(McmcArgs a) {
     unsigned long long acc = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.n; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = c < a.n - a.offset ? c + a.offset : c + a.offset - a.n;
         // p(x') = sum of |f| over the root-0 slots: slot ((g R + 0) K + k) 2 + comp
         double p = 0.0;
         for (int g = 0; g < a.G; ++g)
             for (int s = g * a.R * a.K * 2; s < (g * a.R + 1) * a.K * 2; ++s)
-                p += fabs((double)a.f_prop[(int64_t)s * a.ld_prop + c]);
-        const double jp = (double)a.jac_prop[c];
+                p += fabs((double)a.f_prop[(int64_t)s * a.ld_prop + col]);
+        const double jp = (double)a.jac_prop[col];
         const double qp = 1.0 / jp;
         const double pip = a.alpha * qp + (1.0 - a.alpha) * p;
         // a proposal (or state) whose density or target is not finite and positive is invalid: never
@@ -67,7 +71,7 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accept_kernel(McmcArgs a) {
             a.pi_state[c] = 0.0;  // no valid state yet
         }
         if (take) {
-            for (int s = 0; s < a.S; ++s) a.f_state[(int64_t)s * a.n + c] = a.f_prop[(int64_t)s * a.ld_prop + c];
+            for (int s = 0; s < a.S; ++s) a.f_state[(int64_t)s * a.n + c] = a.f_prop[(int64_t)s * a.ld_prop + col];
             a.q_state[c] = qp;
             a.pi_state[c] = pip;
             ++acc;

@@ -15,6 +15,7 @@ struct McmcArgs {
     const float* f_prop;      // [S][ld_prop]: integrand at the proposals
     int64_t ld_prop;
     const float* jac_prop;    // [n]: 1 / q at the proposals
+    int64_t offset;           // chain c takes proposal (c + offset) mod n, 0 <= offset < n
     float* f_state;           // [S][n]
     double* q_state;          // [n]
     double* pi_state;         // [n]

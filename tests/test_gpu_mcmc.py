@@ -26,8 +26,10 @@ def test_chain_steps_match_oracle(alpha, n, batches):
     taken = 0
     for t in range(4):
         f, jac = synth.chain_proposals(S, n, seed=40 + t, bad=(t < 2))
-        ch.step(torch.from_numpy(f.ravel()).to(dev), torch.from_numpy(jac).to(dev), alpha, seed, measure=True)
-        state, take = mcmc.step(state, f, jac, alpha, seed, t, root0)
+        off = (t * 7919 + 13) % n
+        ch.step(torch.from_numpy(f.ravel()).to(dev), torch.from_numpy(jac).to(dev), alpha, seed, offset=off,
+                measure=True)
+        state, take = mcmc.step(state, f, jac, alpha, seed, t, root0, offset=off)
         taken += int(take.sum())
         ref += mcmc.measure(state, batches)
         sums, nm, na = ch.read()
@@ -51,11 +53,11 @@ def test_alpha_one_equals_importance_sampling():
     s.set_grid(synth.vegas_grid(dmc.dim(n), 50, seed=3).astype(np.float64))
     inst = [(BETA, MU, LAM, ph.coupling(1.0))]
     ks = synth.k_grid(5)
-    m, e, rate, (mi, ei) = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=4, thermal=0, alpha=1.0, seed=9,
-                                              n_batches=4)
-    assert rate == 1.0
-    # same proposals, every one taken: sum (f J) / n in FP64 from FP32 f and J on both paths
-    assert np.allclose(m, mi, rtol=2e-6, atol=1e-7 * np.abs(mi).max())
+    r = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=4, thermal=0, alpha=1.0, seed=9, n_batches=4)
+    assert r.acceptance == 1.0
+    # same proposals (rotated among the chains), every one taken: sum (f J) / n in FP64 from FP32 f and J
+    # on both paths
+    assert np.allclose(r.mean, r.is_mean, rtol=2e-6, atol=1e-7 * np.abs(r.is_mean).max())
 
 
 def test_chain_estimate_agrees_with_importance_sampling():
@@ -69,9 +71,32 @@ def test_chain_estimate_agrees_with_importance_sampling():
     # chains start from the proposal density; with an adapted grid the chain average settles within
     # a few hundred steps (shorter runs read |Sigma| low, the bias of an unthermalised independence
     # sampler), so 400 steps are discarded.  The error is the scatter of 32 independent chain batches.
-    m, e, rate, (mi, ei) = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=800, thermal=400, alpha=0.3, seed=7,
-                                              n_batches=32)
-    assert 0.05 < rate < 1.0
-    z = (m[0, 0].real - mi[0, 0].real) / np.hypot(e[0, 0].real, ei[0, 0].real)
-    print("acceptance", rate, "z", z)
+    r = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=800, thermal=400, alpha=0.3, seed=7, n_batches=32)
+    assert 0.05 < r.acceptance < 1.0
+    z = (r.mean[0, 0].real - r.is_mean[0, 0].real) / np.hypot(r.err[0, 0].real, r.is_err[0, 0].real)
+    print("acceptance", r.acceptance, "z", z, "halves z", r.halves[2][0, 0].real)
+    assert np.all(np.abs(z) < 4.5), z
+    assert np.all(np.abs(r.halves[2][0, 0].real) < 4.5)
+
+
+def test_flow_mixture_chains_agree_with_importance_sampling():
+    # proposals from a defensive mixture whose components differ strongly (an untrained flow, the grid
+    # and a large uniform share), laid out by component along the sample index: without the per-step
+    # rotation the chains fed by one component settle to different distributions and the pooled
+    # estimate is biased
+    torch, dev = torch_dev()
+    n = 1
+    g = dmc.Graph(n)
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    ks = np.array([1.0], dtype=np.float32)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    dmc.adapt_grid(g, inst, ks, s, 1 << 20, 5, seed=2)
+    D = dmc.dim(n)
+    masks = synth.flow_masks(D, 8, 5)
+    f = dmc.Flow(D, masks)
+    f.set_params(synth.flow_params(masks, 11, last_scale=0.3))
+    r = dmc.mcmc_integrate(g, inst, ks, s, 1 << 16, steps=400, thermal=200, alpha=0.3, seed=5, n_batches=32,
+                           flow=f, flow_alpha=0.5, flow_uniform=0.3)
+    z = (r.mean[0, 0].real - r.is_mean[0, 0].real) / np.hypot(r.err[0, 0].real, r.is_err[0, 0].real)
+    print("acceptance", r.acceptance, "z", z, "err", r.err[0, 0].real, "IS err", r.is_err[0, 0].real)
     assert np.all(np.abs(z) < 4.5), z

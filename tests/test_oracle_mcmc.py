@@ -61,6 +61,51 @@ def test_sign_changing_integral_and_target():
     assert abs(naive.mean() - exact) > 10 * naive.std(ddof=1) / np.sqrt(len(naive))
 
 
+def test_rotation_hands_every_chain_the_whole_mixture():
+    # proposals laid out by component: alternate runs of 256 indices from q1 = 1 and from q2 = 2x, both
+    # on (0, 1) (every chain batch holds both); the acceptance test uses the mixture q = (q1 + q2) / 2.  A chain always
+    # fed by component i settles to q_i pi / q / Z_i, and Z_1 != Z_2, so without rotation the pooled
+    # ratio estimate converges to int f w / int q w, w = (q1 / Z_1 + q2 / Z_2) / q, not to int f.
+    alpha, n, steps, thermal = 0.2, 8192, 120, 30
+    exact = np.sin(6.0) / 6.0
+    xm = (np.arange(200000) + 0.5) / 200000
+    q1, q2 = np.ones_like(xm), 2 * xm
+    q = (q1 + q2) / 2
+    pi = alpha * q + (1 - alpha) * np.abs(np.cos(6 * xm))
+    z1, z2 = np.mean(q1 * pi / q), np.mean(q2 * pi / q)
+    w = (q1 / z1 + q2 / z2) / q
+    biased = np.mean(np.cos(6 * xm) * w) / np.mean(q * w)
+    assert abs(biased - exact) > 0.005   # the two limits are apart (16 %)
+    for rotate in (False, True):
+        rng = np.random.default_rng(8)
+        state, cur = None, np.zeros((16, 2, 2))
+        for t in range(thermal + steps):
+            u = rng.uniform(size=n)
+            x = np.where((np.arange(n) // 256) % 2 == 0, u, np.sqrt(u))
+            f = np.cos(6 * x).astype(np.float32)[None, :]
+            jac = (1.0 / ((1.0 + 2.0 * x) / 2.0)).astype(np.float32)
+            off = int(rng.integers(n)) if rotate else 0
+            state, _ = mcmc.step(state, f, jac, alpha, 11, t, [0], offset=off)
+            if t >= thermal:
+                cur += mcmc.measure(state, 16)
+        est = mcmc.ratio_estimate(cur)[:, 0]
+        m = mcmc.ratio_estimate(cur.sum(axis=0))[0]
+        e = est.std(ddof=1) / np.sqrt(len(est))
+        target = exact if rotate else biased
+        assert abs(m - target) < 5 * e, (rotate, m, e, target)
+        assert abs(m - (biased if rotate else exact)) > 5 * e, (rotate, m, e)
+
+
+def test_offset_rotates_the_proposals():
+    rng = np.random.default_rng(2)
+    f = rng.normal(size=(2, 10)).astype(np.float32)
+    jac = rng.uniform(0.5, 2.0, size=10).astype(np.float32)
+    state, take = mcmc.step(None, f, jac, 0.5, 1, 0, [0, 1], offset=3)
+    assert take.all()
+    assert np.array_equal(state["f"], np.roll(f, -3, axis=1))
+    assert np.allclose(state["q"], 1.0 / np.roll(jac, -3).astype(np.float64))
+
+
 def test_batches_partition_the_chains():
     rng = np.random.default_rng(4)
     n = 1001
