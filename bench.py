@@ -188,8 +188,10 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
     of Sec. IV): Re Sigma(k_F, i omega_0) alone (K = 1, so p = |Re f| + |Im f| at k_F).  VEGAS IS:
     ref_factor x n_batches batches of n_chains * steps / n_batches samples from the adapted grid; the
     scatter of the batch means gives sigma at the chains' evaluation count (sigma_b / sqrt(n_batches))
-    and the reference for the z of each chain estimate (sigma_b / sqrt(ref_factor n_batches)).  VEGAS-MCMC (the frozen grid as independent proposal) and, with `flow`,
-    NF-MCMC (the trained flow's defensive mixture as proposal), for each mixing parameter alpha:
+    and the reference for the z of each chain estimate (sigma_b / sqrt(ref_factor n_batches)); the
+    weights are heavy-tailed from order 3 on, so the robust spread (1.4826 x the median absolute
+    deviation of the batch means) is reported beside it.  VEGAS-MCMC (the frozen grid as independent
+    proposal) and, with `flow`, NF-MCMC (the trained flow's defensive mixture as proposal), for each mixing parameter alpha:
     n_chains chains, `thermal` steps discarded, `steps` measured, sigma from n_batches independent
     chain batches.  Equal evaluation counts: the efficiency relative to VEGAS is
     sigma_VEGAS^2 / sigma^2 per evaluation and sigma_VEGAS^2 T_VEGAS / (sigma^2 T) per wall second
@@ -234,15 +236,18 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
             means.append(m[0, 0, 0].real)
         means = np.array(means)
         sb = float(means.std(ddof=1))
-        return float(means.mean()), sb / math.sqrt(n_batches), sb / math.sqrt(n_batches * ref_factor)
+        mad = 1.4826 * float(np.median(np.abs(means - np.median(means))))
+        return (float(means.mean()), sb / math.sqrt(n_batches), sb / math.sqrt(n_batches * ref_factor),
+                mad / math.sqrt(n_batches))
 
-    (v_re, v_sig, v_ref), t_ref = timed(vegas_is)
+    (v_re, v_sig, v_ref, v_mad), t_ref = timed(vegas_is)
     t_v = t_ref / ref_factor
     log(f"VEGAS IS {v_re:.6g} +- {v_ref:.3g} ({ref_factor} x {n_eval} evaluations, {t_ref:.2f} s); "
-        f"sigma at {n_eval}: {v_sig:.3g}")
+        f"sigma at {n_eval}: {v_sig:.3g} (robust {v_mad:.3g})")
     out = {"order": order, "k": 1.0, "evaluations": n_eval, "n_chains": n_chains, "steps": steps,
            "thermal": thermal, "n_batches": n_batches, "adapt_seconds": t_adapt,
-           "vegas": {"re": v_re, "sigma_ref": v_ref, "ref_factor": ref_factor, "sigma": v_sig, "seconds": t_v}}
+           "vegas": {"re": v_re, "sigma_ref": v_ref, "ref_factor": ref_factor, "sigma": v_sig, "sigma_mad": v_mad,
+                     "seconds": t_v}}
 
     def chains(label, fl):
         rows = []
@@ -252,12 +257,13 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
             re, sig = float(r.mean[0, 0, 0].real), float(r.err[0, 0, 0].real)
             zh = float(r.halves[2][0, 0, 0].real)
             rows.append({"alpha": a, "re": re, "sigma": sig, "acceptance": r.acceptance, "seconds": t,
-                         "efficiency_per_eval": (v_sig / sig) ** 2,
+                         "efficiency_per_eval": (v_sig / sig) ** 2, "efficiency_per_eval_mad": (v_mad / sig) ** 2,
                          "efficiency_per_second": (v_sig ** 2 * t_v) / (sig ** 2 * t),
                          "z_vs_vegas": (re - v_re) / math.hypot(sig, v_ref), "z_halves": zh,
                          "proposal_is": {"re": float(r.is_mean[0, 0, 0].real), "sigma": float(r.is_err[0, 0, 0].real)}})
             log(f"{label} alpha {a}: {re:.6g} +- {sig:.3g} (z vs VEGAS {rows[-1]['z_vs_vegas']:+.2f}, halves {zh:+.2f}), "
-                f"acceptance {r.acceptance:.3f}, efficiency/eval {(v_sig / sig) ** 2:.2f} ({t:.2f} s)")
+                f"acceptance {r.acceptance:.3f}, efficiency/eval {(v_sig / sig) ** 2:.2f} "
+                f"(robust {(v_mad / sig) ** 2:.2f}) ({t:.2f} s)")
         # best alpha among the runs that agree with VEGAS and show no trend between their halves
         ok = [r for r in rows if abs(r["z_vs_vegas"]) < 3 and abs(r["z_halves"]) < 3]
         best = max(ok, key=lambda r: r["efficiency_per_eval"]) if ok else None

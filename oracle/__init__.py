@@ -11,7 +11,12 @@ Modules:
   diagrams   brute-force enumeration, canonical labelling, routing (eq. sigma_integration)
   integrand  naive diagram-by-diagram FP64 integrand, forward-mode derivatives, uniform map
   mc         plain Monte Carlo (eq. nf_mcmc_estimator_qft_final_revised at alpha = 1)
-  sampler    Philox4x32-10, VEGAS map and refinement
+  sampler    Philox4x32-10, VEGAS map, inverse map and refinement
+  flow       affine-coupling flow in FP64 (optional BF16 emulation), its gradient, Adam, mixtures
+  mcmc       Markov chains with independent proposals and the ratio estimator (Sec. IV)
+  taylor     truncated Taylor series in (mu, lambda) with a k tangent (Secs. III.B, VI.A)
+  renorm     counterterm recursion, xi series and the effective mass (Secs. III.B, VI.A)
+  enumerate.c (built by build.py) the brute-force diagram enumeration in C, for orders 5-6
 
 Parity status: orders 1-2 are pinned to closed forms (Fock integral, rainbow time integral,
 G0 identities); the diagram set at every order is pinned by the Dyson count identity and
