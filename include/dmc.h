@@ -43,7 +43,8 @@ typedef enum {
     DMC_E_NUMERIC = -6  /* estimate: some sample weights were non-finite and were dropped */
 } dmc_status;
 
-enum { DMC_MAX_ORDER = 6, DMC_MAX_K = 64, DMC_MAX_GROUPS = 8, DMC_MAX_INSTANCES = 64 };
+enum { DMC_MAX_ORDER = 6, DMC_MAX_K = 64, DMC_MAX_GROUPS = 8, DMC_MAX_INSTANCES = 64, DMC_MAX_ROOTS = 64,
+       DMC_MAX_TAYLOR = 6 };
 
 /* Derivative roots (deriv_mask bits): d/dmu (chemical potential), d/dlambda (screening),
  * d/dk (external momentum), each the (m, l) = (1, 0), (0, 1) coefficient of
@@ -60,6 +61,11 @@ typedef struct {
     int32_t diagram_index; /* -1 = all diagrams; otherwise only diagram #i of the exported list */
     int32_t part_size;     /* diagrams per straight-line part of the generated kernel (its parts share
                               nothing and keep the register set bounded); 0 chooses by graph size */
+    int32_t taylor_order;  /* 0: first-order derivative roots along the masked directions (below);
+                              T in 1..DMC_MAX_TAYLOR: Taylor mode (Sec. III.B eq. taylor_node; Sec. VI.A
+                              eq. sigma_xi_dmu_dlambda): every d^m/dmu^m d^l/dlambda^l with m + l <= T
+                              along the masked directions among mu and lambda, and with DMC_D_K also
+                              the k derivative of each (eq. deltam_partitions) */
 } dmc_graph_spec;
 
 typedef struct {
@@ -78,6 +84,8 @@ typedef struct {
      * once per chunk of external momenta is not counted here): ops_*_exec >= ops_* */
     int64_t ops_sample_exec[4];
     int64_t ops_k_exec[4];
+    int32_t n_roots;      /* roots per (lambda group, k, Re/Im): the accumulator's n_roots */
+    int32_t taylor_order; /* as in the spec */
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that
@@ -100,6 +108,11 @@ const char* dmc_version(void);
  * emitted in parts (spec.part_size).  *out is library-owned: free with dmc_graph_destroy. */
 dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out);
 dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* out);
+/* The derivative each root holds: out[3 r + 0..2] = (m, l, e) for root r of d^m/dmu^m d^l/dlambda^l
+ * (d/dk)^e of the self-energy (Sec. VI.A, eq. sigma_xi_dmu_dlambda and eq. deltam_partitions).  First-order
+ * mode: the value, then d/dmu, d/dlambda, d/dk as masked.  Taylor mode: e = 0 before e = 1; within each,
+ * by m + l ascending, then m descending.  cap: ints available at out (3 n_roots needed, else DMC_E_INVALID). */
+dmc_status dmc_graph_root_orders(const dmc_graph* g, int32_t* out, int32_t cap);
 /* Text export of the diagram list, one diagram per line:
  *   "<sigma_0> ... <sigma_{2n-1}> | w <weight> | ext <line> | G src dst c_0..c_{n-1} c_k ; ... | V ..."
  * buf may be NULL to query the length; *len receives the byte count without the final NUL. */
@@ -110,7 +123,9 @@ void dmc_graph_destroy(dmc_graph* g);
 
 /* ---- accumulator (FP64 running sums; the only FP64 arithmetic on the device) ----
  * Holds, per (lambda group, k, Re/Im, root), sum w and sum w^2 in FP64 plus the sample count
- * and the count of non-finite weights.  n_roots = 1 + popcount(deriv_mask) of the graph used. */
+ * and the count of non-finite weights.  n_roots (1..DMC_MAX_ROOTS) = the graph's (dmc_graph_info).
+ * One evaluation workgroup keeps four waves' FP64 totals of all n_groups n_k 2 n_roots slots in LDS:
+ * dmc_eval_batch returns DMC_E_INVALID when they do not fit (about 1900 slots). */
 dmc_status dmc_accum_create(int32_t n_groups, int32_t n_k, int32_t n_roots, dmc_accum** out);
 dmc_status dmc_accum_reset(dmc_accum* acc, void* stream);
 void dmc_accum_destroy(dmc_accum* acc);
@@ -243,6 +258,24 @@ dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int
 /* Zero the sums and the accepted count (the chain states are kept). */
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
 void dmc_chains_destroy(dmc_chains* c);
+
+/* ---- renormalisation post-processing and effective mass (host, FP64) ----
+ * Sec. III.B (eq. sigma_xi_dmu, eq. counterterm) and Sec. VI.A (eq. sigma_xi_dmu_dlambda with
+ * dlambda = -xi lambda_R, eq. dsigma_depsilon_series, eq. deltam_partitions, eq. deltas_partitions,
+ * eq. eff_mass_ratio).  Input: n_coef Fermi-surface coefficients, coefficient c of order
+ * (n, m, l) = nml[3c..3c+2] (n >= 1 interaction lines, m mu-derivatives, l lambda-derivatives):
+ *   sigma_fs[c] = Re Sigma^(n,m,l)(k_F, i w_0)   (standing in for the zero-frequency value)
+ *   a[c] = a^(n,m,l) = (m_e / k_F) d Re Sigma^(n,m,l) / dk at k_F   (m_e / k_F = 1/2 when eps_k = k^2)
+ *   b[c] = b^(n,m,l) = Im Sigma^(n,m,l)(k_F, i w_0) / w_0            (w_0 = pi / beta)
+ * Each table X becomes X(xi) = sum xi^(n+l) dmu(xi)^m / m! (-lambda_R)^l / l! X^(n,m,l) truncated at xi^N.
+ * Counterterms (the pole of the full propagator stays at the Fermi surface): delta_mu^(j) = the xi^j
+ * coefficient of Sigma(k_F), j = 1..N.  Outputs, host double[N + 1] each (index = power of xi):
+ * delta_mu (delta_mu[0] = 0), a_xi, b_xi, mass = the coefficients of (1 - b(xi)) (1 + a(xi))^-1, and
+ * mass_partial[j] = the ratio m_eff/m through order j at xi = 1.  DMC_E_INVALID for N outside 1..32, null pointers,
+ * lambda_R < 0 or a coefficient with n < 1 or m, l < 0. */
+dmc_status dmc_effective_mass(int32_t N, double lambda_R, int32_t n_coef, const int32_t* nml, const double* sigma_fs,
+                              const double* a, const double* b, double* delta_mu, double* a_xi, double* b_xi,
+                              double* mass, double* mass_partial);
 
 #ifdef __cplusplus
 }

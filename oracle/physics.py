@@ -156,6 +156,38 @@ def fock_derivs_finite_T(k: float, beta: float, mu: float, lam: float, gamma: fl
     return c * dmu, c * dlam, dk
 
 
+def nF_mu_derivative_poly(m: int):
+    """Coefficients (ascending powers of n) of P_m with d^m nF(q^2 - mu)/dmu^m = beta^m P_m(nF):
+    P_0 = n, P_{m+1}(n) = P_m'(n) n (1 - n), since d nF/d mu = beta nF (1 - nF)."""
+    P = np.polynomial.Polynomial([0.0, 1.0])
+    w = np.polynomial.Polynomial([0.0, 1.0, -1.0])
+    for _ in range(m):
+        P = P.deriv() * w
+    return P
+
+
+def fock_taylor_finite_T(k: float, beta: float, mu: float, lam: float, gamma: float, m: int, l: int,
+                         qmax: float = 12.0) -> float:
+    """d^m/dmu^m d^l/dlambda^l of fock_finite_T (k > 0): the 1D integral of
+    -(gamma/(pi k)) q [beta^m P_m(nF)] d^l/dlambda^l ln[((k+q)^2+lam)/((k-q)^2+lam)], with
+    d^l/dlambda^l ln(a + lam) = (-1)^(l-1) (l-1)! (a + lam)^(-l) for l >= 1."""
+    kf = math.sqrt(mu)
+    pts = [kf, k] + [math.sqrt(max(0.0, mu + s * 40.0 / beta)) for s in (-1, 1)]
+    pts = sorted(set(p for p in pts if 0 < p < qmax))
+    P = nF_mu_derivative_poly(m)
+
+    def L(q):
+        ap, am = (k + q) ** 2 + lam, (k - q) ** 2 + lam
+        if l == 0:
+            return math.log(ap / am)
+        return (-1) ** (l - 1) * math.factorial(l - 1) * (ap ** -l - am ** -l)
+
+    def f(q):
+        return q * beta ** m * float(P(float(nF(q * q - mu, beta)))) * L(q)
+    val, _ = integrate.quad(f, 0.0, qmax, points=pts, limit=400, epsabs=0, epsrel=1e-12)
+    return -gamma / (math.pi * k) * val
+
+
 def matsubara_of_G0(eps: float, beta: float, n: int = 0, nodes: int = 400) -> complex:
     """int_0^beta e^{i w_n tau} G0(eps, tau) dtau by composite Gauss-Legendre (for the pin
     G0(i w_n) = 1 / (i w_n - eps))."""

@@ -23,12 +23,13 @@ SAMPLER_UNIFORM, SAMPLER_VEGAS = 0, 1
 # every symbol include/dmc.h declares
 ABI_SYMBOLS = [
     "dmc_last_error", "dmc_version", "dmc_compile_graph", "dmc_graph_query", "dmc_graph_export_diagrams",
-    "dmc_graph_source", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
+    "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
     "dmc_chains_create", "dmc_chains_step", "dmc_chains_read", "dmc_chains_reset", "dmc_chains_destroy",
+    "dmc_effective_mass",
 ]
 
 
@@ -40,7 +41,7 @@ class DmcError(RuntimeError):
 
 class GraphSpec(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("deriv_mask", ctypes.c_uint32), ("diagram_index", ctypes.c_int32),
-                ("part_size", ctypes.c_int32)]
+                ("part_size", ctypes.c_int32), ("taylor_order", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -49,7 +50,8 @@ class GraphInfo(ctypes.Structure):
                 ("n_v_leaves", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("n_parts", ctypes.c_int32),
                 ("part_size", ctypes.c_int32), ("ops_sample", ctypes.c_int64 * 4),
                 ("ops_k", ctypes.c_int64 * 4), ("ops_naive", ctypes.c_int64 * 4),
-                ("ops_sample_exec", ctypes.c_int64 * 4), ("ops_k_exec", ctypes.c_int64 * 4)]
+                ("ops_sample_exec", ctypes.c_int64 * 4), ("ops_k_exec", ctypes.c_int64 * 4),
+                ("n_roots", ctypes.c_int32), ("taylor_order", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -85,6 +87,7 @@ def lib():
         "dmc_graph_export_diagrams": (I32, [P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
         "dmc_graph_source": (I32, [P, I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
         "dmc_graph_destroy": (None, [P]),
+        "dmc_graph_root_orders": (I32, [P, P, I32]),
         "dmc_accum_create": (I32, [I32, I32, I32, ctypes.POINTER(P)]),
         "dmc_accum_reset": (I32, [P, P]),
         "dmc_accum_destroy": (None, [P]),
@@ -112,6 +115,7 @@ def lib():
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
         "dmc_chains_destroy": (None, [P]),
+        "dmc_effective_mass": (I32, [I32, F64, I32, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -154,16 +158,30 @@ def dim(order: int) -> int:
     return 4 * order - 1
 
 
+def coupling(rs: float) -> float:
+    """gamma = alpha r_s, alpha = (4 / (9 pi))^(1/3): the Yukawa strength 8 pi gamma / (q^2 + lambda) in units
+    k_F = E_F = 1 (e^2 = 2 Ry a_0, k_F = 1 / (alpha r_s a_0))."""
+    return (4.0 / (9.0 * math.pi)) ** (1.0 / 3.0) * rs
+
+
 class Graph:
     """A compiled diagram graph (dmc_compile_graph)."""
 
-    def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1, part_size: int = 0):
+    def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1, part_size: int = 0,
+                 taylor_order: int = 0):
         self.h = P()
-        spec = GraphSpec(order, deriv_mask, diagram_index, part_size)
+        spec = GraphSpec(order, deriv_mask, diagram_index, part_size, taylor_order)
         _check(lib().dmc_compile_graph(ctypes.byref(spec), ctypes.byref(self.h)))
         self.order = order
         self.deriv_mask = deriv_mask
-        self.n_roots = 1 + bin(deriv_mask).count("1")
+        self.taylor_order = taylor_order
+        self.n_roots = self.info().n_roots
+
+    def root_orders(self):
+        """[(m, l, e)] per root: d^m/dmu^m d^l/dlambda^l (d/dk)^e of the self-energy."""
+        buf = (I32 * (3 * self.n_roots))()
+        _check(lib().dmc_graph_root_orders(self.h, buf, 3 * self.n_roots))
+        return [tuple(buf[3 * r: 3 * r + 3]) for r in range(self.n_roots)]
 
     def info(self) -> GraphInfo:
         gi = GraphInfo()
@@ -627,3 +645,83 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
         z.imag = (m1.imag - m2.imag) / np.hypot(e1.imag, e2.imag)
     mi, ei, _, _ = acc.estimate(len(inst))
     return McmcResult(m, e, accepted / (n_chains * steps), mi, ei, ((m1, e1), (m2, e2), z))
+
+
+
+def effective_mass(N: int, lambda_R: float, sigma_fs: dict, a: dict, b: dict):
+    """dmc_effective_mass: tables {(n, m, l): value} of Re Sigma^(n,m,l)(k_F, i w_0), a^(n,m,l) and b^(n,m,l)
+    (missing entries are zero).  Returns dict of float64 arrays [N + 1]: delta_mu, a_xi, b_xi, mass,
+    mass_partial (m*/m through each order at xi = 1)."""
+    import numpy as np
+    keys = sorted(set(sigma_fs) | set(a) | set(b))
+    nml = np.array(keys, dtype=np.int32).reshape(-1, 3)
+    cols = [np.array([t.get(k, 0.0) for k in keys], dtype=np.float64) for t in (sigma_fs, a, b)]
+    outs = {name: np.zeros(N + 1) for name in ("delta_mu", "a_xi", "b_xi", "mass", "mass_partial")}
+    ptr = lambda arr: arr.ctypes.data_as(P)
+    _check(lib().dmc_effective_mass(N, lambda_R, len(keys), ptr(nml), ptr(cols[0]), ptr(cols[1]), ptr(cols[2]),
+                                    *(ptr(outs[k]) for k in ("delta_mu", "a_xi", "b_xi", "mass", "mass_partial"))))
+    return outs
+
+
+def mass_coefficients(N: int, rs: float, lambda_R: float, beta: float = 25.0, mu: float = 1.0, n_samples: int = 1 << 22,
+                      batches: int = 16, adapt: int = 6, seed: int = 0x5E1F, qmax: float = 6.0, n_bins: int = 50):
+    """Fermi-surface Taylor coefficients for the renormalised series to total order N (n + m + l <= N):
+    per order n a graph with every d^m/dmu^m d^l/dlambda^l, m + l <= N - n, and their k derivatives
+    (Sec. VI.A, eq. sigma_xi_dmu_dlambda and eq. deltam_partitions), integrated at k = k_F with a VEGAS
+    grid adapted to that order.  Returns a list over `batches` independent batches of n_samples points
+    of (sigma_fs, a, b) tables as dmc_effective_mass takes them."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    inst = [(beta, mu, lambda_R, coupling(rs))]
+    ks = np.array([1.0], dtype=np.float32)
+    w0 = math.pi / beta
+    tables = [({}, {}, {}) for _ in range(batches)]
+    for n in range(1, N + 1):
+        T = N - n
+        g = Graph(n, D_MU | D_LAMBDA | D_K, taylor_order=T) if T > 0 else Graph(n, D_K)
+        orders = g.root_orders()
+        s = Sampler(SAMPLER_VEGAS, n, n_bins=n_bins, beta=beta, qmax=qmax)
+        first = adapt_grid(g, inst, ks, s, n_samples, adapt, seed=seed + n)
+        X = torch.empty((dim(n), n_samples), dtype=torch.float32, device=dev)
+        J = torch.empty(n_samples, dtype=torch.float32, device=dev)
+        acc = Accumulator(1, 1, g.n_roots)
+        for bi in range(batches):
+            acc.reset()
+            s.sample(seed + n, first + bi * n_samples, X, J)
+            eval_batch(g, inst, ks, X, J, acc)
+            accumulate(acc)
+            m_, _, _, _ = acc.estimate(1)
+            sig, a, b = tables[bi]
+            for r, (mm, ll, e) in enumerate(orders):
+                v = m_[0, r, 0]
+                if e == 0:
+                    sig[(n, mm, ll)] = float(v.real)
+                    b[(n, mm, ll)] = float(v.imag) / w0
+                else:
+                    a[(n, mm, ll)] = 0.5 * float(v.real)  # m_e / k_F = 1/2 (eps_k = k^2)
+    return tables
+
+
+def effective_mass_estimate(N: int, rs: float, lambda_R: float, **kw):
+    """m*/m of the renormalised series (Sec. VI.A) through orders 1..N with jackknife errors over the
+    independent batches of mass_coefficients (the ratio is a nonlinear function of the coefficients).
+    Returns (mass_partial [N + 1], its errors, delta_mu [N + 1], its errors)."""
+    import numpy as np
+    tables = mass_coefficients(N, rs, lambda_R, **kw)
+    B = len(tables)
+
+    def mean(sub):
+        out = []
+        for t in range(3):
+            keys = set().union(*(tb[t].keys() for tb in sub))
+            out.append({k: float(np.mean([tb[t].get(k, 0.0) for tb in sub])) for k in keys})
+        return out
+
+    full = effective_mass(N, lambda_R, *mean(tables))
+    jk = [effective_mass(N, lambda_R, *mean(tables[:i] + tables[i + 1:])) for i in range(B)]
+    err = {}
+    for name in ("mass_partial", "delta_mu"):
+        v = np.array([j[name] for j in jk])
+        err[name] = np.sqrt((B - 1) / B * np.sum((v - v.mean(axis=0)) ** 2, axis=0))
+    return full["mass_partial"], err["mass_partial"], full["delta_mu"], err["delta_mu"]

@@ -31,6 +31,15 @@ dmc_status fail(dmc_status s, const std::string& msg) {
     return s;
 }
 
+}  // namespace
+
+namespace dmc {
+// the thread-local error text for the other translation units of the library
+dmc_status set_error(dmc_status s, const char* msg) { return fail(s, msg); }
+}  // namespace dmc
+
+namespace {
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -125,7 +134,8 @@ dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
     auto g = std::make_unique<dmc_graph>();
     std::string err;
     try {
-        if (!dmc::compile(spec->order, spec->deriv_mask, spec->diagram_index, spec->part_size, g->c, err))
+        if (!dmc::compile(spec->order, spec->deriv_mask, spec->taylor_order, spec->diagram_index, spec->part_size, g->c,
+                          err))
             return fail(DMC_E_INVALID, err);
         g->exported = dmc::export_text(g->c);
     } catch (const std::bad_alloc&) {
@@ -151,6 +161,16 @@ dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
         o->ops_sample_exec[i] = g->c.stats.sample_exec[i];
         o->ops_k_exec[i] = g->c.stats.k_exec[i];
     }
+    o->n_roots = g->c.n_roots;
+    o->taylor_order = g->c.taylor_order;
+    return DMC_OK;
+}
+
+dmc_status dmc_graph_root_orders(const dmc_graph* g, int32_t* out, int32_t cap) {
+    if (!g || !out) return fail(DMC_E_INVALID, "null argument");
+    if (cap < 3 * g->c.n_roots) return fail(DMC_E_INVALID, "cap must be at least 3 n_roots");
+    for (int r = 0; r < g->c.n_roots; ++r)
+        for (int i = 0; i < 3; ++i) out[3 * r + i] = g->c.root_orders[r][i];
     return DMC_OK;
 }
 
@@ -282,7 +302,7 @@ static dmc_status get_kernel(dmc_graph* g, int n_groups, JitKernel** out) {
 // ------------------------------------------------------------------------------ accumulator
 dmc_status dmc_accum_create(int32_t n_groups, int32_t n_k, int32_t n_roots, dmc_accum** out) {
     if (!out || n_groups < 1 || n_groups > DMC_MAX_GROUPS || n_k < 1 || n_k > DMC_MAX_K || n_roots < 1 ||
-        n_roots > 4)
+        n_roots > DMC_MAX_ROOTS)
         return fail(DMC_E_INVALID, "accumulator shape out of range");
     auto a = std::make_unique<dmc_accum>();
     a->n_groups = n_groups;
@@ -1047,7 +1067,7 @@ extern "C" {
 dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
                              dmc_chains** out) {
     if (!out || n < 1 || n_groups < 1 || n_groups > DMC_MAX_GROUPS || n_k < 1 || n_k > DMC_MAX_K || n_roots < 1 ||
-        n_roots > 4)
+        n_roots > DMC_MAX_ROOTS)
         return fail(DMC_E_INVALID, "chain count or observable shape out of range");
     if (n_batches < 1 || n_batches > DMC_MAX_CHAIN_BATCHES || n_batches > n)
         return fail(DMC_E_INVALID, "n_batches must be in [1, min(n, DMC_MAX_CHAIN_BATCHES)]");

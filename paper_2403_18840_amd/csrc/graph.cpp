@@ -225,28 +225,91 @@ std::string fstr(double v) {
     return s.str();
 }
 
-// A value of the generated code and its first-order tangents along the active directions
-// (0: mu, 1: lambda, 2: k); an empty tangent name means structurally zero.
+// The coefficients a value of the generated code carries: entry 0 is the value, entry j > 0 the
+// coefficient of dmu^m dlambda^l dk^e with (m, l, e) = idx[j].  The set is downward closed, so the
+// product of two series keeps, for each of its entries, every pair of factor entries whose
+// multi-indices add up to it.  First-order mode holds the value and one tangent per masked
+// direction; Taylor mode (eq. taylor_node) holds every coefficient with m + l <= T and, with the k
+// direction, their k tangents.  Coefficients are normalised (Taylor coefficients, not derivatives).
+struct CoefSet {
+    std::vector<std::array<int, 3>> idx;
+    std::vector<std::vector<std::pair<int, int>>> conv;  // (a, b) with idx[a] + idx[b] = idx[j], a ascending
+    int max_m = 0, max_l = 0;
+
+    int find(int m, int l, int e) const {
+        for (size_t j = 0; j < idx.size(); ++j)
+            if (idx[j][0] == m && idx[j][1] == l && idx[j][2] == e) return (int)j;
+        return -1;
+    }
+    void finish() {
+        conv.assign(idx.size(), {});
+        for (size_t j = 0; j < idx.size(); ++j) {
+            max_m = std::max(max_m, idx[j][0]);
+            max_l = std::max(max_l, idx[j][1]);
+            for (size_t a = 0; a < idx.size(); ++a) {
+                const int m = idx[j][0] - idx[a][0], l = idx[j][1] - idx[a][1], e = idx[j][2] - idx[a][2];
+                if (m < 0 || l < 0 || e < 0) continue;
+                const int b = find(m, l, e);
+                if (b >= 0) conv[j].push_back({(int)a, b});
+            }
+        }
+    }
+    static CoefSet first_order(uint32_t mask) {
+        CoefSet s;
+        s.idx.push_back({0, 0, 0});
+        for (int i = 0; i < 3; ++i)
+            if (mask & (1u << i)) s.idx.push_back({i == 0, i == 1, i == 2});
+        s.finish();
+        return s;
+    }
+    static CoefSet taylor(uint32_t mask, int T) {
+        CoefSet s;
+        for (int e = 0; e <= ((mask & 4u) ? 1 : 0); ++e)
+            for (int d = 0; d <= T; ++d)
+                for (int m = d; m >= 0; --m) {
+                    const int l = d - m;
+                    if ((m && !(mask & 1u)) || (l && !(mask & 2u))) continue;
+                    s.idx.push_back({m, l, e});
+                }
+        s.finish();
+        return s;
+    }
+};
+
+// A value of the generated code and its coefficients 1.. of the set (d[j - 1]); an empty name means
+// structurally zero.
 struct Val {
     std::string name;
     bool kdep;
-    std::array<std::string, 3> d{};
+    std::vector<std::string> d{};
 };
 
 class Emitter {
    public:
     std::ostringstream pre, loop;
     int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0};  // add mul fma trans
-    bool act[3] = {false, false, false};
+    bool act[3] = {false, false, false};  // directions with a first-order entry (mu, lambda, k)
+    const CoefSet* cs = nullptr;
 
     std::string prefix = "v";  // name prefix (distinct per part of a partitioned kernel)
     std::string tag;           // prefix of the few names not made by def (empty for one part)
+
+    void set_coefs(const CoefSet* s) {
+        cs = s;
+        act[0] = s->find(1, 0, 0) > 0;
+        act[1] = s->find(0, 1, 0) > 0;
+        act[2] = s->find(0, 0, 1) > 0;
+    }
+    int nco() const { return (int)cs->idx.size(); }
+    static const std::string& cf(const Val& v, int j) { return j == 0 ? v.name : v.d[j - 1]; }
+    // the entry of direction i's first-order coefficient (mu 0, lambda 1, k 2), or -1
+    int dir(int i) const { return cs->find(i == 0, i == 1, i == 2); }
 
     Val def(bool kdep, const std::string& expr, int opclass, int nops = 1) {
         std::string nm = prefix + std::to_string(tmp_++);
         (kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
         if (opclass >= 0) (kdep ? cnt_loop : cnt_pre)[opclass] += nops;
-        return {nm, kdep, {}};
+        return {nm, kdep, std::vector<std::string>(nco() - 1)};
     }
     Val hashed(const std::string& key, bool kdep, const std::string& expr, int opclass,
                const std::function<void(Val&)>& tangents) {
@@ -262,16 +325,20 @@ class Emitter {
         const Val& y = a.name < b.name ? b : a;
         const bool kd = a.kdep || b.kdep;
         return hashed("*" + x.name + "," + y.name, kd, x.name + " * " + y.name, 1, [&](Val& v) {
-            for (int i = 0; i < 3; ++i) {
-                if (!act[i]) continue;
-                const std::string &dx = x.d[i], &dy = y.d[i];
-                if (dx.empty() && dy.empty()) continue;
-                if (dy.empty())
-                    v.d[i] = def(kd, dx + " * " + y.name, 1).name;
-                else if (dx.empty())
-                    v.d[i] = def(kd, x.name + " * " + dy, 1).name;
-                else {
-                    v.d[i] = def(kd, "__builtin_fmaf(" + dx + ", " + y.name + ", " + x.name + " * " + dy + ")", 2).name;
+            for (int j = 1; j < nco(); ++j) {
+                std::string acc;
+                int t = 0;
+                for (auto [ia, ib] : cs->conv[j]) {
+                    const std::string &xa = cf(x, ia), &yb = cf(y, ib);
+                    if (xa.empty() || yb.empty()) continue;
+                    acc = acc.empty() ? xa + " * " + yb : "__builtin_fmaf(" + xa + ", " + yb + ", " + acc + ")";
+                    ++t;
+                }
+                if (t == 0) continue;
+                if (t == 1) {
+                    v.d[j - 1] = def(kd, acc, 1).name;
+                } else {
+                    v.d[j - 1] = def(kd, acc, 2, t - 1).name;
                     (kd ? cnt_loop : cnt_pre)[1] += 1;
                 }
             }
@@ -283,25 +350,21 @@ class Emitter {
         const bool kd = a.kdep || b.kdep || c.kdep;
         return hashed("f" + x.name + "," + y.name + "," + c.name, kd,
                       "__builtin_fmaf(" + x.name + ", " + y.name + ", " + c.name + ")", 2, [&](Val& v) {
-                          for (int i = 0; i < 3; ++i) {
-                              if (!act[i]) continue;
-                              std::string acc = c.d[i];
+                          for (int j = 1; j < nco(); ++j) {
+                              std::string acc = cf(c, j);
                               int nf = 0;
-                              if (!y.d[i].empty()) {
-                                  acc = acc.empty() ? x.name + " * " + y.d[i]
-                                                    : "__builtin_fmaf(" + x.name + ", " + y.d[i] + ", " + acc + ")";
-                                  ++nf;
-                              }
-                              if (!x.d[i].empty()) {
-                                  acc = acc.empty() ? x.d[i] + " * " + y.name
-                                                    : "__builtin_fmaf(" + x.d[i] + ", " + y.name + ", " + acc + ")";
+                              for (auto [ia, ib] : cs->conv[j]) {
+                                  const std::string &xa = cf(x, ia), &yb = cf(y, ib);
+                                  if (xa.empty() || yb.empty()) continue;
+                                  acc = acc.empty() ? xa + " * " + yb
+                                                    : "__builtin_fmaf(" + xa + ", " + yb + ", " + acc + ")";
                                   ++nf;
                               }
                               if (acc.empty()) continue;
                               if (nf == 0) {
-                                  v.d[i] = acc;  // only the addend carries a tangent
+                                  v.d[j - 1] = acc;  // only the addend carries this coefficient
                               } else {
-                                  v.d[i] = def(kd, acc, 2, nf).name;
+                                  v.d[j - 1] = def(kd, acc, 2, nf).name;
                               }
                           }
                       });
@@ -311,14 +374,14 @@ class Emitter {
         const Val& y = a.name < b.name ? b : a;
         const bool kd = a.kdep || b.kdep;
         return hashed("+" + x.name + "," + y.name, kd, x.name + " + " + y.name, 0, [&](Val& v) {
-            for (int i = 0; i < 3; ++i) {
-                if (!act[i]) continue;
-                if (x.d[i].empty())
-                    v.d[i] = y.d[i];
-                else if (y.d[i].empty())
-                    v.d[i] = x.d[i];
+            for (int j = 1; j < nco(); ++j) {
+                const std::string &xj = cf(x, j), &yj = cf(y, j);
+                if (xj.empty())
+                    v.d[j - 1] = yj;
+                else if (yj.empty())
+                    v.d[j - 1] = xj;
                 else
-                    v.d[i] = def(kd, x.d[i] + " + " + y.d[i], 0).name;
+                    v.d[j - 1] = def(kd, xj + " + " + yj, 0).name;
             }
         });
     }
@@ -327,11 +390,11 @@ class Emitter {
         std::ostringstream k;
         k << "c" << c << "*" << a.name;
         return hashed(k.str(), a.kdep, fstr(c) + " * " + a.name, c == -1.0 ? -1 : 1, [&](Val& v) {
-            for (int i = 0; i < 3; ++i)
-                if (act[i] && !a.d[i].empty()) v.d[i] = def(a.kdep, fstr(c) + " * " + a.d[i], c == -1.0 ? -1 : 1).name;
+            for (int j = 1; j < nco(); ++j)
+                if (!cf(a, j).empty()) v.d[j - 1] = def(a.kdep, fstr(c) + " * " + cf(a, j), c == -1.0 ? -1 : 1).name;
         });
     }
-    Val constant(double c) { return {fstr(c), false, {}}; }
+    Val constant(double c) { return {fstr(c), false, std::vector<std::string>(nco() - 1)}; }
 
    private:
     int tmp_ = 0;
@@ -362,11 +425,11 @@ struct Builder {
 
     std::map<int, std::string> mom_dp2;   // d|p|^2/dk of k-dependent momenta
     std::map<int, std::string> mom_bnf;   // beta nF(eps) per momentum
+    CoefSet coefs;
 
     Builder(const Compiled& cc, int ng) : c(cc), n(cc.order), n_groups(ng) {
-        em.act[0] = cc.deriv_mask & 1u;
-        em.act[1] = cc.deriv_mask & 2u;
-        em.act[2] = cc.deriv_mask & 4u;
+        coefs = cc.taylor_order > 0 ? CoefSet::taylor(cc.deriv_mask, cc.taylor_order) : CoefSet::first_order(cc.deriv_mask);
+        em.set_coefs(&coefs);
     }
 
     bool is_k(int m) const { return moms[m][n] != 0; }
@@ -468,14 +531,154 @@ struct Builder {
         Val D = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3);
         Val me = em.def(k, "MU - " + p.name, 0);
         energy[m] = {me, e, D};
-        if (em.act[0] || em.act[2]) {
+        if (c.taylor_order == 0 && (em.act[0] || em.act[2])) {
             Val nf = em.def(k, e.name + " * " + D.name, 1);
             mom_bnf[m] = em.def(k, nf.name + " * BETA", 1).name;
         }
         return energy[m];
     }
 
+    // ---- Taylor mode (eq. taylor_node; eq. green_ct and eq. interaction_ct are the leaves' series) ----
+    std::map<int, std::string> bfac_;                         // beta^i / i!
+    std::map<std::pair<int, int>, std::vector<std::string>> tser_;  // tau'^i / i! per time pair
+    std::map<int, std::string> mom_nf;                        // nF(eps) per momentum
+
+    const std::string& bfac(int i) {
+        auto it = bfac_.find(i);
+        if (it != bfac_.end()) return it->second;
+        std::string v = i == 1 ? std::string("BETA") : em.def(false, bfac(i - 1) + " * BETA * " + fstr(1.0 / i), 1, 2).name;
+        return bfac_[i] = v;
+    }
+
+    // tau'^i / i!, i = 0..M, for the propagator from line a to line b (tau' in (0, beta])
+    const std::vector<std::string>& tser(int a, int b, int M) {
+        auto key = std::make_pair(a, b);
+        auto& t = tser_[key];
+        if (t.empty()) {
+            t.push_back("1.0f");
+            t.push_back(em.def(false, T(a, b).first + " * 0.693147181f", 1).name);
+        }
+        while ((int)t.size() <= M) {
+            const int i = (int)t.size();
+            t.push_back(em.def(false, t[i - 1] + " * " + t[1] + " * " + fstr(1.0 / i), 1, 2).name);
+        }
+        return t;
+    }
+
+    // G0 as a series in dmu: eps = |p|^2 - mu - dmu, so G0(eps) = +-exp(-eps tau') D(eps) with
+    // D = 1 / (1 + exp(-beta eps)) (or nF at equal time).  exp(dmu tau') has coefficients tau'^i / i!;
+    // D's coefficients follow from (1 + e exp(beta dmu)) D = 1: d_0 = D, d_j = -nF sum_{i=1..j} beta^i/i! d_{j-i}
+    // (nF = e D).  The k tangent of coefficient m is -(m + 1) g_{m+1} d|p|^2/dk.
+    int g_leaf_taylor(const Line& ln) {
+        int m = momentum(ln.mom);
+        int a = ln.src / 2, b = ln.dst / 2;
+        auto key = std::make_tuple(m, a, b);
+        auto it = gleaf.find(key);
+        if (it != gleaf.end()) return it->second;
+        const bool k = is_k(m);
+        auto en = E(m);
+        const bool kt = em.act[2] && k;
+        const int M = coefs.max_m + (kt ? 1 : 0);
+        std::vector<std::string> dser(M + 1);
+        dser[0] = en[2].name;
+        std::string nf;
+        if (M >= 1 || a == b) {
+            auto nit = mom_nf.find(m);
+            if (nit == mom_nf.end()) nit = mom_nf.emplace(m, em.def(k, en[1].name + " * " + en[2].name, 1).name).first;
+            nf = nit->second;
+        }
+        for (int j = 1; j <= M; ++j) {
+            std::string acc;
+            int t = 0;
+            for (int i = 1; i <= j; ++i) {
+                acc = acc.empty() ? bfac(i) + " * " + dser[j - i]
+                                  : "__builtin_fmaf(" + bfac(i) + ", " + dser[j - i] + ", " + acc + ")";
+                ++t;
+            }
+            std::string sum = t == 1 ? em.def(k, acc, 1).name : em.def(k, acc, 2, t - 1).name;
+            if (t > 1) (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            dser[j] = em.def(k, "-" + nf + " * " + sum, 1).name;
+        }
+        std::vector<std::string> g(M + 1);
+        Val v;
+        if (a == b) {
+            // equal time (0^-): nF(eps - dmu) = 1 - D(eps - dmu)
+            v = Val{nf, k, std::vector<std::string>(em.nco() - 1)};
+            for (int j = 1; j <= M; ++j) g[j] = em.def(k, "-" + dser[j], -1).name;
+        } else {
+            auto tp = T(a, b);
+            Val ex = em.def(k, "__builtin_amdgcn_exp2f(" + en[0].name + " * " + tp.first + ")", 3);
+            (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            Val g0 = em.def(k, ex.name + " * " + en[2].name, 1);
+            v = em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
+            const auto& ts = tser(a, b, M);
+            for (int j = 1; j <= M; ++j) {
+                std::string acc = dser[j];
+                for (int i = 1; i <= j; ++i) acc = "__builtin_fmaf(" + ts[i] + ", " + dser[j - i] + ", " + acc + ")";
+                Val u = em.def(k, acc, 2, j);
+                Val gj = em.def(k, ex.name + " * " + u.name, 1);
+                g[j] = em.def(k, tp.second + " ? -" + gj.name + " : " + gj.name, 0).name;
+            }
+        }
+        g[0] = v.name;
+        for (int j = 1; j <= coefs.max_m; ++j) {
+            const int e = coefs.find(j, 0, 0);
+            if (e > 0) v.d[e - 1] = g[j];
+        }
+        if (kt) {
+            for (int j = 0; j <= coefs.max_m; ++j) {
+                const int e = coefs.find(j, 0, 1);
+                if (e <= 0) continue;
+                v.d[e - 1] = j == 0 ? em.def(true, "-" + g[1] + " * " + mom_dp2[m], 1).name
+                                    : em.def(true, fstr(-(double)(j + 1)) + " * " + g[j + 1] + " * " + mom_dp2[m], 1, 2).name;
+            }
+        }
+        int id = (int)vals.size();
+        vals.push_back(v);
+        val_k.push_back(k);
+        gleaf[key] = id;
+        ++n_g;
+        return id;
+    }
+
+    // V as a series in dlambda: 1 / (|p|^2 + lambda + dlambda) has coefficients (-1)^l r^(l+1) (the
+    // factor 8 pi gamma is applied at the end); the k tangent of coefficient l is (l + 1) c_{l+1} d|p|^2/dk.
+    int v_leaf_taylor(const Line& ln, int grp) {
+        int m = momentum(ln.mom);
+        auto key = std::make_pair(m, grp);
+        auto it = vleaf.find(key);
+        if (it != vleaf.end()) return it->second;
+        const bool k = is_k(m);
+        Val p = p2(m);
+        Val s = em.def(k, p.name + " + LAM" + std::to_string(grp), 0);
+        Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
+        const bool kt = em.act[2] && k;
+        const int L = coefs.max_l + (kt ? 1 : 0);
+        std::vector<std::string> c(L + 1);
+        c[0] = v.name;
+        for (int l = 1; l <= L; ++l) c[l] = em.def(k, "-" + c[l - 1] + " * " + v.name, 1).name;
+        for (int l = 1; l <= coefs.max_l; ++l) {
+            const int e = coefs.find(0, l, 0);
+            if (e > 0) v.d[e - 1] = c[l];
+        }
+        if (kt) {
+            for (int l = 0; l <= coefs.max_l; ++l) {
+                const int e = coefs.find(0, l, 1);
+                if (e <= 0) continue;
+                v.d[e - 1] = l == 0 ? em.def(true, c[1] + " * " + mom_dp2[m], 1).name
+                                    : em.def(true, fstr((double)(l + 1)) + " * " + c[l + 1] + " * " + mom_dp2[m], 1, 2).name;
+            }
+        }
+        int id = (int)vals.size();
+        vals.push_back(v);
+        val_k.push_back(k);
+        vleaf[key] = id;
+        ++n_v;
+        return id;
+    }
+
     int g_leaf(const Line& ln) {
+        if (c.taylor_order > 0) return g_leaf_taylor(ln);
         int m = momentum(ln.mom);
         int a = ln.src / 2, b = ln.dst / 2;
         auto key = std::make_tuple(m, a, b);
@@ -503,8 +706,8 @@ struct Builder {
             Val lg = a == b ? em.def(k, "BETA * " + en[2].name, 1)
                             : em.def(k, tprime + " - " + mom_bnf[m], 0, 2);
             Val gm = em.def(k, v.name + " * " + lg.name, 1);
-            if (em.act[0]) v.d[0] = gm.name;
-            if (em.act[2] && k) v.d[2] = em.def(true, "-" + gm.name + " * " + mom_dp2[m], 1).name;
+            if (em.act[0]) v.d[em.dir(0) - 1] = gm.name;
+            if (em.act[2] && k) v.d[em.dir(2) - 1] = em.def(true, "-" + gm.name + " * " + mom_dp2[m], 1).name;
         }
         int id = (int)vals.size();
         vals.push_back(v);
@@ -515,6 +718,7 @@ struct Builder {
     }
 
     int v_leaf(const Line& ln, int grp) {
+        if (c.taylor_order > 0) return v_leaf_taylor(ln, grp);
         int m = momentum(ln.mom);
         auto key = std::make_pair(m, grp);
         auto it = vleaf.find(key);
@@ -526,8 +730,8 @@ struct Builder {
         if (em.act[1] || (em.act[2] && k)) {
             // d V / d lambda = -V^2 (times 8 pi gamma, applied at the end); d V / dk = -V^2 d|p|^2/dk
             Val vl = em.def(k, "-" + v.name + " * " + v.name, 1);
-            if (em.act[1]) v.d[1] = vl.name;
-            if (em.act[2] && k) v.d[2] = em.def(true, vl.name + " * " + mom_dp2[m], 1).name;
+            if (em.act[1]) v.d[em.dir(1) - 1] = vl.name;
+            if (em.act[2] && k) v.d[em.dir(2) - 1] = em.def(true, vl.name + " * " + mom_dp2[m], 1).name;
         }
         int id = (int)vals.size();
         vals.push_back(v);
@@ -609,7 +813,8 @@ struct Builder {
 
 int default_part_size(int order, int n_diagrams, int n_roots);
 
-bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, Compiled& out, std::string& err) {
+bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, Compiled& out,
+             std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -618,11 +823,18 @@ bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, C
         err = "unknown derivative bits";
         return false;
     }
+    if (taylor_order < 0 || taylor_order > kMaxTaylor) {
+        err = "taylor_order must be in 0..6";
+        return false;
+    }
     out = Compiled{};
     out.order = order;
     out.dim = 4 * order - 1;
     out.deriv_mask = deriv_mask;
-    out.n_roots = 1 + __builtin_popcount(deriv_mask);
+    out.taylor_order = taylor_order;
+    const CoefSet cs = taylor_order > 0 ? CoefSet::taylor(deriv_mask, taylor_order) : CoefSet::first_order(deriv_mask);
+    out.root_orders = cs.idx;
+    out.n_roots = (int)cs.idx.size();
     out.diagrams = enumerate_sigma(order);
     if (diagram_index >= 0) {
         if (diagram_index >= (int)out.diagrams.size()) {
@@ -696,7 +908,8 @@ std::string kernel_name(const Compiled& c, int n_groups) {
     const int nd = (int)c.diagrams.size();
     const int np = c.part_size > 0 && nd > c.part_size ? (nd + c.part_size - 1) / c.part_size : 1;
     return "dmc_eval_o" + std::to_string(c.order) + "_g" + std::to_string(n_groups) + "_r" + std::to_string(c.n_roots) +
-           (nd == 1 ? "_single" : "") + (np > 1 ? "_p" + std::to_string(np) : "");
+           (c.taylor_order > 0 ? "_t" + std::to_string(c.taylor_order) : "") + (nd == 1 ? "_single" : "") +
+           (np > 1 ? "_p" + std::to_string(np) : "");
 }
 
 // Diagram parts of a partitioned kernel: diagrams sorted by root class and by the leaves that
@@ -754,10 +967,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     for (auto& d : c.diagrams) cls.push_back(d.ext_line());
     std::sort(cls.begin(), cls.end());
     cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
-    std::vector<int> dirs;
-    for (int i = 0; i < 3; ++i)
-        if (c.deriv_mask & (1u << i)) dirs.push_back(i);
-    const int NR = 1 + (int)dirs.size();
+    const int NR = c.n_roots;
     const auto parts = diagram_parts(c, c.part_size);
     const bool split = parts.size() > 1;
 
@@ -803,8 +1013,14 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                 std::string fr, fi;
                 for (size_t ri = 0; ri < pcls.size(); ++ri) {
                     int r = pcls[ri];
-                    std::string rv = ro == 0 ? roots[g][ri].name : roots[g][ri].d[dirs[ro - 1]];
+                    std::string rv = Emitter::cf(roots[g][ri], ro);
                     if (rv.empty()) continue;
+                    // Taylor coefficients become derivatives: times m! l!
+                    const auto& mo = c.root_orders[ro];
+                    double fac = 1.0;
+                    for (int i = 2; i <= mo[0]; ++i) fac *= i;
+                    for (int i = 2; i <= mo[1]; ++i) fac *= i;
+                    if (fac != 1.0) rv = b.em.def(roots[g][ri].kdep, fstr(fac) + " * " + rv, 1).name;
                     std::string pcn = "PC" + std::to_string(g) + "_" + std::to_string(r);
                     std::string psn = "PS" + std::to_string(g) + "_" + std::to_string(r);
                     if (fr.empty()) {

@@ -10,6 +10,7 @@
 namespace dmc {
 
 constexpr int kMaxOrder = 6;
+constexpr int kMaxTaylor = 6;  // highest total mu, lambda derivative order of a Taylor-mode graph
 
 // A line of a routed diagram.  mom[j] (j < n) is the coefficient of loop momentum q_j and
 // mom[n] the coefficient of the external k along the reference direction src -> dst.
@@ -49,7 +50,10 @@ struct Compiled {
     int order = 0, dim = 0, n_root_classes = 0;
     int n_momenta = 0, n_g_leaves = 0, n_v_leaves = 0, n_groups = 0;
     uint32_t deriv_mask = 0;
+    int taylor_order = 0;  // 0: first-order tangents along the masked directions; T >= 1: Taylor mode
     int n_roots = 1;
+    // per root, the coefficient it holds: d^m/dmu^m d^l/dlambda^l (d/dk)^e of the self-energy
+    std::vector<std::array<int, 3>> root_orders;
     int part_size = 0;  // diagrams per straight-line part; 0 = one part
     std::vector<Diagram> diagrams;
     CodeStats stats;
@@ -58,7 +62,10 @@ struct Compiled {
 // Builds the compiled description (diagram subset selection, IR statistics).
 // diagram_index < 0 keeps all diagrams.
 // part_size: diagrams per straight-line part of the kernel; 0 chooses by size.
-bool compile(int order, uint32_t deriv_mask, int diagram_index, int part_size, Compiled& out, std::string& err);
+// taylor_order T >= 1 builds every derivative d^m/dmu^m d^l/dlambda^l with m + l <= T along the masked
+// directions (mu bit 0, lambda bit 1), and with the k bit also the k derivative of each of them.
+bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, Compiled& out,
+             std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);

@@ -1,0 +1,96 @@
+"""GPU Taylor-mode roots (every d^m/dmu^m d^l/dlambda^l with m + l <= T, and their k derivatives) against
+the oracle's truncated series, the first-order mode, and the Fock closed forms."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2403_18840_amd as dmc
+import synth
+from oracle import physics as ph
+from oracle import taylor as ty
+
+from gpu_helpers import BETA, LAM, MU, gpu_integrand, torch_dev
+from golden_diagrams import oracle_diagrams
+
+pytestmark = pytest.mark.gpu
+ALL = dmc.D_MU | dmc.D_LAMBDA | dmc.D_K
+
+# Per-sample tolerance: the error of each FP32 coefficient against the sum over diagrams of its
+# magnitudes, scaled by the number of derivative steps (each G leaf's mu series is a recursion of
+# up to m + 1 terms, each V leaf's lambda series a chain of l products)
+TOL = 2e-5
+
+
+@pytest.mark.parametrize("n,T,N,K", [(1, 4, 600, 3), (2, 4, 400, 3), (3, 3, 250, 2), (4, 2, 96, 2)])
+def test_taylor_roots_per_sample(n, T, N, K):
+    """Orders 3 and 4 run the partitioned kernel (2 and 10 parts)."""
+    x = synth.loop_points(n, N, seed=700 + n)
+    ks = synth.k_grid(K)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, ALL, taylor_order=T)
+    orders = g.root_orders()
+    assert orders == ty.index_set(T, True, True, True)
+    f, _, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
+    x64 = x.astype(np.float64)
+    dgs = oracle_diagrams(n)
+    worst = {}
+    for j, k in enumerate(ks):
+        kk = float(np.float32(k))
+        ref = ty.derivative_roots(x64, n, kk, BETA, MU, LAM, gamma, T, True, True, True, diagrams=dgs)
+        scale = ty.derivative_scale(x64, n, kk, BETA, MU, LAM, gamma, T, True, True, True, diagrams=dgs)
+        for r, ((key, rv), (_, sc)) in enumerate(zip(ref, scale)):
+            err = np.abs(f[0, r, j] - rv)
+            steps = key[0] + key[1] + key[2] + 1
+            ok = err <= TOL * steps * sc + 1e-30
+            assert np.all(ok), f"root {key} k={k}: worst {np.max(err / (sc + 1e-300))}"
+            m = sc > 1e-30
+            if np.any(m):
+                worst[key] = max(worst.get(key, 0.0), float(np.max(err[m] / sc[m])))
+    print(f"order {n} T {T}: worst err/scale " + " ".join(f"{k}:{v:.1e}" for k, v in worst.items()))
+
+
+def test_first_order_taylor_mode_equals_tangent_mode():
+    n, N, K = 3, 300, 2
+    x = synth.loop_points(n, N, seed=811)
+    ks = synth.k_grid(K)
+    gamma = ph.coupling(2.0)
+    ft, _, _ = gpu_integrand(dmc.Graph(n, ALL, taylor_order=1), x, ks, [(BETA, MU, LAM, gamma)])
+    fl, _, _ = gpu_integrand(dmc.Graph(n, ALL), x, ks, [(BETA, MU, LAM, gamma)])
+    # Taylor roots (0,0,0) (1,0,0) (0,1,0) (0,0,1) ... are the tangent mode's four roots
+    x64 = x.astype(np.float64)
+    for j, k in enumerate(ks):
+        scale = ty.derivative_scale(x64, n, float(np.float32(k)), BETA, MU, LAM, gamma, 1, True, True, True,
+                                    diagrams=oracle_diagrams(n))
+        for r in range(4):
+            assert np.all(np.abs(ft[0, r, j] - fl[0, r, j]) <= 2e-5 * scale[r][1] + 1e-30), r
+
+
+def test_order1_taylor_estimates_match_fock_closed_forms():
+    torch, dev = torch_dev()
+    n, N, T = 1, 1 << 21, 3
+    ks = np.array([0.5, 1.0, 1.6], dtype=np.float32)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, dmc.D_MU | dmc.D_LAMBDA, taylor_order=T)
+    orders = g.root_orders()
+    s = dmc.Sampler(dmc.SAMPLER_UNIFORM, n)
+    X = torch.empty((3, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    acc = dmc.Accumulator(1, len(ks), g.n_roots)
+    m_sum = np.zeros((g.n_roots, len(ks)))
+    v_sum = np.zeros((g.n_roots, len(ks)))
+    reps = 4
+    for rep in range(reps):
+        acc.reset()
+        s.sample(91, rep * N, X, J)
+        dmc.eval_batch(g, [(BETA, MU, LAM, gamma)], ks, X, J, acc)
+        dmc.accumulate(acc)
+        m, e, _, _ = acc.estimate(1)
+        m_sum += m[0].real
+        v_sum += e[0].real ** 2
+    est, err = m_sum / reps, np.sqrt(v_sum) / reps
+    for r, (mm, ll, _) in enumerate(orders):
+        for j, k in enumerate(ks):
+            ref = ph.fock_taylor_finite_T(float(k), BETA, MU, LAM, gamma, mm, ll)
+            z = (est[r, j] - ref) / err[r, j]
+            assert abs(z) < 4.0, f"k={k} (m, l)=({mm}, {ll}): est {est[r, j]} ref {ref} z={z}"

@@ -125,3 +125,27 @@ def test_higher_and_mixed_coefficients_against_finite_differences(n):
     for key, ref in checks.items():
         err = np.abs(roots[key] - ref)
         assert np.all(err <= 2e-5 * scale[key] + 1e-12 * np.abs(ref)), (key, float((err / scale[key]).max()))
+
+
+def test_fock_taylor_closed_form_against_finite_differences():
+    # the 1D closed form for d^m/dmu^m d^l/dlambda^l of the Fock self-energy against finite differences of
+    # the value's own quadrature at shifted mu and lambda
+    k = 0.9
+    F = lambda dmu=0.0, dlam=0.0: ph.fock_finite_T(k, BETA, MU + dmu, LAM + dlam, GAMMA)
+    assert np.isclose(ph.fock_taylor_finite_T(k, BETA, MU, LAM, GAMMA, 0, 0), F(), rtol=1e-10)
+    d1 = ph.fock_derivs_finite_T(k, BETA, MU, LAM, GAMMA)
+    assert np.isclose(ph.fock_taylor_finite_T(k, BETA, MU, LAM, GAMMA, 1, 0), d1[0], rtol=1e-9)
+    assert np.isclose(ph.fock_taylor_finite_T(k, BETA, MU, LAM, GAMMA, 0, 1), d1[1], rtol=1e-9)
+    for (m, l), ref in {
+        (2, 0): _fd(lambda h: F(dmu=h), 2e-3, 2),
+        (3, 0): _fd(lambda h: F(dmu=h), 2e-3, 3),
+        (0, 2): _fd(lambda h: F(dlam=h), 2e-2, 2),
+        (0, 3): _fd(lambda h: F(dlam=h), 4e-2, 3),
+        (1, 1): _fd(lambda h: _fd(lambda g: F(dmu=g, dlam=h), 2e-3, 1), 2e-2, 1),
+    }.items():
+        got = ph.fock_taylor_finite_T(k, BETA, MU, LAM, GAMMA, m, l)
+        assert abs(got - ref) <= 1e-5 * abs(ref), (m, l, got, ref)
+    # P_m: the closed forms used in the per-leaf pin above
+    n = 0.3
+    assert np.isclose(ph.nF_mu_derivative_poly(2)(n), n * (1 - n) * (1 - 2 * n))
+    assert np.isclose(ph.nF_mu_derivative_poly(3)(n), n * (1 - n) * (1 - 6 * n + 6 * n * n))
