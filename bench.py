@@ -286,6 +286,26 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
     return out
 
 
+def effective_mass_leg(N, rs, lam_R, beta, log2_samples, batches):
+    """The renormalised m*/m series through total order N (Sec. VI.A): Taylor-mode graphs at each
+    order n <= N (every d^m/dmu^m d^l/dlambda^l with m + l <= N - n, and the k derivatives), VEGAS
+    at k_F, the counterterm recursion and the xi series in the library; jackknife errors over
+    independent batches.  Reports each order's partial sum with its error and the wall time."""
+    import torch
+
+    import paper_2403_18840_amd as dmc
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mp, me, dm, de = dmc.effective_mass_estimate(N, rs, lam_R, beta=beta, n_samples=1 << log2_samples,
+                                                 batches=batches)
+    torch.cuda.synchronize()
+    return {"order": N, "rs": rs, "lambda_R": lam_R, "beta": beta, "samples_per_batch": 1 << log2_samples,
+            "batches": batches, "mass_partial": [float(v) for v in mp], "mass_partial_err": [float(v) for v in me],
+            "delta_mu": [float(v) for v in dm], "delta_mu_err": [float(v) for v in de],
+            "seconds": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +326,12 @@ def main():
     ap.add_argument("--mcmc-steps", type=int, default=1024)
     ap.add_argument("--mcmc-thermal", type=int, default=2000)
     ap.add_argument("--mcmc-no-flow", action="store_true")
+    ap.add_argument("--mass-order", type=int, default=0,
+                    help="total order of the renormalised effective-mass series (0 skips it)")
+    ap.add_argument("--mass-rs", type=float, default=1.0)
+    ap.add_argument("--mass-lambda", type=float, default=1.0)
+    ap.add_argument("--mass-log2-samples", type=int, default=22)
+    ap.add_argument("--mass-batches", type=int, default=16)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -423,6 +449,9 @@ def main():
                                               steps=args.mcmc_steps, thermal=args.mcmc_thermal,
                                               flow=not args.mcmc_no_flow)
                                 for n in args.mcmc_orders.split(",")]
+    if args.mass_order:
+        out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, beta,
+                                                   args.mass_log2_samples, args.mass_batches)
     print(json.dumps(out), flush=True)
 
 

@@ -35,6 +35,7 @@ import numpy as np
 
 from . import diagrams as dg
 from . import integrand as ig
+from . import physics as ph
 
 
 def index_set(T: int, mu: bool = True, lam: bool = True, k: bool = False):
@@ -192,11 +193,55 @@ def derivative_roots(x, n, k, beta, mu, lam, gamma, T, use_mu=True, use_lam=True
     return out
 
 
+def _leaf_majorants(S, p2, dp2, tau, beta, lam, gamma, kind, mu):
+    """Positive series bounding the terms a leaf's own series adds up (the scale of an FP32 evaluation,
+    cancellation inside the leaf included): G: |G0| (tau' + beta)^m / m! (tau' + beta bounds the log-
+    derivatives of exp(-eps tau') and of 1 / (1 + exp(-beta eps)) together); V: r^(l+1), r = 1 / (p^2 + lam);
+    the k tangent of coefficient j: (j + 1) |coefficient j + 1| |d|p|^2/dk|."""
+    N = p2.shape[0]
+    out = {i: np.zeros(N) for i in S}
+    if kind == "G":
+        tp = np.where(tau > 0, tau, tau + beta)
+        g0 = np.abs(ph.G0(p2 - mu, tau, beta))
+        c = lambda m: g0 * (tp + beta) ** m / math.factorial(m)
+        for (m, l, e) in S:
+            if l:
+                continue
+            out[(m, l, e)] = c(m) if e == 0 else (m + 1) * c(m + 1) * np.abs(dp2)
+    else:
+        r = 1.0 / (p2 + lam)
+        c = lambda l: 8.0 * math.pi * gamma * r ** (l + 1)
+        for (m, l, e) in S:
+            if m:
+                continue
+            out[(m, l, e)] = c(l) if e == 0 else (l + 1) * c(l + 1) * np.abs(dp2)
+    return Series(S, out)
+
+
 def derivative_scale(x, n, k, beta, mu, lam, gamma, T, use_mu=True, use_lam=True, use_k=False, diagrams=None):
-    """The scale of each derivative root before cancellation between diagrams: sum over diagrams of
-    |m! l! c_d[m, l, e]| (the cancellation inside one diagram's leaves is not counted)."""
-    ser = diagram_series(x, n, k, beta, mu, lam, gamma, T, use_mu, use_lam, use_k, diagrams)
-    out = []
-    for i in index_set(T, use_mu, use_lam, use_k):
-        out.append((i, np.abs(ser[i]).sum(axis=0) * math.factorial(i[0]) * math.factorial(i[1])))
-    return out
+    """The scale against which an FP32 evaluation of each derivative root is judged: the sum over
+    diagrams of the product of the leaves' majorant series (_leaf_majorants) times |weight|, scaled to
+    derivatives (m! l!).  It bounds the magnitude of every term the evaluation adds, before cancellation
+    between diagrams and inside each leaf's series."""
+    if diagrams is None:
+        diagrams = dg.sigma_diagrams(n)
+    S = index_set(T, use_mu, use_lam, use_k)
+    q, taus = ig._unpack(x, n)
+    N = q.shape[0]
+    pref = (2 * math.pi) ** (-3 * n)
+    tot = {i: np.zeros(N) for i in S}
+    for d in diagrams:
+        val = Series.const(S, np.full(N, abs(d.weight) * pref))
+        for ln in d.lines:
+            p = ig.line_momentum(q, k, ln.mom)
+            p2 = np.sum(p * p, axis=1)
+            dp2 = 2.0 * ln.mom[n] * p[:, 2]
+            if ln.kind == "G":
+                a, b = ln.src // 2, ln.dst // 2
+                tau = np.zeros(N) if a == b else taus[:, b] - taus[:, a]
+            else:
+                tau = None
+            val = val * _leaf_majorants(S, p2, dp2, tau, beta, lam, gamma, ln.kind, mu)
+        for i in S:
+            tot[i] += val.c[i]
+    return [(i, tot[i] * math.factorial(i[0]) * math.factorial(i[1])) for i in S]

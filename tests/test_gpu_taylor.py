@@ -16,9 +16,10 @@ from golden_diagrams import oracle_diagrams
 pytestmark = pytest.mark.gpu
 ALL = dmc.D_MU | dmc.D_LAMBDA | dmc.D_K
 
-# Per-sample tolerance: the error of each FP32 coefficient against the sum over diagrams of its
-# magnitudes, scaled by the number of derivative steps (each G leaf's mu series is a recursion of
-# up to m + 1 terms, each V leaf's lambda series a chain of l products)
+# Per-sample tolerance: the error of each FP32 coefficient against the oracle's scale (the product of
+# the leaves' majorant series summed over diagrams: every term the evaluation adds, before cancellation
+# between diagrams and inside a leaf's own series), per derivative step.  FP32 rounding of an exponent
+# beta eps log2(e) of up to ~1200 alone gives a few 1e-5 of relative error in the deepest tails.
 TOL = 2e-5
 
 
@@ -43,7 +44,9 @@ def test_taylor_roots_per_sample(n, T, N, K):
             err = np.abs(f[0, r, j] - rv)
             steps = key[0] + key[1] + key[2] + 1
             ok = err <= TOL * steps * sc + 1e-30
-            assert np.all(ok), f"root {key} k={k}: worst {np.max(err / (sc + 1e-300))}"
+            if not np.all(ok):
+                i = int(np.argmax(np.where(ok, 0.0, err / (sc + 1e-300))))
+                raise AssertionError(f"root {key} k={k}: sample {i} gpu {f[0, r, j][i]} oracle {rv[i]} scale {sc[i]}")
             m = sc > 1e-30
             if np.any(m):
                 worst[key] = max(worst.get(key, 0.0), float(np.max(err[m] / sc[m])))
