@@ -241,20 +241,29 @@ void dmc_flow_destroy(dmc_flow* f);
  * DMC_MAX_CHAIN_BATCHES)] or an observable shape outside the accumulator's limits. */
 #define DMC_MAX_CHAIN_BATCHES 4096
 typedef struct dmc_chains dmc_chains;
+/* dim_u > 0 (at most 4 DMC_MAX_ORDER - 1): each chain also keeps its state's coordinates (dim_u floats,
+ * e.g. the grid coordinates u' that dmc_flow_sample writes), for dmc_chains_training_data. */
 dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
-                             dmc_chains** out);
-/* One step of every chain: chain c takes proposal (c + offset) mod n (columns of f_prop, entries of
- * jac_prop), 0 <= offset < n.  Draw offset uniformly and afresh every step: a sampler that lays its
+                             int32_t dim_u, dmc_chains** out);
+/* One step of every chain: chain c takes proposal (c + offset) mod n (columns of f_prop and u_prop,
+ * entries of jac_prop), 0 <= offset < n; u_prop (device float[dim_u][ld_u], ld_u >= n) is required when the
+ * chains keep coordinates and ignored otherwise.  Draw offset uniformly and afresh every step: a sampler that lays its
  * proposals out by index (dmc_flow_sample puts each mixture component's share in one index range)
  * then still hands every chain a draw from its full density q, which the acceptance test assumes.
  * measure != 0 accumulates the chains' states after the step. */
-dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, int64_t offset,
-                           double alpha, uint64_t seed, int32_t measure, void* stream);
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* u_prop,
+                           int64_t ld_u, int64_t offset, double alpha, uint64_t seed, int32_t measure, void* stream);
 /* sums: host double[n_batches][S + 1][2], S = n_groups n_roots n_k 2 slots in the f_out order, per batch:
  * [b][s][0] = sum f_s/pi, [b][s][1] = sum (f_s/pi)^2; row S: sum q/pi and its squares.  n_measured: chain
  * states added (all batches);
  * n_accepted: proposals taken since the last reset.  Synchronises `stream`. */
 dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream);
+/* The chain states as training data for a proposal density (Appendix A: samples that represent |f|,
+ * generated by MCMC): u (device float[dim_u][ld], ld >= n) receives the states' coordinates and w
+ * (device float[n]) the weights p / pi, p = sum of |f| over root 0's slots (w = 1 at alpha = 0, where the
+ * chains sample |f| itself; 0 for a chain without a valid state).  Feed them to dmc_flow_train_step.
+ * DMC_E_STATE before the first step. */
+dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* w, void* stream);
 /* Zero the sums and the accepted count (the chain states are kept). */
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
 void dmc_chains_destroy(dmc_chains* c);

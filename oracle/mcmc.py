@@ -33,16 +33,19 @@ def uniforms(seed: int, step: int, n: int):
     return ((w >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
 
 
-def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots, offset=0):
+def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots, offset=0, u_prop=None):
     """One Metropolis-Hastings step of every chain.  state: dict f [S][n] (float32 values), q, pi
-    [n] float64, or None before the first step.  f_prop [S][n] float32, jac_prop [n] float32; chain c
-    proposes column (c + offset) mod n (a uniform offset per step makes every chain's proposal a
-    draw from the whole proposal density when the sampler orders its draws by mixture component).
+    [n] float64 (and u [D][n] float32 when proposals carry coordinates), or None before the first step.
+    f_prop [S][n] float32, jac_prop [n] float32, u_prop [D][n] float32 or None; chain c proposes column
+    (c + offset) mod n (a uniform offset per step makes every chain's proposal a draw from the whole
+    proposal density when the sampler orders its draws by mixture component).
     Returns (new state, taken [n] bool)."""
     n = np.asarray(f_prop).shape[1]
     cols = (np.arange(n) + offset) % n
     f_prop = np.asarray(f_prop, dtype=np.float32)[:, cols]
     jac_prop = np.asarray(jac_prop)[cols]
+    if u_prop is not None:
+        u_prop = np.asarray(u_prop, dtype=np.float32)[:, cols]
     p = np.zeros(n)
     for s in root0_slots:
         p = p + np.abs(f_prop[s].astype(np.float64))
@@ -62,12 +65,29 @@ def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots, offset=0
     take = vp & (~vs | test)
     if state is None:
         new = {"f": np.zeros_like(f_prop), "q": np.zeros(n), "pi": np.zeros(n)}
+        if u_prop is not None:
+            new["u"] = np.zeros_like(u_prop)
     else:
         new = {k: v.copy() for k, v in state.items()}
+    if u_prop is not None:
+        new["u"][:, take] = u_prop[:, take]
     new["f"][:, take] = f_prop[:, take]
     new["q"][take] = qp[take]
     new["pi"][take] = pip[take]
     return new, take
+
+
+def training_data(state, root0_slots):
+    """The chains' states as forward-KL training data for a proposal density (Appendix A: samples that
+    represent |f|): the coordinates u [D][n] and weights w = p / pi [n], p = sum of |f| over the root-0
+    slots (so w = 1 at alpha = 0: the chains sample |f| itself); 0 for a chain without a valid state."""
+    pi = state["pi"]
+    p = np.zeros(len(pi))
+    for s in root0_slots:
+        p = p + np.abs(state["f"][s].astype(np.float64))
+    ok = pi > 0
+    w = np.where(ok, p / np.where(ok, pi, 1.0), 0.0)
+    return state["u"].copy(), w
 
 
 def batch_bounds(n: int, n_batches: int):

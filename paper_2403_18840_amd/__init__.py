@@ -29,6 +29,7 @@ ABI_SYMBOLS = [
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
     "dmc_chains_create", "dmc_chains_step", "dmc_chains_read", "dmc_chains_reset", "dmc_chains_destroy",
+    "dmc_chains_training_data",
     "dmc_effective_mass",
 ]
 
@@ -110,8 +111,9 @@ def lib():
         "dmc_flow_log_density": (I32, [P, P, I64, I64, P, P]),
         "dmc_flow_train_step": (I32, [P, P, I64, U64, U64, I64, P, F64, P, ctypes.POINTER(F64), P]),
         "dmc_flow_destroy": (None, [P]),
-        "dmc_chains_create": (I32, [I64, I32, I32, I32, I32, ctypes.POINTER(P)]),
-        "dmc_chains_step": (I32, [P, P, I64, P, I64, F64, U64, I32, P]),
+        "dmc_chains_create": (I32, [I64, I32, I32, I32, I32, I32, ctypes.POINTER(P)]),
+        "dmc_chains_step": (I32, [P, P, I64, P, P, I64, I64, F64, U64, I32, P]),
+        "dmc_chains_training_data": (I32, [P, P, I64, P, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
         "dmc_chains_destroy": (None, [P]),
@@ -520,23 +522,38 @@ class Chains:
     """Independent-proposal Markov chains, one per sample lane (dmc_chains_*), their sums kept per chain
     batch (batch b: chains [b n // n_batches, (b + 1) n // n_batches))."""
 
-    def __init__(self, n: int, n_groups: int, n_k: int, n_roots: int = 1, n_batches: int = 1):
+    def __init__(self, n: int, n_groups: int, n_k: int, n_roots: int = 1, n_batches: int = 1, dim_u: int = 0):
         self.h = P()
-        _check(lib().dmc_chains_create(n, n_batches, n_groups, n_k, n_roots, ctypes.byref(self.h)))
+        _check(lib().dmc_chains_create(n, n_batches, n_groups, n_k, n_roots, dim_u, ctypes.byref(self.h)))
         self.n, self.n_groups, self.n_k, self.n_roots, self.n_batches = n, n_groups, n_k, n_roots, n_batches
+        self.dim_u = dim_u
         self.S = n_groups * n_roots * n_k * 2
 
-    def step(self, f_prop, jac_prop, alpha: float, seed: int, offset: int = 0, measure: bool = True, stream=None):
+    def step(self, f_prop, jac_prop, alpha: float, seed: int, offset: int = 0, measure: bool = True, u_prop=None,
+             stream=None):
         """f_prop: the f_out capture of eval_batch at the proposals (flat [G][R][K][2][ld]); jac_prop: 1/q;
-        chain c takes proposal (c + offset) mod n."""
+        u_prop: [dim_u][ld_u] coordinates (chains that keep them); chain c takes proposal (c + offset) mod n."""
+        if self.dim_u and (u_prop is None or u_prop.dim() != 2 or u_prop.shape[0] != self.dim_u
+                           or u_prop.shape[1] < self.n):
+            raise ValueError(f"u_prop must be [{self.dim_u}][>= {self.n}]")
         ld = f_prop.numel() // self.S
         if f_prop.numel() != ld * self.S or ld < self.n:
             raise ValueError(f"f_prop must hold [{self.S}][ld >= {self.n}] values, got {f_prop.numel()}")
         if jac_prop.numel() < self.n:
             raise ValueError(f"jac_prop must hold at least {self.n} values")
         _check(lib().dmc_chains_step(self.h, _dptr(f_prop, "float32", "f_prop"), ld,
-                                     _dptr(jac_prop, "float32", "jac_prop"), offset, alpha, seed,
+                                     _dptr(jac_prop, "float32", "jac_prop"), _dptr(u_prop, "float32", "u_prop"),
+                                     u_prop.shape[1] if u_prop is not None else 0, offset, alpha, seed,
                                      1 if measure else 0, _stream(stream)))
+
+    def training_data(self, u_out, w_out, stream=None):
+        """States as forward-KL training data: u_out [dim_u][>= n] coordinates, w_out [n] = p / pi."""
+        if w_out.numel() < self.n or (self.dim_u and (u_out.dim() != 2 or u_out.shape[0] != self.dim_u
+                                                      or u_out.shape[1] < self.n)):
+            raise ValueError("u_out must be [dim_u][>= n] and w_out hold n values")
+        _check(lib().dmc_chains_training_data(self.h, _dptr(u_out, "float32", "u_out"),
+                                              u_out.shape[1] if u_out is not None else 0,
+                                              _dptr(w_out, "float32", "w_out"), _stream(stream)))
 
     def read(self, stream=None):
         """(sums [n_batches][S + 1][2] float64, states measured, proposals accepted)."""
@@ -725,3 +742,53 @@ def effective_mass_estimate(N: int, rs: float, lambda_R: float, **kw):
         v = np.array([j[name] for j in jk])
         err[name] = np.sqrt((B - 1) / B * np.sum((v - v.mean(axis=0)) ** 2, axis=0))
     return full["mass_partial"], err["mass_partial"], full["delta_mu"], err["delta_mu"]
+
+
+
+def train_flow_mcmc(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", rounds: int = 4,
+                    n_chains: int = 1 << 17, thermal: int = 200, collect: int = 8, stride: int = 10,
+                    steps: int = 64, lr: float = 1e-3, alpha: float = 0.0, flow_alpha: float = 0.85,
+                    flow_uniform: float = 0.05, seed: int = 11):
+    """Fit `flow` to |f| on samples generated by Markov chains (Appendix A's MCMC training data).
+
+    Every round starts fresh chains whose independent proposals come from the current flow's mixture
+    (the flow changes between rounds, so old states would carry a stale proposal density), targets
+    pi = alpha q + (1 - alpha)|f|, discards `thermal` steps, then collects the states `collect` times
+    every `stride` steps as points u' with weights p / pi (1 at alpha = 0).  `steps` Adam steps of the
+    weighted forward KL follow, cycling through the collected sets.  Returns the mean loss of each round."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    D = dim(graph.order)
+    if flow.dim != D:
+        raise ValueError("flow dimension does not match the graph's order")
+    ks = np.asarray(k_ext, dtype=np.float32)
+    G, K, R = _n_groups(inst), len(ks), graph.n_roots
+    acc = Accumulator(G, K, R)
+    X = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+    J = torch.empty(n_chains, dtype=torch.float32, device=dev)
+    U = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+    F = torch.empty(G * R * K * 2 * n_chains, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng([seed, 0x7A1])
+    losses = []
+    first = 0
+    for r in range(rounds):
+        ch = Chains(n_chains, G, K, R, 1, D)
+        sets = []
+        for t in range(thermal + collect * stride):
+            flow.sample(sampler, seed, first, X, J, u_out=U, alpha=flow_alpha, uniform=flow_uniform)
+            first += n_chains
+            eval_batch(graph, inst, ks, X, J, acc, f_out=F)
+            acc.reset()
+            ch.step(F, J, alpha, seed + 0x5EED + r, offset=int(rng.integers(n_chains)), measure=False, u_prop=U)
+            if t >= thermal and (t - thermal) % stride == stride - 1:
+                Uc = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+                Wc = torch.empty(n_chains, dtype=torch.float32, device=dev)
+                ch.training_data(Uc, Wc)
+                sets.append((Uc, Wc))
+        ls = []
+        for s_ in range(steps):
+            Uc, Wc = sets[s_ % len(sets)]
+            ls.append(flow.train_step(Wc, u=Uc, lr=lr, want_loss=(s_ % len(sets) == len(sets) - 1)))
+        losses.append(float(np.mean([v for v in ls if v is not None])))
+    return losses

@@ -1048,8 +1048,9 @@ void dmc_flow_destroy(dmc_flow* f) {
 
 struct dmc_chains {
     int64_t n = 0;
-    int n_batches = 0, n_groups = 0, n_k = 0, n_roots = 0, S = 0;
+    int n_batches = 0, n_groups = 0, n_k = 0, n_roots = 0, S = 0, D = 0;
     float* f_state = nullptr;     // device [S][n]
+    float* u_state = nullptr;     // device [D][n] (D > 0)
     double* q_state = nullptr;    // device [n]
     double* pi_state = nullptr;   // device [n]
     double* partial = nullptr;    // device [nblk][n_batches][S + 1][2]
@@ -1065,12 +1066,13 @@ struct dmc_chains {
 extern "C" {
 
 dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int32_t n_k, int32_t n_roots,
-                             dmc_chains** out) {
+                             int32_t dim_u, dmc_chains** out) {
     if (!out || n < 1 || n_groups < 1 || n_groups > DMC_MAX_GROUPS || n_k < 1 || n_k > DMC_MAX_K || n_roots < 1 ||
         n_roots > DMC_MAX_ROOTS)
         return fail(DMC_E_INVALID, "chain count or observable shape out of range");
     if (n_batches < 1 || n_batches > DMC_MAX_CHAIN_BATCHES || n_batches > n)
         return fail(DMC_E_INVALID, "n_batches must be in [1, min(n, DMC_MAX_CHAIN_BATCHES)]");
+    if (dim_u < 0 || dim_u > 4 * DMC_MAX_ORDER - 1) return fail(DMC_E_INVALID, "dim_u must be in 0..4 DMC_MAX_ORDER - 1");
     auto c = std::make_unique<dmc_chains>();
     c->n = n;
     c->n_batches = n_batches;
@@ -1080,6 +1082,8 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
     c->S = n_groups * n_roots * n_k * 2;
     c->nblk = dmc::mcmc_acc_blocks((n + n_batches - 1) / n_batches, &c->chunk);
     HIP_ALLOC(hipMalloc(&c->f_state, sizeof(float) * (size_t)c->S * n));
+    c->D = dim_u;
+    if (dim_u > 0) HIP_ALLOC(hipMalloc(&c->u_state, sizeof(float) * (size_t)dim_u * n));
     HIP_ALLOC(hipMalloc(&c->q_state, sizeof(double) * (size_t)n));
     HIP_ALLOC(hipMalloc(&c->pi_state, sizeof(double) * (size_t)n));
     HIP_ALLOC(hipMalloc(&c->partial, sizeof(double) * (size_t)c->nblk * c->totals_len()));
@@ -1095,10 +1099,12 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
     return DMC_OK;
 }
 
-dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, int64_t offset,
-                           double alpha, uint64_t seed, int32_t measure, void* stream) {
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* u_prop,
+                           int64_t ld_u, int64_t offset, double alpha, uint64_t seed, int32_t measure, void* stream) {
     if (!c || !f_prop || !jac_prop) return fail(DMC_E_INVALID, "null argument");
     if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (c->D > 0 && (!u_prop || ld_u < c->n))
+        return fail(DMC_E_INVALID, "chains that keep coordinates need u_prop with ld_u >= the chain count");
     if (offset < 0 || offset >= c->n) return fail(DMC_E_INVALID, "offset must be in [0, n)");
     if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
     dmc::McmcArgs a;
@@ -1111,6 +1117,10 @@ dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const
     a.ld_prop = ld;
     a.jac_prop = jac_prop;
     a.offset = offset;
+    a.D = c->D;
+    a.u_prop = u_prop;
+    a.ld_u = ld_u;
+    a.u_state = c->u_state;
     a.f_state = c->f_state;
     a.q_state = c->q_state;
     a.pi_state = c->pi_state;
@@ -1150,6 +1160,27 @@ dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int
     return DMC_OK;
 }
 
+dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* w, void* stream) {
+    if (!c || !w || (c->D > 0 && !u)) return fail(DMC_E_INVALID, "null argument");
+    if (c->D > 0 && ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (c->steps == 0) return fail(DMC_E_STATE, "the chains have no state yet");
+    dmc::McmcTrainArgs a;
+    a.n = c->n;
+    a.S = c->S;
+    a.R = c->n_roots;
+    a.K = c->n_k;
+    a.G = c->n_groups;
+    a.D = c->D;
+    a.f_state = c->f_state;
+    a.pi_state = c->pi_state;
+    a.u_state = c->u_state;
+    a.u_out = u;
+    a.ld_out = ld;
+    a.w_out = w;
+    HIP_TRY(dmc::launch_mcmc_training(a, cu_count(), S(stream)));
+    return DMC_OK;
+}
+
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream) {
     if (!c) return fail(DMC_E_INVALID, "null argument");
     HIP_TRY(hipMemsetAsync(c->totals, 0, sizeof(double) * c->totals_len(), S(stream)));
@@ -1161,6 +1192,7 @@ dmc_status dmc_chains_reset(dmc_chains* c, void* stream) {
 void dmc_chains_destroy(dmc_chains* c) {
     if (!c) return;
     (void)hipFree(c->f_state);
+    (void)hipFree(c->u_state);
     (void)hipFree(c->q_state);
     (void)hipFree(c->pi_state);
     (void)hipFree(c->partial);

@@ -8,7 +8,9 @@
 // The target is pi = alpha q + (1 - alpha) p with p = |f| summed over the root-0 observables
 // (every lambda group, external momentum, Re and Im).  A chain's state needs no coordinates (the
 // next proposal does not depend on it): only the integrand values f, q and pi at its point.
-//   dmc_mcmc_accept_kernel      Metropolis-Hastings test (FP64), state update, accepted count
+//   dmc_mcmc_accept_kernel      Metropolis-Hastings test (FP64), state update (values and, when kept,
+//                               the proposal's coordinates), accepted count
+//   dmc_mcmc_training_kernel    the states as forward-KL training data: coordinates and w = p / pi
 //   dmc_mcmc_accumulate_kernel  per block, sums over its chains of f/pi per slot and of q/pi,
 //                               with their squares (FP64, fixed order); the chains fall into
 //                               independent batches, each block within one batch, and the partials
@@ -72,6 +74,7 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accept_kernel(McmcArgs a) {
         }
         if (take) {
             for (int s = 0; s < a.S; ++s) a.f_state[(int64_t)s * a.n + c] = a.f_prop[(int64_t)s * a.ld_prop + col];
+            for (int d = 0; d < a.D; ++d) a.u_state[(int64_t)d * a.n + c] = a.u_prop[(int64_t)d * a.ld_u + col];
             a.q_state[c] = qp;
             a.pi_state[c] = pip;
             ++acc;
@@ -113,6 +116,27 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accumulate_kernel(McmcAccArgs a)
         a.partial[o] = r1[0];
         a.partial[o + 1] = r2[0];
     }
+}
+
+// w = p / pi with p = sum of |f| over the root-0 slots of the state (0 without a valid state), and a copy
+// of the state's coordinates
+__global__ void __launch_bounds__(256) dmc_mcmc_training_kernel(McmcTrainArgs a) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.n; c += (int64_t)gridDim.x * blockDim.x) {
+        double p = 0.0;
+        for (int g = 0; g < a.G; ++g)
+            for (int s = g * a.R * a.K * 2; s < (g * a.R + 1) * a.K * 2; ++s)
+                p += fabs((double)a.f_state[(int64_t)s * a.n + c]);
+        const double pi = a.pi_state[c];
+        a.w_out[c] = pi > 0.0 && __builtin_isfinite(pi) ? (float)(p / pi) : 0.0f;
+        for (int d = 0; d < a.D; ++d) a.u_out[(int64_t)d * a.ld_out + c] = a.u_state[(int64_t)d * a.n + c];
+    }
+}
+
+hipError_t launch_mcmc_training(const McmcTrainArgs& a, int n_cu, hipStream_t st) {
+    const int64_t want = (a.n + 255) / 256;
+    const int64_t cap = (int64_t)n_cu * 8;
+    hipLaunchKernelGGL(dmc_mcmc_training_kernel, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_mcmc_accept(const McmcArgs& a, int n_cu, hipStream_t st) {

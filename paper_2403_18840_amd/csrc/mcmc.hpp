@@ -16,6 +16,10 @@ struct McmcArgs {
     int64_t ld_prop;
     const float* jac_prop;    // [n]: 1 / q at the proposals
     int64_t offset;           // chain c takes proposal (c + offset) mod n, 0 <= offset < n
+    int D;                    // coordinates kept per chain (0: none)
+    const float* u_prop;      // [D][ld_u]: the proposals' coordinates (when D > 0)
+    int64_t ld_u;
+    float* u_state;           // [D][n]
     float* f_state;           // [S][n]
     double* q_state;          // [n]
     double* pi_state;         // [n]
@@ -37,6 +41,18 @@ struct McmcAccArgs {
 };
 
 hipError_t launch_mcmc_accept(const McmcArgs& a, int n_cu, hipStream_t st);
+
+struct McmcTrainArgs {
+    int64_t n;
+    int S, R, K, G, D;
+    const float* f_state;     // [S][n]
+    const double* pi_state;   // [n]
+    const float* u_state;     // [D][n]
+    float* u_out;             // [D][ld_out]
+    int64_t ld_out;
+    float* w_out;             // [n]
+};
+hipError_t launch_mcmc_training(const McmcTrainArgs& a, int n_cu, hipStream_t st);
 // blocks per chain batch (each block sums `chunk` chains of one batch) for batches of at most n chains
 int mcmc_acc_blocks(int64_t n, int* chunk);
 hipError_t launch_mcmc_accumulate(const McmcAccArgs& a, int blocks_per_batch, hipStream_t st);

@@ -133,3 +133,26 @@ def test_invalid_proposals_are_never_taken():
     # a chain without a valid state takes its next valid proposal
     state, take = mcmc.step(state, np.ones((1, 4), dtype=np.float32), np.ones(4, dtype=np.float32), 0.5, 1, 1, [0])
     assert take[1] and take[2]
+
+
+def test_chains_carry_coordinates_and_training_weights():
+    # the state's coordinates follow the taken proposals; at alpha = 0 every valid chain weighs 1
+    rng = np.random.default_rng(6)
+    n, D = 64, 3
+    f = rng.normal(size=(2, n)).astype(np.float32)
+    jac = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    u = rng.uniform(size=(D, n)).astype(np.float32)
+    state, take = mcmc.step(None, f, jac, 0.0, 1, 0, [0, 1], offset=5, u_prop=u)
+    assert np.array_equal(state["u"], np.roll(u, -5, axis=1))
+    f2 = rng.normal(size=(2, n)).astype(np.float32)
+    u2 = rng.uniform(size=(D, n)).astype(np.float32)
+    state2, take2 = mcmc.step(state, f2, jac, 0.0, 1, 1, [0, 1], u_prop=u2)
+    assert 0 < take2.sum() < n
+    assert np.array_equal(state2["u"][:, take2], u2[:, take2])
+    assert np.array_equal(state2["u"][:, ~take2], state["u"][:, ~take2])
+    uu, w = mcmc.training_data(state2, [0, 1])
+    assert np.allclose(w, 1.0)
+    s3, _ = mcmc.step(state2, f2, jac, 0.6, 1, 2, [0, 1], u_prop=u2)
+    _, w3 = mcmc.training_data(s3, [0, 1])
+    p = np.abs(s3["f"].astype(np.float64)).sum(axis=0)
+    assert np.allclose(w3, p / s3["pi"])
