@@ -93,7 +93,7 @@ def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma):
             "sample": "; ".join(desc) + " (numpy FP64, one thread; rate combined with equal samples per order)"}
 
 
-def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004):
+def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004, train="is"):
     """Learned proposal at one order: Re Sigma(k_F, i omega_0) from `batches` independent batches of N
     samples drawn from the adapted VEGAS grid alone and from the trained flow's defensive mixture
     (0.85 flow + 0.10 grid + 0.05 uniform), each with its wall time (GPU-synchronised).  sigma is the
@@ -101,7 +101,9 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     in-run sample sigma understates the error (both are reported), and a few batches can dominate
     the scatter, so the robust spread (1.4826 x the median absolute deviation of the batch means)
     is reported beside it.  Efficiency = (sigma_V^2 T_V) / (sigma_F^2 T_F), without and with
-    adaptation + training time."""
+    adaptation + training time.  train = "is": the flow learns from importance-weighted draws of the
+    grid and then of its own mixture (train_flow); "mcmc": from Markov-chain samples of |f| with
+    proposals from its mixture (train_flow_mcmc), with the same number of Adam steps."""
     import numpy as np
     import torch
 
@@ -150,8 +152,13 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     f = dmc.Flow(D, masks)
     f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
     epochs, steps, mb = 4, 64, 1 << 17
-    losses, t_train = timed(lambda: dmc.train_flow(g, inst, ks, s, f, epochs=epochs, steps=steps, minibatch=mb,
-                                                    lr=1e-3, alpha=a_f, uniform=a_u, seed=seed + 2))
+    if train == "mcmc":
+        losses, t_train = timed(lambda: dmc.train_flow_mcmc(g, inst, ks, s, f, rounds=epochs, n_chains=mb, thermal=200,
+                                                             collect=8, stride=10, steps=steps, lr=1e-3,
+                                                             flow_alpha=a_f, flow_uniform=a_u, seed=seed + 2))
+    else:
+        losses, t_train = timed(lambda: dmc.train_flow(g, inst, ks, s, f, epochs=epochs, steps=steps, minibatch=mb,
+                                                        lr=1e-3, alpha=a_f, uniform=a_u, seed=seed + 2))
     fl, t_f = timed(lambda: run(lambda b: f.sample(s, seed + 3, b * N, X, J, alpha=a_f, uniform=a_u)))
     # the sampler kernel alone (all N samples through the flow), HIP events on its stream
     stream = torch.cuda.current_stream()
@@ -166,7 +173,8 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     ev, ef = vg["sigma"], fl["sigma"]
     vg["seconds"] = t_v
     fl.update({"seconds": t_f, "layers": 8, "width": 128, "mixture": {"flow": a_f, "grid": 1 - a_f - a_u, "uniform": a_u},
-               "training": {"samples": epochs * steps * mb, "seconds": t_train, "loss": [float(x) for x in losses]}})
+               "training": {"kind": train, "adam_steps": epochs * steps, "minibatch": mb, "seconds": t_train,
+                            "loss": [float(x) for x in losses]}})
     return {
         "order": order, "k": float(ks[jf]), "samples_per_batch": N, "batches": batches,
         "vegas": vg, "flow": fl, "adapt_seconds": t_adapt,
@@ -320,6 +328,8 @@ def main():
                     help="order of the learned-proposal comparison (0 skips it)")
     ap.add_argument("--flow-batches", type=int, default=64)
     ap.add_argument("--flow-log2-samples", type=int, default=22)
+    ap.add_argument("--flow-train", choices=["is", "mcmc"], default="is",
+                    help="training data of the flow: importance-weighted draws or Markov-chain samples of |f|")
     ap.add_argument("--mcmc-orders", default="2",
                     help="orders of the Markov-chain vs VEGAS comparison, comma-separated (empty skips it)")
     ap.add_argument("--mcmc-log2-chains", type=int, default=16)
@@ -443,7 +453,7 @@ def main():
                        "im_err": float(last[1][0, 0, j].imag)}
     if args.flow_order:
         out["flow_vs_vegas"] = flow_vs_vegas(args.flow_order, K, 1 << args.flow_log2_samples, args.flow_batches, beta, mu,
-                                             lam, inst[0][3])
+                                             lam, inst[0][3], train=args.flow_train)
     if args.mcmc_orders:
         out["mcmc_vs_vegas"] = [mcmc_vs_vegas(int(n), beta, mu, lam, inst[0][3], n_chains=1 << args.mcmc_log2_chains,
                                               steps=args.mcmc_steps, thermal=args.mcmc_thermal,

@@ -191,6 +191,17 @@ dmc_status dmc_accum_read(dmc_accum* acc, double* sums, int64_t* n_samples, void
  * s_hat_b = output b, t_b = output 16 + b. */
 typedef struct dmc_flow dmc_flow;
 dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, dmc_flow** out);
+/* The paper's flow (Appendix A): coupling layers whose transformed coordinates go through monotonic
+ * rational-quadratic splines with 8 bins on [0, 1], parameters from a residual network with two hidden
+ * layers of 32 ReLU units (a1 = relu(W1 z_A + b1), a2 = relu(W2 a1 + b2) + a1, theta = W3 a2 + b3), and a
+ * uniform base on [0, 1]^dim.  Spline parameters of a transformed coordinate: 8 width logits, 8 height
+ * logits, 7 interior derivative logits; widths and heights 1e-3 + (1 - 8e-3) softmax, interior derivatives
+ * 1e-3 + softplus, boundary derivatives 1.  Parameters: one FP32 vector, per layer W1 [32][dA], b1 [32],
+ * W2 [32][32], b2 [32], W3 [23 dB][32], b3 [23 dB] (row-major; dA, dB: the layer's kept and transformed
+ * counts), layers in order.  Created as the identity flow: output layer zero, hidden weights He-normal
+ * from a fixed seed (so that every weight receives a gradient).  Every dmc_flow_* call below accepts it; its
+ * sampling, density and training run in FP32 on the vector units. */
+dmc_status dmc_flow_create_spline(int32_t dim, int32_t n_layers, const int8_t* masks, dmc_flow** out);
 dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n_params);
 dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream);  /* also resets Adam state */
 dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream);

@@ -26,7 +26,7 @@ ABI_SYMBOLS = [
     "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
-    "dmc_accum_read", "dmc_flow_create", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
+    "dmc_accum_read", "dmc_flow_create", "dmc_flow_create_spline", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
     "dmc_chains_create", "dmc_chains_step", "dmc_chains_read", "dmc_chains_reset", "dmc_chains_destroy",
     "dmc_chains_training_data",
@@ -104,6 +104,7 @@ def lib():
         "dmc_estimate": (I32, [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_accum_read": (I32, [P, P, ctypes.POINTER(I64), P]),
         "dmc_flow_create": (I32, [I32, I32, P, ctypes.POINTER(P)]),
+        "dmc_flow_create_spline": (I32, [I32, I32, P, ctypes.POINTER(P)]),
         "dmc_flow_param_count": (I32, [P, ctypes.POINTER(I64)]),
         "dmc_flow_set_params": (I32, [P, P, P]),
         "dmc_flow_get_params": (I32, [P, P, P]),
@@ -465,14 +466,19 @@ def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int 
 
 
 class Flow:
-    """Affine-coupling flow on the VEGAS coordinates (dmc_flow_*)."""
+    """Coupling flow on the VEGAS coordinates (dmc_flow_*): kind "affine" (dmc_flow_create: affine couplings,
+    BF16 matrix cores) or "spline" (dmc_flow_create_spline: the paper's rational-quadratic spline couplings,
+    uniform base)."""
 
-    def __init__(self, dim_: int, masks):
+    def __init__(self, dim_: int, masks, kind: str = "affine"):
         import numpy as np
         m = np.ascontiguousarray(masks, dtype=np.int8)
         self.h = P()
-        _check(lib().dmc_flow_create(dim_, m.shape[0], m.ctypes.data_as(P), ctypes.byref(self.h)))
-        self.dim, self.n_layers, self.masks = dim_, m.shape[0], m
+        if kind not in ("affine", "spline"):
+            raise ValueError("kind must be 'affine' or 'spline'")
+        create = lib().dmc_flow_create if kind == "affine" else lib().dmc_flow_create_spline
+        _check(create(dim_, m.shape[0], m.ctypes.data_as(P), ctypes.byref(self.h)))
+        self.dim, self.n_layers, self.masks, self.kind = dim_, m.shape[0], m, kind
         n = I64()
         _check(lib().dmc_flow_param_count(self.h, ctypes.byref(n)))
         self.n_params = n.value

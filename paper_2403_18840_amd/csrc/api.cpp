@@ -21,6 +21,7 @@
 #include "flow.hpp"
 #include "kernels.hpp"
 #include "mcmc.hpp"
+#include "nsf.hpp"
 
 namespace {
 
@@ -693,9 +694,32 @@ struct dmc_flow {
     double* sums = nullptr;
     float* mix_buf = nullptr;  // mixture scratch: log q, J_V, u' of the uniform share
     int64_t mix_cap = 0;
+    // kind 1: rational-quadratic spline couplings (FP32 parameters in `master`, no shadow)
+    int kind = 0;
+    int64_t n_params = 0;
+    int max_layer_floats = 0;
+    std::vector<int> offs_h, dA_h, aidx_h, bidx_h;  // [L], [L], [L][NSF_MAXD], [L][NSF_MAXD]
+    int* d_offs = nullptr;
+    float* s_grad = nullptr;   // [n_params]
+    float* s_zs = nullptr;     // [L + 1][D][cap]
+    float* s_adj = nullptr;    // [D][cap]
+    float* s_vec = nullptr;    // per-sample vectors of one layer's reverse step
+    float* s_partial = nullptr;
+    float* s_lq = nullptr;     // [cap]
+    int64_t s_cap = 0;
 };
 
 namespace {
+void free_spline_train(dmc_flow* f) {
+    (void)hipFree(f->s_zs);
+    (void)hipFree(f->s_adj);
+    (void)hipFree(f->s_vec);
+    (void)hipFree(f->s_partial);
+    (void)hipFree(f->s_lq);
+    f->s_zs = f->s_adj = f->s_vec = f->s_partial = f->s_lq = nullptr;
+    f->s_cap = 0;
+}
+
 void free_train(dmc_flow* f) {
     (void)hipFree(f->states);
     (void)hipFree(f->G);
@@ -713,6 +737,7 @@ constexpr int kWgradChunk = 1024;
 }  // namespace
 
 static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n);
+static dmc::NsfArgs nsf_args(dmc_flow* f, dmc_sampler* s);
 
 extern "C" {
 
@@ -764,15 +789,97 @@ dmc_status dmc_flow_create(int32_t dim, int32_t n_layers, const int8_t* masks, d
     return DMC_OK;
 }
 
+dmc_status dmc_flow_create_spline(int32_t dim, int32_t n_layers, const int8_t* masks, dmc_flow** out) {
+    if (!masks || !out) return fail(DMC_E_INVALID, "null argument");
+    if (dim != 3 && dim != 7 && dim != 11 && dim != 15 && dim != 19 && dim != 23)
+        return fail(DMC_E_INVALID, "dim must be 4n - 1 for an order n in 1..6");
+    if (n_layers < 1 || n_layers > 32) return fail(DMC_E_INVALID, "n_layers in 1..32");
+    const int MD = dmc::NSF_MAXD, H = dmc::NSF_H;
+    auto f = std::make_unique<dmc_flow>();
+    f->kind = 1;
+    f->dim = dim;
+    f->n_layers = n_layers;
+    f->masks.assign(masks, masks + (size_t)n_layers * dim);
+    f->aidx_h.assign((size_t)n_layers * MD, 0);
+    f->bidx_h.assign((size_t)n_layers * MD, 0);
+    f->dA_h.assign(n_layers, 0);
+    f->offs_h.assign(n_layers, 0);
+    int64_t off = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        int na = 0, nb = 0;
+        for (int d = 0; d < dim; ++d) {
+            const int8_t mk = masks[l * dim + d];
+            if (mk == 1)
+                f->aidx_h[l * MD + na++] = d;
+            else if (mk == 0)
+                f->bidx_h[l * MD + nb++] = d;
+            else
+                return fail(DMC_E_INVALID, "mask entries must be 0 or 1");
+        }
+        if (na == 0 || nb == 0) return fail(DMC_E_INVALID, "every layer needs both parts");
+        f->dA_h[l] = na;
+        f->offs_h[l] = (int)off;
+        const int P = dmc::NSF_NP * nb;
+        const int count = H * na + H + H * H + H + P * H + P;
+        f->max_layer_floats = std::max(f->max_layer_floats, count);
+        off += count;
+    }
+    f->n_params = off;
+    HIP_ALLOC(hipMalloc(&f->d_aidx, sizeof(int) * f->aidx_h.size()));
+    HIP_ALLOC(hipMalloc(&f->d_bidx, sizeof(int) * f->bidx_h.size()));
+    HIP_ALLOC(hipMalloc(&f->d_dA, sizeof(int) * n_layers));
+    HIP_ALLOC(hipMalloc(&f->d_offs, sizeof(int) * n_layers));
+    HIP_ALLOC(hipMalloc(&f->master, sizeof(float) * (size_t)off));
+    HIP_ALLOC(hipMalloc(&f->m, sizeof(float) * (size_t)off));
+    HIP_ALLOC(hipMalloc(&f->v, sizeof(float) * (size_t)off));
+    HIP_ALLOC(hipMalloc(&f->s_grad, sizeof(float) * (size_t)off));
+    HIP_ALLOC(hipMalloc(&f->sums, sizeof(double) * 4));
+    HIP_TRY(hipMemcpy(f->d_aidx, f->aidx_h.data(), sizeof(int) * f->aidx_h.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_bidx, f->bidx_h.data(), sizeof(int) * f->bidx_h.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_dA, f->dA_h.data(), sizeof(int) * n_layers, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_offs, f->offs_h.data(), sizeof(int) * n_layers, hipMemcpyHostToDevice));
+    // the identity flow until parameters are set: the output layer zero, interior-derivative biases at
+    // softplus^-1(1 - 1e-3) (all spline derivatives 1, widths and heights equal), and He-normal hidden
+    // weights from a fixed seed (zero hidden weights would leave every conditioner gradient but the
+    // output biases' zero)
+    std::vector<float> init((size_t)off, 0.0f);
+    const float dzero = (float)std::log(std::exp(1.0 - 1e-3) - 1.0);
+    uint64_t st = 0x5EEDF10Full;
+    auto normal = [&st]() {  // splitmix64 uniforms, Box-Muller
+        auto next = [&st]() {
+            uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            return ((double)((z ^ (z >> 31)) >> 11) + 0.5) * 0x1p-53;
+        };
+        const double u1 = next(), u2 = next();
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    for (int l = 0; l < n_layers; ++l) {
+        const int na = f->dA_h[l], nb = dim - na, P = dmc::NSF_NP * nb;
+        const size_t o = (size_t)f->offs_h[l];
+        for (int i = 0; i < H * na; ++i) init[o + i] = (float)(normal() * std::sqrt(2.0 / na));
+        for (int i = 0; i < H * H; ++i) init[o + H * na + H + i] = (float)(normal() * std::sqrt(2.0 / H));
+        const size_t b3 = o + H * na + H + H * H + H + (size_t)P * H;
+        for (int j = 0; j < nb; ++j)
+            for (int r = 2 * dmc::NSF_K; r < dmc::NSF_NP; ++r) init[b3 + j * dmc::NSF_NP + r] = dzero;
+    }
+    HIP_TRY(hipMemcpy(f->master, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(f->m, 0, sizeof(float) * (size_t)off));
+    HIP_TRY(hipMemset(f->v, 0, sizeof(float) * (size_t)off));
+    *out = f.release();
+    return DMC_OK;
+}
+
 dmc_status dmc_flow_param_count(const dmc_flow* f, int64_t* n) {
     if (!f || !n) return fail(DMC_E_INVALID, "null argument");
-    *n = (int64_t)f->n_layers * dmc::LAYER_SIZE;
+    *n = f->kind == 1 ? f->n_params : (int64_t)f->n_layers * dmc::LAYER_SIZE;
     return DMC_OK;
 }
 
 dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream) {
     if (!f || !theta) return fail(DMC_E_INVALID, "null argument");
-    const size_t P = (size_t)f->n_layers * dmc::LAYER_SIZE;
+    const size_t P = f->kind == 1 ? (size_t)f->n_params : (size_t)f->n_layers * dmc::LAYER_SIZE;
     for (size_t i = 0; i < P; ++i)
         if (!std::isfinite(theta[i])) return fail(DMC_E_INVALID, "parameters must be finite");
     HIP_TRY(hipStreamSynchronize(S(stream)));
@@ -780,14 +887,15 @@ dmc_status dmc_flow_set_params(dmc_flow* f, const float* theta, void* stream) {
     HIP_TRY(hipMemset(f->m, 0, sizeof(float) * P));
     HIP_TRY(hipMemset(f->v, 0, sizeof(float) * P));
     f->step = 0;
-    HIP_TRY(dmc::launch_flow_shadow(f->master, f->shadow, f->n_layers, cu_count(), S(stream)));
+    if (f->kind == 0) HIP_TRY(dmc::launch_flow_shadow(f->master, f->shadow, f->n_layers, cu_count(), S(stream)));
     return DMC_OK;
 }
 
 dmc_status dmc_flow_get_params(dmc_flow* f, float* theta, void* stream) {
     if (!f || !theta) return fail(DMC_E_INVALID, "null argument");
     HIP_TRY(hipStreamSynchronize(S(stream)));
-    HIP_TRY(hipMemcpy(theta, f->master, sizeof(float) * (size_t)f->n_layers * dmc::LAYER_SIZE, hipMemcpyDeviceToHost));
+    const size_t P = f->kind == 1 ? (size_t)f->n_params : (size_t)f->n_layers * dmc::LAYER_SIZE;
+    HIP_TRY(hipMemcpy(theta, f->master, sizeof(float) * P, hipMemcpyDeviceToHost));
     return DMC_OK;
 }
 
@@ -839,6 +947,15 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
         ua.jl = (float)(4.0 * M_PI * s->qmax);
         ua.jt = (float)std::pow(s->beta, s->order - 1);
         HIP_TRY(dmc::launch_flow_uniform(ua, ncu, S(stream)));
+        if (f->kind == 1) {
+            dmc::NsfArgs na = nsf_args(f, s);
+            na.u_in = u_out ? u_out : up_s;
+            na.ld = u_out ? ld : n_u;
+            na.n = n_u;
+            na.lq_out = lq_out ? lq_out : lq_s;
+            HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
+            HIP_TRY(dmc::launch_flow_mix(jac, na.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
+        } else {
         dmc::FlowTrainArgs a;
         train_args(f, a, n_u);
         a.u_in = u_out ? u_out : up_s;
@@ -851,10 +968,24 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
         a.lq_out = lq_out ? lq_out : lq_s;
         HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_u, ncu), S(stream)));
         HIP_TRY(dmc::launch_flow_mix(jac, a.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
+        }
     }
     if (n_g > 0) {
         dmc_status st = dmc_sample(s, seed, first + (uint64_t)n_u, n_g, x + n_u, ld, jac + n_u, stream);
         if (st != DMC_OK) return st;
+        if (f->kind == 1) {
+            dmc::NsfArgs na = nsf_args(f, s);
+            na.u_in = nullptr;
+            na.seed = seed;
+            na.first = first + (uint64_t)n_u;
+            na.n = n_g;
+            na.ld = ld;
+            na.lq_out = lq_out ? lq_out + n_u : lq_s + n_u;
+            na.u_out = u_out ? u_out + n_u : nullptr;
+            na.jv_out = jv_s + n_u;
+            HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
+            HIP_TRY(dmc::launch_flow_mix(jac + n_u, na.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
+        } else {
         dmc::FlowTrainArgs a;
         train_args(f, a, n_g);
         a.u_in = nullptr;
@@ -873,8 +1004,24 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
         a.jv_out = jv_s + n_u;
         HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_g, ncu), S(stream)));
         HIP_TRY(dmc::launch_flow_mix(jac + n_u, a.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
+        }
     }
-    if (n_f > 0) {
+    if (n_f > 0 && f->kind == 1) {
+        const int64_t o = n_u + n_g;
+        dmc::NsfArgs na = nsf_args(f, s);
+        na.seed = seed;
+        na.first = first + (uint64_t)o;
+        na.n = n_f;
+        na.ld = ld;
+        na.x = x + o;
+        na.jac = jac + o;
+        na.u_out = u_out ? u_out + o : nullptr;
+        na.lq_out = lq_out ? lq_out + o : nullptr;
+        na.mix_f = af;
+        na.mix_g = ag;
+        na.mix_u = au;
+        HIP_TRY(dmc::launch_nsf_sample(na, ncu, S(stream)));
+    } else if (n_f > 0) {
         const int64_t o = n_u + n_g;
         dmc::FlowSampleArgs a;
         a.seed = seed;
@@ -955,9 +1102,126 @@ static void train_args(dmc_flow* f, dmc::FlowTrainArgs& a, int64_t n) {
     a.act_dp1 = p;
 }
 
+static dmc::NsfArgs nsf_args(dmc_flow* f, dmc_sampler* s) {
+    dmc::NsfArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = f->master;
+    a.offs = f->d_offs;
+    a.aidx = f->d_aidx;
+    a.bidx = f->d_bidx;
+    a.dA = f->d_dA;
+    a.n_layers = f->n_layers;
+    a.dim = f->dim;
+    a.max_layer_floats = f->max_layer_floats;
+    if (s) {
+        a.edges = s->d_edges;
+        a.n_bins = s->n_bins;
+        a.beta = (float)s->beta;
+        a.qmax = (float)s->qmax;
+        a.jl = (float)(4.0 * M_PI * s->qmax);
+        a.jt = (float)std::pow(s->beta, s->order - 1);
+    }
+    return a;
+}
+
+// One weighted forward-KL step of a spline flow: the inverse pass keeps every layer's points, then the
+// layers' reverse steps run in application order (the adjoint of the base point is zero under the
+// uniform base), each followed by its weight-gradient sums; finally Adam.
+static dmc_status spline_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t seed, uint64_t first, int64_t n,
+                                    const float* w, double lr, float* grad_out, double* loss, void* stream) {
+    const int D = f->dim, L = f->n_layers, H = dmc::NSF_H;
+    int maxP = 0, maxA = 0;
+    for (int l = 0; l < L; ++l) {
+        maxP = std::max(maxP, dmc::NSF_NP * (D - f->dA_h[l]));
+        maxA = std::max(maxA, f->dA_h[l]);
+    }
+    if (n > f->s_cap) {
+        free_spline_train(f);
+        HIP_ALLOC(hipMalloc(&f->s_zs, sizeof(float) * (size_t)(L + 1) * D * n));
+        HIP_ALLOC(hipMalloc(&f->s_adj, sizeof(float) * (size_t)D * n));
+        HIP_ALLOC(hipMalloc(&f->s_vec, sizeof(float) * (size_t)(maxP + 4 * H + maxA) * n));
+        HIP_ALLOC(hipMalloc(&f->s_partial, sizeof(float) * (size_t)dmc::nsf_outer_chunks(n) * maxP * (H + 1)));
+        HIP_ALLOC(hipMalloc(&f->s_lq, sizeof(float) * (size_t)n));
+        f->s_cap = n;
+    }
+    const int ncu = cu_count();
+    dmc::NsfArgs na = nsf_args(f, nullptr);
+    na.u_in = u;
+    na.ld = u ? ld : n;
+    na.seed = seed;
+    na.first = first;
+    na.n = n;
+    na.lq_out = f->s_lq;
+    na.zs = f->s_zs;
+    HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
+    HIP_TRY(dmc::launch_nsf_loss(w, f->s_lq, n, f->sums, 1, S(stream)));
+    HIP_TRY(hipMemsetAsync(f->s_adj, 0, sizeof(float) * (size_t)D * n, S(stream)));
+    for (int l = 0; l < L; ++l) {
+        const int dA = f->dA_h[l], dB = D - dA, P = dmc::NSF_NP * dB;
+        dmc::NsfBackArgs b;
+        b.params = f->master;
+        b.off = f->offs_h[l];
+        b.dA = dA;
+        b.dB = dB;
+        b.dim = D;
+        b.aidx = f->d_aidx + l * dmc::NSF_MAXD;
+        b.bidx = f->d_bidx + l * dmc::NSF_MAXD;
+        b.z = f->s_zs + (size_t)(l + 1) * D * n;
+        b.adj = f->s_adj;
+        b.w = w;
+        b.inv_wsum = f->sums + 2;
+        b.n = n;
+        float* v = f->s_vec;
+        b.d_theta = v;
+        v += (size_t)P * n;
+        b.a2 = v;
+        v += (size_t)H * n;
+        b.d_pre2 = v;
+        v += (size_t)H * n;
+        b.a1 = v;
+        v += (size_t)H * n;
+        b.d_pre1 = v;
+        v += (size_t)H * n;
+        b.zA = v;
+        HIP_TRY(dmc::launch_nsf_backward(b, ncu, S(stream)));
+        float* g = f->s_grad + f->offs_h[l];
+        // W1 [H][dA], b1 [H]; W2 [H][H], b2 [H]; W3 [P][H], b3 [P]
+        HIP_TRY(dmc::launch_nsf_outer(b.d_pre1, H, b.zA, dA, n, f->s_partial, S(stream)));
+        HIP_TRY(dmc::launch_nsf_outer_fold(f->s_partial, H, dA, n, g, S(stream)));
+        HIP_TRY(dmc::launch_nsf_outer(b.d_pre2, H, b.a1, H, n, f->s_partial, S(stream)));
+        HIP_TRY(dmc::launch_nsf_outer_fold(f->s_partial, H, H, n, g + H * dA + H, S(stream)));
+        HIP_TRY(dmc::launch_nsf_outer(b.d_theta, P, b.a2, H, n, f->s_partial, S(stream)));
+        HIP_TRY(dmc::launch_nsf_outer_fold(f->s_partial, P, H, n, g + H * dA + H + H * H + H, S(stream)));
+    }
+    if (grad_out)
+        HIP_TRY(hipMemcpyAsync(grad_out, f->s_grad, sizeof(float) * (size_t)f->n_params, hipMemcpyDeviceToDevice,
+                               S(stream)));
+    if (lr > 0) {
+        ++f->step;
+        HIP_TRY(dmc::launch_nsf_adam(f->master, f->m, f->v, f->s_grad, f->n_params, f->step, (float)lr, S(stream)));
+    }
+    if (loss) {
+        double h[4];
+        HIP_TRY(hipStreamSynchronize(S(stream)));
+        HIP_TRY(hipMemcpy(h, f->sums, sizeof(h), hipMemcpyDeviceToHost));
+        *loss = h[3];
+        if (!std::isfinite(h[0]) || !(h[0] > 0)) return fail(DMC_E_NUMERIC, "weights sum to zero or are not finite");
+    }
+    return DMC_OK;
+}
+
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream) {
     if (!f || !u || !lq) return fail(DMC_E_INVALID, "null argument");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
+    if (f->kind == 1) {
+        dmc::NsfArgs na = nsf_args(f, nullptr);
+        na.u_in = u;
+        na.ld = ld;
+        na.n = n;
+        na.lq_out = lq;
+        HIP_TRY(dmc::launch_nsf_inverse(na, cu_count(), S(stream)));
+        return DMC_OK;
+    }
     const int nblk = dmc::flow_inverse_blocks(n, cu_count());
     dmc::FlowTrainArgs a;
     train_args(f, a, n);
@@ -978,6 +1242,7 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
     if (!f || !w) return fail(DMC_E_INVALID, "null argument");
     if (n < 1 || (u && ld < n)) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
     if (!(lr >= 0)) return fail(DMC_E_INVALID, "lr must be >= 0");
+    if (f->kind == 1) return spline_train_step(f, u, ld, seed, first, n, w, lr, grad_out, loss, stream);
     const int ncu = cu_count();
     const int nblk = dmc::flow_train_blocks(n, ncu);
     const int nblk_inv = dmc::flow_inverse_blocks(n, ncu);
@@ -1030,6 +1295,9 @@ dmc_status dmc_flow_train_step(dmc_flow* f, const float* u, int64_t ld, uint64_t
 void dmc_flow_destroy(dmc_flow* f) {
     if (!f) return;
     free_train(f);
+    free_spline_train(f);
+    (void)hipFree(f->d_offs);
+    (void)hipFree(f->s_grad);
     (void)hipFree(f->d_aidx);
     (void)hipFree(f->d_bidx);
     (void)hipFree(f->d_dA);

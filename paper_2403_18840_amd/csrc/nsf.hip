@@ -1,0 +1,563 @@
+// Neural spline flow kernels (Appendix A): rational-quadratic spline couplings on [0, 1] with a residual
+// conditioner, uniform base.  One lane carries one sample through every layer; a block stages one
+// layer's parameters in LDS at a time, so a tile of samples goes layer by layer.  FP32 arithmetic; the
+// conditioner is a few thousand multiply-adds per sample and layer, far from the matrix cores' size.
+//   dmc_nsf_sample_kernel     Philox z -> couplings -> u' -> VEGAS map -> physical map, mixture weight
+//   dmc_nsf_inverse_kernel    u' -> z by the inverse couplings: log q(u'), optionally J_V(u') and every z_l
+//   dmc_nsf_backward_kernel   one layer of the reverse sweep of the weighted forward KL
+//   dmc_nsf_outer_kernel      sums over samples of outer products (the weight gradients), in chunks
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nsf.hpp"
+
+namespace dmc {
+
+namespace {
+
+constexpr float MINV = 1e-3f;  // minimum bin width, height and interior derivative
+
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+// the uniform sampler's draw: coordinate d of sample i from counter (i lo, i hi, d / 4, 0), word d % 4
+__device__ __forceinline__ void philox_point(uint64_t seed, uint64_t i, int D, float* u) {
+    for (int q = 0; q < (D + 3) / 4; ++q) {
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)q, 0u};
+        philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        for (int w = 0; w < 4 && 4 * q + w < D; ++w) u[4 * q + w] = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
+    }
+}
+
+__device__ __forceinline__ float softplusf(float t) { return log1pf(expf(-fabsf(t))) + fmaxf(t, 0.0f); }
+__device__ __forceinline__ float sigmoidf_(float t) { return 1.0f / (1.0f + expf(-t)); }
+
+// knots of one coordinate's spline from its NP parameters: x[0..K], y[0..K], d[0..K]; sw, sh: the
+// softmax probabilities (for the reverse sweep)
+__device__ __forceinline__ void knots(const float* th, float* x, float* y, float* d, float* sw, float* sh) {
+    float mw = th[0], mh = th[NSF_K];
+    for (int i = 1; i < NSF_K; ++i) {
+        mw = fmaxf(mw, th[i]);
+        mh = fmaxf(mh, th[NSF_K + i]);
+    }
+    float zw = 0.0f, zh = 0.0f;
+    for (int i = 0; i < NSF_K; ++i) {
+        sw[i] = expf(th[i] - mw);
+        sh[i] = expf(th[NSF_K + i] - mh);
+        zw += sw[i];
+        zh += sh[i];
+    }
+    const float cw = 1.0f / zw, ch = 1.0f / zh, scale = 1.0f - NSF_K * MINV;
+    x[0] = 0.0f;
+    y[0] = 0.0f;
+    for (int i = 0; i < NSF_K; ++i) {
+        sw[i] *= cw;
+        sh[i] *= ch;
+        x[i + 1] = x[i] + (MINV + scale * sw[i]);
+        y[i + 1] = y[i] + (MINV + scale * sh[i]);
+    }
+    x[NSF_K] = 1.0f;
+    y[NSF_K] = 1.0f;
+    d[0] = 1.0f;
+    d[NSF_K] = 1.0f;
+    for (int i = 1; i < NSF_K; ++i) d[i] = MINV + softplusf(th[2 * NSF_K + i - 1]);
+}
+
+__device__ __forceinline__ int find_bin(const float* kn, float v) {
+    int k = 0;
+    for (int i = 1; i < NSF_K; ++i) k += kn[i] <= v;
+    return k;
+}
+
+// forward spline: v -> y, returns log dy/dx
+__device__ __forceinline__ float spline_fwd(const float* th, float& v) {
+    float x[NSF_K + 1], y[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
+    knots(th, x, y, d, sw, sh);
+    const int k = find_bin(x, v);
+    const float W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
+    const float xi = fminf(fmaxf((v - x[k]) / W, 0.0f), 1.0f), t = xi * (1.0f - xi);
+    const float den = s + (d[k + 1] + d[k] - 2.0f * s) * t;
+    v = y[k] + H * (s * xi * xi + d[k] * t) / den;
+    const float num = d[k + 1] * xi * xi + 2.0f * s * t + d[k] * (1.0f - xi) * (1.0f - xi);
+    return 2.0f * logf(s) + logf(num) - 2.0f * logf(den);
+}
+
+// inverse spline: v (an output) -> x, returns log dy/dx at x
+__device__ __forceinline__ float spline_inv(const float* th, float& v) {
+    float x[NSF_K + 1], y[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
+    knots(th, x, y, d, sw, sh);
+    const int k = find_bin(y, v);
+    const float W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
+    const float dy = v - y[k], g = d[k + 1] + d[k] - 2.0f * s;
+    const float a = H * (s - d[k]) + dy * g, b = H * d[k] - dy * g, c = -s * dy;
+    const float sq = sqrtf(fmaxf(b * b - 4.0f * a * c, 0.0f));
+    const float xi = fminf(fmaxf(2.0f * c / (-b - sq), 0.0f), 1.0f), t = xi * (1.0f - xi);
+    v = x[k] + xi * W;
+    const float den = s + g * t;
+    const float num = d[k + 1] * xi * xi + 2.0f * s * t + d[k] * (1.0f - xi) * (1.0f - xi);
+    return 2.0f * logf(s) + logf(num) - 2.0f * logf(den);
+}
+
+// Reverse sweep of phi = gx x + gl log(dy/dx) through the inverse spline at output v: returns
+// d phi / d v and writes d phi / d theta (NP values).
+__device__ __forceinline__ float spline_inv_adjoint(const float* th, float v, float gx, float gl, float* gth) {
+    float xs[NSF_K + 1], ys[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
+    knots(th, xs, ys, d, sw, sh);
+    const int k = find_bin(ys, v);
+    const float W = xs[k + 1] - xs[k], H = ys[k + 1] - ys[k], s = H / W;
+    const float d0 = d[k], d1 = d[k + 1];
+    const float dy = v - ys[k], g = d1 + d0 - 2.0f * s;
+    const float a = H * (s - d0) + dy * g, b = H * d0 - dy * g, c = -s * dy;
+    const float sq = sqrtf(fmaxf(b * b - 4.0f * a * c, 0.0f));
+    const float q = -b - sq;
+    const float xi = 2.0f * c / q, t = xi * (1.0f - xi);
+    const float den = s + g * t;
+    const float num = d1 * xi * xi + 2.0f * s * t + d0 * (1.0f - xi) * (1.0f - xi);
+    // adjoints
+    float b_xk = gx, b_xi = gx * W, b_W = gx * xi;
+    float b_s = 2.0f * gl / s;
+    const float b_num = gl / num, b_den = -2.0f * gl / den;
+    b_s += b_den;
+    float b_g = b_den * t, b_t = b_den * g;
+    float b_d1 = b_num * xi * xi, b_d0 = b_num * (1.0f - xi) * (1.0f - xi);
+    b_xi += b_num * (2.0f * d1 * xi - 2.0f * d0 * (1.0f - xi));
+    b_s += b_num * 2.0f * t;
+    b_t += b_num * 2.0f * s;
+    b_xi += b_t * (1.0f - 2.0f * xi);
+    float b_c = 2.0f * b_xi / q;
+    const float b_q = -b_xi * xi / q;
+    float b_b = -b_q;
+    const float b_sq = -b_q;
+    const float b_disc = sq > 0.0f ? b_sq / (2.0f * sq) : 0.0f;
+    b_b += b_disc * 2.0f * b;
+    const float b_a = -4.0f * c * b_disc;
+    b_c += -4.0f * a * b_disc;
+    b_s += -dy * b_c;
+    float b_dy = -s * b_c;
+    float b_H = b_b * d0;
+    b_d0 += b_b * H;
+    b_dy += -b_b * g;
+    b_g += -b_b * dy;
+    b_H += b_a * (s - d0);
+    b_s += b_a * H;
+    b_d0 += -b_a * H;
+    b_dy += b_a * g;
+    b_g += b_a * dy;
+    b_d1 += b_g;
+    b_d0 += b_g;
+    b_s += -2.0f * b_g;
+    const float b_v = b_dy, b_yk = -b_dy;
+    b_H += b_s / W;
+    b_W += -b_s * H / (W * W);
+    // knots: x_k = sum_{i<k} w_i, W = w_k; likewise y, H
+    float bw[NSF_K], bh[NSF_K];
+    for (int i = 0; i < NSF_K; ++i) {
+        bw[i] = i < k ? b_xk : 0.0f;
+        bh[i] = i < k ? b_yk : 0.0f;
+    }
+    bw[k] += b_W;
+    bh[k] += b_H;
+    // w = m + (1 - K m) softmax(theta_w): dtheta_i = (1 - K m) sw_i (bw_i - sum_j sw_j bw_j)
+    float pw = 0.0f, ph = 0.0f;
+    for (int i = 0; i < NSF_K; ++i) {
+        pw += sw[i] * bw[i];
+        ph += sh[i] * bh[i];
+    }
+    const float scale = 1.0f - NSF_K * MINV;
+    for (int i = 0; i < NSF_K; ++i) {
+        gth[i] = scale * sw[i] * (bw[i] - pw);
+        gth[NSF_K + i] = scale * sh[i] * (bh[i] - ph);
+    }
+    for (int i = 0; i < NSF_K - 1; ++i) gth[2 * NSF_K + i] = 0.0f;
+    // interior derivatives d_i (i = 1..K-1) = m + softplus(theta[2K + i - 1])
+    if (k >= 1) gth[2 * NSF_K + k - 1] += b_d0 * sigmoidf_(th[2 * NSF_K + k - 1]);
+    if (k + 1 <= NSF_K - 1) gth[2 * NSF_K + k] += b_d1 * sigmoidf_(th[2 * NSF_K + k]);
+    return b_v;
+}
+
+struct Layer {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    int dA, dB, P;
+};
+
+// stage layer l's parameters in LDS (the whole block) and return views of them
+__device__ Layer stage_layer(const float* params, int off, int dA, int dB, float* lds) {
+    const int P = NSF_NP * dB;
+    const int count = NSF_H * dA + NSF_H + NSF_H * NSF_H + NSF_H + P * NSF_H + P;
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = params[off + i];
+    __syncthreads();
+    Layer L;
+    L.dA = dA;
+    L.dB = dB;
+    L.P = P;
+    L.W1 = lds;
+    L.b1 = L.W1 + NSF_H * dA;
+    L.W2 = L.b1 + NSF_H;
+    L.b2 = L.W2 + NSF_H * NSF_H;
+    L.W3 = L.b2 + NSF_H;
+    L.b3 = L.W3 + P * NSF_H;
+    return L;
+}
+
+// a1 = relu(W1 zA + b1), a2 = relu(W2 a1 + b2) + a1; pre-activation signs in m1, m2
+__device__ __forceinline__ void conditioner(const Layer& L, const float* zA, float* a1, float* a2, uint32_t& m1,
+                                            uint32_t& m2) {
+    m1 = m2 = 0u;
+    for (int h = 0; h < NSF_H; ++h) {
+        float p = L.b1[h];
+        for (int i = 0; i < L.dA; ++i) p = __builtin_fmaf(L.W1[h * L.dA + i], zA[i], p);
+        a1[h] = fmaxf(p, 0.0f);
+        m1 |= (p > 0.0f ? 1u : 0u) << h;
+    }
+    for (int h = 0; h < NSF_H; ++h) {
+        float p = L.b2[h];
+        for (int i = 0; i < NSF_H; ++i) p = __builtin_fmaf(L.W2[h * NSF_H + i], a1[i], p);
+        a2[h] = fmaxf(p, 0.0f) + a1[h];
+        m2 |= (p > 0.0f ? 1u : 0u) << h;
+    }
+}
+
+__device__ __forceinline__ void spline_params(const Layer& L, const float* a2, int j, float* th) {
+    for (int r = 0; r < NSF_NP; ++r) {
+        const int row = j * NSF_NP + r;
+        float p = L.b3[row];
+        for (int h = 0; h < NSF_H; ++h) p = __builtin_fmaf(L.W3[row * NSF_H + h], a2[h], p);
+        th[r] = p;
+    }
+}
+
+}  // namespace
+
+// flow share: Philox z -> every coupling forward -> u'; VEGAS map, physical map, mixture weight
+__global__ void __launch_bounds__(256) dmc_nsf_sample_kernel(NsfArgs a) {
+    extern __shared__ float lds[];
+    const int D = a.dim, N = (D + 1) / 4;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = base + threadIdx.x;
+        const bool valid = s < a.n;
+        float z[NSF_MAXD];
+        philox_point(a.seed, a.first + (uint64_t)(valid ? s : 0), D, z);
+        float lq = 0.0f;
+        for (int l = 0; l < a.n_layers; ++l) {
+            const Layer L = stage_layer(a.params, a.offs[l], a.dA[l], D - a.dA[l], lds);
+            float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
+            uint32_t m1, m2;
+            for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
+            conditioner(L, zA, a1, a2, m1, m2);
+            for (int j = 0; j < L.dB; ++j) {
+                spline_params(L, a2, j, th);
+                const int col = a.bidx[l * NSF_MAXD + j];
+                float v = z[col];
+                lq -= spline_fwd(th, v);
+                z[col] = v;
+            }
+        }
+        if (!valid) continue;
+        float J = 1.0f, jv = 1.0f, y[NSF_MAXD];
+        for (int d = 0; d < D; ++d) {
+            const float up = z[d];
+            if (a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
+            const float ub = up * (float)a.n_bins;
+            const int bin = (int)fminf(fmaxf(ub, 0.0f), (float)(a.n_bins - 1));
+            const float fr = ub - (float)bin;
+            const float lo = a.edges[d * (a.n_bins + 1) + bin];
+            const float hi = a.edges[d * (a.n_bins + 1) + bin + 1];
+            y[d] = __builtin_fmaf(fr, hi - lo, lo);
+            jv *= (float)a.n_bins * (hi - lo);
+        }
+        for (int q = 0; q < N; ++q) {
+            const float r = a.qmax * y[3 * q];
+            const float ct = __builtin_fmaf(2.0f, y[3 * q + 1], -1.0f);
+            const float st = sqrtf(fmaxf(0.0f, __builtin_fmaf(-ct, ct, 1.0f)));
+            float sp, cp;
+            sincospif(2.0f * y[3 * q + 2], &sp, &cp);
+            a.x[(int64_t)(3 * q) * a.ld + s] = r * st * cp;
+            a.x[(int64_t)(3 * q + 1) * a.ld + s] = r * st * sp;
+            a.x[(int64_t)(3 * q + 2) * a.ld + s] = r * ct;
+            J *= a.jl * r * r;
+        }
+        for (int jt = 1; jt < N; ++jt) a.x[(int64_t)(3 * N + jt - 1) * a.ld + s] = a.beta * y[3 * N + jt - 1];
+        a.jac[s] = J * jv * a.jt / __builtin_fmaf(a.mix_f, expf(lq), __builtin_fmaf(a.mix_u, jv, a.mix_g));
+        if (a.lq_out) a.lq_out[s] = lq;
+    }
+}
+
+// u' -> z by the inverse couplings (last layer first); log q(u') = -sum of the layers' log dy/dx
+__global__ void __launch_bounds__(256) dmc_nsf_inverse_kernel(NsfArgs a) {
+    extern __shared__ float lds[];
+    const int D = a.dim, L_ = a.n_layers;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = base + threadIdx.x;
+        const bool valid = s < a.n;
+        const int64_t sc = valid ? s : 0;
+        float z[NSF_MAXD];
+        if (a.u_in) {
+            for (int d = 0; d < D; ++d) z[d] = a.u_in[(int64_t)d * a.ld + sc];
+        } else {
+            philox_point(a.seed, a.first + (uint64_t)sc, D, z);
+        }
+        if (valid) {
+            if (a.u_out && !a.u_in)
+                for (int d = 0; d < D; ++d) a.u_out[(int64_t)d * a.ld + s] = z[d];
+            if (a.jv_out) {
+                float jv = 1.0f;
+                for (int d = 0; d < D; ++d) {
+                    const float ub = z[d] * (float)a.n_bins;
+                    const int bin = (int)fminf(fmaxf(ub, 0.0f), (float)(a.n_bins - 1));
+                    jv *= (float)a.n_bins * (a.edges[d * (a.n_bins + 1) + bin + 1] - a.edges[d * (a.n_bins + 1) + bin]);
+                }
+                a.jv_out[s] = jv;
+            }
+            if (a.zs)
+                for (int d = 0; d < D; ++d) a.zs[((int64_t)L_ * D + d) * a.n + s] = z[d];
+        }
+        float lq = 0.0f;
+        for (int l = L_ - 1; l >= 0; --l) {
+            const Layer L = stage_layer(a.params, a.offs[l], a.dA[l], D - a.dA[l], lds);
+            float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
+            uint32_t m1, m2;
+            for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
+            conditioner(L, zA, a1, a2, m1, m2);
+            for (int j = 0; j < L.dB; ++j) {
+                spline_params(L, a2, j, th);
+                const int col = a.bidx[l * NSF_MAXD + j];
+                float v = z[col];
+                lq -= spline_inv(th, v);
+                z[col] = v;
+            }
+            if (valid && a.zs)
+                for (int d = 0; d < D; ++d) a.zs[((int64_t)l * D + d) * a.n + s] = z[d];
+        }
+        if (valid && a.lq_out) a.lq_out[s] = lq;
+    }
+}
+
+// Layer reverse step: adj holds dL/dz_{l-1} (the layer's input side) on entry and dL/dz_l on exit
+__global__ void __launch_bounds__(256) dmc_nsf_backward_kernel(NsfBackArgs a) {
+    extern __shared__ float lds[];
+    const Layer L = stage_layer(a.params, a.off, a.dA, a.dB, lds);
+    const double inv = *a.inv_wsum;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * blockDim.x) {
+        const float wn = (float)((double)a.w[s] * inv);
+        float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], da2[NSF_H], th[NSF_NP], gth[NSF_NP];
+        uint32_t m1, m2;
+        for (int i = 0; i < a.dA; ++i) zA[i] = a.z[(int64_t)a.aidx[i] * a.n + s];
+        conditioner(L, zA, a1, a2, m1, m2);
+        for (int h = 0; h < NSF_H; ++h) da2[h] = 0.0f;
+        for (int j = 0; j < a.dB; ++j) {
+            spline_params(L, a2, j, th);
+            const int col = a.bidx[j];
+            const float v = a.z[(int64_t)col * a.n + s];
+            const float gx = a.adj[(int64_t)col * a.n + s];
+            const float gv = spline_inv_adjoint(th, v, gx, wn, gth);
+            a.adj[(int64_t)col * a.n + s] = gv;
+            for (int r = 0; r < NSF_NP; ++r) {
+                const int row = j * NSF_NP + r;
+                a.d_theta[(int64_t)row * a.n + s] = gth[r];
+                for (int h = 0; h < NSF_H; ++h) da2[h] = __builtin_fmaf(L.W3[row * NSF_H + h], gth[r], da2[h]);
+            }
+        }
+        // a2 = relu(pre2) + a1, a1 = relu(pre1)
+        float dp2[NSF_H], da1[NSF_H];
+        for (int h = 0; h < NSF_H; ++h) {
+            dp2[h] = (m2 >> h) & 1u ? da2[h] : 0.0f;
+            da1[h] = da2[h];
+        }
+        for (int i = 0; i < NSF_H; ++i) {
+            float acc = da1[i];
+            for (int h = 0; h < NSF_H; ++h) acc = __builtin_fmaf(L.W2[h * NSF_H + i], dp2[h], acc);
+            da1[i] = acc;
+        }
+        for (int h = 0; h < NSF_H; ++h) {
+            const float dp1 = (m1 >> h) & 1u ? da1[h] : 0.0f;
+            a.a2[(int64_t)h * a.n + s] = a2[h];
+            a.d_pre2[(int64_t)h * a.n + s] = dp2[h];
+            a.a1[(int64_t)h * a.n + s] = a1[h];
+            a.d_pre1[(int64_t)h * a.n + s] = dp1;
+            da1[h] = dp1;
+        }
+        for (int i = 0; i < a.dA; ++i) {
+            float acc = 0.0f;
+            for (int h = 0; h < NSF_H; ++h) acc = __builtin_fmaf(L.W1[h * a.dA + i], da1[h], acc);
+            const int col = a.aidx[i];
+            a.adj[(int64_t)col * a.n + s] += acc;
+            a.zA[(int64_t)i * a.n + s] = zA[i];
+        }
+    }
+}
+
+// Sums over samples of outer products, one chunk of OUTER_CHUNK samples and a tile of 16 rows of A per
+// block: partial[c][i][j] = sum_n A[i][n] B[j][n] (j < rowsB), partial[c][i][rowsB] = sum_n A[i][n].
+constexpr int OUTER_CHUNK = 4096;
+constexpr int OUTER_ROWS = 16;
+
+__global__ void __launch_bounds__(256) dmc_nsf_outer_kernel(const float* A, int rowsA, const float* B, int rowsB,
+                                                             int64_t n, float* partial) {
+    __shared__ float ta[OUTER_ROWS][65];
+    __shared__ float tb[NSF_MAXD > NSF_H ? NSF_MAXD + 1 : NSF_H + 1][65];
+    const int i0 = blockIdx.x * OUTER_ROWS;
+    const int64_t c = blockIdx.y;
+    const int64_t n0 = c * OUTER_CHUNK, n1 = n0 + OUTER_CHUNK < n ? n0 + OUTER_CHUNK : n;
+    const int cols = rowsB + 1;
+    // each thread owns up to three (i, j) outputs of the 16 x cols tile (cols <= 33)
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int64_t nb = n0; nb < n1; nb += 64) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < OUTER_ROWS * 64; e += 256) {
+            const int r = e / 64, q = e % 64;
+            const int64_t nn = nb + q;
+            ta[r][q] = (i0 + r < rowsA && nn < n1) ? A[(int64_t)(i0 + r) * n + nn] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < cols * 64; e += 256) {
+            const int r = e / 64, q = e % 64;
+            const int64_t nn = nb + q;
+            tb[r][q] = r < rowsB ? ((nn < n1) ? B[(int64_t)r * n + nn] : 0.0f) : 1.0f;
+        }
+        __syncthreads();
+        for (int o = 0; o < 3; ++o) {
+            const int t = threadIdx.x + 256 * o;
+            if (t >= OUTER_ROWS * cols) continue;
+            const int r = t / cols, j = t % cols;
+            float sacc = acc[o];
+            for (int q = 0; q < 64; ++q) sacc = __builtin_fmaf(ta[r][q], tb[j][q], sacc);
+            acc[o] = sacc;
+        }
+    }
+    for (int o = 0; o < 3; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        if (t >= OUTER_ROWS * cols) continue;
+        const int r = t / cols, j = t % cols;
+        if (i0 + r < rowsA) partial[(c * rowsA + i0 + r) * cols + j] = acc[o];
+    }
+}
+
+__global__ void __launch_bounds__(256) dmc_nsf_outer_fold_kernel(const float* partial, int rowsA, int rowsB,
+                                                                  int chunks, float* grad) {
+    const int cols = rowsB + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rowsA * cols) return;
+    float s = 0.0f;
+    for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * rowsA * cols + t];
+    const int i = t / cols, j = t % cols;
+    // weights [rowsA][rowsB] then biases [rowsA]
+    if (j < rowsB)
+        grad[i * rowsB + j] = s;
+    else
+        grad[rowsA * rowsB + i] = s;
+}
+
+__global__ void __launch_bounds__(1024) dmc_nsf_loss_kernel(const float* w, const float* lq, int64_t n, double* out) {
+    __shared__ double r0[1024], r1[1024];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double wi = (double)w[i];
+        const double li = (double)lq[i];
+        if (wi > 0.0 && __builtin_isfinite(li)) {
+            s0 += wi;
+            s1 += wi * li;
+        }
+    }
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            r0[threadIdx.x] += r0[threadIdx.x + o];
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = r0[0];
+        out[1] = r1[0];
+        out[2] = r0[0] > 0.0 ? 1.0 / r0[0] : 0.0;  // 1 / sum w
+        out[3] = r0[0] > 0.0 ? -r1[0] / r0[0] : 0.0;  // the loss
+    }
+}
+
+__global__ void __launch_bounds__(256) dmc_nsf_adam_kernel(float* p, float* m, float* v, const float* g, int64_t count,
+                                                            float lr, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        if (!__builtin_isfinite(gi)) continue;
+        const float mi = 0.9f * m[i] + 0.1f * gi;
+        const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    }
+}
+
+static int grid_for(int64_t n, int n_cu) {
+    const int64_t want = (n + 255) / 256;
+    const int64_t cap = (int64_t)n_cu * 4;
+    return (int)(want < cap ? (want > 0 ? want : 1) : cap);
+}
+
+hipError_t launch_nsf_sample(const NsfArgs& a, int n_cu, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_nsf_sample_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), a.max_layer_floats * sizeof(float),
+                       st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_nsf_inverse_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), a.max_layer_floats * sizeof(float),
+                       st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_backward(const NsfBackArgs& a, int n_cu, hipStream_t st) {
+    const int P = NSF_NP * a.dB;
+    const int count = NSF_H * a.dA + NSF_H + NSF_H * NSF_H + NSF_H + P * NSF_H + P;
+    hipLaunchKernelGGL(dmc_nsf_backward_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), count * sizeof(float), st, a);
+    return hipGetLastError();
+}
+
+int nsf_outer_chunks(int64_t n) { return (int)((n + OUTER_CHUNK - 1) / OUTER_CHUNK); }
+
+hipError_t launch_nsf_outer(const float* A, int rowsA, const float* B, int rowsB, int64_t n, float* partial,
+                            hipStream_t st) {
+    const dim3 grid((rowsA + OUTER_ROWS - 1) / OUTER_ROWS, nsf_outer_chunks(n));
+    hipLaunchKernelGGL(dmc_nsf_outer_kernel, grid, dim3(256), 0, st, A, rowsA, B, rowsB, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_outer_fold(const float* partial, int rowsA, int rowsB, int64_t n, float* grad, hipStream_t st) {
+    const int t = rowsA * (rowsB + 1);
+    hipLaunchKernelGGL(dmc_nsf_outer_fold_kernel, dim3((t + 255) / 256), dim3(256), 0, st, partial, rowsA, rowsB,
+                       nsf_outer_chunks(n), grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_loss(const float* w, const float* lq, int64_t n, double* out, int, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_nsf_loss_kernel, dim3(1), dim3(1024), 0, st, w, lq, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_adam(float* params, float* m, float* v, const float* grad, int64_t count, int64_t step, float lr,
+                           hipStream_t st) {
+    const float c1 = 1.0f / (1.0f - powf(0.9f, (float)step));
+    const float c2 = 1.0f / (1.0f - powf(0.999f, (float)step));
+    const int64_t want = (count + 255) / 256;
+    hipLaunchKernelGGL(dmc_nsf_adam_kernel, dim3((unsigned)(want < 2048 ? want : 2048)), dim3(256), 0, st, params, m, v,
+                       grad, count, lr, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace dmc

@@ -117,6 +117,29 @@ def flow_params(masks: np.ndarray, seed: int, last_scale: float = 0.0) -> np.nda
     return np.concatenate(out).astype(np.float32)
 
 
+def spline_flow_params(masks: np.ndarray, seed: int, scale: float = 0.0) -> np.ndarray:
+    """Flat FP32 parameters of a spline-coupling flow (per layer W1 [32][dA], b1 [32], W2 [32][32], b2 [32],
+    W3 [23 dB][32], b3 [23 dB]): He-normal hidden weights, zero hidden biases, output weights normal of
+    std `scale`, output biases `scale`-normal around the values whose spline is the identity (width and
+    height logits 0, interior-derivative logits log(exp(1 - 1e-3) - 1)).  scale = 0: the identity flow."""
+    g = rng(seed)
+    ident = np.log(np.exp(1.0 - 1e-3) - 1.0)
+    out = []
+    for m in masks:
+        dA = int(np.sum(m))
+        dB = len(m) - dA
+        P = 23 * dB
+        W1 = g.normal(size=(32, dA)) * np.sqrt(2.0 / dA)
+        W2 = g.normal(size=(32, 32)) * np.sqrt(2.0 / 32)
+        W3 = g.normal(size=(P, 32)) * scale
+        b3 = np.zeros(P)
+        for j in range(dB):
+            b3[j * 23 + 16:(j + 1) * 23] = ident
+        b3 = b3 + g.normal(size=P) * scale
+        out += [W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), W3.ravel(), b3]
+    return np.concatenate(out).astype(np.float32)
+
+
 def chain_proposals(S: int, n: int, seed: int, bad: bool = True):
     """Integrand values f[S][n] float32 (signed, log-uniform magnitudes over six decades) and proposal
     Jacobians jac[n] float32 (log-uniform in [1e-3, 1e3]) for the Markov-chain step; with `bad`, a few

@@ -1,0 +1,169 @@
+"""GPU neural spline flow (dmc_flow_create_spline) against the oracle: identity start, log density,
+samples, the training gradient against torch autograd, one Adam step, and a trained flow at order 2."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2403_18840_amd as dmc
+import synth
+from oracle import integrand as ig
+from oracle import nsf
+from oracle import physics as ph
+from oracle import sampler as osp
+
+from gpu_helpers import BETA, LAM, MU, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(err, ref, tight, loose):
+    """FP32 against FP64: the inverse of a spline with a derivative near its floor (1e-3) magnifies a rounding
+    of its argument a thousandfold into the next layer's conditioner, so a few samples of a peaked flow
+    carry larger errors.  99 % of the samples within `tight`, every one within `loose`, relative to
+    1 + |ref|."""
+    r = np.abs(err) / (1.0 + np.abs(ref))
+    return float(np.quantile(r, 0.99)) <= tight and float(r.max()) <= loose, (float(np.quantile(r, 0.99)),
+                                                                                float(r.max()))
+
+
+def _flow(D, L=6, seed=5, scale=0.2):
+    masks = synth.flow_masks(D, L, seed)
+    f = dmc.Flow(D, masks, kind="spline")
+    return f, masks, synth.spline_flow_params(masks, seed + 100, scale)
+
+
+def test_spline_flow_starts_as_the_identity():
+    torch, dev = torch_dev()
+    D, N = 7, 1000
+    masks = synth.flow_masks(D, 4, 3)
+    f = dmc.Flow(D, masks, kind="spline")
+    assert f.n_params == len(nsf.identity_params([list(m) for m in masks]))
+    th = f.params().astype(np.float64)
+    u = np.random.default_rng(1).uniform(size=(N, D))
+    lq_ref, z = nsf.log_density(u, [list(m) for m in masks], th)
+    # identity map (up to the FP32 rounding of the identity-derivative logit) ...
+    assert np.allclose(z, u, atol=1e-6) and np.allclose(lq_ref, 0.0, atol=1e-6)
+    assert np.abs(th).max() > 0.1                                                   # ... with live hidden layers
+    U = torch.from_numpy(np.ascontiguousarray(u.T.astype(np.float32))).to(dev)
+    lq = torch.empty(N, dtype=torch.float32, device=dev)
+    f.log_density(U, lq)
+    assert np.abs(lq.cpu().numpy()).max() < 1e-5
+
+
+@pytest.mark.parametrize("D,N", [(3, 1000), (7, 2049), (15, 4097), (23, 777)])
+def test_log_density_matches_oracle(D, N):
+    torch, dev = torch_dev()
+    f, masks, theta = _flow(D)
+    f.set_params(theta)
+    th32 = f.params().astype(np.float64)
+    u = np.random.default_rng(D).uniform(size=(N, D)).astype(np.float32)
+    U = torch.from_numpy(np.ascontiguousarray(u.T)).to(dev)
+    lq = torch.empty(N, dtype=torch.float32, device=dev)
+    f.log_density(U, lq)
+    ref, _ = nsf.log_density(u.astype(np.float64), [list(m) for m in masks], th32)
+    got = lq.cpu().numpy().astype(np.float64)
+    ok, stats = _close(got - ref, ref, 1e-4, 2e-3)
+    assert ok, stats
+
+
+@pytest.mark.parametrize("D,N", [(7, 3000), (15, 2049)])
+def test_samples_match_oracle(D, N):
+    torch, dev = torch_dev()
+    n = (D + 1) // 4
+    f, masks, theta = _flow(D, seed=9)
+    f.set_params(theta)
+    th32 = f.params().astype(np.float64)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    edges = synth.vegas_grid(D, 50, seed=4).astype(np.float64)
+    s.set_grid(edges)
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    Uo = torch.empty((D, N), dtype=torch.float32, device=dev)
+    lq = torch.empty(N, dtype=torch.float32, device=dev)
+    seed, first = 0x5EED, 77
+    f.sample(s, seed, first, X, J, u_out=Uo, lq_out=lq, alpha=1.0, uniform=0.0)
+    z, _ = osp.uniforms(seed, first, N, D)
+    u_ref, lq_ref = nsf.forward(z, [list(m) for m in masks], th32)
+    u = Uo.cpu().numpy().T.astype(np.float64)
+    ok, stats = _close(np.abs(u - u_ref).max(axis=1), 0.0 * lq_ref, 2e-5, 1e-3)
+    assert ok, stats
+    ok, stats = _close(lq.cpu().numpy() - lq_ref, lq_ref, 1e-4, 2e-3)
+    assert ok, stats
+    # x and the weight J_phys J_V / q at the flow's points (the grid map of the kernel's own u')
+    y, JV, _ = osp.vegas_map_float(Uo.cpu().numpy().T, edges)
+    x_ref, Jp = ig.physical_map(y, n, BETA, 6.0)
+    assert np.allclose(X.cpu().numpy().T, x_ref, rtol=2e-5, atol=2e-5)
+    # the weight inherits the log-density bounds: log w = log(J_phys J_V) - log q
+    # (weights below 1e-15 carry intermediates outside FP32's range in a peaked flow and are only checked
+    # for being negligible)
+    lw_ref = np.log(Jp * JV) - lq_ref
+    Jg = J.cpu().numpy().astype(np.float64)
+    big = lw_ref > math.log(1e-15)
+    assert np.all(Jg[~big] < 1e-13)
+    ok, stats = _close(np.log(Jg[big]) - lw_ref[big], lw_ref[big], 1e-4, 2e-3)
+    assert ok, stats
+
+
+def test_training_gradient_matches_torch_and_adam_step():
+    torch, dev = torch_dev()
+    D, N = 7, 1500
+    # a mild flow: with bins near the width floor (s = H/W ~ 1e3) the width adjoints reach 1e6 before the
+    # softmax projection cancels them, beyond FP32's reach; the formulas are what is checked here
+    f, masks, theta = _flow(D, L=4, seed=13, scale=0.08)
+    f.set_params(theta)
+    th32 = f.params().astype(np.float64)
+    rng = np.random.default_rng(21)
+    u = rng.uniform(0.001, 0.999, size=(N, D)).astype(np.float32)
+    w = rng.uniform(0.1, 3.0, size=N).astype(np.float32)
+    U = torch.from_numpy(np.ascontiguousarray(u.T)).to(dev)
+    W = torch.from_numpy(w).to(dev)
+    G = torch.empty(f.n_params, dtype=torch.float32, device=dev)
+    loss = f.train_step(W, u=U, lr=0.0, grad_out=G)
+    L_ref, g_ref, _ = nsf.loss_and_grad_torch(u.astype(np.float64), w.astype(np.float64), [list(m) for m in masks],
+                                              th32)
+    assert abs(loss - L_ref) <= 1e-5 * (1 + abs(L_ref))
+    g = G.cpu().numpy().astype(np.float64)
+    scale = np.abs(g_ref).max()
+    err = np.abs(g - g_ref)
+    assert np.all(err <= 1e-3 * np.abs(g_ref) + 1e-4 * scale), (float(err.max()), scale)
+    # one Adam step from zero moments: theta - lr g / (|g| + 1e-8) (bias-corrected moments equal g and g^2)
+    lr = 1e-3
+    f.train_step(W, u=U, lr=lr, want_loss=False)
+    new = f.params().astype(np.float64)
+    want = th32 - lr * g / (np.abs(g) + 1e-8)
+    ok = np.abs(g) > 1e-6 * scale   # tiny gradients: the sign, hence the step, is rounding-dependent
+    assert np.allclose(new[ok], want[ok], atol=2e-6)
+
+
+def test_spline_flow_trained_at_order2_beats_the_grid():
+    torch, dev = torch_dev()
+    n = 2
+    g = dmc.Graph(n)
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    ks = np.array([1.0], dtype=np.float32)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    dmc.adapt_grid(g, inst, ks, s, 1 << 20, 5, seed=2)
+    D = dmc.dim(n)
+    f = dmc.Flow(D, synth.flow_masks(D, 6, 5), kind="spline")
+    losses = dmc.train_flow(g, inst, ks, s, f, epochs=4, steps=48, minibatch=1 << 16, lr=2e-3, seed=3)
+    assert losses[-1] < losses[0], losses
+    N = 1 << 20
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    est = {}
+    for name in ("grid", "flow"):
+        acc = dmc.Accumulator(1, 1, 1)
+        if name == "grid":
+            s.sample(50, 0, X, J)
+        else:
+            f.sample(s, 51, 0, X, J, alpha=0.85, uniform=0.05)
+        dmc.eval_batch(g, inst, ks, X, J, acc)
+        dmc.accumulate(acc)
+        m, e, _, _ = acc.estimate(1)
+        est[name] = (m[0, 0, 0].real, e[0, 0, 0].real)
+    z = (est["grid"][0] - est["flow"][0]) / math.hypot(est["grid"][1], est["flow"][1])
+    ratio = (est["grid"][1] / est["flow"][1]) ** 2
+    print("spline flow losses", losses, "variance ratio", ratio, "z", z)
+    assert abs(z) < 4.5
+    assert ratio > 2.0
