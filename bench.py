@@ -93,7 +93,21 @@ def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma):
             "sample": "; ".join(desc) + " (numpy FP64, one thread; rate combined with equal samples per order)"}
 
 
-def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004, train="is"):
+def _make_flow(D, kind):
+    """The learned proposal: "affine" (8 affine couplings, 128-wide MLPs, BF16 matrix cores; He-normal hidden
+    weights, zero output layer) or "spline" (the paper's flow: 6 rational-quadratic spline couplings with
+    8 bins and a residual conditioner of two 32-unit layers; the library's identity start)."""
+    import paper_2403_18840_amd as dmc
+    import synth
+    if kind == "spline":
+        return dmc.Flow(D, synth.flow_masks(D, 6, 5), kind="spline")
+    masks = synth.flow_masks(D, 8, 5)
+    f = dmc.Flow(D, masks)
+    f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+    return f
+
+
+def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004, train="is", kind="affine"):
     """Learned proposal at one order: Re Sigma(k_F, i omega_0) from `batches` independent batches of N
     samples drawn from the adapted VEGAS grid alone and from the trained flow's defensive mixture
     (0.85 flow + 0.10 grid + 0.05 uniform), each with its wall time (GPU-synchronised).  sigma is the
@@ -148,9 +162,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
                 "sigma_in_run": float(math.sqrt(np.mean(np.square(sig)) / batches)), "nonfinite": int(nonfin)}
 
     vg, t_v = timed(lambda: run(lambda b: s.sample(seed + 1, b * N, X, J)))
-    masks = synth.flow_masks(D, 8, 5)
-    f = dmc.Flow(D, masks)
-    f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+    f = _make_flow(D, kind)
     epochs, steps, mb = 4, 64, 1 << 17
     if train == "mcmc":
         losses, t_train = timed(lambda: dmc.train_flow_mcmc(g, inst, ks, s, f, rounds=epochs, n_chains=mb, thermal=200,
@@ -169,18 +181,24 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
         b.record(stream)
     torch.cuda.synchronize()
     k_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
-    flop = N * FLOW_FLOP_PER_SAMPLE
+    if kind == "spline":
+        # conditioner multiply-adds per sample (2 FLOP each): 32 dA + 32 x 32 + 23 dB x 32 per layer
+        per = sum(2 * (32 * int(m.sum()) + 32 * 32 + 23 * (D - int(m.sum())) * 32) for m in f.masks)
+        flop, peak, bound, kname = N * per, PEAK_ALU_TFLOPS, "alu", f"dmc_nsf_sample_kernel (D = {D})"
+    else:
+        flop, peak, bound, kname = N * FLOW_FLOP_PER_SAMPLE, PEAK_BF16_TFLOPS, "mfma", f"dmc_flow_sample_kernel<{D}>"
     ev, ef = vg["sigma"], fl["sigma"]
     vg["seconds"] = t_v
-    fl.update({"seconds": t_f, "layers": 8, "width": 128, "mixture": {"flow": a_f, "grid": 1 - a_f - a_u, "uniform": a_u},
+    fl.update({"seconds": t_f, "kind": kind, "layers": f.n_layers,
+               "mixture": {"flow": a_f, "grid": 1 - a_f - a_u, "uniform": a_u},
                "training": {"kind": train, "adam_steps": epochs * steps, "minibatch": mb, "seconds": t_train,
                             "loss": [float(x) for x in losses]}})
     return {
         "order": order, "k": float(ks[jf]), "samples_per_batch": N, "batches": batches,
         "vegas": vg, "flow": fl, "adapt_seconds": t_adapt,
-        "roofline": {"bound": "mfma", "kernel": f"dmc_flow_sample_kernel<{D}>", "achieved": flop / (k_ms * 1e-3) / 1e12,
-                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": flop / (k_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, "kernel_ms": k_ms,
+        "roofline": {"bound": bound, "kernel": kname, "achieved": flop / (k_ms * 1e-3) / 1e12,
+                     "peak": peak, "unit": "TFLOP/s",
+                     "frac": flop / (k_ms * 1e-3) / 1e12 / peak, "kernel_ms": k_ms,
                      "flop_per_launch": flop},
         "z": float((vg["re"] - fl["re"]) / math.hypot(ev, ef)),
         "variance_ratio": float((ev / ef) ** 2),
@@ -191,7 +209,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
 
 
 def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, thermal=2000, n_batches=64,
-                  alphas=(0.05, 0.2, 0.5, 0.8), seed=0x2403188400000005, flow=True, ref_factor=16):
+                  alphas=(0.05, 0.2, 0.5, 0.8), seed=0x2403188400000005, flow=True, ref_factor=16, flow_kind="affine"):
     """Markov-chain estimators against plain VEGAS importance sampling at one order (the comparison
     of Sec. IV): Re Sigma(k_F, i omega_0) alone (K = 1, so p = |Re f| + |Im f| at k_F).  VEGAS IS:
     ref_factor x n_batches batches of n_chains * steps / n_batches samples from the adapted grid; the
@@ -281,15 +299,13 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
 
     out["vegas_mcmc"] = chains("VEGAS-MCMC", None)
     if flow:
-        masks = synth.flow_masks(D, 8, 5)
-        f = dmc.Flow(D, masks)
-        f.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+        f = _make_flow(D, flow_kind)
         epochs, tsteps, mb = 4, 64, 1 << 17
         losses, t_train = timed(lambda: dmc.train_flow(g, inst, ks, s, f, epochs=epochs, steps=tsteps, minibatch=mb,
                                                         lr=1e-3, seed=seed + 2))
         log(f"flow trained ({t_train:.1f} s), losses {[round(float(x), 3) for x in losses]}")
         out["nf_mcmc"] = chains("NF-MCMC", f)
-        out["nf_mcmc"]["training"] = {"samples": epochs * tsteps * mb, "seconds": t_train,
+        out["nf_mcmc"]["training"] = {"samples": epochs * tsteps * mb, "seconds": t_train, "kind": flow_kind,
                                       "loss": [float(x) for x in losses], "mixture": {"flow": 0.85, "uniform": 0.05}}
     return out
 
@@ -328,6 +344,8 @@ def main():
                     help="order of the learned-proposal comparison (0 skips it)")
     ap.add_argument("--flow-batches", type=int, default=64)
     ap.add_argument("--flow-log2-samples", type=int, default=22)
+    ap.add_argument("--flow-kind", choices=["affine", "spline"], default="affine",
+                    help="learned proposal of the flow and NF-MCMC legs")
     ap.add_argument("--flow-train", choices=["is", "mcmc"], default="is",
                     help="training data of the flow: importance-weighted draws or Markov-chain samples of |f|")
     ap.add_argument("--mcmc-orders", default="2",
@@ -453,11 +471,11 @@ def main():
                        "im_err": float(last[1][0, 0, j].imag)}
     if args.flow_order:
         out["flow_vs_vegas"] = flow_vs_vegas(args.flow_order, K, 1 << args.flow_log2_samples, args.flow_batches, beta, mu,
-                                             lam, inst[0][3], train=args.flow_train)
+                                             lam, inst[0][3], train=args.flow_train, kind=args.flow_kind)
     if args.mcmc_orders:
         out["mcmc_vs_vegas"] = [mcmc_vs_vegas(int(n), beta, mu, lam, inst[0][3], n_chains=1 << args.mcmc_log2_chains,
                                               steps=args.mcmc_steps, thermal=args.mcmc_thermal,
-                                              flow=not args.mcmc_no_flow)
+                                              flow=not args.mcmc_no_flow, flow_kind=args.flow_kind)
                                 for n in args.mcmc_orders.split(",")]
     if args.mass_order:
         out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, beta,

@@ -252,6 +252,7 @@ class Sampler:
         _check(lib().dmc_sampler_create(kind, order, n_bins, beta, qmax, ctypes.byref(self.h)))
         self.kind, self.order, self.dim = kind, order, dim(order)
         self.n_bins = n_bins if kind == SAMPLER_VEGAS else 1
+        self.beta, self.qmax = beta, qmax
 
     def sample(self, seed: int, first: int, x, jac, stream=None):
         n = jac.numel()
@@ -378,7 +379,8 @@ def adapt_grid(graph: Graph, inst, k_ext, sampler: Sampler, n_samples: int, iter
 
 
 def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs: int = 8, steps: int = 16,
-               minibatch: int = 1 << 17, lr: float = 1e-3, alpha: float = 0.85, uniform: float = 0.05, seed: int = 3):
+               minibatch: int = 1 << 17, lr: float = 1e-3, alpha: float = 0.85, uniform: float = 0.05, seed: int = 3,
+               anneal=None):
     """Fit `flow` (on the VEGAS coordinates of `sampler`, whose grid stays frozen) to the absolute
     integrand by the weighted forward KL of Appendix A, with Adam on the device.
 
@@ -387,7 +389,10 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
     first epoch draws from the grid alone; later epochs from the mixture alpha q_flow + uniform
     q_uniform + (rest) q_grid of the current flow, so the training points follow the flow as it
     sharpens.  k_ext selects the external momenta whose |Sigma| integrand the flow learns (the figure
-    of merit's).  Returns the loss of the last step of every epoch."""
+    of merit's).  anneal: a list of one beta per epoch (Appendix A's annealing in temperature: start hot,
+    where the integrand is smoother, and cool to the target); every epoch then trains on the integrand at
+    its beta through a sampler of that beta with the same grid (the flow lives on the grid coordinates,
+    where tau = beta u, so what it learns carries over).  Returns the loss of the last step of every epoch."""
     import numpy as np
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -400,20 +405,28 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
     J = torch.empty(minibatch, dtype=torch.float32, device=dev)
     U = torch.empty((D, minibatch), dtype=torch.float32, device=dev)
     imp = torch.empty(minibatch, dtype=torch.float32, device=dev)
+    if anneal is not None and len(anneal) != epochs:
+        raise ValueError("anneal needs one beta per epoch")
     losses = []
     step = 0
     for ep in range(epochs):
         loss = None
+        s_ep, inst_ep = sampler, inst
+        if anneal is not None:
+            b_ep = float(anneal[ep])
+            s_ep = Sampler(SAMPLER_VEGAS, graph.order, n_bins=sampler.n_bins, beta=b_ep, qmax=sampler.qmax)
+            s_ep.set_grid(sampler.grid())
+            inst_ep = [(b_ep,) + tuple(p[1:]) for p in inst]
         for b in range(steps):
             first = step * minibatch
             last = b == steps - 1
             if ep == 0:
-                sampler.sample(seed, first, X, J)
-                eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
+                s_ep.sample(seed, first, X, J)
+                eval_batch(graph, inst_ep, ks, X, J, acc, imp_out=imp)
                 loss = flow.train_step(imp, seed=seed, first=first, lr=lr, want_loss=last)
             else:
-                flow.sample(sampler, seed, first, X, J, u_out=U, alpha=alpha, uniform=uniform)
-                eval_batch(graph, inst, ks, X, J, acc, imp_out=imp)
+                flow.sample(s_ep, seed, first, X, J, u_out=U, alpha=alpha, uniform=uniform)
+                eval_batch(graph, inst_ep, ks, X, J, acc, imp_out=imp)
                 loss = flow.train_step(imp, u=U, lr=lr, want_loss=last)
             acc.reset()
             step += 1

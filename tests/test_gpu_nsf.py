@@ -167,3 +167,39 @@ def test_spline_flow_trained_at_order2_beats_the_grid():
     print("spline flow losses", losses, "variance ratio", ratio, "z", z)
     assert abs(z) < 4.5
     assert ratio > 2.0
+
+
+
+def test_annealed_training_reaches_the_target_temperature():
+    # Appendix A's annealing: epochs at beta 8, 14, 20, 25 (hot to the target); the flow then samples the
+    # target integrand without bias and better than the grid
+    torch, dev = torch_dev()
+    n = 2
+    g = dmc.Graph(n)
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    ks = np.array([1.0], dtype=np.float32)
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, n, n_bins=50)
+    dmc.adapt_grid(g, inst, ks, s, 1 << 20, 5, seed=2)
+    D = dmc.dim(n)
+    f = dmc.Flow(D, synth.flow_masks(D, 6, 5), kind="spline")
+    losses = dmc.train_flow(g, inst, ks, s, f, epochs=4, steps=48, minibatch=1 << 16, lr=2e-3, seed=3,
+                            anneal=[8.0, 14.0, 20.0, BETA])
+    N = 1 << 20
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    est = {}
+    for name in ("grid", "flow"):
+        acc = dmc.Accumulator(1, 1, 1)
+        if name == "grid":
+            s.sample(60, 0, X, J)
+        else:
+            f.sample(s, 61, 0, X, J, alpha=0.85, uniform=0.05)
+        dmc.eval_batch(g, inst, ks, X, J, acc)
+        dmc.accumulate(acc)
+        m, e, _, _ = acc.estimate(1)
+        est[name] = (m[0, 0, 0].real, e[0, 0, 0].real)
+    z = (est["grid"][0] - est["flow"][0]) / math.hypot(est["grid"][1], est["flow"][1])
+    ratio = (est["grid"][1] / est["flow"][1]) ** 2
+    print("annealed losses", losses, "variance ratio", ratio, "z", z)
+    assert abs(z) < 4.5
+    assert ratio > 2.0
