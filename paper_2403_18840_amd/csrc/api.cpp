@@ -956,18 +956,18 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
             HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
             HIP_TRY(dmc::launch_flow_mix(jac, na.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
         } else {
-        dmc::FlowTrainArgs a;
-        train_args(f, a, n_u);
-        a.u_in = u_out ? u_out : up_s;
-        a.ld = u_out ? ld : n_u;
-        a.states = nullptr;
-        a.G = nullptr;
-        a.weff = nullptr;
-        a.w = nullptr;
-        a.loss_part = nullptr;
-        a.lq_out = lq_out ? lq_out : lq_s;
-        HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_u, ncu), S(stream)));
-        HIP_TRY(dmc::launch_flow_mix(jac, a.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
+            dmc::FlowTrainArgs a;
+            train_args(f, a, n_u);
+            a.u_in = u_out ? u_out : up_s;
+            a.ld = u_out ? ld : n_u;
+            a.states = nullptr;
+            a.G = nullptr;
+            a.weff = nullptr;
+            a.w = nullptr;
+            a.loss_part = nullptr;
+            a.lq_out = lq_out ? lq_out : lq_s;
+            HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_u, ncu), S(stream)));
+            HIP_TRY(dmc::launch_flow_mix(jac, a.lq_out, jv_s, n_u, af, ag, au, true, S(stream)));
         }
     }
     if (n_g > 0) {
@@ -986,24 +986,24 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
             HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
             HIP_TRY(dmc::launch_flow_mix(jac + n_u, na.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
         } else {
-        dmc::FlowTrainArgs a;
-        train_args(f, a, n_g);
-        a.u_in = nullptr;
-        a.seed = seed;
-        a.first = first + (uint64_t)n_u;
-        a.ld = ld;
-        a.states = nullptr;
-        a.G = nullptr;
-        a.weff = nullptr;
-        a.w = nullptr;
-        a.loss_part = nullptr;
-        a.lq_out = lq_out ? lq_out + n_u : lq_s + n_u;
-        a.u_out = u_out ? u_out + n_u : nullptr;
-        a.edges = s->d_edges;
-        a.n_bins = s->n_bins;
-        a.jv_out = jv_s + n_u;
-        HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_g, ncu), S(stream)));
-        HIP_TRY(dmc::launch_flow_mix(jac + n_u, a.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
+            dmc::FlowTrainArgs a;
+            train_args(f, a, n_g);
+            a.u_in = nullptr;
+            a.seed = seed;
+            a.first = first + (uint64_t)n_u;
+            a.ld = ld;
+            a.states = nullptr;
+            a.G = nullptr;
+            a.weff = nullptr;
+            a.w = nullptr;
+            a.loss_part = nullptr;
+            a.lq_out = lq_out ? lq_out + n_u : lq_s + n_u;
+            a.u_out = u_out ? u_out + n_u : nullptr;
+            a.edges = s->d_edges;
+            a.n_bins = s->n_bins;
+            a.jv_out = jv_s + n_u;
+            HIP_TRY(dmc::launch_flow_inverse(a, dmc::flow_inverse_blocks(n_g, ncu), S(stream)));
+            HIP_TRY(dmc::launch_flow_mix(jac + n_u, a.lq_out, jv_s + n_u, n_g, af, ag, au, false, S(stream)));
         }
     }
     if (n_f > 0 && f->kind == 1) {
