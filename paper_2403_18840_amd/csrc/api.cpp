@@ -697,7 +697,6 @@ struct dmc_flow {
     // kind 1: rational-quadratic spline couplings (FP32 parameters in `master`, no shadow)
     int kind = 0;
     int64_t n_params = 0;
-    int max_layer_floats = 0;
     std::vector<int> offs_h, dA_h, aidx_h, bidx_h;  // [L], [L], [L][NSF_MAXD], [L][NSF_MAXD]
     int* d_offs = nullptr;
     float* s_grad = nullptr;   // [n_params]
@@ -821,7 +820,6 @@ dmc_status dmc_flow_create_spline(int32_t dim, int32_t n_layers, const int8_t* m
         f->offs_h[l] = (int)off;
         const int P = dmc::NSF_NP * nb;
         const int count = H * na + H + H * H + H + P * H + P;
-        f->max_layer_floats = std::max(f->max_layer_floats, count);
         off += count;
     }
     f->n_params = off;
@@ -1112,7 +1110,6 @@ static dmc::NsfArgs nsf_args(dmc_flow* f, dmc_sampler* s) {
     a.dA = f->d_dA;
     a.n_layers = f->n_layers;
     a.dim = f->dim;
-    a.max_layer_floats = f->max_layer_floats;
     if (s) {
         a.edges = s->d_edges;
         a.n_bins = s->n_bins;

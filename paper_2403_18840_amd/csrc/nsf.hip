@@ -1,11 +1,12 @@
 // Neural spline flow kernels (Appendix A): rational-quadratic spline couplings on [0, 1] with a residual
-// conditioner, uniform base.  One lane carries one sample through every layer; a block stages one
-// layer's parameters in LDS at a time, so a tile of samples goes layer by layer.  FP32 arithmetic; the
-// conditioner is a few thousand multiply-adds per sample and layer, far from the matrix cores' size.
+// conditioner, uniform base.  One lane carries one sample through every layer, layer by layer; the
+// conditioner's weights, the same for every lane, come through scalar loads, so each multiply-add takes
+// one operand from a scalar register and none from LDS.  FP32 arithmetic.  The weight gradients, sums
+// over samples of outer products, run on the FP32 matrix cores.
 //   dmc_nsf_sample_kernel     Philox z -> couplings -> u' -> VEGAS map -> physical map, mixture weight
 //   dmc_nsf_inverse_kernel    u' -> z by the inverse couplings: log q(u'), optionally J_V(u') and every z_l
 //   dmc_nsf_backward_kernel   one layer of the reverse sweep of the weighted forward KL
-//   dmc_nsf_outer_kernel      sums over samples of outer products (the weight gradients), in chunks
+//   dmc_nsf_outer_kernel      sums over samples of outer products (the weight gradients) on the FP32 matrix cores
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -190,23 +191,22 @@ __device__ __forceinline__ float spline_inv_adjoint(const float* th, float v, fl
     return b_v;
 }
 
+// parameters are read through the constant address space: the addresses are uniform across a wave, so the
+// compiler loads them into scalar registers (no LDS traffic per multiply-add)
+typedef const __attribute__((address_space(4))) float* cfloat_p;
 struct Layer {
-    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    cfloat_p W1, b1, W2, b2, W3, b3;
     int dA, dB, P;
 };
 
-// stage layer l's parameters in LDS (the whole block) and return views of them
-__device__ Layer stage_layer(const float* params, int off, int dA, int dB, float* lds) {
+// views of layer l's parameters, read in place
+__device__ __forceinline__ Layer layer_view(const float* params, int off, int dA, int dB) {
     const int P = NSF_NP * dB;
-    const int count = NSF_H * dA + NSF_H + NSF_H * NSF_H + NSF_H + P * NSF_H + P;
-    __syncthreads();
-    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = params[off + i];
-    __syncthreads();
     Layer L;
     L.dA = dA;
     L.dB = dB;
     L.P = P;
-    L.W1 = lds;
+    L.W1 = (cfloat_p)(params + off);
     L.b1 = L.W1 + NSF_H * dA;
     L.W2 = L.b1 + NSF_H;
     L.b2 = L.W2 + NSF_H * NSF_H;
@@ -233,20 +233,30 @@ __device__ __forceinline__ void conditioner(const Layer& L, const float* zA, flo
     }
 }
 
+// the NP parameters of transformed coordinate j, two rows of W3 at a time
 __device__ __forceinline__ void spline_params(const Layer& L, const float* a2, int j, float* th) {
-    for (int r = 0; r < NSF_NP; ++r) {
+    for (int r = 0; r + 1 < NSF_NP; r += 2) {
         const int row = j * NSF_NP + r;
+        float p0 = L.b3[row], p1 = L.b3[row + 1];
+        for (int h = 0; h < NSF_H; ++h) {
+            p0 = __builtin_fmaf(L.W3[row * NSF_H + h], a2[h], p0);
+            p1 = __builtin_fmaf(L.W3[(row + 1) * NSF_H + h], a2[h], p1);
+        }
+        th[r] = p0;
+        th[r + 1] = p1;
+    }
+    if (NSF_NP % 2) {
+        const int row = j * NSF_NP + NSF_NP - 1;
         float p = L.b3[row];
         for (int h = 0; h < NSF_H; ++h) p = __builtin_fmaf(L.W3[row * NSF_H + h], a2[h], p);
-        th[r] = p;
+        th[NSF_NP - 1] = p;
     }
 }
 
 }  // namespace
 
 // flow share: Philox z -> every coupling forward -> u'; VEGAS map, physical map, mixture weight
-__global__ void __launch_bounds__(256) dmc_nsf_sample_kernel(NsfArgs a) {
-    extern __shared__ float lds[];
+__global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
     const int D = a.dim, N = (D + 1) / 4;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = base + threadIdx.x;
@@ -255,7 +265,7 @@ __global__ void __launch_bounds__(256) dmc_nsf_sample_kernel(NsfArgs a) {
         philox_point(a.seed, a.first + (uint64_t)(valid ? s : 0), D, z);
         float lq = 0.0f;
         for (int l = 0; l < a.n_layers; ++l) {
-            const Layer L = stage_layer(a.params, a.offs[l], a.dA[l], D - a.dA[l], lds);
+            const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
             float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
             uint32_t m1, m2;
             for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
@@ -299,8 +309,7 @@ __global__ void __launch_bounds__(256) dmc_nsf_sample_kernel(NsfArgs a) {
 }
 
 // u' -> z by the inverse couplings (last layer first); log q(u') = -sum of the layers' log dy/dx
-__global__ void __launch_bounds__(256) dmc_nsf_inverse_kernel(NsfArgs a) {
-    extern __shared__ float lds[];
+__global__ void __launch_bounds__(256, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
     const int D = a.dim, L_ = a.n_layers;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = base + threadIdx.x;
@@ -329,7 +338,7 @@ __global__ void __launch_bounds__(256) dmc_nsf_inverse_kernel(NsfArgs a) {
         }
         float lq = 0.0f;
         for (int l = L_ - 1; l >= 0; --l) {
-            const Layer L = stage_layer(a.params, a.offs[l], a.dA[l], D - a.dA[l], lds);
+            const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
             float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
             uint32_t m1, m2;
             for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
@@ -350,8 +359,7 @@ __global__ void __launch_bounds__(256) dmc_nsf_inverse_kernel(NsfArgs a) {
 
 // Layer reverse step: adj holds dL/dz_{l-1} (the layer's input side) on entry and dL/dz_l on exit
 __global__ void __launch_bounds__(256) dmc_nsf_backward_kernel(NsfBackArgs a) {
-    extern __shared__ float lds[];
-    const Layer L = stage_layer(a.params, a.off, a.dA, a.dB, lds);
+    const Layer L = layer_view(a.params, a.off, a.dA, a.dB);
     const double inv = *a.inv_wsum;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * blockDim.x) {
         const float wn = (float)((double)a.w[s] * inv);
@@ -402,64 +410,112 @@ __global__ void __launch_bounds__(256) dmc_nsf_backward_kernel(NsfBackArgs a) {
     }
 }
 
-// Sums over samples of outer products, one chunk of OUTER_CHUNK samples and a tile of 16 rows of A per
-// block: partial[c][i][j] = sum_n A[i][n] B[j][n] (j < rowsB), partial[c][i][rowsB] = sum_n A[i][n].
-constexpr int OUTER_CHUNK = 4096;
-constexpr int OUTER_ROWS = 16;
+// Sums over samples of outer products on the matrix cores (FP32 MFMA 32x32x2), C[i][j] = sum_n A[i][n] B[j][n]
+// with rowsB <= 32.  A block takes one chunk of OUTER_CHUNK samples and up to OUTER_TILES tiles of 32 rows of
+// A against every row of B.  Each wave sweeps groups of 32 samples of the chunk: lane half h feeds samples
+// 16 h .. 16 h + 15 of the group into the two K slots of 16 successive MFMAs, so a lane reads 16 consecutive
+// values of one row of A and of one row of B.  The row sums of A (the bias gradient) ride along on the VALU.
+// The waves' tiles are added in LDS in wave order, and the chunks in chunk order by the fold: deterministic.
+constexpr int OUTER_CHUNK = 512;
+constexpr int OUTER_TILES = 4;
+constexpr int OUTER_WAVES = 4;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__global__ void __launch_bounds__(256) dmc_nsf_outer_kernel(const float* A, int rowsA, const float* B, int rowsB,
-                                                             int64_t n, float* partial) {
-    __shared__ float ta[OUTER_ROWS][65];
-    __shared__ float tb[NSF_MAXD > NSF_H ? NSF_MAXD + 1 : NSF_H + 1][65];
-    const int i0 = blockIdx.x * OUTER_ROWS;
-    const int64_t c = blockIdx.y;
-    const int64_t n0 = c * OUTER_CHUNK, n1 = n0 + OUTER_CHUNK < n ? n0 + OUTER_CHUNK : n;
-    const int cols = rowsB + 1;
-    // each thread owns up to three (i, j) outputs of the 16 x cols tile (cols <= 33)
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    for (int64_t nb = n0; nb < n1; nb += 64) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < OUTER_ROWS * 64; e += 256) {
-            const int r = e / 64, q = e % 64;
-            const int64_t nn = nb + q;
-            ta[r][q] = (i0 + r < rowsA && nn < n1) ? A[(int64_t)(i0 + r) * n + nn] : 0.0f;
+__device__ __forceinline__ void load16(const float* M, int row, int rows, int64_t s0, int64_t n1, int64_t n, bool vec,
+                                       float* v) {
+    if (vec && row < rows && s0 + 16 <= n1) {
+        const float4* q = reinterpret_cast<const float4*>(M + (int64_t)row * n + s0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 t = q[k];
+            v[4 * k] = t.x;
+            v[4 * k + 1] = t.y;
+            v[4 * k + 2] = t.z;
+            v[4 * k + 3] = t.w;
         }
-        for (int e = threadIdx.x; e < cols * 64; e += 256) {
-            const int r = e / 64, q = e % 64;
-            const int64_t nn = nb + q;
-            tb[r][q] = r < rowsB ? ((nn < n1) ? B[(int64_t)r * n + nn] : 0.0f) : 1.0f;
-        }
-        __syncthreads();
-        for (int o = 0; o < 3; ++o) {
-            const int t = threadIdx.x + 256 * o;
-            if (t >= OUTER_ROWS * cols) continue;
-            const int r = t / cols, j = t % cols;
-            float sacc = acc[o];
-            for (int q = 0; q < 64; ++q) sacc = __builtin_fmaf(ta[r][q], tb[j][q], sacc);
-            acc[o] = sacc;
-        }
-    }
-    for (int o = 0; o < 3; ++o) {
-        const int t = threadIdx.x + 256 * o;
-        if (t >= OUTER_ROWS * cols) continue;
-        const int r = t / cols, j = t % cols;
-        if (i0 + r < rowsA) partial[(c * rowsA + i0 + r) * cols + j] = acc[o];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = (row < rows && s0 + k < n1) ? M[(int64_t)row * n + s0 + k] : 0.0f;
     }
 }
 
-__global__ void __launch_bounds__(256) dmc_nsf_outer_fold_kernel(const float* partial, int rowsA, int rowsB,
-                                                                  int chunks, float* grad) {
+__global__ void __launch_bounds__(64 * OUTER_WAVES) dmc_nsf_outer_kernel(const float* A, int rowsA, const float* B,
+                                                                          int rowsB, int64_t n, float* partial) {
+    __shared__ float red[OUTER_WAVES][32 * 32 + 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, r = lane & 31;
+    const int t0 = blockIdx.x * OUTER_TILES, tiles = (rowsA + 31) / 32;
+    const int nt = tiles - t0 < OUTER_TILES ? tiles - t0 : OUTER_TILES;
+    const int64_t c = blockIdx.y, n0 = c * OUTER_CHUNK, n1 = n0 + OUTER_CHUNK < n ? n0 + OUTER_CHUNK : n;
+    // 16-byte loads when every row starts 16-byte aligned (chunk starts are multiples of 16 samples)
+    const bool vec = (n & 3) == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+    f32x16 acc[OUTER_TILES];
+    float bias[OUTER_TILES];
+#pragma unroll
+    for (int q = 0; q < OUTER_TILES; ++q) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
+        bias[q] = 0.0f;
+    }
+    for (int64_t g = n0 + 32 * wave; g < n1; g += 32 * OUTER_WAVES) {
+        const int64_t s0 = g + 16 * h;
+        float bv[16];
+        load16(B, r, rowsB, s0, n1, n, vec, bv);
+#pragma unroll
+        for (int q = 0; q < OUTER_TILES; ++q) {
+            if (q < nt) {
+                float av[16];
+                load16(A, (t0 + q) * 32 + r, rowsA, s0, n1, n, vec, av);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k], bv[k], acc[q], 0, 0, 0);
+                    bias[q] += av[k];
+                }
+            }
+        }
+    }
     const int cols = rowsB + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rowsA * cols) return;
+#pragma unroll
+    for (int q = 0; q < OUTER_TILES; ++q) {
+        if (q >= nt) break;
+        __syncthreads();
+        // accumulator register v of lane (h, r): tile row 8 (v / 4) + 4 h + v % 4, column r
+#pragma unroll
+        for (int v = 0; v < 16; ++v) red[wave][(8 * (v / 4) + 4 * h + v % 4) * 32 + r] = acc[q][v];
+        red[wave][1024 + lane] = bias[q];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * cols; e += 64 * OUTER_WAVES) {
+            const int i = e / cols, j = e % cols, row = (t0 + q) * 32 + i;
+            if (row >= rowsA) continue;
+            float s = 0.0f;
+            for (int w = 0; w < OUTER_WAVES; ++w)
+                s += j < rowsB ? red[w][i * 32 + j] : red[w][1024 + i] + red[w][1024 + 32 + i];
+            partial[(c * rowsA + row) * cols + j] = s;
+        }
+    }
+}
+
+// grad[i][j] = sum over chunks of partial[c][i][j]: a block of 1024 threads takes 64 outputs, its 16 waves
+// take every 16th chunk, and the 16 sums are added in wave order
+__global__ void __launch_bounds__(1024) dmc_nsf_outer_fold_kernel(const float* partial, int rowsA, int rowsB,
+                                                                   int chunks, float* grad) {
+    __shared__ float red[16][64];
+    const int cols = rowsB + 1, total = rowsA * cols;
+    const int o = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + o;
     float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * rowsA * cols + t];
+    if (t < total)
+        for (int c = part; c < chunks; c += 16) s += partial[(int64_t)c * total + t];
+    red[part][o] = s;
+    __syncthreads();
+    if (part != 0 || t >= total) return;
+    float u = 0.0f;
+    for (int p = 0; p < 16; ++p) u += red[p][o];
     const int i = t / cols, j = t % cols;
     // weights [rowsA][rowsB] then biases [rowsA]
     if (j < rowsB)
-        grad[i * rowsB + j] = s;
+        grad[i * rowsB + j] = u;
     else
-        grad[rowsA * rowsB + i] = s;
+        grad[rowsA * rowsB + i] = u;
 }
 
 __global__ void __launch_bounds__(1024) dmc_nsf_loss_kernel(const float* w, const float* lq, int64_t n, double* out) {
@@ -511,21 +567,17 @@ static int grid_for(int64_t n, int n_cu) {
 }
 
 hipError_t launch_nsf_sample(const NsfArgs& a, int n_cu, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_nsf_sample_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), a.max_layer_floats * sizeof(float),
-                       st, a);
+    hipLaunchKernelGGL(dmc_nsf_sample_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_nsf_inverse_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), a.max_layer_floats * sizeof(float),
-                       st, a);
+    hipLaunchKernelGGL(dmc_nsf_inverse_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_nsf_backward(const NsfBackArgs& a, int n_cu, hipStream_t st) {
-    const int P = NSF_NP * a.dB;
-    const int count = NSF_H * a.dA + NSF_H + NSF_H * NSF_H + NSF_H + P * NSF_H + P;
-    hipLaunchKernelGGL(dmc_nsf_backward_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), count * sizeof(float), st, a);
+    hipLaunchKernelGGL(dmc_nsf_backward_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -533,14 +585,18 @@ int nsf_outer_chunks(int64_t n) { return (int)((n + OUTER_CHUNK - 1) / OUTER_CHU
 
 hipError_t launch_nsf_outer(const float* A, int rowsA, const float* B, int rowsB, int64_t n, float* partial,
                             hipStream_t st) {
-    const dim3 grid((rowsA + OUTER_ROWS - 1) / OUTER_ROWS, nsf_outer_chunks(n));
-    hipLaunchKernelGGL(dmc_nsf_outer_kernel, grid, dim3(256), 0, st, A, rowsA, B, rowsB, n, partial);
+    if (rowsB > 32 || rowsA < 1 || rowsB < 0) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    const int tiles = (rowsA + 31) / 32;
+    const dim3 grid((tiles + OUTER_TILES - 1) / OUTER_TILES, nsf_outer_chunks(n));
+    hipLaunchKernelGGL(dmc_nsf_outer_kernel, grid, dim3(64 * OUTER_WAVES), 0, st, A, rowsA, B, rowsB, n, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_nsf_outer_fold(const float* partial, int rowsA, int rowsB, int64_t n, float* grad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
     const int t = rowsA * (rowsB + 1);
-    hipLaunchKernelGGL(dmc_nsf_outer_fold_kernel, dim3((t + 255) / 256), dim3(256), 0, st, partial, rowsA, rowsB,
+    hipLaunchKernelGGL(dmc_nsf_outer_fold_kernel, dim3((t + 63) / 64), dim3(1024), 0, st, partial, rowsA, rowsB,
                        nsf_outer_chunks(n), grad);
     return hipGetLastError();
 }

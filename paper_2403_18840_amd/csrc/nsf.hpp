@@ -23,7 +23,7 @@ struct NsfArgs {
     const int* aidx;   // [L][NSF_MAXD]: kept coordinates
     const int* bidx;   // [L][NSF_MAXD]: transformed coordinates
     const int* dA;     // [L]
-    int n_layers, dim, max_layer_floats;
+    int n_layers, dim;
     // points: u_in [D][ld], or (u_in == NULL) the Philox uniforms (seed, first + i) of the uniform sampler
     const float* u_in;
     uint64_t seed, first;
@@ -68,12 +68,12 @@ struct NsfBackArgs {
 };
 hipError_t launch_nsf_backward(const NsfBackArgs& a, int n_cu, hipStream_t st);
 
-// out_partial[c][i][j] = sum over the samples of chunk c of A[i][n] B[j][n] (j < rowsB), and
-// out_partial[c][i][rowsB] = sum of A[i][n] (the bias gradient); deterministic order
+// out_partial[c][i][j] = sum over the samples of chunk c of A[i][n] B[j][n] (j < rowsB <= 32), and
+// out_partial[c][i][rowsB] = sum of A[i][n] (the bias gradient); FP32 matrix cores, deterministic order
 int nsf_outer_chunks(int64_t n);
 hipError_t launch_nsf_outer(const float* A, int rowsA, const float* B, int rowsB, int64_t n, float* partial,
                             hipStream_t st);
-// grad[i][j] (row stride rowsB + 1) = sum over chunks of partial, in chunk order
+// grad = the weights [rowsA][rowsB] then the biases [rowsA]: the sum over chunks of partial, in a fixed order
 hipError_t launch_nsf_outer_fold(const float* partial, int rowsA, int rowsB, int64_t n, float* grad, hipStream_t st);
 // the loss sums: per block (sum w, sum w lq) in FP64
 hipError_t launch_nsf_loss(const float* w, const float* lq, int64_t n, double* partial, int nblk, hipStream_t st);
