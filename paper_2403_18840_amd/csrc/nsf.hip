@@ -1,8 +1,9 @@
 // Neural spline flow kernels (Appendix A): rational-quadratic spline couplings on [0, 1] with a residual
-// conditioner, uniform base.  One lane carries one sample through every layer, layer by layer; the
-// conditioner's weights, the same for every lane, come through scalar loads, so each multiply-add takes
-// one operand from a scalar register and none from LDS.  FP32 arithmetic.  The weight gradients, sums
-// over samples of outer products, run on the FP32 matrix cores.
+// conditioner, uniform base.  One lane carries one sample through every layer, layer by layer.  In the
+// sampling and inverse passes the 32 x 32 hidden layer and the spline-parameter layer run on the FP32
+// matrix cores over the wave's 64 samples, handed back lane by lane; the first layer and the reverse
+// sweep stay on the VALU with their weights, the same for every lane, in scalar registers.  The weight
+// gradients, sums over samples of outer products, run on the matrix cores as well.  FP32 throughout.
 //   dmc_nsf_sample_kernel     Philox z -> couplings -> u' -> VEGAS map -> physical map, mixture weight
 //   dmc_nsf_inverse_kernel    u' -> z by the inverse couplings: log q(u'), optionally J_V(u') and every z_l
 //   dmc_nsf_backward_kernel   one layer of the reverse sweep of the weighted forward KL
@@ -45,84 +46,124 @@ __device__ __forceinline__ void philox_point(uint64_t seed, uint64_t i, int D, f
     }
 }
 
-__device__ __forceinline__ float softplusf(float t) { return log1pf(expf(-fabsf(t))) + fmaxf(t, 0.0f); }
+// Elementary functions of the spline.  With Fast, e^x comes from the hardware 2^x of x log2(e), whose
+// rounding gives a relative error of about 6e-8 |x| (the arguments are softmax logits less their maximum
+// and -|t|, a few tens at most); otherwise from the accurate library exp.  Reciprocals come from the
+// hardware reciprocal (1 ulp) wherever the divisor is bounded away from zero and overflow.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// softplus(t) = max(t, 0) + log1p(e^-|t|), with log1p(e) = log(u) e / (u - 1) for u = 1 + e rounded
+// (Goldberg's formula: exact to a few ulp from an accurate log)
+template <bool Fast>
+__device__ __forceinline__ float softplusf(float t) {
+    const float e = Fast ? __expf(-fabsf(t)) : expf(-fabsf(t)), u = 1.0f + e;
+    const float lp = u == 1.0f ? e : logf(u) * (e * rcp(u - 1.0f));
+    return lp + fmaxf(t, 0.0f);
+}
 __device__ __forceinline__ float sigmoidf_(float t) { return 1.0f / (1.0f + expf(-t)); }
 
-// knots of one coordinate's spline from its NP parameters: x[0..K], y[0..K], d[0..K]; sw, sh: the
-// softmax probabilities (for the reverse sweep)
-__device__ __forceinline__ void knots(const float* th, float* x, float* y, float* d, float* sw, float* sh) {
+// Softmax probabilities of the widths (sw) and heights (sh) and the knot derivatives d[0..K] of one
+// coordinate's spline from its NP parameters
+template <bool Fast>
+__device__ __forceinline__ void spline_shape(const float* th, float* sw, float* sh, float* d) {
     float mw = th[0], mh = th[NSF_K];
+#pragma unroll
     for (int i = 1; i < NSF_K; ++i) {
         mw = fmaxf(mw, th[i]);
         mh = fmaxf(mh, th[NSF_K + i]);
     }
     float zw = 0.0f, zh = 0.0f;
+#pragma unroll
     for (int i = 0; i < NSF_K; ++i) {
-        sw[i] = expf(th[i] - mw);
-        sh[i] = expf(th[NSF_K + i] - mh);
+        sw[i] = Fast ? __expf(th[i] - mw) : expf(th[i] - mw);
+        sh[i] = Fast ? __expf(th[NSF_K + i] - mh) : expf(th[NSF_K + i] - mh);
         zw += sw[i];
         zh += sh[i];
     }
-    const float cw = 1.0f / zw, ch = 1.0f / zh, scale = 1.0f - NSF_K * MINV;
-    x[0] = 0.0f;
-    y[0] = 0.0f;
+    const float cw = Fast ? rcp(zw) : 1.0f / zw, ch = Fast ? rcp(zh) : 1.0f / zh;
+#pragma unroll
     for (int i = 0; i < NSF_K; ++i) {
         sw[i] *= cw;
         sh[i] *= ch;
-        x[i + 1] = x[i] + (MINV + scale * sw[i]);
-        y[i + 1] = y[i] + (MINV + scale * sh[i]);
     }
-    x[NSF_K] = 1.0f;
-    y[NSF_K] = 1.0f;
     d[0] = 1.0f;
     d[NSF_K] = 1.0f;
-    for (int i = 1; i < NSF_K; ++i) d[i] = MINV + softplusf(th[2 * NSF_K + i - 1]);
+#pragma unroll
+    for (int i = 1; i < NSF_K; ++i) d[i] = MINV + softplusf<Fast>(th[2 * NSF_K + i - 1]);
 }
 
-__device__ __forceinline__ int find_bin(const float* kn, float v) {
-    int k = 0;
-    for (int i = 1; i < NSF_K; ++i) k += kn[i] <= v;
-    return k;
+// The bin holding v and its knots.  Knot i + 1 is knot i plus m + (1 - K m) times the softmax probability,
+// the last knot is 1 on both axes; the bin is the last one whose left knot (on x, or on y for the inverse)
+// is <= v.  An unrolled scan with selects: every array index is a constant, so nothing leaves registers.
+struct Bin {
+    float xk, yk, W, H, d0, d1;
+    int k;
+};
+
+__device__ __forceinline__ Bin find_bin(const float* sw, const float* sh, const float* d, float v, bool on_y) {
+    const float scale = 1.0f - NSF_K * MINV;
+    Bin b;
+    float cx = 0.0f, cy = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NSF_K; ++i) {
+        const float nx = i == NSF_K - 1 ? 1.0f : cx + (MINV + scale * sw[i]);
+        const float ny = i == NSF_K - 1 ? 1.0f : cy + (MINV + scale * sh[i]);
+        if (i == 0 || (on_y ? cy : cx) <= v) {
+            b.xk = cx;
+            b.yk = cy;
+            b.W = nx - cx;
+            b.H = ny - cy;
+            b.d0 = d[i];
+            b.d1 = d[i + 1];
+            b.k = i;
+        }
+        cx = nx;
+        cy = ny;
+    }
+    return b;
 }
 
 // forward spline: v -> y, returns log dy/dx
 __device__ __forceinline__ float spline_fwd(const float* th, float& v) {
-    float x[NSF_K + 1], y[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
-    knots(th, x, y, d, sw, sh);
-    const int k = find_bin(x, v);
-    const float W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
-    const float xi = fminf(fmaxf((v - x[k]) / W, 0.0f), 1.0f), t = xi * (1.0f - xi);
-    const float den = s + (d[k + 1] + d[k] - 2.0f * s) * t;
-    v = y[k] + H * (s * xi * xi + d[k] * t) / den;
-    const float num = d[k + 1] * xi * xi + 2.0f * s * t + d[k] * (1.0f - xi) * (1.0f - xi);
-    return 2.0f * logf(s) + logf(num) - 2.0f * logf(den);
+    float sw[NSF_K], sh[NSF_K], d[NSF_K + 1];
+    spline_shape<true>(th, sw, sh, d);
+    const Bin b = find_bin(sw, sh, d, v, false);
+    const float rW = rcp(b.W), s = b.H * rW;
+    const float xi = fminf(fmaxf((v - b.xk) * rW, 0.0f), 1.0f), t = xi * (1.0f - xi);
+    const float den = s + (b.d1 + b.d0 - 2.0f * s) * t, rden = rcp(den);
+    v = b.yk + b.H * (s * xi * xi + b.d0 * t) * rden;
+    const float num = b.d1 * xi * xi + 2.0f * s * t + b.d0 * (1.0f - xi) * (1.0f - xi);
+    // log(s^2 num / den^2): s, num and den lie within [1e-3, 1e3] or so, far from FP32's limits
+    return logf(s * s * num * (rden * rden));
 }
 
 // inverse spline: v (an output) -> x, returns log dy/dx at x
+template <bool Fast>
 __device__ __forceinline__ float spline_inv(const float* th, float& v) {
-    float x[NSF_K + 1], y[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
-    knots(th, x, y, d, sw, sh);
-    const int k = find_bin(y, v);
-    const float W = x[k + 1] - x[k], H = y[k + 1] - y[k], s = H / W;
-    const float dy = v - y[k], g = d[k + 1] + d[k] - 2.0f * s;
-    const float a = H * (s - d[k]) + dy * g, b = H * d[k] - dy * g, c = -s * dy;
-    const float sq = sqrtf(fmaxf(b * b - 4.0f * a * c, 0.0f));
-    const float xi = fminf(fmaxf(2.0f * c / (-b - sq), 0.0f), 1.0f), t = xi * (1.0f - xi);
-    v = x[k] + xi * W;
-    const float den = s + g * t;
-    const float num = d[k + 1] * xi * xi + 2.0f * s * t + d[k] * (1.0f - xi) * (1.0f - xi);
-    return 2.0f * logf(s) + logf(num) - 2.0f * logf(den);
+    float sw[NSF_K], sh[NSF_K], d[NSF_K + 1];
+    spline_shape<Fast>(th, sw, sh, d);
+    const Bin b = find_bin(sw, sh, d, v, true);
+    const float W = b.W, H = b.H, s = H * rcp(W);
+    const float dy = v - b.yk, g = b.d1 + b.d0 - 2.0f * s;
+    const float qa = H * (s - b.d0) + dy * g, qb = H * b.d0 - dy * g, qc = -s * dy;
+    const float sq = sqrtf(fmaxf(qb * qb - 4.0f * qa * qc, 0.0f));
+    // the root of the quadratic in its stable form; -qb - sq < 0 unless dy = 0, where 0 / 0 is clamped to 0
+    const float xi = fminf(fmaxf(2.0f * qc / (-qb - sq), 0.0f), 1.0f), t = xi * (1.0f - xi);
+    v = b.xk + xi * W;
+    const float den = s + g * t, rden = rcp(den);
+    const float num = b.d1 * xi * xi + 2.0f * s * t + b.d0 * (1.0f - xi) * (1.0f - xi);
+    return logf(s * s * num * (rden * rden));
 }
 
 // Reverse sweep of phi = gx x + gl log(dy/dx) through the inverse spline at output v: returns
 // d phi / d v and writes d phi / d theta (NP values).
 __device__ __forceinline__ float spline_inv_adjoint(const float* th, float v, float gx, float gl, float* gth) {
-    float xs[NSF_K + 1], ys[NSF_K + 1], d[NSF_K + 1], sw[NSF_K], sh[NSF_K];
-    knots(th, xs, ys, d, sw, sh);
-    const int k = find_bin(ys, v);
-    const float W = xs[k + 1] - xs[k], H = ys[k + 1] - ys[k], s = H / W;
-    const float d0 = d[k], d1 = d[k + 1];
-    const float dy = v - ys[k], g = d1 + d0 - 2.0f * s;
+    float sw[NSF_K], sh[NSF_K], d[NSF_K + 1];
+    spline_shape<false>(th, sw, sh, d);
+    const Bin bn = find_bin(sw, sh, d, v, true);
+    const int k = bn.k;
+    const float W = bn.W, H = bn.H, s = H / W;
+    const float d0 = bn.d0, d1 = bn.d1;
+    const float dy = v - bn.yk, g = d1 + d0 - 2.0f * s;
     const float a = H * (s - d0) + dy * g, b = H * d0 - dy * g, c = -s * dy;
     const float sq = sqrtf(fmaxf(b * b - 4.0f * a * c, 0.0f));
     const float q = -b - sq;
@@ -167,27 +208,30 @@ __device__ __forceinline__ float spline_inv_adjoint(const float* th, float v, fl
     b_W += -b_s * H / (W * W);
     // knots: x_k = sum_{i<k} w_i, W = w_k; likewise y, H
     float bw[NSF_K], bh[NSF_K];
+#pragma unroll
     for (int i = 0; i < NSF_K; ++i) {
-        bw[i] = i < k ? b_xk : 0.0f;
-        bh[i] = i < k ? b_yk : 0.0f;
+        bw[i] = i < k ? b_xk : (i == k ? b_W : 0.0f);
+        bh[i] = i < k ? b_yk : (i == k ? b_H : 0.0f);
     }
-    bw[k] += b_W;
-    bh[k] += b_H;
     // w = m + (1 - K m) softmax(theta_w): dtheta_i = (1 - K m) sw_i (bw_i - sum_j sw_j bw_j)
     float pw = 0.0f, ph = 0.0f;
+#pragma unroll
     for (int i = 0; i < NSF_K; ++i) {
         pw += sw[i] * bw[i];
         ph += sh[i] * bh[i];
     }
     const float scale = 1.0f - NSF_K * MINV;
+#pragma unroll
     for (int i = 0; i < NSF_K; ++i) {
         gth[i] = scale * sw[i] * (bw[i] - pw);
         gth[NSF_K + i] = scale * sh[i] * (bh[i] - ph);
     }
-    for (int i = 0; i < NSF_K - 1; ++i) gth[2 * NSF_K + i] = 0.0f;
-    // interior derivatives d_i (i = 1..K-1) = m + softplus(theta[2K + i - 1])
-    if (k >= 1) gth[2 * NSF_K + k - 1] += b_d0 * sigmoidf_(th[2 * NSF_K + k - 1]);
-    if (k + 1 <= NSF_K - 1) gth[2 * NSF_K + k] += b_d1 * sigmoidf_(th[2 * NSF_K + k]);
+    // interior derivatives d_i (i = 1..K-1) = m + softplus(theta[2K + i - 1]): d_k takes b_d0, d_{k+1} b_d1
+#pragma unroll
+    for (int i = 1; i < NSF_K; ++i) {
+        const float bd = i == k ? b_d0 : (i == k + 1 ? b_d1 : 0.0f);
+        gth[2 * NSF_K + i - 1] = bd * sigmoidf_(th[2 * NSF_K + i - 1]);
+    }
     return b_v;
 }
 
@@ -253,6 +297,81 @@ __device__ __forceinline__ void spline_params(const Layer& L, const float* a2, i
     }
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// lanes 32..63 of x trade places with lanes 0..31 of y
+__device__ __forceinline__ void swap32(float& x, float& y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+
+// Matrix-core products of the conditioner for the wave's 64 samples (lane = sample), y[r] = sum_h W[row0 + r][h]
+// x[h] for r < 32, on FP32 MFMA 32x32x2: samples 0..31 form one output tile, samples 32..63 the other.  In
+// MFMA step t the two K slots carry h = t (lanes 0..31) and h = 16 + t (lanes 32..63).  mfma_operands turns a
+// lane's own x into those B operands; rows_mfma takes a lane's 16 weights of row row0 + lane % 32 and hands
+// every lane the 32 outputs of its own sample.  Every lane of the wave must take part.
+__device__ __forceinline__ void mfma_operands(const float* x, float* b0, float* b1) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        b0[t] = x[t];
+        b1[t] = x[16 + t];
+        swap32(b0[t], b1[t]);
+    }
+}
+
+__device__ __forceinline__ void rows_mfma(const float* W, int rows, int row0, const float* b0, const float* b1,
+                                          float* y) {
+    const int lane = threadIdx.x & 63, m = lane & 31, hh = lane >> 5;
+    const int row = row0 + m;
+    const bool ok = row < rows;
+    const float* wr = W + (int64_t)(ok ? row : 0) * NSF_H + 16 * hh;
+    f32x16 c0, c1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) c0[v] = c1[v] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const float w = ok ? wr[t] : 0.0f;
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(w, b0[t], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w, b1[t], c1, 0, 0, 0);
+    }
+    // register v of a tile holds row 8 (v / 4) + 4 (lane / 32) + v % 4 for sample lane % 32 of the tile
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        float p = c0[v], q = c1[v];
+        swap32(p, q);
+        y[8 * (v / 4) + v % 4] = p;
+        y[8 * (v / 4) + 4 + v % 4] = q;
+    }
+}
+
+// a1 = relu(W1 zA + b1) on the VALU, a2 = relu(W2 a1 + b2) + a1 on the matrix cores; b0, b1 receive a2 as
+// B operands for the spline-parameter rows
+__device__ __forceinline__ void conditioner_mfma(const Layer& L, const float* Wg, const float* zA, float* b0,
+                                                 float* b1) {
+    float a1[NSF_H], pre[NSF_H];
+    for (int h = 0; h < NSF_H; ++h) {
+        float p = L.b1[h];
+        for (int i = 0; i < L.dA; ++i) p = __builtin_fmaf(L.W1[h * L.dA + i], zA[i], p);
+        a1[h] = fmaxf(p, 0.0f);
+    }
+    mfma_operands(a1, b0, b1);
+    rows_mfma(Wg + NSF_H * L.dA + NSF_H, NSF_H, 0, b0, b1, pre);
+    float a2[NSF_H];
+#pragma unroll
+    for (int h = 0; h < NSF_H; ++h) a2[h] = fmaxf(pre[h] + L.b2[h], 0.0f) + a1[h];
+    mfma_operands(a2, b0, b1);
+}
+
+// the NP parameters of transformed coordinate j from the B operands of a2
+__device__ __forceinline__ void spline_params_mfma(const Layer& L, const float* Wg, const float* b0, const float* b1,
+                                                   int j, float* th) {
+    float t[32];
+    rows_mfma(Wg + NSF_H * L.dA + NSF_H + NSF_H * NSF_H + NSF_H, L.P, j * NSF_NP, b0, b1, t);
+#pragma unroll
+    for (int r = 0; r < NSF_NP; ++r) th[r] = t[r] + L.b3[j * NSF_NP + r];
+}
+
 }  // namespace
 
 // flow share: Philox z -> every coupling forward -> u'; VEGAS map, physical map, mixture weight
@@ -266,12 +385,12 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
         float lq = 0.0f;
         for (int l = 0; l < a.n_layers; ++l) {
             const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
-            float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
-            uint32_t m1, m2;
+            const float* Wg = a.params + a.offs[l];
+            float zA[NSF_MAXD], b0[16], b1[16], th[NSF_NP];
             for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
-            conditioner(L, zA, a1, a2, m1, m2);
+            conditioner_mfma(L, Wg, zA, b0, b1);
             for (int j = 0; j < L.dB; ++j) {
-                spline_params(L, a2, j, th);
+                spline_params_mfma(L, Wg, b0, b1, j, th);
                 const int col = a.bidx[l * NSF_MAXD + j];
                 float v = z[col];
                 lq -= spline_fwd(th, v);
@@ -308,7 +427,10 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
     }
 }
 
-// u' -> z by the inverse couplings (last layer first); log q(u') = -sum of the layers' log dy/dx
+// u' -> z by the inverse couplings (last layer first); log q(u') = -sum of the layers' log dy/dx.  The pass
+// that feeds training (Fast = false) takes the accurate e^x: the weight gradients of a peaked flow magnify
+// its rounding.
+template <bool Fast>
 __global__ void __launch_bounds__(256, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
     const int D = a.dim, L_ = a.n_layers;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
@@ -339,15 +461,15 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
         float lq = 0.0f;
         for (int l = L_ - 1; l >= 0; --l) {
             const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
-            float zA[NSF_MAXD], a1[NSF_H], a2[NSF_H], th[NSF_NP];
-            uint32_t m1, m2;
+            const float* Wg = a.params + a.offs[l];
+            float zA[NSF_MAXD], b0[16], b1[16], th[NSF_NP];
             for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
-            conditioner(L, zA, a1, a2, m1, m2);
+            conditioner_mfma(L, Wg, zA, b0, b1);
             for (int j = 0; j < L.dB; ++j) {
-                spline_params(L, a2, j, th);
+                spline_params_mfma(L, Wg, b0, b1, j, th);
                 const int col = a.bidx[l * NSF_MAXD + j];
                 float v = z[col];
-                lq -= spline_inv(th, v);
+                lq -= spline_inv<Fast>(th, v);
                 z[col] = v;
             }
             if (valid && a.zs)
@@ -419,8 +541,6 @@ __global__ void __launch_bounds__(256) dmc_nsf_backward_kernel(NsfBackArgs a) {
 constexpr int OUTER_CHUNK = 512;
 constexpr int OUTER_TILES = 4;
 constexpr int OUTER_WAVES = 4;
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 __device__ __forceinline__ void load16(const float* M, int row, int rows, int64_t s0, int64_t n1, int64_t n, bool vec,
                                        float* v) {
     if (vec && row < rows && s0 + 16 <= n1) {
@@ -572,7 +692,10 @@ hipError_t launch_nsf_sample(const NsfArgs& a, int n_cu, hipStream_t st) {
 }
 
 hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_nsf_inverse_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
+    if (a.zs)
+        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<false>, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<true>, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
