@@ -200,12 +200,17 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
                      "peak": peak, "unit": "TFLOP/s",
                      "frac": flop / (k_ms * 1e-3) / 1e12 / peak, "kernel_ms": k_ms,
                      "flop_per_launch": flop},
-        "z": float((vg["re"] - fl["re"]) / math.hypot(ev, ef)),
-        "variance_ratio": float((ev / ef) ** 2),
-        "variance_ratio_mad": float((vg["sigma_mad"] / fl["sigma_mad"]) ** 2),
-        "efficiency_steady": float((ev ** 2 * t_v) / (ef ** 2 * t_f)),
-        "efficiency_total": float((ev ** 2 * (t_adapt + t_v)) / (ef ** 2 * (t_adapt + t_train + t_f))),
+        # ratios of spreads are undefined with a single batch (zero spread): null
+        "z": _ratio(vg["re"] - fl["re"], math.hypot(ev, ef)),
+        "variance_ratio": _ratio(ev ** 2, ef ** 2),
+        "variance_ratio_mad": _ratio(vg["sigma_mad"] ** 2, fl["sigma_mad"] ** 2),
+        "efficiency_steady": _ratio(ev ** 2 * t_v, ef ** 2 * t_f),
+        "efficiency_total": _ratio(ev ** 2 * (t_adapt + t_v), ef ** 2 * (t_adapt + t_train + t_f)),
     }
+
+
+def _ratio(a, b):
+    return float(a / b) if b > 0 and math.isfinite(b) else None
 
 
 def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, thermal=2000, n_batches=64,

@@ -38,13 +38,22 @@ __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1
 }
 
 // the uniform sampler's draw: coordinate d of sample i from counter (i lo, i hi, d / 4, 0), word d % 4
-__device__ __forceinline__ void philox_point(uint64_t seed, uint64_t i, int D, float* u) {
+template <class V>
+__device__ __forceinline__ void philox_point(uint64_t seed, uint64_t i, int D, V u) {
     for (int q = 0; q < (D + 3) / 4; ++q) {
         uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)q, 0u};
         philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
         for (int w = 0; w < 4 && 4 * q + w < D; ++w) u[4 * q + w] = ((float)(c[w] >> 8) + 0.5f) * 0x1p-24f;
     }
 }
+
+// A lane's D coordinates in LDS, one column per thread of a 256-thread block: indexed by the coupling
+// masks, which are known only at run time, the coordinates would otherwise live in scratch memory
+constexpr int NSF_BLOCK = 256;
+struct LdsCol {
+    float* p;
+    __device__ __forceinline__ float& operator[](int d) const { return p[d * NSF_BLOCK]; }
+};
 
 // Elementary functions of the spline.  With Fast, e^x comes from the hardware 2^x of x log2(e), whose
 // rounding gives a relative error of about 6e-8 |x| (the arguments are softmax logits less their maximum
@@ -320,20 +329,24 @@ __device__ __forceinline__ void mfma_operands(const float* x, float* b0, float* 
     }
 }
 
-__device__ __forceinline__ void rows_mfma(const float* W, int rows, int row0, const float* b0, const float* b1,
-                                          float* y) {
+// a lane's 16 weights of row row0 + lane % 32 (zero past the last row)
+__device__ __forceinline__ void load_rows(const float* W, int rows, int row0, float* w) {
     const int lane = threadIdx.x & 63, m = lane & 31, hh = lane >> 5;
     const int row = row0 + m;
     const bool ok = row < rows;
     const float* wr = W + (int64_t)(ok ? row : 0) * NSF_H + 16 * hh;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) w[t] = ok ? wr[t] : 0.0f;
+}
+
+__device__ __forceinline__ void rows_mfma(const float* w, const float* b0, const float* b1, float* y) {
     f32x16 c0, c1;
 #pragma unroll
     for (int v = 0; v < 16; ++v) c0[v] = c1[v] = 0.0f;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        const float w = ok ? wr[t] : 0.0f;
-        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(w, b0[t], c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w, b1[t], c1, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(w[t], b0[t], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w[t], b1[t], c1, 0, 0, 0);
     }
     // register v of a tile holds row 8 (v / 4) + 4 (lane / 32) + v % 4 for sample lane % 32 of the tile
 #pragma unroll
@@ -345,29 +358,46 @@ __device__ __forceinline__ void rows_mfma(const float* W, int rows, int row0, co
     }
 }
 
-// a1 = relu(W1 zA + b1) on the VALU, a2 = relu(W2 a1 + b2) + a1 on the matrix cores; b0, b1 receive a2 as
-// B operands for the spline-parameter rows
-__device__ __forceinline__ void conditioner_mfma(const Layer& L, const float* Wg, const float* zA, float* b0,
+// a1 = relu(W1 zA + b1) on the VALU (zA: the coordinates z[aidx[i]], i < dA), a2 = relu(W2 a1 + b2) + a1 on the
+// matrix cores; b0, b1 receive a2 as B operands for the spline-parameter rows
+template <class V>
+__device__ __forceinline__ void conditioner_mfma(const Layer& L, const float* Wg, V z, const int* aidx, float* b0,
                                                  float* b1) {
+    // the first layer takes the kept coordinates one at a time (the same order of sums as row by row), so
+    // that no array is indexed at run time
     float a1[NSF_H], pre[NSF_H];
-    for (int h = 0; h < NSF_H; ++h) {
-        float p = L.b1[h];
-        for (int i = 0; i < L.dA; ++i) p = __builtin_fmaf(L.W1[h * L.dA + i], zA[i], p);
-        a1[h] = fmaxf(p, 0.0f);
+#pragma unroll
+    for (int h = 0; h < NSF_H; ++h) a1[h] = L.b1[h];
+    for (int i = 0; i < L.dA; ++i) {
+        const float zi = z[aidx[i]];
+#pragma unroll
+        for (int h = 0; h < NSF_H; ++h) a1[h] = __builtin_fmaf(L.W1[h * L.dA + i], zi, a1[h]);
     }
+#pragma unroll
+    for (int h = 0; h < NSF_H; ++h) a1[h] = fmaxf(a1[h], 0.0f);
     mfma_operands(a1, b0, b1);
-    rows_mfma(Wg + NSF_H * L.dA + NSF_H, NSF_H, 0, b0, b1, pre);
+    float w[16];
+    load_rows(Wg + NSF_H * L.dA + NSF_H, NSF_H, 0, w);
+    rows_mfma(w, b0, b1, pre);
     float a2[NSF_H];
 #pragma unroll
     for (int h = 0; h < NSF_H; ++h) a2[h] = fmaxf(pre[h] + L.b2[h], 0.0f) + a1[h];
     mfma_operands(a2, b0, b1);
 }
 
-// the NP parameters of transformed coordinate j from the B operands of a2
-__device__ __forceinline__ void spline_params_mfma(const Layer& L, const float* Wg, const float* b0, const float* b1,
-                                                   int j, float* th) {
+// the spline-parameter rows: W3 of the layer (its P rows start at row j NP for coordinate j)
+__device__ __forceinline__ const float* w3_rows(const Layer& L, const float* Wg) {
+    return Wg + NSF_H * L.dA + NSF_H + NSF_H * NSF_H + NSF_H;
+}
+
+// the NP parameters of transformed coordinate j from the B operands of a2 and the lane's W3 weights w (as
+// load_rows gives them for row0 = j NP); w then receives those of coordinate j + 1, so that their loads
+// overlap the spline of coordinate j
+__device__ __forceinline__ void spline_params_mfma(const Layer& L, const float* W3, const float* b0, const float* b1,
+                                                   int j, float* w, float* th) {
     float t[32];
-    rows_mfma(Wg + NSF_H * L.dA + NSF_H + NSF_H * NSF_H + NSF_H, L.P, j * NSF_NP, b0, b1, t);
+    rows_mfma(w, b0, b1, t);
+    if (j + 1 < L.dB) load_rows(W3, L.P, (j + 1) * NSF_NP, w);
 #pragma unroll
     for (int r = 0; r < NSF_NP; ++r) th[r] = t[r] + L.b3[j * NSF_NP + r];
 }
@@ -375,22 +405,25 @@ __device__ __forceinline__ void spline_params_mfma(const Layer& L, const float* 
 }  // namespace
 
 // flow share: Philox z -> every coupling forward -> u'; VEGAS map, physical map, mixture weight
-__global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
+__global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_sample_kernel(NsfArgs a) {
+    __shared__ float zl[NSF_MAXD * NSF_BLOCK];
     const int D = a.dim, N = (D + 1) / 4;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = base + threadIdx.x;
         const bool valid = s < a.n;
-        float z[NSF_MAXD];
+        const LdsCol z{zl + threadIdx.x};
         philox_point(a.seed, a.first + (uint64_t)(valid ? s : 0), D, z);
         float lq = 0.0f;
         for (int l = 0; l < a.n_layers; ++l) {
             const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
             const float* Wg = a.params + a.offs[l];
-            float zA[NSF_MAXD], b0[16], b1[16], th[NSF_NP];
-            for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
-            conditioner_mfma(L, Wg, zA, b0, b1);
+            float b0[16], b1[16], th[NSF_NP];
+            conditioner_mfma(L, Wg, z, a.aidx + l * NSF_MAXD, b0, b1);
+            const float* W3 = w3_rows(L, Wg);
+            float w[16];
+            load_rows(W3, L.P, 0, w);
             for (int j = 0; j < L.dB; ++j) {
-                spline_params_mfma(L, Wg, b0, b1, j, th);
+                spline_params_mfma(L, W3, b0, b1, j, w, th);
                 const int col = a.bidx[l * NSF_MAXD + j];
                 float v = z[col];
                 lq -= spline_fwd(th, v);
@@ -398,7 +431,9 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
             }
         }
         if (!valid) continue;
-        float J = 1.0f, jv = 1.0f, y[NSF_MAXD];
+        // the grid map replaces each u' by y in the lane's LDS column
+        const LdsCol& y = z;
+        float J = 1.0f, jv = 1.0f;
         for (int d = 0; d < D; ++d) {
             const float up = z[d];
             if (a.u_out) a.u_out[(int64_t)d * a.ld + s] = up;
@@ -431,13 +466,14 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_sample_kernel(NsfArgs a) {
 // that feeds training (Fast = false) takes the accurate e^x: the weight gradients of a peaked flow magnify
 // its rounding.
 template <bool Fast>
-__global__ void __launch_bounds__(256, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
+__global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
+    __shared__ float zl[NSF_MAXD * NSF_BLOCK];
     const int D = a.dim, L_ = a.n_layers;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = base + threadIdx.x;
         const bool valid = s < a.n;
         const int64_t sc = valid ? s : 0;
-        float z[NSF_MAXD];
+        const LdsCol z{zl + threadIdx.x};
         if (a.u_in) {
             for (int d = 0; d < D; ++d) z[d] = a.u_in[(int64_t)d * a.ld + sc];
         } else {
@@ -462,11 +498,13 @@ __global__ void __launch_bounds__(256, 4) dmc_nsf_inverse_kernel(NsfArgs a) {
         for (int l = L_ - 1; l >= 0; --l) {
             const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
             const float* Wg = a.params + a.offs[l];
-            float zA[NSF_MAXD], b0[16], b1[16], th[NSF_NP];
-            for (int i = 0; i < L.dA; ++i) zA[i] = z[a.aidx[l * NSF_MAXD + i]];
-            conditioner_mfma(L, Wg, zA, b0, b1);
+            float b0[16], b1[16], th[NSF_NP];
+            conditioner_mfma(L, Wg, z, a.aidx + l * NSF_MAXD, b0, b1);
+            const float* W3 = w3_rows(L, Wg);
+            float w[16];
+            load_rows(W3, L.P, 0, w);
             for (int j = 0; j < L.dB; ++j) {
-                spline_params_mfma(L, Wg, b0, b1, j, th);
+                spline_params_mfma(L, W3, b0, b1, j, w, th);
                 const int col = a.bidx[l * NSF_MAXD + j];
                 float v = z[col];
                 lq -= spline_inv<Fast>(th, v);
@@ -687,15 +725,15 @@ static int grid_for(int64_t n, int n_cu) {
 }
 
 hipError_t launch_nsf_sample(const NsfArgs& a, int n_cu, hipStream_t st) {
-    hipLaunchKernelGGL(dmc_nsf_sample_kernel, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(dmc_nsf_sample_kernel, dim3(grid_for(a.n, n_cu)), dim3(NSF_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st) {
     if (a.zs)
-        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<false>, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<false>, dim3(grid_for(a.n, n_cu)), dim3(NSF_BLOCK), 0, st, a);
     else
-        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<true>, dim3(grid_for(a.n, n_cu)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(dmc_nsf_inverse_kernel<true>, dim3(grid_for(a.n, n_cu)), dim3(NSF_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 
