@@ -121,12 +121,19 @@ __device__ __forceinline__ Bin find_bin(const float* sw, const float* sh, const 
             b.yk = cy;
             b.W = nx - cx;
             b.H = ny - cy;
-            b.d0 = d[i];
-            b.d1 = d[i + 1];
             b.k = i;
         }
         cx = nx;
         cy = ny;
+    }
+    // the knot derivatives by a second pass of selects on the bin index (selecting them in the scan above
+    // lets the compiler turn d into a scratch array indexed at run time)
+    b.d0 = d[0];
+    b.d1 = d[1];
+#pragma unroll
+    for (int i = 1; i < NSF_K; ++i) {
+        b.d0 = b.k == i ? d[i] : b.d0;
+        b.d1 = b.k == i ? d[i + 1] : b.d1;
     }
     return b;
 }
