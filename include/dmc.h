@@ -224,6 +224,20 @@ dmc_status dmc_flow_sample(dmc_flow* f, dmc_sampler* s, uint64_t seed, uint64_t 
                            void* stream);
 /* log q(u') by the inverse couplings; u: device float[D][ld]; lq: device float[n]. */
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream);
+/* Random-walk proposals in the base space of a spline flow T (Sec. IV, the optional base-space moves of
+ * NF-MCMC), one per chain state.  u_state (device float[D][ld_u]): the states' grid coordinates u' (as
+ * the chains keep them).  Each state's base point z = T^-1(u') moves to z' = z + sigma xi wrapped onto
+ * [0, 1)^D, xi standard normals: pair j of coordinates (2j, 2j + 1) of chain i = first + index takes the
+ * Philox4x32-10 words w0, w1 of counter (i mod 2^32, i div 2^32, j, 1) and key seed, u_k = ((w_k >> 8) +
+ * 1/2) 2^-24, r = sqrt(-2 log u0), xi = (r cos 2 pi u1, r sin 2 pi u1) (Box-Muller).  The proposal u'' =
+ * T(z') is mapped like dmc_flow_sample's flow share: x (device float[D][ld]), jac (1/q of the mixture with
+ * shares mix_flow, mix_uniform and the rest on the grid, as dmc_flow_sample uses them), u_out (device
+ * float[D][ld]: u''), jac_flow (the flow's own weight J_phys J_V J_t / q_T(u'')) and jac_flow_state (the
+ * same at each state).  Feed them to dmc_chains_step_walk.  DMC_E_INVALID for an affine flow, sigma not
+ * positive and finite, or the shapes of dmc_flow_sample. */
+dmc_status dmc_flow_walk(dmc_flow* f, dmc_sampler* s, const float* u_state, int64_t ld_u, int64_t n, double sigma,
+                         uint64_t seed, uint64_t first, float* x, int64_t ld, float* jac, float* jac_flow, float* u_out,
+                         float* jac_flow_state, double mix_flow, double mix_uniform, void* stream);
 /* One step of the weighted forward KL L = -sum_i w_i log q(u'_i) / sum_i w_i over n points:
  * u' = u (device float[D][ld]) or, if u is NULL, the Philox uniforms (seed, first .. first+n-1);
  * w: device float[n] >= 0.  lr > 0 applies one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) to the
@@ -264,6 +278,18 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
  * measure != 0 accumulates the chains' states after the step. */
 dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* u_prop,
                            int64_t ld_u, int64_t offset, double alpha, uint64_t seed, int32_t measure, void* stream);
+/* One random-walk step in the flow's base space (Sec. IV: the optional base-space proposals of NF-MCMC):
+ * chain c's proposal is column c, made by dmc_flow_walk from the chain's own state.  jac_prop (1/q of the
+ * sampler's mixture, for the target pi) as in dmc_chains_step; jac_flow_prop and jac_flow_state (device
+ * float[n]) are the flow's own weights 1/q_T at the proposals and at the current states.  In base
+ * coordinates the target is pi / q_T and the move is symmetric, so the proposal is taken when
+ * u pi(x) q_T(x') < pi(x') q_T(x), with the step's uniform u as in dmc_chains_step.  A chain without a
+ * valid state, or with a q_T that is not finite and positive on either side, stays.  The chains must keep
+ * their coordinates (dim_u = the flow's dimension) and have taken an independence step (else
+ * DMC_E_INVALID). */
+dmc_status dmc_chains_step_walk(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop,
+                                const float* jac_flow_prop, const float* jac_flow_state, const float* u_prop,
+                                int64_t ld_u, double alpha, uint64_t seed, int32_t measure, void* stream);
 /* sums: host double[n_batches][S + 1][2], S = n_groups n_roots n_k 2 slots in the f_out order, per batch:
  * [b][s][0] = sum f_s/pi, [b][s][1] = sum (f_s/pi)^2; row S: sum q/pi and its squares.  n_measured: chain
  * states added (all batches);

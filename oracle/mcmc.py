@@ -1,5 +1,5 @@
-"""Oracle Markov-chain estimator with independent proposals (test infrastructure; only tests/, the
-smoke check and the bench's CPU leg use it).
+"""Oracle Markov-chain estimator with independent proposals and random-walk moves in a flow's base space
+(test infrastructure; only tests/, the smoke check and the bench's CPU leg use it).
 
 Follows Sec. IV: the target pi = alpha q + (1 - alpha) p with p = |f| (eq.
 target_distr_nf_mcmc_qft_revised), the Metropolis-Hastings acceptance
@@ -71,6 +71,68 @@ def step(state, f_prop, jac_prop, alpha, seed, step_index, root0_slots, offset=0
         new = {k: v.copy() for k, v in state.items()}
     if u_prop is not None:
         new["u"][:, take] = u_prop[:, take]
+    new["f"][:, take] = f_prop[:, take]
+    new["q"][take] = qp[take]
+    new["pi"][take] = pip[take]
+    return new, take
+
+
+def normals(seed: int, first: int, n: int, D: int):
+    """Standard normals [n][D] of the base-space walk (a reading: the paper names no generator).
+    Coordinates (2j, 2j + 1) of point i = first + index take the first two Philox4x32-10 words w0, w1 of
+    counter (i mod 2^32, i div 2^32, j, 1), key (seed mod 2^32, seed div 2^32); with
+    u_k = ((w_k >> 8) + 1/2) 2^-24 and r = sqrt(-2 log u0) they are r cos(2 pi u1), r sin(2 pi u1)
+    (the Box-Muller transform)."""
+    i = np.arange(first, first + n, dtype=np.uint64)
+    key = np.broadcast_to(np.array([seed & MASK, (seed >> 32) & MASK], dtype=np.uint64), (n, 2))
+    out = np.empty((n, 2 * ((D + 1) // 2)))
+    for j in range((D + 1) // 2):
+        ctr = np.stack([i & np.uint64(MASK), i >> np.uint64(32), np.full(n, j, dtype=np.uint64),
+                        np.ones(n, dtype=np.uint64)], axis=-1)
+        w = osp.philox4x32_10(ctr, key)
+        u0 = ((w[:, 0] >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+        u1 = ((w[:, 1] >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+        r = np.sqrt(-2.0 * np.log(u0))
+        out[:, 2 * j] = r * np.cos(2.0 * np.pi * u1)
+        out[:, 2 * j + 1] = r * np.sin(2.0 * np.pi * u1)
+    return out[:, :D]
+
+
+def walk_base(z, xi, sigma):
+    """The symmetric move of base points on the unit torus: z' = (z + sigma xi) mod 1."""
+    return np.mod(np.asarray(z, dtype=np.float64) + sigma * np.asarray(xi, dtype=np.float64), 1.0)
+
+
+def step_walk(state, f_prop, jac_prop, jflow_prop, jflow_state, alpha, seed, step_index, root0_slots, u_prop=None):
+    """One random-walk step in the base space of the flow T (Sec. IV: the optional base-space proposals
+    of NF-MCMC).  Chain c proposes column c, reached from its own state by a symmetric move of the base
+    point z = T^-1(x).  In base coordinates the target is pi(T(z)) |det dT/dz| = pi(x) / q_T(x) for the
+    uniform base (q_T: the flow's own density, 1 / jflow in x), so Metropolis-Hastings takes x' with
+    probability min(1, [pi(x') / q_T(x')] / [pi(x) / q_T(x)]): the test u pi(x) q_T(x') < pi(x') q_T(x),
+    with the uniform u of step().  pi = alpha q + (1 - alpha) p keeps the sampler's mixture q = 1 / jac.
+    A chain without a valid state, or with a q_T that is not finite and positive on either side, stays.
+    Returns (new state, taken)."""
+    f_prop = np.asarray(f_prop, dtype=np.float32)
+    n = f_prop.shape[1]
+    p = np.zeros(n)
+    for s in root0_slots:
+        p = p + np.abs(f_prop[s].astype(np.float64))
+    jp = np.asarray(jac_prop, dtype=np.float32).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        qp = 1.0 / jp
+        pip = alpha * qp + (1.0 - alpha) * p
+        vp = (jp > 0) & np.isfinite(qp) & np.isfinite(pip) & (pip > 0)
+        gp = 1.0 / np.asarray(jflow_prop, dtype=np.float32).astype(np.float64)
+        gs = 1.0 / np.asarray(jflow_state, dtype=np.float32).astype(np.float64)
+        vg = np.isfinite(gp) & (gp > 0) & np.isfinite(gs) & (gs > 0)
+        pis = state["pi"]
+        vs = (pis > 0) & np.isfinite(pis)
+        u = uniforms(seed, step_index, n)
+        test = u * pis * gp < pip * gs
+    take = vp & vs & vg & test
+    new = {k: v.copy() for k, v in state.items()}
+    if u_prop is not None and "u" in new:
+        new["u"][:, take] = np.asarray(u_prop, dtype=np.float32)[:, take]
     new["f"][:, take] = f_prop[:, take]
     new["q"][take] = qp[take]
     new["pi"][take] = pip[take]

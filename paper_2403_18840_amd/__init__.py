@@ -27,8 +27,9 @@ ABI_SYMBOLS = [
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_create_spline", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
-    "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_train_step", "dmc_flow_destroy",
-    "dmc_chains_create", "dmc_chains_step", "dmc_chains_read", "dmc_chains_reset", "dmc_chains_destroy",
+    "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_walk", "dmc_flow_train_step", "dmc_flow_destroy",
+    "dmc_chains_create", "dmc_chains_step", "dmc_chains_step_walk", "dmc_chains_read", "dmc_chains_reset",
+    "dmc_chains_destroy",
     "dmc_chains_training_data",
     "dmc_effective_mass",
 ]
@@ -114,6 +115,8 @@ def lib():
         "dmc_flow_destroy": (None, [P]),
         "dmc_chains_create": (I32, [I64, I32, I32, I32, I32, I32, ctypes.POINTER(P)]),
         "dmc_chains_step": (I32, [P, P, I64, P, P, I64, I64, F64, U64, I32, P]),
+        "dmc_chains_step_walk": (I32, [P, P, I64, P, P, P, P, I64, F64, U64, I32, P]),
+        "dmc_flow_walk": (I32, [P, P, P, I64, I64, F64, U64, U64, P, I64, P, P, P, P, F64, F64, P]),
         "dmc_chains_training_data": (I32, [P, P, I64, P, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
@@ -517,6 +520,18 @@ class Flow:
                                      _dptr(jac, "float32", "jac"), _dptr(u_out, "float32", "u_out"),
                                      _dptr(lq_out, "float32", "lq_out"), alpha, uniform, _stream(stream)))
 
+    def walk(self, sampler: Sampler, u_state, sigma: float, seed: int, first: int, x, jac, jac_flow, u_out,
+             jac_flow_state, alpha: float = 1.0, uniform: float = 0.0, stream=None):
+        """Base-space random-walk proposals from the states u_state [D][>= n] (dmc_flow_walk, spline flows):
+        x, jac (1/q of the mixture alpha, uniform), jac_flow (1/q_T), u_out [D][>= n] at the proposals, and
+        jac_flow_state (1/q_T at the states)."""
+        n = jac.numel()
+        _check(lib().dmc_flow_walk(self.h, sampler.h, _dptr(u_state, "float32", "u_state"), u_state.shape[1], n,
+                                   sigma, seed, first, _dptr(x, "float32", "x"), x.shape[1],
+                                   _dptr(jac, "float32", "jac"), _dptr(jac_flow, "float32", "jac_flow"),
+                                   _dptr(u_out, "float32", "u_out"), _dptr(jac_flow_state, "float32", "jac_flow_state"),
+                                   alpha, uniform, _stream(stream)))
+
     def log_density(self, u, lq, stream=None):
         _check(lib().dmc_flow_log_density(self.h, _dptr(u, "float32", "u"), u.shape[1], lq.numel(),
                                           _dptr(lq, "float32", "lq"), _stream(stream)))
@@ -565,6 +580,24 @@ class Chains:
                                      u_prop.shape[1] if u_prop is not None else 0, offset, alpha, seed,
                                      1 if measure else 0, _stream(stream)))
 
+    def step_walk(self, f_prop, jac_prop, jac_flow_prop, jac_flow_state, u_prop, alpha: float, seed: int,
+                  measure: bool = True, stream=None):
+        """A base-space random-walk step (dmc_chains_step_walk): chain c's proposal is column c of the
+        output of Flow.walk, evaluated by eval_batch into f_prop."""
+        ld = f_prop.numel() // self.S
+        if f_prop.numel() != ld * self.S or ld < self.n:
+            raise ValueError(f"f_prop must hold [{self.S}][ld >= {self.n}] values, got {f_prop.numel()}")
+        if min(jac_prop.numel(), jac_flow_prop.numel(), jac_flow_state.numel()) < self.n:
+            raise ValueError(f"the weights must hold at least {self.n} values")
+        if u_prop.dim() != 2 or u_prop.shape[0] != self.dim_u or u_prop.shape[1] < self.n:
+            raise ValueError(f"u_prop must be [{self.dim_u}][>= {self.n}]")
+        _check(lib().dmc_chains_step_walk(self.h, _dptr(f_prop, "float32", "f_prop"), ld,
+                                          _dptr(jac_prop, "float32", "jac_prop"),
+                                          _dptr(jac_flow_prop, "float32", "jac_flow_prop"),
+                                          _dptr(jac_flow_state, "float32", "jac_flow_state"),
+                                          _dptr(u_prop, "float32", "u_prop"), u_prop.shape[1], alpha, seed,
+                                          1 if measure else 0, _stream(stream)))
+
     def training_data(self, u_out, w_out, stream=None):
         """States as forward-KL training data: u_out [dim_u][>= n] coordinates, w_out [n] = p / pi."""
         if w_out.numel() < self.n or (self.dim_u and (u_out.dim() != 2 or u_out.shape[0] != self.dim_u
@@ -609,13 +642,16 @@ class McmcResult(NamedTuple):
 
 def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, steps: int, thermal: int = 200,
                    alpha: float = 0.5, seed: int = 1, n_batches: int = 32, flow: "Flow | None" = None,
-                   flow_alpha: float = 0.85, flow_uniform: float = 0.05) -> McmcResult:
+                   flow_alpha: float = 0.85, flow_uniform: float = 0.05, walk_every: int = 0,
+                   walk_sigma: float = 0.05) -> McmcResult:
     """Markov-chain estimate (eq. nf_mcmc_estimator_qft_final_revised) with independent proposals from
     `sampler` (its grid frozen) or, with `flow`, from the flow's mixture.  Every step draws n_chains
     proposals and hands chain c proposal (c + r) mod n_chains with r uniform and fresh (the
     mixture orders its draws by component).  The first `thermal` steps are discarded: chains start
     from the proposal density, and an independence sampler whose proposal is far from |f| needs many
-    steps to reach the target.  Every later step is measured."""
+    steps to reach the target.  Every later step is measured.  With a spline `flow` and walk_every = m > 0,
+    every m-th step after the first is instead a random-walk move in the flow's base space (Flow.walk,
+    step size walk_sigma); its proposals stay out of the importance-sampling estimate."""
     import numpy as np
     import torch
     if steps < 2:
@@ -628,21 +664,41 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
     G = _n_groups(inst)
     R = graph.n_roots
     D = dim(graph.order)
-    ch = Chains(n_chains, G, K, R, n_batches)
+    walk = walk_every > 0
+    if walk and (flow is None or flow.kind != "spline"):
+        raise ValueError("the base-space walk needs a spline flow")
+    ch = Chains(n_chains, G, K, R, n_batches, dim_u=D if walk else 0)
     acc = Accumulator(G, K, R)
     X = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
     J = torch.empty(n_chains, dtype=torch.float32, device=dev)
     F = torch.empty(G * R * K * 2 * n_chains, dtype=torch.float32, device=dev)
+    if walk:
+        U = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+        US = torch.empty((D, n_chains), dtype=torch.float32, device=dev)
+        JF = torch.empty(n_chains, dtype=torch.float32, device=dev)
+        JFS = torch.empty(n_chains, dtype=torch.float32, device=dev)
+        WS = torch.empty(n_chains, dtype=torch.float32, device=dev)
+        acc_walk = Accumulator(G, K, R)  # walk proposals are no draws from q: kept out of the IS estimate
     offsets = np.random.default_rng([seed, 0x0FF5E7]).integers(0, n_chains, size=thermal + steps)
     half = None
     for t in range(thermal + steps):
-        if flow is not None:
-            flow.sample(sampler, seed, t * n_chains, X, J, alpha=flow_alpha, uniform=flow_uniform)
+        if walk and t > 0 and t % walk_every == walk_every - 1:
+            ch.training_data(US, WS)
+            flow.walk(sampler, US, walk_sigma, seed + 0x3A1C, t * n_chains, X, J, JF, U, JFS, alpha=flow_alpha,
+                      uniform=flow_uniform)
+            eval_batch(graph, inst, ks, X, J, acc_walk, f_out=F)
+            accumulate(acc_walk)
+            ch.step_walk(F, J, JF, JFS, U, alpha, seed + 0x5EED, measure=t >= thermal)
         else:
-            sampler.sample(seed, t * n_chains, X, J)
-        eval_batch(graph, inst, ks, X, J, acc, f_out=F)
-        accumulate(acc)
-        ch.step(F, J, alpha, seed + 0x5EED, offset=int(offsets[t]), measure=t >= thermal)
+            if flow is not None:
+                flow.sample(sampler, seed, t * n_chains, X, J, u_out=U if walk else None, alpha=flow_alpha,
+                            uniform=flow_uniform)
+            else:
+                sampler.sample(seed, t * n_chains, X, J)
+            eval_batch(graph, inst, ks, X, J, acc, f_out=F)
+            accumulate(acc)
+            ch.step(F, J, alpha, seed + 0x5EED, offset=int(offsets[t]), measure=t >= thermal,
+                    u_prop=U if walk else None)
         if t + 1 == thermal:
             ch.reset()  # the acceptance rate counts the measured steps only
         if t + 1 == thermal + steps // 2:

@@ -693,6 +693,8 @@ struct dmc_flow {
     float* partial = nullptr;
     double* sums = nullptr;
     float* mix_buf = nullptr;  // mixture scratch: log q, J_V, u' of the uniform share
+    float* walk_buf = nullptr;  // base points of a random walk, [D][walk_cap]
+    int64_t walk_cap = 0;
     int64_t mix_cap = 0;
     // kind 1: rational-quadratic spline couplings (FP32 parameters in `master`, no shadow)
     int kind = 0;
@@ -1207,6 +1209,55 @@ static dmc_status spline_train_step(dmc_flow* f, const float* u, int64_t ld, uin
     return DMC_OK;
 }
 
+dmc_status dmc_flow_walk(dmc_flow* f, dmc_sampler* s, const float* u_state, int64_t ld_u, int64_t n, double sigma,
+                         uint64_t seed, uint64_t first, float* x, int64_t ld, float* jac, float* jac_flow, float* u_out,
+                         float* jac_flow_state, double mix_flow, double mix_uniform, void* stream) {
+    if (!f || !s || !u_state || !x || !jac || !jac_flow || !u_out || !jac_flow_state)
+        return fail(DMC_E_INVALID, "null argument");
+    if (f->kind != 1) return fail(DMC_E_INVALID, "the base-space walk is built for spline flows");
+    if (s->dim != f->dim || s->kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_INVALID, "need a VEGAS sampler of the flow's dimension");
+    if (n < 1 || ld < n || ld_u < n) return fail(DMC_E_INVALID, "need n >= 1, ld >= n and ld_u >= n");
+    if (!(sigma > 0.0 && sigma < 1e6)) return fail(DMC_E_INVALID, "sigma must be positive and finite");
+    if (!(mix_flow > 0.0 && mix_flow <= 1.0) || !(mix_uniform >= 0.0 && mix_uniform < 1.0) ||
+        mix_flow + mix_uniform > 1.0 + 1e-12)
+        return fail(DMC_E_INVALID, "mixture shares: flow in (0, 1], uniform in [0, 1), flow + uniform <= 1");
+    const int D = f->dim;
+    if (f->walk_cap < n) {
+        (void)hipFree(f->walk_buf);
+        f->walk_buf = nullptr;
+        f->walk_cap = 0;
+        HIP_ALLOC(hipMalloc(&f->walk_buf, sizeof(float) * (size_t)D * (size_t)n));
+        f->walk_cap = n;
+    }
+    const int ncu = cu_count();
+    // the states' base points z = T^-1(u') and the flow's own weights there
+    dmc::NsfArgs na = nsf_args(f, s);
+    na.u_in = u_state;
+    na.ld = ld_u;
+    na.n = n;
+    na.z0_out = f->walk_buf;
+    na.ld_z = n;
+    na.jf_out = jac_flow_state;
+    HIP_TRY(dmc::launch_nsf_inverse(na, ncu, S(stream)));
+    // the symmetric move, then the flow from the moved base points: proposals with their mixture weight
+    // (for the target) and the flow's own weight (for the test)
+    HIP_TRY(dmc::launch_nsf_walk(f->walk_buf, D, n, n, (float)sigma, seed, first, ncu, S(stream)));
+    dmc::NsfArgs sa = nsf_args(f, s);
+    sa.z_in = f->walk_buf;
+    sa.ld_z = n;
+    sa.n = n;
+    sa.ld = ld;
+    sa.x = x;
+    sa.jac = jac;
+    sa.jf_out = jac_flow;
+    sa.u_out = u_out;
+    sa.mix_f = (float)mix_flow;
+    sa.mix_g = (float)std::max(0.0, 1.0 - mix_flow - mix_uniform);
+    sa.mix_u = (float)mix_uniform;
+    HIP_TRY(dmc::launch_nsf_sample(sa, ncu, S(stream)));
+    return DMC_OK;
+}
+
 dmc_status dmc_flow_log_density(dmc_flow* f, const float* u, int64_t ld, int64_t n, float* lq, void* stream) {
     if (!f || !u || !lq) return fail(DMC_E_INVALID, "null argument");
     if (n < 1 || ld < n) return fail(DMC_E_INVALID, "need n >= 1 and ld >= n");
@@ -1304,6 +1355,7 @@ void dmc_flow_destroy(dmc_flow* f) {
     (void)hipFree(f->shadow);
     (void)hipFree(f->sums);
     (void)hipFree(f->mix_buf);
+    (void)hipFree(f->walk_buf);
     delete f;
 }
 
@@ -1364,15 +1416,13 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
     return DMC_OK;
 }
 
-dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* u_prop,
-                           int64_t ld_u, int64_t offset, double alpha, uint64_t seed, int32_t measure, void* stream) {
-    if (!c || !f_prop || !jac_prop) return fail(DMC_E_INVALID, "null argument");
-    if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
-    if (c->D > 0 && (!u_prop || ld_u < c->n))
-        return fail(DMC_E_INVALID, "chains that keep coordinates need u_prop with ld_u >= the chain count");
-    if (offset < 0 || offset >= c->n) return fail(DMC_E_INVALID, "offset must be in [0, n)");
-    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
+static dmc_status chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* g_prop,
+                              const float* g_state, const float* u_prop, int64_t ld_u, int64_t offset, double alpha,
+                              uint64_t seed, int32_t measure, void* stream) {
     dmc::McmcArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g_prop = g_prop;
+    a.g_state = g_state;
     a.n = c->n;
     a.S = c->S;
     a.R = c->n_roots;
@@ -1412,6 +1462,30 @@ dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const
         c->measured += c->n;
     }
     return DMC_OK;
+}
+
+dmc_status dmc_chains_step(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop, const float* u_prop,
+                           int64_t ld_u, int64_t offset, double alpha, uint64_t seed, int32_t measure, void* stream) {
+    if (!c || !f_prop || !jac_prop) return fail(DMC_E_INVALID, "null argument");
+    if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (c->D > 0 && (!u_prop || ld_u < c->n))
+        return fail(DMC_E_INVALID, "chains that keep coordinates need u_prop with ld_u >= the chain count");
+    if (offset < 0 || offset >= c->n) return fail(DMC_E_INVALID, "offset must be in [0, n)");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
+    return chains_step(c, f_prop, ld, jac_prop, nullptr, nullptr, u_prop, ld_u, offset, alpha, seed, measure, stream);
+}
+
+dmc_status dmc_chains_step_walk(dmc_chains* c, const float* f_prop, int64_t ld, const float* jac_prop,
+                                const float* jac_flow_prop, const float* jac_flow_state, const float* u_prop,
+                                int64_t ld_u, double alpha, uint64_t seed, int32_t measure, void* stream) {
+    if (!c || !f_prop || !jac_prop || !jac_flow_prop || !jac_flow_state || !u_prop)
+        return fail(DMC_E_INVALID, "null argument");
+    if (c->D == 0) return fail(DMC_E_INVALID, "a walk needs chains that keep their coordinates (dim_u > 0)");
+    if (ld < c->n || ld_u < c->n) return fail(DMC_E_INVALID, "ld and ld_u must be at least the chain count");
+    if (c->steps == 0) return fail(DMC_E_INVALID, "a walk moves existing states: take an independence step first");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
+    return chains_step(c, f_prop, ld, jac_prop, jac_flow_prop, jac_flow_state, u_prop, ld_u, 0, alpha, seed, measure,
+                       stream);
 }
 
 dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream) {

@@ -9,7 +9,8 @@
 // (every lambda group, external momentum, Re and Im).  A chain's state needs no coordinates (the
 // next proposal does not depend on it): only the integrand values f, q and pi at its point.
 //   dmc_mcmc_accept_kernel      Metropolis-Hastings test (FP64), state update (values and, when kept,
-//                               the proposal's coordinates), accepted count
+//                               the proposal's coordinates), accepted count; also the test of a
+//                               random-walk move in the flow's base space
 //   dmc_mcmc_training_kernel    the states as forward-KL training data: coordinates and w = p / pi
 //   dmc_mcmc_accumulate_kernel  per block, sums over its chains of f/pi per slot and of q/pi,
 //                               with their squares (FP64, fixed order); the chains fall into
@@ -60,7 +61,19 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accept_kernel(McmcArgs a) {
         const double pis = a.first ? 0.0 : a.pi_state[c], qs = a.first ? 0.0 : a.q_state[c];
         const bool vs = pis > 0.0 && __builtin_isfinite(pis);
         bool take = false;
-        if (vp && !vs) {
+        if (a.g_prop) {
+            // random walk in the flow's base space: in base coordinates the chain's target is pi / q_T and the
+            // move is symmetric, so x' is taken when u pi(x) q_T(x') < pi(x') q_T(x); a chain without a valid
+            // state (it has no base point) stays
+            const double gp = 1.0 / (double)a.g_prop[col], gs = 1.0 / (double)a.g_state[c];
+            const bool vg = __builtin_isfinite(gp) && gp > 0.0 && __builtin_isfinite(gs) && gs > 0.0;
+            if (vp && vs && vg) {
+                uint32_t w[4] = {(uint32_t)c, (uint32_t)((uint64_t)c >> 32), (uint32_t)a.step, (uint32_t)(a.step >> 32)};
+                philox_round10(w, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+                const double u = ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
+                take = u * pis * gp < pip * gs;
+            }
+        } else if (vp && !vs) {
             take = true;
         } else if (vp) {
             uint32_t w[4] = {(uint32_t)c, (uint32_t)((uint64_t)c >> 32), (uint32_t)a.step, (uint32_t)(a.step >> 32)};

@@ -26,6 +26,10 @@ struct McmcArgs {
     double alpha;
     uint64_t seed, step;
     int first;                // accept every proposal (initial state)
+    // base-space random walk (nullable): the flow's own weights 1 / q_T at the proposals and at the states;
+    // chain c's proposal is column c, and the test uses q_T in place of the proposal density
+    const float* g_prop;
+    const float* g_state;
     unsigned long long* n_acc;
 };
 

@@ -5,7 +5,9 @@
 // sweep stay on the VALU with their weights, the same for every lane, in scalar registers.  The weight
 // gradients, sums over samples of outer products, run on the matrix cores as well.  FP32 throughout.
 //   dmc_nsf_sample_kernel     Philox z -> couplings -> u' -> VEGAS map -> physical map, mixture weight
-//   dmc_nsf_inverse_kernel    u' -> z by the inverse couplings: log q(u'), optionally J_V(u') and every z_l
+//   dmc_nsf_inverse_kernel    u' -> z by the inverse couplings: log q(u'), optionally J_V(u'), every z_l, the
+//                             base point and the flow's own weight
+//   dmc_nsf_walk_kernel       the random-walk move of base points
 //   dmc_nsf_backward_kernel   one layer of the reverse sweep of the weighted forward KL
 //   dmc_nsf_outer_kernel      sums over samples of outer products (the weight gradients) on the FP32 matrix cores
 #include <hip/hip_runtime.h>
@@ -419,7 +421,11 @@ __global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_sample_kernel(NsfArgs a)
         const int64_t s = base + threadIdx.x;
         const bool valid = s < a.n;
         const LdsCol z{zl + threadIdx.x};
-        philox_point(a.seed, a.first + (uint64_t)(valid ? s : 0), D, z);
+        if (a.z_in) {
+            for (int d = 0; d < D; ++d) z[d] = a.z_in[(int64_t)d * a.ld_z + (valid ? s : 0)];
+        } else {
+            philox_point(a.seed, a.first + (uint64_t)(valid ? s : 0), D, z);
+        }
         float lq = 0.0f;
         for (int l = 0; l < a.n_layers; ++l) {
             const Layer L = layer_view(a.params, a.offs[l], a.dA[l], D - a.dA[l]);
@@ -465,6 +471,7 @@ __global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_sample_kernel(NsfArgs a)
         }
         for (int jt = 1; jt < N; ++jt) a.x[(int64_t)(3 * N + jt - 1) * a.ld + s] = a.beta * y[3 * N + jt - 1];
         a.jac[s] = J * jv * a.jt / __builtin_fmaf(a.mix_f, expf(lq), __builtin_fmaf(a.mix_u, jv, a.mix_g));
+        if (a.jf_out) a.jf_out[s] = J * jv * a.jt / expf(lq);
         if (a.lq_out) a.lq_out[s] = lq;
     }
 }
@@ -486,17 +493,28 @@ __global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_inverse_kernel(NsfArgs a
         } else {
             philox_point(a.seed, a.first + (uint64_t)sc, D, z);
         }
+        float jphys = 0.0f;
         if (valid) {
             if (a.u_out && !a.u_in)
                 for (int d = 0; d < D; ++d) a.u_out[(int64_t)d * a.ld + s] = z[d];
-            if (a.jv_out) {
-                float jv = 1.0f;
+            if (a.jv_out || a.jf_out) {
+                // the grid's Jacobian, and with jf_out the physical map's (r = qmax y per loop) as the
+                // sampling pass forms them
+                float jv = 1.0f, J = 1.0f;
                 for (int d = 0; d < D; ++d) {
                     const float ub = z[d] * (float)a.n_bins;
                     const int bin = (int)fminf(fmaxf(ub, 0.0f), (float)(a.n_bins - 1));
-                    jv *= (float)a.n_bins * (a.edges[d * (a.n_bins + 1) + bin + 1] - a.edges[d * (a.n_bins + 1) + bin]);
+                    const float fr = ub - (float)bin;
+                    const float lo = a.edges[d * (a.n_bins + 1) + bin];
+                    const float hi = a.edges[d * (a.n_bins + 1) + bin + 1];
+                    if (d % 3 == 0 && d < 3 * ((D + 1) / 4)) {
+                        const float r = a.qmax * __builtin_fmaf(fr, hi - lo, lo);
+                        J *= a.jl * r * r;
+                    }
+                    jv *= (float)a.n_bins * (hi - lo);
                 }
-                a.jv_out[s] = jv;
+                if (a.jv_out) a.jv_out[s] = jv;
+                jphys = J * jv * a.jt;
             }
             if (a.zs)
                 for (int d = 0; d < D; ++d) a.zs[((int64_t)L_ * D + d) * a.n + s] = z[d];
@@ -521,6 +539,33 @@ __global__ void __launch_bounds__(NSF_BLOCK, 4) dmc_nsf_inverse_kernel(NsfArgs a
                 for (int d = 0; d < D; ++d) a.zs[((int64_t)l * D + d) * a.n + s] = z[d];
         }
         if (valid && a.lq_out) a.lq_out[s] = lq;
+        if (valid && a.jf_out) a.jf_out[s] = jphys / expf(lq);
+        if (valid && a.z0_out)
+            for (int d = 0; d < D; ++d) a.z0_out[(int64_t)d * a.ld_z + s] = z[d];
+    }
+}
+
+// Base-space random walk (Sec. IV's optional proposal): z <- z + sigma xi, wrapped onto [0, 1).  Pair j of
+// coordinates (2j, 2j + 1) of point i takes the Philox words of counter (i lo, i hi, j, 1), key seed: with
+// u_k = ((w_k >> 8) + 1/2) 2^-24 and r = sqrt(-2 log u_0), xi = r cos(2 pi u_1), r sin(2 pi u_1) (Box-Muller).
+__global__ void __launch_bounds__(256) dmc_nsf_walk_kernel(float* z, int D, int64_t n, int64_t ld, float sigma,
+                                                            uint64_t seed, uint64_t first) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = first + (uint64_t)i;
+        for (int j = 0; 2 * j < D; ++j) {
+            uint32_t c[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)j, 1u};
+            philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+            const float u0 = ((float)(c[0] >> 8) + 0.5f) * 0x1p-24f, u1 = ((float)(c[1] >> 8) + 0.5f) * 0x1p-24f;
+            const float r = sqrtf(-2.0f * logf(u0));
+            float sn, cs;
+            sincospif(2.0f * u1, &sn, &cs);
+            for (int k = 0; k < 2 && 2 * j + k < D; ++k) {
+                float* p = z + (int64_t)(2 * j + k) * ld + i;
+                float v = __builtin_fmaf(sigma, r * (k ? sn : cs), *p);
+                v -= floorf(v);
+                *p = v < 1.0f ? v : 0.0f;  // a tiny negative step rounds v - floor(v) up to 1
+            }
+        }
     }
 }
 
@@ -741,6 +786,12 @@ hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st) {
         hipLaunchKernelGGL(dmc_nsf_inverse_kernel<false>, dim3(grid_for(a.n, n_cu)), dim3(NSF_BLOCK), 0, st, a);
     else
         hipLaunchKernelGGL(dmc_nsf_inverse_kernel<true>, dim3(grid_for(a.n, n_cu)), dim3(NSF_BLOCK), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nsf_walk(float* z, int D, int64_t n, int64_t ld, float sigma, uint64_t seed, uint64_t first,
+                           int n_cu, hipStream_t st) {
+    hipLaunchKernelGGL(dmc_nsf_walk_kernel, dim3(grid_for(n, n_cu)), dim3(256), 0, st, z, D, n, ld, sigma, seed, first);
     return hipGetLastError();
 }
 

@@ -35,6 +35,13 @@ struct NsfArgs {
     float* lq_out;   // nullable [n]: log q(u')
     float* jv_out;   // nullable [n]: the grid's Jacobian at u' (inverse pass)
     float* zs;       // nullable [L + 1][D][n]: z_l of the inverse pass, l = L .. 0 (training)
+    // base points of the flow for the random walk in its base space, [D][ld_z]: given (sampling, replacing the
+    // Philox draws) or returned (inverse pass); nullable
+    const float* z_in;
+    float* z0_out;
+    int64_t ld_z;
+    float* jf_out;   // nullable [n]: the flow's own weight J_phys J_V J_t / q_flow at the point (sampling; inverse
+                     // pass with a sampler's grid)
     // grid and physical map (sampling; jv_out)
     const float* edges;
     int n_bins;
@@ -46,6 +53,10 @@ struct NsfArgs {
 hipError_t launch_nsf_sample(const NsfArgs& a, int n_cu, hipStream_t st);
 // u' -> log q(u') by the inverse couplings (optionally J_V(u'), u' itself when drawn, and every z_l)
 hipError_t launch_nsf_inverse(const NsfArgs& a, int n_cu, hipStream_t st);
+
+// base-space random walk: z <- z + sigma xi wrapped onto [0, 1), xi standard normals from Philox
+hipError_t launch_nsf_walk(float* z, int D, int64_t n, int64_t ld, float sigma, uint64_t seed, uint64_t first,
+                           int n_cu, hipStream_t st);
 
 // Reverse sweep of one layer of the weighted forward KL L = -sum_i w_i log q(u_i) / sum_i w_i.
 struct NsfBackArgs {

@@ -156,3 +156,70 @@ def test_chains_carry_coordinates_and_training_weights():
     _, w3 = mcmc.training_data(s3, [0, 1])
     p = np.abs(s3["f"].astype(np.float64)).sum(axis=0)
     assert np.allclose(w3, p / s3["pi"])
+
+
+def test_walk_normals_are_standard_and_follow_the_counter():
+    # Box-Muller of the documented Philox stream: moments of a standard normal, independent pair members,
+    # and point i's draws do not depend on where a batch starts
+    x = mcmc.normals(11, 0, 400000, 3)
+    se = 1.0 / np.sqrt(len(x))
+    assert np.all(np.abs(x.mean(axis=0)) < 5 * se)
+    assert np.all(np.abs(x.var(axis=0) - 1.0) < 5 * np.sqrt(2.0) * se)
+    assert np.all(np.abs(np.mean(x ** 4, axis=0) - 3.0) < 5 * np.sqrt(96.0) * se)
+    assert abs(np.corrcoef(x[:, 0], x[:, 1])[0, 1]) < 5 * se
+    assert np.array_equal(mcmc.normals(11, 1000, 50, 3), x[1000:1050])
+    # the move wraps onto the torus
+    z = mcmc.walk_base([[0.95, 0.02]], [[1.0, -1.0]], 0.1)
+    assert np.allclose(z, [[0.05, 0.92]])
+
+
+def _toy_walk(use_flow_density=True, n=4000, thermal=150, steps=300, batches=20, sigma=0.25, alpha=0.5, seed=9):
+    # 2D toy: flow T(z) = (z0^2, z1), so q_T(x) = 1 / (2 sqrt(x0)); the sampler's mixture is
+    # q = 0.5 q_T + 0.5 (uniform); f(x) = (3 x0^2 - 1/2)(1 + x1) changes sign, integral 0.75.  One
+    # independence step from q, then base-space walks only: the ratio estimate converges to the integral
+    # only if the walk samples pi.  use_flow_density=False plants the mistake of testing with q for q_T.
+    rng = np.random.default_rng(seed)
+    f_of = lambda x: ((3 * x[:, 0] ** 2 - 0.5) * (1 + x[:, 1])).astype(np.float32)[None, :]
+    qT = lambda x: 1.0 / (2.0 * np.sqrt(x[:, 0]))
+    q = lambda x: 0.5 * qT(x) + 0.5
+    flow = rng.uniform(size=n) < 0.5
+    z0 = rng.uniform(size=(n, 2))
+    x = np.where(flow[:, None], np.stack([z0[:, 0] ** 2, z0[:, 1]], axis=1), rng.uniform(size=(n, 2)))
+    state, _ = mcmc.step(None, f_of(x), (1.0 / q(x)).astype(np.float32), alpha, seed, 0, [0])
+    cur = np.zeros((batches, 2, 2))
+    for t in range(1, thermal + steps):
+        z = np.stack([np.sqrt(x[:, 0]), x[:, 1]], axis=1)
+        zp = mcmc.walk_base(z, mcmc.normals(seed + 1, t * n, n, 2), sigma)
+        xp = np.stack([zp[:, 0] ** 2, zp[:, 1]], axis=1)
+        g = qT if use_flow_density else q
+        state, take = mcmc.step_walk(state, f_of(xp), (1.0 / q(xp)).astype(np.float32),
+                                     (1.0 / g(xp)).astype(np.float32), (1.0 / g(x)).astype(np.float32),
+                                     alpha, seed, t, [0])
+        x = np.where(take[:, None], xp, x)
+        if t >= thermal:
+            cur += mcmc.measure(state, batches)
+    est = mcmc.ratio_estimate(cur)[:, 0]
+    return est.mean(), est.std(ddof=1) / np.sqrt(batches)
+
+
+def test_base_space_walk_samples_the_target():
+    m, e = _toy_walk()
+    assert abs(m - 0.75) < 5 * e, (m, e)
+    assert e < 0.02
+    # testing with the sampler's mixture density in place of the flow's own one biases the chain
+    m_bad, e_bad = _toy_walk(use_flow_density=False)
+    assert abs(m_bad - 0.75) > 5 * max(e, e_bad), (m_bad, e_bad)
+
+
+def test_walk_step_keeps_invalid_chains():
+    # a chain without a valid state, or with a non-positive flow density on either side, does not move
+    n = 6
+    f = np.ones((1, n), dtype=np.float32)
+    state, _ = mcmc.step(None, f, np.ones(n, dtype=np.float32), 0.5, 1, 0, [0])
+    state["pi"][0] = 0.0
+    jfp = np.ones(n, dtype=np.float32)
+    jfs = np.ones(n, dtype=np.float32)
+    jfp[1] = 0.0
+    jfs[2] = np.inf
+    new, take = mcmc.step_walk(state, 2 * f, np.ones(n, dtype=np.float32), jfp, jfs, 0.5, 1, 1, [0])
+    assert not take[:3].any() and take[3:].all()  # pi' > pi with equal q_T: always taken
