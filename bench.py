@@ -214,7 +214,8 @@ def _ratio(a, b):
 
 
 def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, thermal=2000, n_batches=64,
-                  alphas=(0.05, 0.2, 0.5, 0.8), seed=0x2403188400000005, flow=True, ref_factor=16, flow_kind="affine"):
+                  alphas=(0.05, 0.2, 0.5, 0.8), seed=0x2403188400000005, flow=True, ref_factor=16, flow_kind="affine",
+                  walk_every=2, walk_sigma=0.05):
     """Markov-chain estimators against plain VEGAS importance sampling at one order (the comparison
     of Sec. IV): Re Sigma(k_F, i omega_0) alone (K = 1, so p = |Re f| + |Im f| at k_F).  VEGAS IS:
     ref_factor x n_batches batches of n_chains * steps / n_batches samples from the adapted grid; the
@@ -226,7 +227,8 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
     n_chains chains, `thermal` steps discarded, `steps` measured, sigma from n_batches independent
     chain batches.  Equal evaluation counts: the efficiency relative to VEGAS is
     sigma_VEGAS^2 / sigma^2 per evaluation and sigma_VEGAS^2 T_VEGAS / (sigma^2 T) per wall second
-    (the thermalisation steps count in T)."""
+    (the thermalisation steps count in T).  With a spline flow and walk_every > 0, NF-MCMC runs a second
+    time with every walk_every-th step a random-walk move of step walk_sigma in the flow's base space."""
     import numpy as np
     import torch
 
@@ -280,11 +282,12 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
            "vegas": {"re": v_re, "sigma_ref": v_ref, "ref_factor": ref_factor, "sigma": v_sig, "sigma_mad": v_mad,
                      "seconds": t_v}}
 
-    def chains(label, fl):
+    def chains(label, fl, walk=0):
         rows = []
         for a in alphas:
             r, t = timed(lambda: dmc.mcmc_integrate(g, inst, ks, s, n_chains, steps, thermal=thermal, alpha=a,
-                                                    seed=seed + 7, n_batches=n_batches, flow=fl))
+                                                    seed=seed + 7, n_batches=n_batches, flow=fl, walk_every=walk,
+                                                    walk_sigma=walk_sigma))
             re, sig = float(r.mean[0, 0, 0].real), float(r.err[0, 0, 0].real)
             zh = float(r.halves[2][0, 0, 0].real)
             rows.append({"alpha": a, "re": re, "sigma": sig, "acceptance": r.acceptance, "seconds": t,
@@ -312,6 +315,9 @@ def mcmc_vs_vegas(order, beta, mu, lam, gamma, n_chains=1 << 16, steps=1024, the
         out["nf_mcmc"] = chains("NF-MCMC", f)
         out["nf_mcmc"]["training"] = {"samples": epochs * tsteps * mb, "seconds": t_train, "kind": flow_kind,
                                       "loss": [float(x) for x in losses], "mixture": {"flow": 0.85, "uniform": 0.05}}
+        if flow_kind == "spline" and walk_every > 0:
+            out["nf_mcmc_walk"] = chains("NF-MCMC + walk", f, walk=walk_every)
+            out["nf_mcmc_walk"].update({"walk_every": walk_every, "walk_sigma": walk_sigma})
     return out
 
 
@@ -359,6 +365,9 @@ def main():
     ap.add_argument("--mcmc-steps", type=int, default=1024)
     ap.add_argument("--mcmc-thermal", type=int, default=2000)
     ap.add_argument("--mcmc-no-flow", action="store_true")
+    ap.add_argument("--mcmc-walk-every", type=int, default=2,
+                    help="with --flow-kind spline, also run NF-MCMC with every m-th step a base-space walk (0: off)")
+    ap.add_argument("--mcmc-walk-sigma", type=float, default=0.05)
     ap.add_argument("--mass-order", type=int, default=0,
                     help="total order of the renormalised effective-mass series (0 skips it)")
     ap.add_argument("--mass-rs", type=float, default=1.0)
@@ -480,7 +489,8 @@ def main():
     if args.mcmc_orders:
         out["mcmc_vs_vegas"] = [mcmc_vs_vegas(int(n), beta, mu, lam, inst[0][3], n_chains=1 << args.mcmc_log2_chains,
                                               steps=args.mcmc_steps, thermal=args.mcmc_thermal,
-                                              flow=not args.mcmc_no_flow, flow_kind=args.flow_kind)
+                                              flow=not args.mcmc_no_flow, flow_kind=args.flow_kind,
+                                              walk_every=args.mcmc_walk_every, walk_sigma=args.mcmc_walk_sigma)
                                 for n in args.mcmc_orders.split(",")]
     if args.mass_order:
         out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, beta,
