@@ -58,39 +58,81 @@ def traffic_for(graph, n_groups=1):
     return d["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma):
-    """The oracle (numpy FP64, diagram by diagram) on a bounded sample of each order.  The rate is
-    combined with the workload's mix (equal samples per order): value = sum_n N_diag(n) / sum_n t_n,
-    t_n being the oracle's seconds per (sample, k) at order n."""
+def _oracle_times(orders, K, per, beta, mu, lam, gamma, seed0=1000):
+    """Per order: (samples done, seconds spent) of the oracle (numpy FP64, diagram by diagram) on about
+    `per` seconds of work, batches doubling from 256 samples."""
     import numpy as np
 
     import synth
-    from oracle import diagrams as dg
     from oracle import integrand as ig
 
     ks = synth.k_grid(K)
-    per = seconds / len(orders)
-    desc = []
-    t_per = 0.0
-    nd_sum = 0
+    out = []
     for n in orders:
-        nd = len(dg.sigma_diagrams(n))
-        N = 256
-        spent = 0.0
-        done = 0
+        N, spent, done = 256, 0.0, 0
         while spent < per:
-            x = synth.loop_points(n, N, seed=1000 + n + done).astype(np.float64)
+            x = synth.loop_points(n, N, seed=seed0 + n + done).astype(np.float64)
             t0 = time.perf_counter()
             for k in ks:
                 ig.integrand(x, n, float(k), beta, mu, lam, gamma)
             spent += time.perf_counter() - t0
             done += N
             N = min(N * 2, 1 << 15)
-        t_per += spent / (done * K)
-        nd_sum += nd
-        desc.append(f"order {n}: {done} samples x {K} k in {spent:.1f} s")
-    return {"value": nd_sum / t_per, "unit": "samples·diagrams/s", "cores": 1, "kind": "oracle",
-            "sample": "; ".join(desc) + " (numpy FP64, one thread; rate combined with equal samples per order)"}
+        out.append((done, spent))
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma, workers=0):
+    """The oracle (numpy FP64, diagram by diagram) on a bounded sample of each order, on one thread.  The
+    rate is combined with the workload's mix (equal samples per order): value = sum_n N_diag(n) / sum_n t_n,
+    t_n being the oracle's seconds per (sample, k) at order n.  With workers > 1 the same loop also runs in
+    that many child processes at once (disjoint samples; they touch no GPU), t_n = the slowest worker's
+    seconds / all workers' (samples x K): the rate on the host's cores."""
+    import subprocess
+
+    from oracle import diagrams as dg
+
+    per = seconds / len(orders)
+    nds = [len(dg.sigma_diagrams(n)) for n in orders]
+    times = _oracle_times(orders, K, per, beta, mu, lam, gamma)
+    t_per = sum(sp / (dn * K) for dn, sp in times)
+    desc = [f"order {n}: {dn} samples x {K} k in {sp:.1f} s" for n, (dn, sp) in zip(orders, times)]
+    out = {"value": sum(nds) / t_per, "unit": "samples·diagrams/s", "cores": 1, "kind": "oracle",
+           "sample": "; ".join(desc) + " (numpy FP64, one thread; rate combined with equal samples per order)",
+           "cpu_model": _cpu_model()}
+    if workers > 1:
+        code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+                "print(json.dumps(bench._oracle_times(%r, %d, %r, %r, %r, %r, %r, seed0=%%d)))"
+                % (os.path.dirname(os.path.abspath(__file__)), list(orders), K, per / 2, beta, mu, lam, gamma))
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-c", code % (100000 * (w + 1))], stdout=subprocess.PIPE,
+                                  env=env, text=True) for w in range(workers)]
+        res = []
+        for p in procs:
+            o, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError("oracle worker failed")
+            res.append(json.loads(o.strip().splitlines()[-1]))
+        wall = time.perf_counter() - t0
+        t_all = 0.0
+        for i in range(len(orders)):
+            done = sum(r[i][0] for r in res)
+            t_all += max(r[i][1] for r in res) / (done * K)
+        out["all_cores"] = {"value": sum(nds) / t_all, "cores": workers, "wall_seconds": wall,
+                            "sample": f"{workers} processes x {per / 2:.1f} s per order, disjoint samples"}
+    return out
 
 
 def _make_flow(D, kind):
@@ -351,6 +393,9 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-workers", type=int,
+                    default=min(16, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))),
+                    help="processes of the all-cores oracle timing (the host's CPU share; 1 or less skips it)")
     ap.add_argument("--flow-order", type=int, default=4,
                     help="order of the learned-proposal comparison (0 skips it)")
     ap.add_argument("--flow-batches", type=int, default=64)
@@ -477,7 +522,8 @@ def main():
         },
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(orders, K, args.cpu_seconds, beta, mu, lam, inst[0][3])
+        out["cpu_baseline"] = cpu_baseline(orders, K, args.cpu_seconds, beta, mu, lam, inst[0][3],
+                                           workers=args.cpu_workers)
     last = dom["last"]
     j = int(np.argmin(np.abs(ks - 1.0)))
     out["estimate"] = {"order": dom["n"], "k": float(ks[j]), "re": float(last[0][0, 0, j].real),
