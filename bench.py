@@ -135,6 +135,23 @@ def cpu_baseline(orders, K, seconds, beta, mu, lam, gamma, workers=0):
     return out
 
 
+def measured_peaks():
+    """The roofline denominators measured on this device (dmc_probe): unpacked FP32 FMA (TFLOP/s, FMA = 2),
+    the hardware 2^x and reciprocal (operations per compute unit and clock at the 2.4 GHz peak clock), and a
+    1 GiB device copy (TB/s, bytes read plus written).  Best of three launches each."""
+    import paper_2403_18840_amd as dmc
+
+    def best(kind, work):
+        runs = [dmc.probe(kind, work) for _ in range(3)]
+        return max(o / (m * 1e-3) for m, o in runs)
+
+    per_clk = 256 * 2.4e9
+    return {"fp32_fma_tflops": 2 * best(0, 4096) / 1e12, "exp2_per_cu_clock": best(1, 1024) / per_clk,
+            "rcp_per_cu_clock": best(2, 1024) / per_clk, "fma_per_cu_clock": best(0, 4096) / per_clk,
+            "hbm_copy_tbs": best(3, 1 << 30) / 1e12,
+            "assumed": {"fp32_vector_tflops": PEAK_ALU_TFLOPS, "hbm_tbs": 8.0, "clock_ghz": 2.4, "cus": 256}}
+
+
 def _make_flow(D, kind):
     """The learned proposal: "affine" (8 affine couplings, 128-wide MLPs, BF16 matrix cores; He-normal hidden
     weights, zero output layer) or "spline" (the paper's flow: 6 rational-quadratic spline couplings with
@@ -393,6 +410,7 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the throughput probes of the roofline denominators")
     ap.add_argument("--cpu-workers", type=int,
                     default=min(16, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))),
                     help="processes of the all-cores oracle timing (the host's CPU share; 1 or less skips it)")
@@ -521,6 +539,8 @@ def main():
             "kernel_ms": kern_ms, "flop_per_launch": fl_launch,
         },
     }
+    if not args.no_peaks:
+        out["peaks"] = measured_peaks()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(orders, K, args.cpu_seconds, beta, mu, lam, inst[0][3],
                                            workers=args.cpu_workers)

@@ -305,6 +305,16 @@ dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* 
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
 void dmc_chains_destroy(dmc_chains* c);
 
+/* ---- throughput probes (the roofline denominators on the device at hand) ----
+ * kind 0: FP32 fused multiply-add (unpacked), 1: the hardware 2^x, 2: the hardware reciprocal; each runs
+ * 8 x (compute units) blocks of 256 lanes, every lane 8 independent chains of 16 x `work` operations
+ * (work: iterations, 1 .. 2^20).  kind 3: a device-to-device copy of `work` bytes (a multiple of 16, up to
+ * 64 GiB; the library allocates and frees both buffers).  After one warm-up launch, *ms receives one
+ * launch's time (HIP events on `stream`, which is synchronised) and *ops its operations (kind 3: bytes read
+ * plus written).  Not for the hot path: it allocates.  DMC_E_INVALID for an unknown kind or work out of
+ * range, DMC_E_NOMEM when an allocation fails. */
+dmc_status dmc_probe(int32_t kind, int64_t work, double* ms, double* ops, void* stream);
+
 /* ---- renormalisation post-processing and effective mass (host, FP64) ----
  * Sec. III.B (eq. sigma_xi_dmu, eq. counterterm) and Sec. VI.A (eq. sigma_xi_dmu_dlambda with
  * dlambda = -xi lambda_R, eq. dsigma_depsilon_series, eq. deltam_partitions, eq. deltas_partitions,

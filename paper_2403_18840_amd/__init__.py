@@ -31,7 +31,7 @@ ABI_SYMBOLS = [
     "dmc_chains_create", "dmc_chains_step", "dmc_chains_step_walk", "dmc_chains_read", "dmc_chains_reset",
     "dmc_chains_destroy",
     "dmc_chains_training_data",
-    "dmc_effective_mass",
+    "dmc_effective_mass", "dmc_probe",
 ]
 
 
@@ -117,6 +117,7 @@ def lib():
         "dmc_chains_step": (I32, [P, P, I64, P, P, I64, I64, F64, U64, I32, P]),
         "dmc_chains_step_walk": (I32, [P, P, I64, P, P, P, P, I64, F64, U64, I32, P]),
         "dmc_flow_walk": (I32, [P, P, P, I64, I64, F64, U64, U64, P, I64, P, P, P, P, F64, F64, P]),
+        "dmc_probe": (I32, [I32, I64, ctypes.POINTER(F64), ctypes.POINTER(F64), P]),
         "dmc_chains_training_data": (I32, [P, P, I64, P, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
@@ -738,6 +739,14 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
     mi, ei, _, _ = acc.estimate(len(inst))
     return McmcResult(m, e, accepted / (n_chains * steps), mi, ei, ((m1, e1), (m2, e2), z))
 
+
+
+def probe(kind: int, work: int, stream=None):
+    """dmc_probe: (milliseconds of one launch, operations or bytes moved) of a throughput probe: kind 0
+    FP32 FMA, 1 hardware 2^x, 2 hardware reciprocal (work = iterations), 3 device copy (work = bytes)."""
+    ms, ops = F64(), F64()
+    _check(lib().dmc_probe(kind, work, ctypes.byref(ms), ctypes.byref(ops), _stream(stream)))
+    return ms.value, ops.value
 
 
 def effective_mass(N: int, lambda_R: float, sigma_fs: dict, a: dict, b: dict):

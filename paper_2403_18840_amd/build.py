@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
     objs = []
     for src, lang in [("graph.cpp", "c++"), ("api.cpp", "c++"), ("renorm.cpp", "c++"), ("kernels.hip", "hip"),
-                      ("flow.hip", "hip"), ("mcmc.hip", "hip"), ("nsf.hip", "hip")]:
+                      ("flow.hip", "hip"), ("mcmc.hip", "hip"), ("nsf.hip", "hip"), ("probe.hip", "hip")]:
         o = os.path.join(obj, src + ".o")
         cmd = [hipcc, "-c", *common, *inc]
         if lang == "hip":

@@ -22,6 +22,7 @@
 #include "kernels.hpp"
 #include "mcmc.hpp"
 #include "nsf.hpp"
+#include "probe.hpp"
 
 namespace {
 
@@ -1543,3 +1544,52 @@ void dmc_chains_destroy(dmc_chains* c) {
 }
 
 }  // extern "C"
+
+dmc_status dmc_probe(int32_t kind, int64_t work, double* ms, double* ops, void* stream) {
+    if (!ms || !ops) return fail(DMC_E_INVALID, "null argument");
+    if (kind < 0 || kind > 3) return fail(DMC_E_INVALID, "kind must be 0 (FMA), 1 (2^x), 2 (reciprocal) or 3 (copy)");
+    if (work < 1 || (kind < 3 && work > (1 << 20)) || (kind == 3 && (work % 16 != 0 || work > ((int64_t)1 << 36))))
+        return fail(DMC_E_INVALID, "work: iterations in [1, 2^20], or bytes, a multiple of 16, up to 64 GiB");
+    const int blocks = 8 * cu_count();
+    float *out = nullptr, *in = nullptr, *dst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    dmc_status st = DMC_OK;
+    auto done = [&]() {
+        (void)hipFree(out);
+        (void)hipFree(in);
+        (void)hipFree(dst);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return st;
+    };
+    int64_t n4 = 0;
+    if (kind < 3) {
+        if (hipMalloc(&out, sizeof(float) * (size_t)blocks * 256) != hipSuccess) {
+            st = fail(DMC_E_NOMEM, "probe allocation failed");
+            return done();
+        }
+        *ops = (double)blocks * 256.0 * (double)work * 16.0 * 8.0;
+    } else {
+        n4 = work / 16;
+        if (hipMalloc(&in, (size_t)work) != hipSuccess || hipMalloc(&dst, (size_t)work) != hipSuccess ||
+            hipMemsetAsync(in, 0, (size_t)work, S(stream)) != hipSuccess) {
+            st = fail(DMC_E_NOMEM, "probe allocation failed");
+            return done();
+        }
+        *ops = 2.0 * (double)work;  // bytes read plus bytes written
+    }
+    const int it = (int)std::min<int64_t>(work, 1 << 20);
+    const int grid = kind < 3 ? blocks : 4 * blocks;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        dmc::launch_probe(kind, out, grid, it, in, dst, n4, S(stream)) != hipSuccess ||  // warm-up
+        hipEventRecord(e0, S(stream)) != hipSuccess ||
+        dmc::launch_probe(kind, out, grid, it, in, dst, n4, S(stream)) != hipSuccess ||
+        hipEventRecord(e1, S(stream)) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(DMC_E_DEVICE, "probe launch failed");
+        return done();
+    }
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) st = fail(DMC_E_DEVICE, "probe timing failed");
+    *ms = t;
+    return done();
+}
