@@ -150,6 +150,13 @@ dmc_status dmc_sampler_set_grid(dmc_sampler* s, const double* edges, void* strea
  * (smoothing, compression with exponent alpha, equal-weight re-gridding; Lepage 1978).
  * Synchronises `stream`.  Clears the histogram. */
 dmc_status dmc_sampler_refine(dmc_sampler* s, double alpha, void* stream);
+/* The same refinement on the host, for any histogram (FP64, no device): edges host double[dim][n_bins + 1],
+ * hist host double[dim][n_bins] (the per-bin sums of the squared importance), out host double[dim][n_bins + 1]
+ * receives the new edges (a dimension whose edges would not rise strictly keeps its old ones).
+ * dmc_sampler_refine applies it to the histogram it gathered.  DMC_E_INVALID for null pointers, dim < 1,
+ * n_bins < 2 or alpha < 0. */
+dmc_status dmc_vegas_refine(int32_t dim, int32_t n_bins, const double* edges, const double* hist, double alpha,
+                            double* out);
 dmc_status dmc_sampler_read_histogram(dmc_sampler* s, double* hist /* host [D][n_bins] */, void* stream);
 void dmc_sampler_destroy(dmc_sampler* s);
 

@@ -25,6 +25,7 @@ ABI_SYMBOLS = [
     "dmc_last_error", "dmc_version", "dmc_compile_graph", "dmc_graph_query", "dmc_graph_export_diagrams",
     "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
+    "dmc_vegas_refine",
     "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_create_spline", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_walk", "dmc_flow_train_step", "dmc_flow_destroy",
@@ -118,6 +119,7 @@ def lib():
         "dmc_chains_step_walk": (I32, [P, P, I64, P, P, P, P, I64, F64, U64, I32, P]),
         "dmc_flow_walk": (I32, [P, P, P, I64, I64, F64, U64, U64, P, I64, P, P, P, P, F64, F64, P]),
         "dmc_probe": (I32, [I32, I64, ctypes.POINTER(F64), ctypes.POINTER(F64), P]),
+        "dmc_vegas_refine": (I32, [I32, I32, P, P, F64, P]),
         "dmc_chains_training_data": (I32, [P, P, I64, P, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_chains_reset": (I32, [P, P]),
@@ -739,6 +741,19 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
     mi, ei, _, _ = acc.estimate(len(inst))
     return McmcResult(m, e, accepted / (n_chains * steps), mi, ei, ((m1, e1), (m2, e2), z))
 
+
+
+def vegas_refine(edges, hist, alpha: float = 0.5):
+    """dmc_vegas_refine: the VEGAS refinement of grid edges [D][B + 1] by a histogram [D][B], on the host."""
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    if e.ndim != 2 or h.shape != (e.shape[0], e.shape[1] - 1):
+        raise ValueError("edges must be [D][B + 1] and hist [D][B]")
+    out = np.empty_like(e)
+    _check(lib().dmc_vegas_refine(e.shape[0], h.shape[1], e.ctypes.data_as(P), h.ctypes.data_as(P), alpha,
+                                  out.ctypes.data_as(P)))
+    return out
 
 
 def probe(kind: int, work: int, stream=None):

@@ -631,6 +631,27 @@ static void refine_dim(const double* e, const double* h, int B, double alpha, do
     }
 }
 
+dmc_status dmc_vegas_refine(int32_t dim, int32_t n_bins, const double* edges, const double* hist, double alpha,
+                            double* out) {
+    if (!edges || !hist || !out) return fail(DMC_E_INVALID, "null argument");
+    if (dim < 1 || n_bins < 2) return fail(DMC_E_INVALID, "need dim >= 1 and n_bins >= 2");
+    if (!(alpha >= 0)) return fail(DMC_E_INVALID, "alpha must be >= 0");
+    const int B = n_bins;
+    for (int d = 0; d < dim; ++d)
+        refine_dim(&edges[(size_t)d * (B + 1)], &hist[(size_t)d * B], B, alpha, &out[(size_t)d * (B + 1)]);
+    // keep strictly rising edges (guard against empty histogram cells rounding to equal edges)
+    for (int d = 0; d < dim; ++d)
+        for (int b = 0; b < B; ++b) {
+            const double lo = out[(size_t)d * (B + 1) + b];
+            const double hi = out[(size_t)d * (B + 1) + b + 1];
+            if (!(hi > lo)) {
+                std::copy(&edges[(size_t)d * (B + 1)], &edges[(size_t)d * (B + 1)] + B + 1, &out[(size_t)d * (B + 1)]);
+                break;
+            }
+        }
+    return DMC_OK;
+}
+
 dmc_status dmc_sampler_refine(dmc_sampler* s, double alpha, void* stream) {
     if (!s) return fail(DMC_E_INVALID, "null sampler");
     if (s->kind != DMC_SAMPLER_VEGAS) return fail(DMC_E_STATE, "only a VEGAS sampler has a grid");
@@ -640,19 +661,8 @@ dmc_status dmc_sampler_refine(dmc_sampler* s, double alpha, void* stream) {
     dmc_status st = dmc_sampler_read_histogram(s, h.data(), stream);
     if (st != DMC_OK) return st;
     std::vector<double> ne(s->edges.size());
-    for (int d = 0; d < s->dim; ++d)
-        refine_dim(&s->edges[(size_t)d * (B + 1)], &h[(size_t)d * B], B, alpha, &ne[(size_t)d * (B + 1)]);
-    // keep strictly rising edges (guard against empty histogram cells rounding to equal edges)
-    for (int d = 0; d < s->dim; ++d)
-        for (int b = 0; b < B; ++b) {
-            double& lo = ne[(size_t)d * (B + 1) + b];
-            double& hi = ne[(size_t)d * (B + 1) + b + 1];
-            if (!(hi > lo)) {
-                std::copy(&s->edges[(size_t)d * (B + 1)], &s->edges[(size_t)d * (B + 1)] + B + 1,
-                          &ne[(size_t)d * (B + 1)]);
-                break;
-            }
-        }
+    st = dmc_vegas_refine(s->dim, B, s->edges.data(), h.data(), alpha, ne.data());
+    if (st != DMC_OK) return st;
     s->edges = ne;
     std::vector<float> ef(ne.begin(), ne.end());
     HIP_TRY(hipMemcpy(s->d_edges, ef.data(), sizeof(float) * ef.size(), hipMemcpyHostToDevice));

@@ -169,7 +169,9 @@ def test_flow_trained_on_chain_samples_beats_the_grid():
 def _spline_flow(D, seed, scale):
     masks = synth.flow_masks(D, 6, seed)
     f = dmc.Flow(D, masks, kind="spline")
-    f.set_params(synth.spline_flow_params(masks, seed + 100, scale))
+    theta = synth.spline_flow_params(masks, seed + 100, scale)
+    f.set_params(theta)
+    f.theta32 = np.asarray(theta, dtype=np.float32).astype(np.float64)  # the library keeps FP32 parameters
     return f, [list(m) for m in masks]
 
 
@@ -182,7 +184,7 @@ def _log_close(got, ref, tight, loose):
                                                                                float(r.max()))
 
 
-@pytest.mark.parametrize("D,n", [(7, 3000), (15, 2049)])
+@pytest.mark.parametrize("D,n", [(7, 3000), (15, 2049), (23, 700)])
 def test_flow_walk_matches_oracle(D, n):
     # base points of the states by the inverse flow, the Box-Muller move on the torus, the flow forward,
     # and the mixture and flow weights at both ends, against the oracle flow in FP64
@@ -194,7 +196,7 @@ def test_flow_walk_matches_oracle(D, n):
     # a moderately peaked flow: both traversals of the walk (inverse, forward) magnify FP32 rounding where a
     # spline derivative nears its floor
     f, masks = _spline_flow(D, 9, 0.1)
-    th = f.params().astype(np.float64)
+    th = f.theta32
     s = dmc.Sampler(dmc.SAMPLER_VEGAS, order, n_bins=50)
     edges = synth.vegas_grid(D, 50, seed=4).astype(np.float64)
     s.set_grid(edges)

@@ -130,3 +130,22 @@ def test_accumulator_and_sampler_argument_errors():
             dmc.Sampler(*args)
     with pytest.raises(dmc.DmcError):
         dmc.Sampler(dmc.SAMPLER_VEGAS, 2, n_bins=500)
+
+
+def test_host_vegas_refine_matches_oracle():
+    # the library's FP64 refinement (host code; the sampler applies it to its gathered histogram) against the
+    # oracle's, on histograms spanning many decades with empty and tiny bins, and an already adapted grid
+    import numpy as np
+    from oracle import sampler as osp
+    import synth
+    rng = np.random.default_rng(4)
+    for D, B, alpha in ((3, 50, 0.5), (7, 50, 1.0), (11, 20, 0.0), (2, 2, 0.5)):
+        edges = synth.vegas_grid(D, B, seed=D).astype(np.float64) if B == 50 else \
+            np.tile(np.linspace(0.0, 1.0, B + 1), (D, 1))
+        h = 10.0 ** rng.uniform(-80, 3, size=(D, B))
+        h[rng.random((D, B)) < 0.2] = 0.0
+        got = dmc.vegas_refine(edges, h, alpha)
+        want = osp.refine_grid(edges, h, alpha)
+        assert np.allclose(got, want, rtol=0, atol=1e-12), (D, B, alpha, np.abs(got - want).max())
+    with pytest.raises(dmc.DmcError):
+        dmc.vegas_refine(np.zeros((2, 3)), np.zeros((2, 2)), -1.0)
