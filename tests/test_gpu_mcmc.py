@@ -184,7 +184,7 @@ def _log_close(got, ref, tight, loose):
                                                                                float(r.max()))
 
 
-@pytest.mark.parametrize("D,n", [(7, 3000), (15, 2049), (23, 700)])
+@pytest.mark.parametrize("D,n", [(7, 3000), (15, 2049), (23, 700), (3, 1), (11, 67)])
 def test_flow_walk_matches_oracle(D, n):
     # base points of the states by the inverse flow, the Box-Muller move on the torus, the flow forward,
     # and the mixture and flow weights at both ends, against the oracle flow in FP64
@@ -245,7 +245,7 @@ def test_flow_walk_matches_oracle(D, n):
     assert good, stats
 
 
-@pytest.mark.parametrize("alpha,n", [(0.2, 1500), (0.8, 4099)])
+@pytest.mark.parametrize("alpha,n", [(0.2, 1500), (0.8, 4099), (0.5, 1)])
 def test_walk_step_matches_oracle(alpha, n):
     # the walk's Metropolis-Hastings test and state update on synthetic values, after an independence step
     torch, dev = torch_dev()
@@ -253,14 +253,15 @@ def test_walk_step_matches_oracle(alpha, n):
     S = G * R * K * 2
     root0 = list(range(K * 2))
     seed = 0x3A1C
-    ch = dmc.Chains(n, G, K, R, 2, dim_u=D)
+    nb = min(2, n)
+    ch = dmc.Chains(n, G, K, R, nb, dim_u=D)
     rng = np.random.default_rng(5)
     f, jac = synth.chain_proposals(S, n, seed=70, bad=False)
     u = rng.uniform(size=(D, n)).astype(np.float32)
     tens = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ch.step(tens(f.ravel()), tens(jac), alpha, seed, offset=0, measure=False, u_prop=tens(u))
     state, _ = mcmc.step(None, f, jac, alpha, seed, 0, root0, u_prop=u)
-    ref = np.zeros((2, S + 1, 2))
+    ref = np.zeros((nb, S + 1, 2))
     taken = 0
     for t in range(1, 4):
         f, jac = synth.chain_proposals(S, n, seed=70 + t, bad=(t == 1))
@@ -270,7 +271,7 @@ def test_walk_step_matches_oracle(alpha, n):
         ch.step_walk(tens(f.ravel()), tens(jac), tens(jf), tens(jfs), tens(u), alpha, seed, measure=True)
         state, take = mcmc.step_walk(state, f, jac, jf, jfs, alpha, seed, t, root0, u_prop=u)
         taken += int(take.sum())
-        ref += mcmc.measure(state, 2)
+        ref += mcmc.measure(state, nb)
         sums, nm, na = ch.read()
         assert na - n == taken, f"step {t}"  # the first (independence) step took every valid proposal
         fin = np.isfinite(ref)
@@ -278,7 +279,7 @@ def test_walk_step_matches_oracle(alpha, n):
         with np.errstate(invalid="ignore"):
             close = np.abs(sums - ref) <= 1e-12 * scale + 1e-300
         assert np.all(np.where(fin, close, sums == ref)), f"step {t}"
-    assert 0 < taken < 3 * n
+    assert 0 < taken < 3 * n or n < 10
     U = torch.empty((D, n), dtype=torch.float32, device=dev)
     W = torch.empty(n, dtype=torch.float32, device=dev)
     ch.training_data(U, W)

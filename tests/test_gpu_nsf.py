@@ -110,7 +110,7 @@ def test_samples_match_oracle(D, N):
     assert ok, stats
 
 
-@pytest.mark.parametrize("D,N", [(7, 1500), (11, 1499)])
+@pytest.mark.parametrize("D,N", [(7, 1500), (11, 1499), (3, 1), (7, 70)])
 def test_training_gradient_matches_torch_and_adam_step(D, N):
     # N = 1499: rows that do not start on 16-byte boundaries take the weight-gradient contraction's
     # element-wise loads; both sizes end in a partial chunk of samples
