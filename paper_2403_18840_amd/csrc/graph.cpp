@@ -1126,9 +1126,10 @@ struct EvalArgs {
                     }
                 }
             s << pc[pi].pre;
-            s << "    for (int kq = 0; kq < KC; ++kq) {\n";
+            // external momenta past the last one are skipped (their stage slots stay zero)
+            s << "    for (int kq = 0; kq < KC && kb + kq < ap->n_k; ++kq) {\n";
             s << "        const int ki = kb + kq;\n";
-            s << "        const float kk = ap->k[ki < ap->n_k ? ki : 0];\n";
+            s << "        const float kk = ap->k[ki];\n";
             indent(s, pc[pi].loop, "    ");
             indent(s, pc[pi].epi, "");
             s << "    }\n}\n";
@@ -1179,8 +1180,13 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         for (int kb = 0; kb < a.n_k; kb += KC) {
             for (int kq = 0; kq < KC; ++kq) {
                 const int ki = kb + kq;
-                const bool kv = ki < a.n_k;
-                const float kk = a.k[kv ? ki : 0];
+                if (ki >= a.n_k) {
+                    // past the last external momentum: empty stage slots and no graph work (uniform)
+                    for (int sl = 0; sl < SPK; ++sl) stage[(kq * SPK + sl) * 64 + lane] = 0.0f;
+                    continue;
+                }
+                const bool kv = true;
+                const float kk = a.k[ki];
 )K";
         indent(s, pc[0].loop, "            ");
         indent(s, pc[0].epi, "            ");
