@@ -480,6 +480,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     def iteration(it, adapt, ev=None):
+        # every order's sampling, evaluation and reduction is queued before the first estimate waits on the
+        # stream (one synchronisation per step; the orders share X and J in stream order); an adapting
+        # iteration refines each grid from its own histogram before the next order reuses imp
         for r in runs:
             n = r["n"]
             Xn = X.narrow(0, 0, dmc.dim(n))
@@ -491,10 +494,12 @@ def main():
             if ev is not None and n == orders[-1]:
                 ev[1].record(stream)
             dmc.accumulate(r["acc"], r["s"] if adapt else None, imp if adapt else None)
-            m, e, ns, nf = r["acc"].estimate(len(inst))
-            r["last"] = (m, e)
             if adapt:
+                r["last"] = r["acc"].estimate(len(inst))[:2]
                 r["s"].refine(0.5)
+        if not adapt:
+            for r in runs:
+                r["last"] = r["acc"].estimate(len(inst))[:2]
 
     for w in range(args.warmup):
         iteration(w, adapt=True)
