@@ -1064,7 +1064,10 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         pc.push_back(std::move(p));
     }
 
-    const int SPK = 2 * n_groups * NR;
+    // a graph whose roots all sit at external time 0 (order 1) has no phase: its imaginary parts are zero, so
+    // only the real slots are staged and reduced (the imaginary sums stay 0; f_out still receives zeros)
+    const bool real_only = !split && cls.size() == 1 && cls[0] == 0;
+    const int SPK = (real_only ? 1 : 2) * n_groups * NR;
     const int KC = SPK <= 16 ? 16 / SPK : 1;
     const int SCH = KC * SPK;
     const int M = (SCH + 15) / 16;
@@ -1176,6 +1179,7 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         }
     if (!split) {
         s << pc[0].pre;
+        if (real_only) s << "        const unsigned int jbad = (valid && !__builtin_isfinite(J)) ? 1u : 0u;\n";
         s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += KC) {
             for (int kq = 0; kq < KC; ++kq) {
@@ -1193,7 +1197,14 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         for (int g = 0; g < n_groups; ++g)
             for (int ro = 0; ro < NR; ++ro)
                 for (int comp = 0; comp < 2; ++comp) {
-                    int slot = (g * NR + ro) * 2 + comp;
+                    if (real_only && comp == 1) {
+                        // 0 * J: not finite exactly when J is not
+                        s << "                nonfin += jbad;\n";
+                        s << "                if (a.f_out && valid) a.f_out[(((long long)(" << (g * NR + ro)
+                          << ") * a.n_k + ki) * 2 + 1) * a.n + s] = 0.0f;\n";
+                        continue;
+                    }
+                    int slot = real_only ? g * NR + ro : (g * NR + ro) * 2 + comp;
                     s << "                {\n";
                     s << "                    const float f = " << (comp ? "FI" : "FR") << g << "_" << ro << ";\n";
                     s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
@@ -1253,8 +1264,12 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
                 }
                 s1 += __shfl_xor(s1, 1); s2 += __shfl_xor(s2, 1);
                 s1 += __shfl_xor(s1, 2); s2 += __shfl_xor(s2, 2);
-                const int gs = (kb / KC) * SCH + sl;
-                if ((lane & 3) == 0 && sl < SCH && gs < a.s_total) { tot[2 * gs] += s1; tot[2 * gs + 1] += s2; }
+)K";
+    if (real_only)  // staged slot sl = (k - kb) SPK + j holds the real part of slot 2 j of momentum k
+        s << "                const int gs = (kb + sl / SPK) * (2 * SPK) + 2 * (sl % SPK);\n";
+    else
+        s << "                const int gs = (kb / KC) * SCH + sl;\n";
+    s << R"K(                if ((lane & 3) == 0 && sl < SCH && gs < a.s_total) { tot[2 * gs] += s1; tot[2 * gs + 1] += s2; }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
