@@ -263,4 +263,4 @@ def loss_and_grad_torch(u, w, masks, params, K=K_BINS, H=HIDDEN):
     wt = torch.tensor(np.asarray(w, dtype=np.float64))
     L = -(wt * lq).sum() / wt.sum()
     L.backward()
-    return float(L), th.grad.numpy().copy(), lq.detach().numpy()
+    return float(L.detach()), th.grad.numpy().copy(), lq.detach().numpy()
