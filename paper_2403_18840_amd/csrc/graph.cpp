@@ -412,17 +412,22 @@ struct Builder {
     Emitter em;
     std::vector<Val> vals;      // factor values
     std::vector<char> val_k;    // k-dependence of each factor
+    std::vector<int> val_sgn;   // a k-dependent propagator's sign factor (+-1, hoisted), or -1
+    std::vector<char> is_sgn;   // the factor is a propagator sign
+    std::map<std::pair<int, int>, int> sgn_id_;  // time pair -> sign factor
     // momentum, time-pair, energy caches
     std::map<Mom, int> mom_id;
     std::vector<Mom> moms;
     std::map<int, std::array<std::string, 3>> mom_q;   // Qx Qy Qz
     std::map<int, Val> mom_q2, mom_p2;
     std::map<std::pair<int, int>, std::pair<std::string, std::string>> tpair;  // T2, pos
-    std::map<int, std::array<Val, 3>> energy;  // me = mu - p2, e = exp2(-bl eps), D
+    std::map<int, std::array<Val, 3>> energy;  // p2, e = exp2(-bl eps), D
+    std::map<std::pair<int, int>, std::string> tmu_;  // mu tau' (log2 units) per time pair
     std::map<std::tuple<int, int, int>, int> gleaf;  // (mom, a, b) -> factor id
     std::map<std::pair<int, int>, int> vleaf;        // (mom, group) -> factor id
     int n_g = 0, n_v = 0;
 
+    std::map<int, std::string> mom_t;     // 2 ck Qz + k of k-dependent momenta
     std::map<int, std::string> mom_dp2;   // d|p|^2/dk of k-dependent momenta
     std::map<int, std::string> mom_bnf;   // beta nF(eps) per momentum
     CoefSet coefs;
@@ -484,21 +489,34 @@ struct Builder {
         return v;
     }
 
+    // 2 ck Qz + k of a k-dependent momentum Q + ck k z, so that |Q + ck k z|^2 = Q^2 + k (2 ck Qz + k)
+    const std::string& kt(int m) {
+        auto it = mom_t.find(m);
+        if (it != mom_t.end()) return it->second;
+        auto q = Q(m);
+        const int ck = moms[m][n];
+        const std::string t = em.def(true, "__builtin_fmaf(" + fstr(2.0 * ck) + ", " + q[2] + ", kk)", 2).name;
+        if (em.act[2]) mom_dp2[m] = em.def(true, t + " + kk", 0).name;  // 2 ck Qz + 2k
+        return mom_t[m] = t;
+    }
+
     Val p2(int m) {
         auto it = mom_p2.find(m);
         if (it != mom_p2.end()) return it->second;
         Val base = q2(m);
         Val v = base;
-        if (is_k(m)) {
-            auto q = Q(m);
-            int ck = moms[m][n];
-            // |Q + ck k z|^2 = Q^2 + k (2 ck Qz + k)
-            Val t = em.def(true, "__builtin_fmaf(" + fstr(2.0 * ck) + ", " + q[2] + ", kk)", 2);
-            v = em.def(true, "__builtin_fmaf(kk, " + t.name + ", " + base.name + ")", 2);
-            if (em.act[2]) mom_dp2[m] = em.def(true, t.name + " + kk", 0).name;  // 2 ck Qz + 2k
-        }
+        if (is_k(m)) v = em.def(true, "__builtin_fmaf(kk, " + kt(m) + ", " + base.name + ")", 2);
         mom_p2[m] = v;
         return v;
+    }
+
+    // |p|^2 + lambda_g, the interaction's denominator: for a k-dependent momentum lambda joins the hoisted
+    // Q^2, so that the loop spends one fused multiply-add on it
+    Val p2_lam(int m, int grp) {
+        const std::string lam = "LAM" + std::to_string(grp);
+        if (!is_k(m)) return em.def(false, p2(m).name + " + " + lam, 0);
+        Val base = em.def(false, q2(m).name + " + " + lam, 0);
+        return em.def(true, "__builtin_fmaf(kk, " + kt(m) + ", " + base.name + ")", 2);
     }
 
     // time pair: propagator from interaction line a to line b (a != b)
@@ -520,6 +538,35 @@ struct Builder {
         return tpair[key];
     }
 
+    // mu tau' for the propagator from line a to line b, hoisted: the exponent (mu - |p|^2) tau' is then one
+    // fused multiply-add on |p|^2
+    const std::string& tmu(int a, int b) {
+        auto key = std::make_pair(a, b);
+        auto it = tmu_.find(key);
+        if (it != tmu_.end()) return it->second;
+        return tmu_[key] = em.def(false, "MU * " + T(a, b).first, 1).name;
+    }
+
+    int add_factor(const Val& v, bool k, int sgn = -1) {
+        vals.push_back(v);
+        val_k.push_back(k);
+        val_sgn.push_back(sgn);
+        is_sgn.push_back(0);
+        return (int)vals.size() - 1;
+    }
+
+    // the sign of the propagator from line a to line b (-1 when b precedes a) as a hoisted factor: a
+    // k-dependent propagator is computed without it and the sign joins the hoisted multipliers
+    int sign_factor(int a, int b) {
+        auto key = std::make_pair(a, b);
+        auto it = sgn_id_.find(key);
+        if (it != sgn_id_.end()) return it->second;
+        Val sv = em.def(false, T(a, b).second + " ? -1.0f : 1.0f", 0);
+        const int id = add_factor(sv, false);
+        is_sgn[id] = 1;
+        return sgn_id_[key] = id;
+    }
+
     std::array<Val, 3> E(int m) {
         auto it = energy.find(m);
         if (it != energy.end()) return it->second;
@@ -529,8 +576,7 @@ struct Builder {
         Val e = em.def(k, "__builtin_amdgcn_exp2f(" + arg.name + ")", 3);
         Val den = em.def(k, e.name + " + 1.0f", 0);
         Val D = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3);
-        Val me = em.def(k, "MU - " + p.name, 0);
-        energy[m] = {me, e, D};
+        energy[m] = {p, e, D};
         if (c.taylor_order == 0 && (em.act[0] || em.act[2])) {
             Val nf = em.def(k, e.name + " * " + D.name, 1);
             mom_bnf[m] = em.def(k, nf.name + " * BETA", 1).name;
@@ -607,17 +653,17 @@ struct Builder {
             for (int j = 1; j <= M; ++j) g[j] = em.def(k, "-" + dser[j], -1).name;
         } else {
             auto tp = T(a, b);
-            Val ex = em.def(k, "__builtin_amdgcn_exp2f(" + en[0].name + " * " + tp.first + ")", 3);
-            (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            Val ex = em.def(k, "__builtin_amdgcn_exp2f(__builtin_fmaf(" + en[0].name + ", -" + tp.first + ", " + tmu(a, b) + "))", 3);
+            (k ? em.cnt_loop : em.cnt_pre)[2] += 1;  // the exponent's fused multiply-add
             Val g0 = em.def(k, ex.name + " * " + en[2].name, 1);
-            v = em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
+            v = k ? g0 : em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
             const auto& ts = tser(a, b, M);
             for (int j = 1; j <= M; ++j) {
                 std::string acc = dser[j];
                 for (int i = 1; i <= j; ++i) acc = "__builtin_fmaf(" + ts[i] + ", " + dser[j - i] + ", " + acc + ")";
                 Val u = em.def(k, acc, 2, j);
                 Val gj = em.def(k, ex.name + " * " + u.name, 1);
-                g[j] = em.def(k, tp.second + " ? -" + gj.name + " : " + gj.name, 0).name;
+                g[j] = k ? gj.name : em.def(k, tp.second + " ? -" + gj.name + " : " + gj.name, 0).name;
             }
         }
         g[0] = v.name;
@@ -633,9 +679,7 @@ struct Builder {
                                     : em.def(true, fstr(-(double)(j + 1)) + " * " + g[j + 1] + " * " + mom_dp2[m], 1, 2).name;
             }
         }
-        int id = (int)vals.size();
-        vals.push_back(v);
-        val_k.push_back(k);
+        const int id = add_factor(v, k, k && a != b ? sign_factor(a, b) : -1);
         gleaf[key] = id;
         ++n_g;
         return id;
@@ -649,8 +693,7 @@ struct Builder {
         auto it = vleaf.find(key);
         if (it != vleaf.end()) return it->second;
         const bool k = is_k(m);
-        Val p = p2(m);
-        Val s = em.def(k, p.name + " + LAM" + std::to_string(grp), 0);
+        Val s = p2_lam(m, grp);
         Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
         const bool kt = em.act[2] && k;
         const int L = coefs.max_l + (kt ? 1 : 0);
@@ -669,9 +712,7 @@ struct Builder {
                                     : em.def(true, fstr((double)(l + 1)) + " * " + c[l + 1] + " * " + mom_dp2[m], 1, 2).name;
             }
         }
-        int id = (int)vals.size();
-        vals.push_back(v);
-        val_k.push_back(k);
+        const int id = add_factor(v, k);
         vleaf[key] = id;
         ++n_v;
         return id;
@@ -694,10 +735,10 @@ struct Builder {
             tprime = "BETA";
         } else {
             auto tp = T(a, b);
-            Val ex = em.def(k, "__builtin_amdgcn_exp2f(" + en[0].name + " * " + tp.first + ")", 3);
-            (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            Val ex = em.def(k, "__builtin_amdgcn_exp2f(__builtin_fmaf(" + en[0].name + ", -" + tp.first + ", " + tmu(a, b) + "))", 3);
+            (k ? em.cnt_loop : em.cnt_pre)[2] += 1;  // the exponent's fused multiply-add
             Val g = em.def(k, ex.name + " * " + en[2].name, 1);
-            v = em.def(k, tp.second + " ? -" + g.name + " : " + g.name, 0);
+            v = k ? g : em.def(k, tp.second + " ? -" + g.name + " : " + g.name, 0);
             tprime = tp.first + " * 0.693147181f";
         }
         if (em.act[0] || (em.act[2] && k)) {
@@ -709,9 +750,7 @@ struct Builder {
             if (em.act[0]) v.d[em.dir(0) - 1] = gm.name;
             if (em.act[2] && k) v.d[em.dir(2) - 1] = em.def(true, "-" + gm.name + " * " + mom_dp2[m], 1).name;
         }
-        int id = (int)vals.size();
-        vals.push_back(v);
-        val_k.push_back(k);
+        const int id = add_factor(v, k, k && a != b ? sign_factor(a, b) : -1);
         gleaf[key] = id;
         ++n_g;
         return id;
@@ -724,8 +763,7 @@ struct Builder {
         auto it = vleaf.find(key);
         if (it != vleaf.end()) return it->second;
         bool k = is_k(m);
-        Val p = p2(m);
-        Val s = em.def(k, p.name + " + LAM" + std::to_string(grp), 0);
+        Val s = p2_lam(m, grp);
         Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
         if (em.act[1] || (em.act[2] && k)) {
             // d V / d lambda = -V^2 (times 8 pi gamma, applied at the end); d V / dk = -V^2 d|p|^2/dk
@@ -733,17 +771,115 @@ struct Builder {
             if (em.act[1]) v.d[em.dir(1) - 1] = vl.name;
             if (em.act[2] && k) v.d[em.dir(2) - 1] = em.def(true, vl.name + " * " + mom_dp2[m], 1).name;
         }
-        int id = (int)vals.size();
-        vals.push_back(v);
-        val_k.push_back(k);
+        const int id = add_factor(v, k);
         vleaf[key] = id;
         ++n_v;
         return id;
     }
 
+    // A factored value with a pending multiplier: c * prod_{i in m} vals[i] * v, where m is a sorted multiset
+    // of hoisted factors (k-independent values and the signs of k-dependent propagators) and c a constant.
+    // Multipliers travel up the factored sum and are applied where the external-momentum loop pays least
+    // for them: folded into a hoisted operand, as the constant of a fused multiply-add, or (value-only
+    // graphs) on the root's per-sample phase factor.  A sign flip is free anywhere (an operand modifier).
+    // Invariant: a hoisted v carries no m.
+    struct SVal {
+        Val v;
+        std::vector<int> m{};
+        double c = 1.0;
+    };
+
+    std::map<std::vector<int>, Val> hoist_;
+
+    // the hoisted product c prod vals[ids]
+    Val hoist(const std::vector<int>& ids, double c = 1.0) {
+        if (ids.empty()) return em.constant(c);
+        auto it = hoist_.find(ids);
+        Val p;
+        if (it != hoist_.end()) {
+            p = it->second;
+        } else {
+            p = vals[ids[0]];
+            for (size_t i = 1; i < ids.size(); ++i) p = em.mul(p, vals[ids[i]]);
+            hoist_[ids] = p;
+        }
+        return em.scale(p, c);
+    }
+
+    // m with pairs of equal signs cancelled, sorted
+    std::vector<int> msort(std::vector<int> m) const {
+        std::sort(m.begin(), m.end());
+        std::vector<int> out;
+        for (size_t i = 0; i < m.size(); ++i) {
+            if (is_sgn[m[i]] && i + 1 < m.size() && m[i + 1] == m[i]) {
+                ++i;
+                continue;
+            }
+            out.push_back(m[i]);
+        }
+        return out;
+    }
+
+    SVal norm(SVal s) {
+        s.m = msort(s.m);
+        if (!s.v.kdep && !s.m.empty()) {
+            s.v = em.mul(s.v, hoist(s.m));
+            s.m.clear();
+        }
+        return s;
+    }
+
+    // x times the hoisted r prod vals[q]: free when x is hoisted or the multiplier is +-1
+    Val apply(const Val& x, const std::vector<int>& q, double r) {
+        if (q.empty()) return em.scale(x, r);
+        return em.mul(x, hoist(q, r));
+    }
+
+    static std::vector<int> common(const std::vector<int>& a, const std::vector<int>& b) {
+        std::vector<int> o;
+        std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+        return o;
+    }
+    static std::vector<int> minus(const std::vector<int>& a, const std::vector<int>& b) {
+        std::vector<int> o;
+        std::set_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+        return o;
+    }
+    // the loop cost of applying (q, r) to x
+    static int cost(const Val& x, const std::vector<int>& q, double r) {
+        return x.kdep && (!q.empty() || (r != 1.0 && r != -1.0)) ? 1 : 0;
+    }
+
+    // r prod vals[q] * x + y in one operation
+    Val madd(const Val& x, const std::vector<int>& q, double r, const Val& y) {
+        if (q.empty() && r == 1.0) return em.add(x, y);
+        if (q.empty() && r == -1.0) return em.add(em.scale(x, -1.0), y);
+        return em.fma(hoist(q, r), x, y);
+    }
+
+    // f a + b for a k-dependent factor f, or a + b when f is null.  The multipliers both sides share stay
+    // pending; the rest are applied, each side's constant ratio riding on whichever operand is cheapest.
+    SVal combine(const Val* f, SVal a, SVal b) {
+        a = norm(a);
+        b = norm(b);
+        const std::vector<int> P = common(a.m, b.m);
+        const std::vector<int> qa = minus(a.m, P), qb = minus(b.m, P);
+        const double r = a.c / b.c;
+        if (!f) {
+            if (!a.v.kdep && !b.v.kdep) return norm({em.add(em.scale(a.v, r), b.v), P, b.c});
+            if (cost(b.v, qb, 1.0) <= cost(a.v, qa, 1.0)) return norm({madd(a.v, qa, r, apply(b.v, qb, 1.0)), P, b.c});
+            return norm({madd(b.v, qb, 1.0 / r, apply(a.v, qa, 1.0)), P, a.c});
+        }
+        if (cost(a.v, qa, r) + cost(b.v, qb, 1.0) <= cost(a.v, qa, 1.0) + cost(b.v, qb, 1.0 / r))
+            return norm({em.fma(*f, apply(a.v, qa, r), apply(b.v, qb, 1.0)), P, b.c});
+        return norm({em.fma(*f, apply(a.v, qa, 1.0), apply(b.v, qb, 1.0 / r)), P, a.c});
+    }
+
     // greedy multivariate Horner factoring of sum_t coef_t prod f_t
-    Val horner(std::vector<Term> terms) {
-        if (terms.empty()) return em.constant(0.0);
+    SVal horner(std::vector<Term> terms) {
+        terms.erase(std::remove_if(terms.begin(), terms.end(), [](const Term& t) { return t.coef == 0.0; }),
+                    terms.end());
+        if (terms.empty()) return {em.constant(0.0)};
         if (terms.size() == 1) return product(terms[0]);
         std::map<int, int> count;
         for (auto& t : terms) {
@@ -762,9 +898,9 @@ struct Builder {
             }
         }
         if (best < 0) {
-            // no shared factor: plain sum, accumulated with fused multiply-adds
-            Val acc = product(terms[0]);
-            for (size_t i = 1; i < terms.size(); ++i) acc = accumulate(acc, terms[i]);
+            // no shared factor: plain sum
+            SVal acc = product(terms[0]);
+            for (size_t i = 1; i < terms.size(); ++i) acc = combine(nullptr, product(terms[i]), acc);
             return acc;
         }
         std::vector<Term> A, B;
@@ -778,34 +914,60 @@ struct Builder {
                 B.push_back(t);
             }
         }
-        Val ha = horner(A);
-        if (B.empty()) return em.mul(vals[best], ha);
-        Val hb = horner(B);
-        return em.fma(vals[best], ha, hb);
+        SVal ha = horner(A);
+        if (B.empty()) return times(ha, best);
+        SVal hb = horner(B);
+        if (!val_k[best]) return combine(nullptr, times(ha, best), hb);
+        if (val_sgn[best] >= 0) ha.m.push_back(val_sgn[best]);
+        return combine(&vals[best], ha, hb);
     }
 
-    Val product(const Term& t) {
-        if (t.f.empty()) return em.constant(t.coef);
-        // multiply the k-independent factors first so that their product is hoisted
-        std::vector<int> f = t.f;
-        std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return val_k[a] < val_k[b]; });
-        Val p = vals[f[0]];
-        for (size_t i = 1; i < f.size(); ++i) p = em.mul(p, vals[f[i]]);
-        return em.scale(p, t.coef);
+    std::map<std::string, int> hoisted_id_;
+
+    // a hoisted value (a factored sum) as a factor of its own, so that it can join a multiplier
+    int hoisted_factor(const Val& v) {
+        auto it = hoisted_id_.find(v.name);
+        if (it != hoisted_id_.end()) return it->second;
+        return hoisted_id_[v.name] = add_factor(v, false);
     }
 
-    Val accumulate(const Val& acc, const Term& t) {
-        if (t.f.empty()) return em.add(acc, em.constant(t.coef));
-        std::vector<int> f = t.f;
-        std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return val_k[a] < val_k[b]; });
-        if (f.size() == 1) {
-            if (t.coef == 1.0) return em.add(acc, vals[f[0]]);
-            return em.fma(em.constant(t.coef), vals[f[0]], acc);
+    // s times factor f: a hoisted factor (and a propagator's sign) joins the multiplier; a hoisted s
+    // times a k-dependent f becomes f with s as its multiplier
+    SVal times(SVal s, int f) {
+        if (!val_k[f]) {
+            s.m.push_back(f);
+        } else if (!s.v.kdep) {
+            const bool one = s.v.name == em.constant(1.0).name;
+            if (!one) s.m = {hoisted_factor(s.v)};
+            s.v = vals[f];
+            if (val_sgn[f] >= 0) s.m.push_back(val_sgn[f]);
+        } else {
+            s.v = em.mul(vals[f], s.v);
+            if (val_sgn[f] >= 0) s.m.push_back(val_sgn[f]);
         }
-        Val p = vals[f[0]];
-        for (size_t i = 1; i + 1 < f.size(); ++i) p = em.mul(p, vals[f[i]]);
-        p = em.scale(p, t.coef);
-        return em.fma(p, vals[f.back()], acc);
+        return norm(s);
+    }
+
+    SVal product(const Term& t) {
+        SVal s{em.constant(1.0), {}, t.coef};
+        bool have = false;
+        std::vector<int> f = t.f;
+        std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return val_k[a] < val_k[b]; });
+        for (int id : f) {
+            if (!val_k[id]) {
+                s.m.push_back(id);
+                continue;
+            }
+            s.v = have ? em.mul(s.v, vals[id]) : vals[id];
+            have = true;
+            if (val_sgn[id] >= 0) s.m.push_back(val_sgn[id]);
+        }
+        if (!have) {
+            s.v = hoist(msort(s.m));
+            s.m.clear();
+            return s;
+        }
+        return norm(s);
     }
 };
 
@@ -950,13 +1112,15 @@ static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_s
 }
 
 int default_part_size(int order, int n_diagrams, int n_roots) {
-    // Measured on MI355X (2^24 samples, 32 k): order 5 runs in 587 ms as one spilling part, 115 ms
-    // in parts of 800 diagrams, 130 ms in parts of 400; order 4 with three derivative roots in
-    // 147 ms as one part, 65 ms in parts of 95; order 5 with them in 696 ms in parts of 120.
-    // Parts of about 800 / R^1.5 diagrams (R roots) keep each part's live set within the register
-    // file without recomputing more leaves than needed; order-6 diagrams have more lines (parts of
-    // 800 spill 300 registers, parts of 400 none).
-    const double base = order >= 6 ? 400.0 : 800.0;
+    // Measured on MI355X (2^24 samples, 32 k, the factoring with pending hoisted multipliers): order 5
+    // runs in 313 ms in parts of 800 diagrams (their hoisted multipliers spill), 100 ms in parts of
+    // 450, 104 ms in parts of 400, 118 ms in parts of 200; order 6 in 1109 ms in parts of 400, 1185 ms
+    // in parts of 300; order 4 with three derivative roots in 61 ms in parts of 100, 71 ms in parts of
+    // 50, 92 ms in parts of 200; order 5 with them in 580 ms in parts of 100, 674 ms in parts of 60.
+    // Parts of about 800 / R^1.5 diagrams (R roots) keep a part's live set within the register file
+    // without recomputing more leaves than needed; single-root graphs from order 5 on, whose diagrams
+    // have more lines, take smaller parts.
+    const double base = order >= 6 ? 400.0 : order == 5 && n_roots == 1 ? 450.0 : 800.0;
     const int per = std::max(16, (int)(base / std::pow((double)n_roots, 1.5)));
     return n_diagrams <= per ? 0 : per;
 }
@@ -989,7 +1153,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         std::sort(pcls.begin(), pcls.end());
         pcls.erase(std::unique(pcls.begin(), pcls.end()), pcls.end());
         // roots[g][class index within the part]
-        std::vector<std::vector<Val>> roots(n_groups);
+        std::vector<std::vector<Builder::SVal>> roots(n_groups);
         for (int g = 0; g < n_groups; ++g) {
             for (int r : pcls) {
                 std::vector<Term> terms;
@@ -1002,7 +1166,13 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                     std::sort(t.f.begin(), t.f.end());
                     terms.push_back(t);
                 }
-                roots[g].push_back(b.horner(terms));
+                Builder::SVal rt = b.horner(terms);
+                // with derivative entries the multiplier's own coefficients enter by the product rule
+                if (b.em.nco() > 1 && !rt.m.empty()) {
+                    rt.v = b.em.mul(rt.v, b.hoist(rt.m));
+                    rt.m.clear();
+                }
+                roots[g].push_back(rt);
             }
         }
         // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
@@ -1013,16 +1183,25 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                 std::string fr, fi;
                 for (size_t ri = 0; ri < pcls.size(); ++ri) {
                     int r = pcls[ri];
-                    std::string rv = Emitter::cf(roots[g][ri], ro);
+                    const std::string rv = Emitter::cf(roots[g][ri].v, ro);
                     if (rv.empty()) continue;
-                    // Taylor coefficients become derivatives: times m! l!
+                    // the root's pending coefficient and, for Taylor coefficients becoming derivatives, m! l!,
+                    // go onto the per-sample phase factors
                     const auto& mo = c.root_orders[ro];
-                    double fac = 1.0;
+                    double fac = roots[g][ri].c;
                     for (int i = 2; i <= mo[0]; ++i) fac *= i;
                     for (int i = 2; i <= mo[1]; ++i) fac *= i;
-                    if (fac != 1.0) rv = b.em.def(roots[g][ri].kdep, fstr(fac) + " * " + rv, 1).name;
                     std::string pcn = "PC" + std::to_string(g) + "_" + std::to_string(r);
                     std::string psn = "PS" + std::to_string(g) + "_" + std::to_string(r);
+                    if (!roots[g][ri].m.empty()) {
+                        const std::string mh = b.hoist(roots[g][ri].m).name;
+                        pcn = b.em.def(false, mh + " * " + pcn, 1).name;
+                        if (r != 0) psn = b.em.def(false, mh + " * " + psn, 1).name;
+                    }
+                    if (fac != 1.0) {
+                        pcn = b.em.def(false, fstr(fac) + " * " + pcn, 1).name;
+                        if (r != 0) psn = b.em.def(false, fstr(fac) + " * " + psn, 1).name;
+                    }
                     if (fr.empty()) {
                         fr = rv + " * " + pcn;
                         epi_ops[1]++;
