@@ -1138,6 +1138,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     struct Part {
         std::vector<int> cls;
         std::string pre, loop, epi;
+        std::vector<std::string> fplain;  // one straight-line part: f per (group, root, component) without J
         int64_t cnt_pre[4], cnt_loop[4];
     };
     std::vector<Part> pc;
@@ -1178,9 +1179,10 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
         // every derivative root (the phases and scale depend on none of mu, lambda, k)
         std::ostringstream epi;
+        std::vector<std::string> fplain;
         for (int g = 0; g < n_groups; ++g) {
             for (int ro = 0; ro < NR; ++ro) {
-                std::string fr, fi;
+                std::string fr, fi, frp, fip;  // with J folded in (one straight-line part), and without
                 for (size_t ri = 0; ri < pcls.size(); ++ri) {
                     int r = pcls[ri];
                     const std::string rv = Emitter::cf(roots[g][ri].v, ro);
@@ -1202,27 +1204,28 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                         pcn = b.em.def(false, fstr(fac) + " * " + pcn, 1).name;
                         if (r != 0) psn = b.em.def(false, fstr(fac) + " * " + psn, 1).name;
                     }
-                    if (fr.empty()) {
-                        fr = rv + " * " + pcn;
-                        epi_ops[1]++;
-                    } else {
-                        fr = "__builtin_fmaf(" + rv + ", " + pcn + ", " + fr + ")";
-                        epi_ops[2]++;
-                    }
+                    // one straight-line part: the Jacobian joins the per-sample factors, so the weight f J
+                    // comes out of the root sum itself (f alone is formed only for f_out)
+                    const std::string pcj = split ? pcn : b.em.def(false, pcn + " * J", 1).name;
+                    const std::string psj = split || r == 0 ? psn : b.em.def(false, psn + " * J", 1).name;
+                    auto term = [](std::string& acc, const std::string& x, const std::string& y) {
+                        acc = acc.empty() ? x + " * " + y : "__builtin_fmaf(" + x + ", " + y + ", " + acc + ")";
+                    };
+                    epi_ops[fr.empty() ? 1 : 2]++;
+                    term(fr, rv, pcj);
+                    term(frp, rv, pcn);
                     if (r == 0) continue;
-                    if (fi.empty()) {
-                        fi = rv + " * " + psn;
-                        epi_ops[1]++;
-                    } else {
-                        fi = "__builtin_fmaf(" + rv + ", " + psn + ", " + fi + ")";
-                        epi_ops[2]++;
-                    }
+                    epi_ops[fi.empty() ? 1 : 2]++;
+                    term(fi, rv, psj);
+                    term(fip, rv, psn);
                 }
                 if (!split) {
-                    if (fr.empty()) fr = "0.0f";
-                    if (fi.empty()) fi = "0.0f";
+                    if (fr.empty()) fr = frp = "0.0f";
+                    if (fi.empty()) fi = fip = "0.0f";
                     epi << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
                     epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
+                    fplain.push_back(frp);
+                    fplain.push_back(fip);
                 } else {
                     const int slot = (g * NR + ro) * 2;
                     if (!fr.empty()) epi << "        st[(kq * SPK + " << slot << ") * 64] += " << fr << ";\n";
@@ -1236,6 +1239,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         p.pre = b.em.pre.str();
         p.loop = b.em.loop.str();
         p.epi = epi.str();
+        p.fplain = fplain;
         for (int i = 0; i < 4; ++i) {
             p.cnt_pre[i] = b.em.cnt_pre[i];
             p.cnt_loop[i] = b.em.cnt_loop[i];
@@ -1250,6 +1254,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     const int KC = SPK <= 16 ? 16 / SPK : 1;
     const int SCH = KC * SPK;
     const int M = (SCH + 15) / 16;
+    int zero_slots = 0;  // one straight-line part: (group, root, component) slots with no term
 
     auto indent = [](std::ostringstream& out, const std::string& text, const std::string& pad) {
         std::istringstream in(text);
@@ -1358,9 +1363,13 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         }
     if (!split) {
         s << pc[0].pre;
-        if (real_only) s << "        const unsigned int jbad = (valid && !__builtin_isfinite(J)) ? 1u : 0u;\n";
+        // slots whose weight is structurally zero: 0 * J is not finite exactly when J is not, counted once per
+        // such slot and external momentum after the tile
+        for (const auto& f : pc[0].fplain) zero_slots += f == "0.0f";
+        if (zero_slots) s << "        const unsigned int jbad = (valid && !__builtin_isfinite(J)) ? 1u : 0u;\n";
         s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += KC) {
+            float impc = 0.0f, chk = 0.0f;  // this chunk's importance, and the sum of the other weights
             for (int kq = 0; kq < KC; ++kq) {
                 const int ki = kb + kq;
                 if (ki >= a.n_k) {
@@ -1376,22 +1385,18 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         for (int g = 0; g < n_groups; ++g)
             for (int ro = 0; ro < NR; ++ro)
                 for (int comp = 0; comp < 2; ++comp) {
+                    const std::string fo = "if (a.f_out && valid) a.f_out[(((long long)(" + std::to_string(g * NR + ro) +
+                                           ") * a.n_k + ki) * 2 + " + std::to_string(comp) + ") * a.n + s] = ";
                     if (real_only && comp == 1) {
-                        // 0 * J: not finite exactly when J is not
-                        s << "                nonfin += jbad;\n";
-                        s << "                if (a.f_out && valid) a.f_out[(((long long)(" << (g * NR + ro)
-                          << ") * a.n_k + ki) * 2 + 1) * a.n + s] = 0.0f;\n";
+                        s << "                " << fo << "0.0f;\n";
                         continue;
                     }
                     int slot = real_only ? g * NR + ro : (g * NR + ro) * 2 + comp;
                     s << "                {\n";
-                    s << "                    const float f = " << (comp ? "FI" : "FR") << g << "_" << ro << ";\n";
-                    s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
-                    s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
-                    if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
+                    s << "                    const float w = " << (comp ? "FI" : "FR") << g << "_" << ro << ";  // f J\n";
+                    s << "                    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
                     s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
-                    s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
-                      << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
+                    s << "                    " << fo << pc[0].fplain[(g * NR + ro) * 2 + comp] << ";\n";
                     s << "                }\n";
                 }
         s << "            }\n";
@@ -1403,6 +1408,7 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
         for (size_t i = 0; i < ins.size(); ++i) s << "        cin[" << i * 64 << "] = " << ins[i] << ";\n";
         s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += KC) {
+            float impc = 0.0f, chk = 0.0f;  // this chunk's importance, and the sum of the other weights
             for (int i = 0; i < SCH; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
         for (size_t pi = 0; pi < pc.size(); ++pi)
@@ -1416,9 +1422,8 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
                     int slot = (g * NR + ro) * 2 + comp;
                     s << "                {\n";
                     s << "                    const float f = stage[(kq * SPK + " << slot << ") * 64 + lane];\n";
-                    s << "                    float w = (valid && kv) ? f * J : 0.0f;\n";
-                    s << "                    if (!__builtin_isfinite(w)) { nonfin += 1u; w = 0.0f; }\n";
-                    if (ro == 0) s << "                    imp += __builtin_fabsf(w);\n";
+                    s << "                    const float w = kv ? f * J : 0.0f;\n";
+                    s << "                    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
                     s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
                     s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
                       << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
@@ -1426,6 +1431,25 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
                 }
         s << "            }\n";
     }
+    // a weight that is not finite makes the chunk's sums non-finite: only then (rarely, per lane) are this
+    // lane's staged weights scanned, each non-finite one zeroed and counted (valid samples only), and the
+    // chunk's importance recomputed
+    const std::string imp_slot = real_only ? "(j % NROOT) == 0" : "((j >> 1) % NROOT) == 0";
+    s << R"K(            if (!__builtin_isfinite(impc + chk)) {
+                impc = 0.0f;
+                for (int sl = 0; sl < SCH; ++sl) {
+                    const int j = sl % SPK;
+                    float v = stage[sl * 64 + lane];
+                    if (!__builtin_isfinite(v)) {
+                        if (valid) nonfin += 1u;
+                        v = 0.0f;
+                        stage[sl * 64 + lane] = 0.0f;
+                    }
+                    if ()K" << imp_slot << R"K() impc += __builtin_fabsf(v);
+                }
+            }
+            imp += impc;
+)K";
     s << R"K(            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1455,7 +1479,9 @@ extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) 
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (a.imp_out && valid) a.imp_out[s] = imp;
-    }
+)K";
+    if (zero_slots) s << "        nonfin += jbad * (unsigned int)(a.n_k * " << zero_slots << ");\n";
+    s << R"K(    }
     // fold the four waves in a fixed order into one FP64 partial per slot
     for (int o = 32; o > 0; o >>= 1) nonfin += __shfl_xor(nonfin, o);
     __shared__ unsigned int nf_w[4];

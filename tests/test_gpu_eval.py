@@ -77,7 +77,9 @@ def test_reduction_matches_fsum_and_is_deterministic():
     n, N, K = 2, 3000, 6
     x = synth.loop_points(n, N, seed=11)
     rng = np.random.default_rng(3)
-    jac = rng.uniform(0.5, 2.0, N).astype(np.float32)
+    # powers of two: the kernel folds J into its per-sample phase factors, and scaling by 2^j commutes with
+    # FP32 rounding, so the staged weight is exactly fp32(f) J and the FP64 fold can be held to fsum
+    jac = (2.0 ** rng.integers(-1, 2, N)).astype(np.float32)
     ks = synth.k_grid(K)
     g = dmc.Graph(n)
     inst = [(BETA, MU, LAM, ph.coupling(1.0))]
@@ -86,7 +88,7 @@ def test_reduction_matches_fsum_and_is_deterministic():
     assert ns == N
     for j in range(K):
         for c, part in enumerate([f[0, 0, j].real, f[0, 0, j].imag]):
-            w = (part.astype(np.float32) * jac).astype(np.float64)  # the kernel's FP32 product
+            w = (part.astype(np.float32) * jac).astype(np.float64)  # the kernel's staged weight
             s1 = math.fsum(w)
             s2 = math.fsum(w * w)
             assert abs(sums[0, 0, j, c, 0] - s1) <= 1e-12 * math.fsum(np.abs(w)) + 1e-300
@@ -100,18 +102,30 @@ def test_reduction_matches_fsum_and_is_deterministic():
     assert np.array_equal(sums, sums2)
 
 
-def test_nonfinite_weights_are_counted_and_dropped():
-    n, N = 1, 512
+@pytest.mark.parametrize("n,mask,part,N,bad", [(1, 0, 0, 512, [3, 300]), (2, 0, 0, 300, [0, 299]),
+                                               (2, 7, 0, 300, [5, 299]), (1, 7, 0, 70, [69]),
+                                               (4, 0, 40, 300, [7, 299])])
+def test_nonfinite_weights_are_counted_and_dropped(n, mask, part, N, bad):
+    # an infinite Jacobian makes every weight of its sample non-finite (inf, or NaN where f = 0): each is
+    # dropped and counted once per (root, Re/Im, k), for valid samples only (N = 300 and 70 end in a partial
+    # tile whose idle lanes re-read the last sample); the sums and importances are those of the same batch
+    # with these Jacobians set to 0.  Derivative roots go through the non-importance check, order 1 through
+    # the structurally zero imaginary slots, part size 40 through the partitioned kernel.
     x = synth.loop_points(n, N, seed=5)
+    g = dmc.Graph(n, deriv_mask=mask, part_size=part)
+    ks = [0.0, 1.0]
+    inst = [(BETA, MU, LAM, 0.5)]
     jac = np.ones(N, dtype=np.float32)
-    jac[[3, 300]] = np.inf
-    torch, dev = torch_dev()
-    acc = dmc.Accumulator(1, 2, 1)
-    dmc.eval_batch(dmc.Graph(n), [(BETA, MU, LAM, 0.5)], [0.0, 1.0], to_soa(x), torch.from_numpy(jac).to(dev), acc)
-    dmc.accumulate(acc)
+    jac[bad] = np.inf
+    _, acc, imp = gpu_integrand(g, x, ks, inst, jac=jac)
+    jac0 = jac.copy()
+    jac0[bad] = 0.0
+    _, acc0, imp0 = gpu_integrand(g, x, ks, inst, jac=jac0)
     m, e, ns, nf = acc.estimate(1)
-    assert nf == 2 * 2 * 2   # 2 samples x 2 k x (Re, Im)
-    assert np.all(np.isfinite(m))
+    assert nf == len(bad) * len(ks) * g.n_roots * 2
+    assert np.all(np.isfinite(m)) and np.all(np.isfinite(e))
+    assert np.array_equal(acc.read()[0], acc0.read()[0])
+    assert np.array_equal(imp, imp0) and np.all(imp[bad] == 0.0)
 
 
 @pytest.mark.parametrize("kind,n", [(dmc.SAMPLER_UNIFORM, 1), (dmc.SAMPLER_VEGAS, 2), (dmc.SAMPLER_VEGAS, 3)])
