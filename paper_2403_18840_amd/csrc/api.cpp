@@ -389,7 +389,7 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
             jk->max_blocks_per_cu = nb;
     }
     const int64_t ntiles = (n + 255) / 256;
-    const int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 4);
+    const int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 8);
     const int nb = (int)std::min<int64_t>(ntiles, cap);
     if (nb > acc->cap_blocks) {
         (void)hipFree(acc->partial);
