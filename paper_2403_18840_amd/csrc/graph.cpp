@@ -1322,8 +1322,12 @@ struct EvalArgs {
             s << "    }\n}\n";
         }
     }
+    // small single-part value graphs (orders 1-3) are held to 5 waves per SIMD: order 3 otherwise takes 98
+    // registers, 4 waves, and the fifth hides more of the transcendentals' latency
+    const bool five = !split && NR == 1 && n <= 3;
+    s << "\nextern \"C\" __global__ void __launch_bounds__(256" << (five ? ", 5" : "") << ") KERNEL_NAME(const EvalArgs a) {";
     s << R"K(
-extern "C" __global__ void __launch_bounds__(256) KERNEL_NAME(const EvalArgs a) {
+
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float* stage = smem + wv * (16 * MST * 64);
