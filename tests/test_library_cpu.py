@@ -116,6 +116,26 @@ def test_compaction_reduces_operation_count():
         assert sum(i.ops_naive) > factor * (sum(i.ops_k))
 
 
+def _k_loop(src):
+    a = src.index("const float kk = a.k[ki];")
+    return src[a:src.index("const float FR0_0", a)]
+
+
+def test_factoring_keeps_multipliers_out_of_the_momentum_loop():
+    # hoisted multipliers (propagator signs, k-independent factors, constants) are applied outside the loop
+    # over external momenta: no sign select, no lambda add and no mu subtraction inside it, and the sample's
+    # Jacobian sits in the per-sample phase factors; issue slots per (sample, k) (transcendentals twice)
+    # stay at or below the factored counts
+    for n, most in [(2, 26), (3, 97), (4, 488)]:
+        g = dmc.Graph(n)
+        src = g.source(1)
+        loop = _k_loop(src)
+        assert " ? -" not in loop and "+ LAM0" not in loop and "MU - " not in loop
+        assert " * J;" in src[:src.index("const float kk = a.k[ki];")]
+        i = g.info()
+        assert sum(i.ops_k) + i.ops_k[3] <= most, (n, list(i.ops_k))
+
+
 def test_generated_source_mentions_every_group():
     src = dmc.Graph(2).source(3)
     assert "LAM2" in src and "#define NGRP 3" in src
