@@ -21,9 +21,10 @@ legs.  F = (number of cycles of sigma) - 1 closed fermion loops.
 This module enumerates ALL (2n)! permutations and tests each one with a plain graph search,
 which is slow on purpose and shares nothing with the library's generator.  Each topology is
 reduced to a canonical labelling by a breadth-first relabelling that starts at the in-vertex;
-the routing of loop momenta is a reverse-delete spanning tree over the canonical labels.  Both
-rules are stated in the functions below; they are the agreed naming of variables (a data
-convention), not arithmetic of the method.
+the routing puts the external momentum on a short path of chords and the other loop momenta on
+a reverse-delete spanning tree over the canonical labels.  Both rules are stated in the
+functions below; they are the agreed naming of variables (a data convention), not arithmetic of
+the method.
 """
 from __future__ import annotations
 
@@ -171,7 +172,8 @@ class Diagram:
     n_loops_f: int       # closed fermion loops F
     weight: float        # (-1)^(n+F) 2^F
     lines: list          # propagators then interaction lines
-    chords: list         # propagator source vertices carrying q_0..q_{n-1}
+    chords: list         # the lines carrying q_0..q_{n-1}: (kind, src, dst) each
+    k_path: list = field(default_factory=list)   # indices into `lines` of the lines that carry k
 
     @property
     def ext_line(self) -> int:
@@ -179,33 +181,89 @@ class Diagram:
         return self.out_vertex // 2
 
 
-def route(sigma) -> Diagram:
-    """Momentum routing by reverse delete.
+def external_path(n2, edges, o):
+    """The lines that carry the external momentum: a simple path from the in-vertex 0 to the
+    out-vertex o with the fewest propagators, then the fewest lines, then the first in the order
+    of line indices (compared position by position).  Returned as [(line index, +1 or -1)], +1
+    when the walk from 0 to o follows the line's reference direction.
 
-    Propagators are visited in order of their source vertex (the external o->0 skipped); a
-    propagator is removed if the remaining internal graph stays connected.  The removed
-    propagators are the chords: the j-th removed carries loop momentum q_j along its own
-    direction.  What is left (all interaction lines and n-1 propagators) is a spanning tree.
-    The loop momentum of chord u->w returns from w to u along the tree path; the external k
-    enters at vertex 0 and leaves at the out-vertex along the tree path.  Interaction line i
-    has reference direction 2i -> 2i+1."""
+    Search: for each (propagator count g, length L) in increasing order, a depth-first walk that
+    tries the lines at each vertex in index order finds the first path of exactly that count and
+    length; the first (g, L) that has one wins."""
+    inc = [[] for _ in range(n2)]
+    for idx, (_, a, b) in enumerate(edges):
+        inc[a].append((idx, +1, b))
+        inc[b].append((idx, -1, a))
+    for row in inc:
+        row.sort()
+
+    def search(g, L):
+        path, seen = [], {0}
+
+        def walk(v, g_left):
+            if len(path) == L:
+                return v == o and g_left == 0
+            for idx, sgn, w in inc[v]:
+                if w in seen:
+                    continue
+                isg = edges[idx][0] == "f"
+                if isg and g_left == 0:
+                    continue
+                path.append((idx, sgn))
+                seen.add(w)
+                if walk(w, g_left - isg):
+                    return True
+                path.pop()
+                seen.discard(w)
+            return False
+
+        return list(path) if walk(0, g) else None
+
+    for g in range(len(edges) + 1):
+        for L in range(max(g, 1), n2):
+            p = search(g, L)
+            if p is not None:
+                return p
+    raise AssertionError("the out-vertex is not reachable")
+
+
+def route(sigma) -> Diagram:
+    """Momentum routing with the external momentum on a path of chords.
+
+    Internal lines, in this order, are the propagators v -> sigma[v] by source vertex (the
+    external o -> 0 skipped), then the interaction lines (reference direction 2i -> 2i+1).
+    1. Chords by reverse delete: first the lines of `external_path` in path order, then the
+       other lines in order; a line becomes the next chord when the lines still left connect
+       every vertex, until there are n chords.  The j-th chord carries q_j, along the walk from
+       the in-vertex to the out-vertex if it lies on that path, else along its reference
+       direction.
+    2. What is left is a spanning tree.  The loop momentum of a chord returns along the tree
+       path from its head to its tail.
+    3. k enters at the in-vertex and follows `external_path` to the out-vertex.
+    Only the lines of the external path depend on k, and a chord on it carries q_j + k."""
     n2 = len(sigma)
     n = n2 // 2
     o = sigma.index(0)
     fe, ve = _edges(sigma)
-    tree = fe + ve
-    chords = []
-    for e in fe:
-        trial = [x for x in tree if x != e]
-        if _connected(n2, trial):
-            tree = trial
-            chords.append(e)
-    assert len(chords) == n and len(tree) == n2 - 1
+    edges = fe + ve
+    kp = external_path(n2, edges, o)
+    on_path = dict(kp)
+    chord = {}                      # line index -> (loop index, direction)
+    for idx in [i for i, _ in kp] + [i for i in range(len(edges)) if i not in on_path]:
+        if len(chord) == n:
+            break
+        rest = [e for i, e in enumerate(edges) if i not in chord and i != idx]
+        if _connected(n2, rest):
+            chord[idx] = (len(chord), on_path.get(idx, +1))
+    assert len(chord) == n
+    tree = [i for i in range(len(edges)) if i not in chord]
+    assert len(tree) == n2 - 1
 
     def tree_path(a, b):
-        """Edges (with +1/-1 traversal sign) of the unique tree path a -> b."""
+        """(line index, +1/-1) along the unique tree path a -> b."""
         adj = [[] for _ in range(n2)]
-        for idx, (_, x, y) in enumerate(tree):
+        for idx in tree:
+            _, x, y = edges[idx]
             adj[x].append((y, idx, +1))
             adj[y].append((x, idx, -1))
         prev = {a: None}
@@ -224,28 +282,24 @@ def route(sigma) -> Diagram:
             v = u
         return path
 
-    mom = {e: [0] * (n + 1) for e in tree}
-    chord_mom = {}
-    for j, e in enumerate(chords):
-        c = [0] * (n + 1)
-        c[j] = 1
-        chord_mom[e] = c
-        _, u, w = e
-        for idx, sgn in tree_path(w, u):
-            mom[tree[idx]][j] += sgn
-    for idx, sgn in tree_path(0, o):
-        mom[tree[idx]][n] += sgn
+    mom = [[0] * (n + 1) for _ in edges]
+    for idx, (j, sgn) in chord.items():
+        mom[idx][j] = sgn
+        _, u, w = edges[idx]
+        head, tail = (w, u) if sgn > 0 else (u, w)
+        for t, s in tree_path(head, tail):
+            mom[t][j] += s
+    for idx, sgn in kp:
+        mom[idx][n] += sgn
 
-    lines = []
-    for e in fe:
-        c = chord_mom[e] if e in chord_mom else mom[e]
-        lines.append(Line("G", e[1], e[2], tuple(c)))
-    for e in ve:
-        lines.append(Line("V", e[1], e[2], tuple(mom[e])))
+    lines = [Line("G" if e[0] == "f" else "V", e[1], e[2], tuple(mom[i])) for i, e in enumerate(edges)]
     F = n_cycles(sigma) - 1
+    chords = [None] * n
+    for idx, (j, _) in chord.items():
+        chords[j] = (lines[idx].kind, lines[idx].src, lines[idx].dst)
     return Diagram(sigma=tuple(sigma), order=n, out_vertex=o, n_loops_f=F,
                    weight=float((-1) ** (n + F) * 2 ** F), lines=lines,
-                   chords=[e[1] for e in chords])
+                   chords=chords, k_path=[i for i, _ in kp])
 
 
 def check_conservation(d: Diagram) -> bool:

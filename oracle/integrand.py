@@ -89,6 +89,57 @@ def abs_sum(x, n, k, beta, mu, lam, gamma, diagrams=None):
 
 
 # ----------------------------------------------------------------------------------------
+# The per-sample tolerance an FP32 evaluation is held to.  A diagram is a product of leaves; a
+# propagator's leaf is exp(-|eps| S) / (1 + exp(-beta |eps|)), S = tau' for eps >= 0 and
+# beta - tau' for eps < 0 (tau' in (0, beta], the time shifted into that interval), written so
+# that no factor exceeds 1.  In FP32 every operation rounds with relative error u = 2^-24, so a
+# diagram carries a relative error of a few u per leaf, plus the error of each exponential's
+# argument, which is absolute: rounding eps = |p|^2 - mu (|p|^2 summed from the rounded components
+# of p, each the sum of rounded terms of size m_p = sum_j |c_j| |q_j| + |c_k| k) and S (times of size
+# up to beta) gives at first order
+#     |delta arg| <= u (|eps| (S + beta) + S (|p|^2 + 2 |p| m_p)) = u c_G.
+# The rule: |f_FP32 - f| <= 1e-5 A + 2 u B + 1e-30, A = sum_d |W_d|, B = sum_d |W_d| sum_{G in d} c_G.
+# The 1e-5 A term is the stated relative tolerance taken against the terms before cancellation
+# (FP32 cannot resolve a cancelled sum better than its largest terms); the 2 u B term is the
+# first-order error of the exponentials, which dominates only in samples whose every diagram is
+# exponentially small.
+# ----------------------------------------------------------------------------------------
+U32 = 2.0 ** -24
+
+
+def exponent_condition(x, n, k, beta, mu, diagrams=None):
+    """C_d(x) = sum over the propagators G of diagram d of c_G (above): real [Ndiag, N]."""
+    if diagrams is None:
+        diagrams = dg.sigma_diagrams(n)
+    q, taus = _unpack(x, n)
+    N = q.shape[0]
+    qn = np.linalg.norm(q, axis=2)                     # |q_j| [N, n]
+    out = np.zeros((len(diagrams), N))
+    for di, d in enumerate(diagrams):
+        for ln in d.lines:
+            if ln.kind != "G":
+                continue
+            p = line_momentum(q, k, ln.mom)
+            p2 = np.sum(p * p, axis=1)
+            eps = p2 - mu
+            a, b = ln.src // 2, ln.dst // 2
+            tp = np.full(N, beta) if a == b else taus[:, b] - taus[:, a]
+            tp = np.where(tp > 0, tp, tp + beta)
+            S = np.where(eps >= 0, tp, beta - tp)
+            mp = sum(abs(ln.mom[j]) * qn[:, j] for j in range(n)) + abs(ln.mom[n]) * abs(k)
+            out[di] += np.abs(eps) * (S + beta) + S * (p2 + 2.0 * np.sqrt(p2) * mp)
+    return out
+
+
+def fp32_tolerance(x, n, k, beta, mu, lam, gamma, diagrams=None, rel=1e-5):
+    """(tol, A): the per-sample bound rel A + 2 u B + 1e-30 of the FP32 integrand, and A."""
+    W = np.abs(diagram_values(x, n, k, beta, mu, lam, gamma, diagrams))
+    C = exponent_condition(x, n, k, beta, mu, diagrams)
+    A = W.sum(axis=0)
+    return rel * A + 2.0 * U32 * (W * C).sum(axis=0) + 1e-30, A
+
+
+# ----------------------------------------------------------------------------------------
 # Derivatives by forward-mode dual numbers on the plain product of each diagram: every line
 # value carries its value and its derivatives with respect to (mu, lambda, k); products follow
 # the Leibniz rule.  Pinned by central differences and by the Fock closed forms.

@@ -70,6 +70,10 @@ struct JitKernel {
     hipFunction_t fn = nullptr;
     int max_blocks_per_cu = 1;
     std::string src;
+    // kernels in parts: the chunk of external momenta staged per pass and the blocks per CU it allows,
+    // by the number of external momenta (0: not chosen yet)
+    int kc[65] = {0};
+    int kc_blocks[65] = {0};
 };
 
 // the EvalArgs layout the generated kernel declares
@@ -82,7 +86,7 @@ struct EvalArgs {
     unsigned int* nonfinite;
     float* f_out;
     float* imp_out;
-    int n_k, s_total, pad0, pad1;
+    int n_k, s_total, kc, pad1;
     float mu, beta, bl, blmu, inv2beta, pad2;
     float lam[8];
     float scale[8];
@@ -375,18 +379,54 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     if (st != DMC_OK) return st;
 
     const int NR = g->c.n_roots;
-    const int SPK = 2 * ng * NR;
-    const int KC = SPK <= 16 ? 16 / SPK : 1;
-    const int M = (KC * SPK + 15) / 16;
-    // stage, FP64 totals, and for a kernel in parts the lanes' inputs (3n + 2(n - 1) rows per wave)
-    const int nin = g->c.stats.parts > 1 ? 3 * g->c.order + 2 * (g->c.order - 1) : 0;
-    const size_t smem = (size_t)4 * 16 * M * 64 * sizeof(float) + (size_t)4 * 2 * acc->s_total * sizeof(double) +
-                        (size_t)4 * nin * 64 * sizeof(float);
-    if (smem > 160 * 1024) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
-    if (jk->max_blocks_per_cu <= 1) {
+    const bool split = g->c.stats.parts > 1;
+    // LDS per block of four waves: the stage, the FP64 totals and, for a kernel in parts, the lanes' inputs
+    // (3n + 2(n - 1) rows per wave).  A single-part kernel stages KC momenta of every group (fixed at
+    // compile time); a kernel in parts stages kc momenta of one group, kc chosen here: the largest chunk
+    // that keeps the blocks per CU its registers allow (each extra chunk reruns the parts' k-independent
+    // code), else the chunk with the most blocks per CU
+    const int nin = split ? 3 * g->c.order + 2 * (g->c.order - 1) : 0;
+    auto smem_for = [&](int stage_floats) {
+        return (size_t)4 * stage_floats * 64 * sizeof(float) + (size_t)4 * 2 * acc->s_total * sizeof(double) +
+               (size_t)4 * nin * 64 * sizeof(float);
+    };
+    auto blocks_for = [&](size_t smem) {
         int nb = 0;
-        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jk->fn, 256, smem) == hipSuccess && nb > 0)
-            jk->max_blocks_per_cu = nb;
+        if (smem > 160 * 1024 ||
+            hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jk->fn, 256, smem) != hipSuccess)
+            return 0;
+        return nb;
+    };
+    int kc = 0;
+    size_t smem = 0;
+    if (!split) {
+        const int SPK = 2 * ng * NR;
+        const int KC = SPK <= 16 ? 16 / SPK : 1;
+        smem = smem_for(16 * ((KC * SPK + 15) / 16));
+        if (smem > 160 * 1024) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
+        if (jk->max_blocks_per_cu <= 1) {
+            const int nb = blocks_for(smem);
+            if (nb > 0) jk->max_blocks_per_cu = nb;
+        }
+    } else {
+        if (!jk->kc[n_k]) {
+            const int best = blocks_for(smem_for(2 * NR));
+            if (best < 1) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
+            int pick = 1, pick_nb = best;
+            for (int c = n_k; c >= 1; --c) {
+                const int nb = blocks_for(smem_for(c * 2 * NR));
+                if (nb >= best) {
+                    pick = c;
+                    pick_nb = nb;
+                    break;
+                }
+            }
+            jk->kc[n_k] = pick;
+            jk->kc_blocks[n_k] = pick_nb;
+        }
+        kc = jk->kc[n_k];
+        smem = smem_for(kc * 2 * NR);
+        jk->max_blocks_per_cu = jk->kc_blocks[n_k];
     }
     const int64_t ntiles = (n + 255) / 256;
     const int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 8);
@@ -413,6 +453,7 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     a.imp_out = imp_out;
     a.n_k = n_k;
     a.s_total = acc->s_total;
+    a.kc = kc;
     a.mu = (float)mu;
     a.beta = (float)beta;
     a.bl = (float)(beta * M_LOG2E);

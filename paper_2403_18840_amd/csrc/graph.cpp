@@ -94,6 +94,51 @@ int count_cycles(const std::vector<int>& sigma) {
     return c;
 }
 
+// The external momentum's path: a simple path from the in-vertex 0 to the out-vertex with the fewest
+// propagators, then the fewest lines, then the smallest sequence of line indices.  Returned as line
+// indices in path order with the traversal sign (+1 along the line's reference direction).
+std::vector<std::pair<int, int>> k_path(int nv, const std::vector<Edge>& es, int out) {
+    std::vector<std::vector<std::pair<int, int>>> adj(nv);  // (line, +-1)
+    for (int i = 0; i < (int)es.size(); ++i) {
+        adj[es[i].a].push_back({i, +1});
+        adj[es[i].b].push_back({i, -1});
+    }
+    for (auto& a : adj) std::sort(a.begin(), a.end());
+    std::vector<std::pair<int, int>> best, cur;
+    int best_g = 1 << 30;
+    std::vector<char> onv(nv, 0);
+    std::function<void(int, int)> dfs = [&](int v, int g) {
+        if (v == out) {
+            bool take = best.empty() || g < best_g || (g == best_g && cur.size() < best.size());
+            if (!take && g == best_g && cur.size() == best.size())
+                for (size_t i = 0; i < cur.size(); ++i)
+                    if (cur[i].first != best[i].first) {
+                        take = cur[i].first < best[i].first;
+                        break;
+                    }
+            if (take) {
+                best = cur;
+                best_g = g;
+            }
+            return;
+        }
+        // no extension of a path that already has more propagators, or as many and at least as many lines
+        if (!best.empty() && (g > best_g || (g == best_g && cur.size() >= best.size()))) return;
+        for (auto [e, sg] : adj[v]) {
+            const int w = sg > 0 ? es[e].b : es[e].a;
+            if (onv[w]) continue;
+            onv[w] = 1;
+            cur.push_back({e, sg});
+            dfs(w, g + (es[e].kind == 'G'));
+            cur.pop_back();
+            onv[w] = 0;
+        }
+    };
+    onv[0] = 1;
+    dfs(0, 0);
+    return best;
+}
+
 Diagram route(const std::vector<int>& sigma) {
     const int nv = (int)sigma.size(), n = nv / 2;
     Diagram d;
@@ -107,15 +152,27 @@ Diagram route(const std::vector<int>& sigma) {
     int nf;
     std::vector<Edge> es = internal_edges(sigma, nf);
     std::vector<char> in_tree(es.size(), 1);
-    std::vector<int> chord_of(es.size(), -1);
+    std::vector<int> chord_of(es.size(), -1), chord_sgn(es.size(), 1);
     int n_ch = 0;
-    for (int i = 0; i < nf; ++i) {
+    // chords by reverse delete: the external momentum's path first (in path order), then the other lines
+    // in order; a line becomes a chord when the lines left still connect every vertex
+    const auto kp = k_path(nv, es, d.out_vertex);
+    std::vector<int> order_, path_sgn(es.size(), 0);
+    for (auto [e, sg] : kp) {
+        order_.push_back(e);
+        path_sgn[e] = sg;
+    }
+    for (int i = 0; i < (int)es.size(); ++i)
+        if (!path_sgn[i]) order_.push_back(i);
+    for (int i : order_) {
+        if (n_ch == n) break;
         std::vector<Edge> rest;
         for (int j = 0; j < (int)es.size(); ++j)
             if (in_tree[j] && j != i) rest.push_back(es[j]);
         if (connected(nv, rest, -1)) {
             in_tree[i] = 0;
             chord_of[i] = n_ch++;
+            if (path_sgn[i]) chord_sgn[i] = path_sgn[i];
         }
     }
     // tree adjacency
@@ -127,7 +184,7 @@ Diagram route(const std::vector<int>& sigma) {
         }
     std::vector<std::array<int, kMaxOrder + 1>> mom(es.size());
     for (auto& m : mom) m.fill(0);
-    // add `coef` units of momentum component `comp` along the tree path from a to b
+    // add one unit of momentum component `comp` along the tree path from a to b
     auto flow = [&](int a, int b, int comp) {
         std::vector<int> prev_v(nv, -2), prev_e(nv, -1);
         std::vector<int> st{a};
@@ -149,10 +206,16 @@ Diagram route(const std::vector<int>& sigma) {
     };
     for (int i = 0; i < (int)es.size(); ++i)
         if (chord_of[i] >= 0) {
-            mom[i][chord_of[i]] = 1;
-            flow(es[i].b, es[i].a, chord_of[i]);
+            // a chord carries its loop momentum along the external path's direction (chords on that
+            // path) or its reference direction, and the tree carries it back
+            const int sg = chord_sgn[i];
+            mom[i][chord_of[i]] = sg;
+            if (sg > 0)
+                flow(es[i].b, es[i].a, chord_of[i]);
+            else
+                flow(es[i].a, es[i].b, chord_of[i]);
         }
-    flow(0, d.out_vertex, n);
+    for (auto [e, sg] : kp) mom[e][n] += sg;  // the external momentum along its path
     for (int i = 0; i < (int)es.size(); ++i) {
         Line ln;
         ln.kind = es[i].kind;
@@ -421,13 +484,20 @@ struct Builder {
     std::map<int, std::array<std::string, 3>> mom_q;   // Qx Qy Qz
     std::map<int, Val> mom_q2, mom_p2;
     std::map<std::pair<int, int>, std::pair<std::string, std::string>> tpair;  // T2, pos
-    std::map<int, std::array<Val, 3>> energy;  // p2, e = exp2(-bl eps), D
-    std::map<std::pair<int, int>, std::string> tmu_;  // mu tau' (log2 units) per time pair
+    std::map<std::pair<int, int>, std::string> tcomp;                            // beta - tau' (log2 units)
+    // per momentum: |eps| = ||p|^2 - mu|, eps >= 0, em = 2^(-beta |eps| log2 e), r = 1 / (1 + em);
+    // nF = em r (eps >= 0) or r (eps < 0), 1 - nF the other one
+    struct Energy {
+        std::string ae, pos, em, r;
+        bool k;
+    };
+    std::map<int, Energy> energy;
     std::map<std::tuple<int, int, int>, int> gleaf;  // (mom, a, b) -> factor id
     std::map<std::pair<int, int>, int> vleaf;        // (mom, group) -> factor id
     int n_g = 0, n_v = 0;
 
-    std::map<int, std::string> mom_t;     // 2 ck Qz + k of k-dependent momenta
+    std::map<int, std::string> mom_t;     // Qz + ck k of k-dependent momenta
+    std::map<int, Val> mom_qxy2;          // Qx^2 + Qy^2 of k-dependent momenta
     std::map<int, std::string> mom_dp2;   // d|p|^2/dk of k-dependent momenta
     std::map<int, std::string> mom_bnf;   // beta nF(eps) per momentum
     CoefSet coefs;
@@ -489,34 +559,53 @@ struct Builder {
         return v;
     }
 
-    // 2 ck Qz + k of a k-dependent momentum Q + ck k z, so that |Q + ck k z|^2 = Q^2 + k (2 ck Qz + k)
-    const std::string& kt(int m) {
+    // Qx^2 + Qy^2 of a k-dependent momentum Q + ck k z (hoisted)
+    Val qxy2(int m) {
+        auto it = mom_qxy2.find(m);
+        if (it != mom_qxy2.end()) return it->second;
+        auto q = Q(m);
+        Val v = em.def(false, "__builtin_fmaf(" + q[0] + ", " + q[0] + ", " + q[1] + " * " + q[1] + ")", 2);
+        em.cnt_pre[1] += 1;
+        return mom_qxy2[m] = v;
+    }
+
+    // Qz + ck k of a k-dependent momentum (a line carries k at most once: ck = +-1), so that
+    // |Q + ck k z|^2 = Qx^2 + Qy^2 + (Qz + ck k)^2 is formed without cancelling against |Q|^2; and
+    // d|p|^2/dk = 2 ck (Qz + ck k)
+    const std::string& kz(int m) {
         auto it = mom_t.find(m);
         if (it != mom_t.end()) return it->second;
         auto q = Q(m);
         const int ck = moms[m][n];
-        const std::string t = em.def(true, "__builtin_fmaf(" + fstr(2.0 * ck) + ", " + q[2] + ", kk)", 2).name;
-        if (em.act[2]) mom_dp2[m] = em.def(true, t + " + kk", 0).name;  // 2 ck Qz + 2k
+        const std::string t = ck == 1    ? em.def(true, q[2] + " + kk", 0).name
+                              : ck == -1 ? em.def(true, q[2] + " - kk", 0).name
+                                         : em.def(true, "__builtin_fmaf(" + fstr(ck) + ", kk, " + q[2] + ")", 2).name;
+        if (em.act[2]) mom_dp2[m] = em.def(true, fstr(2.0 * ck) + " * " + t, 1).name;
         return mom_t[m] = t;
     }
 
     Val p2(int m) {
         auto it = mom_p2.find(m);
         if (it != mom_p2.end()) return it->second;
-        Val base = q2(m);
-        Val v = base;
-        if (is_k(m)) v = em.def(true, "__builtin_fmaf(kk, " + kt(m) + ", " + base.name + ")", 2);
+        Val v;
+        if (is_k(m)) {
+            const std::string& t = kz(m);
+            v = em.def(true, "__builtin_fmaf(" + t + ", " + t + ", " + qxy2(m).name + ")", 2);
+        } else {
+            v = q2(m);
+        }
         mom_p2[m] = v;
         return v;
     }
 
     // |p|^2 + lambda_g, the interaction's denominator: for a k-dependent momentum lambda joins the hoisted
-    // Q^2, so that the loop spends one fused multiply-add on it
+    // Qx^2 + Qy^2, so that the loop spends one fused multiply-add on it
     Val p2_lam(int m, int grp) {
         const std::string lam = "LAM" + std::to_string(grp);
         if (!is_k(m)) return em.def(false, p2(m).name + " + " + lam, 0);
-        Val base = em.def(false, q2(m).name + " + " + lam, 0);
-        return em.def(true, "__builtin_fmaf(kk, " + kt(m) + ", " + base.name + ")", 2);
+        Val base = em.def(false, qxy2(m).name + " + " + lam, 0);
+        const std::string& t = kz(m);
+        return em.def(true, "__builtin_fmaf(" + t + ", " + t + ", " + base.name + ")", 2);
     }
 
     // time pair: propagator from interaction line a to line b (a != b)
@@ -534,17 +623,19 @@ struct Builder {
         Val d = em.def(false, dexpr, 0, (la.empty() || lb.empty()) ? 0 : 1);
         Val t2 = em.def(false, pos + " ? " + d.name + " : " + d.name + " + BL", 0, 2);  // add + select
         em.cnt_pre[0] += 1;  // the compare
+        // beta - tau' (log2 units), formed from the time difference so that it is exact as tau' -> beta
+        Val c2 = em.def(false, pos + " ? BL - " + d.name + " : -" + d.name, 0, 2);
+        tcomp[key] = c2.name;
         tpair[key] = {t2.name, pos};
         return tpair[key];
     }
 
-    // mu tau' for the propagator from line a to line b, hoisted: the exponent (mu - |p|^2) tau' is then one
-    // fused multiply-add on |p|^2
-    const std::string& tmu(int a, int b) {
-        auto key = std::make_pair(a, b);
-        auto it = tmu_.find(key);
-        if (it != tmu_.end()) return it->second;
-        return tmu_[key] = em.def(false, "MU * " + T(a, b).first, 1).name;
+    // the exponent's time for a propagator from line a to line b: tau' when eps >= 0, beta - tau' when
+    // eps < 0 (log2 units), so that G0 = s 2^(-|eps| S) / (1 + 2^(-beta |eps|)) has no factor above 1
+    Val S(int m, int a, int b) {
+        T(a, b);
+        const auto& en = E(m);
+        return em.def(is_k(m), en.pos + " ? " + tpair[{a, b}].first + " : " + tcomp[{a, b}], 0);
     }
 
     int add_factor(const Val& v, bool k, int sgn = -1) {
@@ -567,27 +658,57 @@ struct Builder {
         return sgn_id_[key] = id;
     }
 
-    std::array<Val, 3> E(int m) {
+    const Energy& E(int m) {
         auto it = energy.find(m);
         if (it != energy.end()) return it->second;
-        bool k = is_k(m);
+        const bool k = is_k(m);
         Val p = p2(m);
-        Val arg = em.def(k, "__builtin_fmaf(" + p.name + ", -BL, BLMU)", 2);
-        Val e = em.def(k, "__builtin_amdgcn_exp2f(" + arg.name + ")", 3);
-        Val den = em.def(k, e.name + " + 1.0f", 0);
-        Val D = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3);
-        energy[m] = {p, e, D};
-        if (c.taylor_order == 0 && (em.act[0] || em.act[2])) {
-            Val nf = em.def(k, e.name + " * " + D.name, 1);
-            mom_bnf[m] = em.def(k, nf.name + " * BETA", 1).name;
-        }
+        Energy en;
+        en.k = k;
+        Val e = em.def(k, p.name + " - MU", 0);
+        en.ae = "__builtin_fabsf(" + e.name + ")";  // an operand modifier: free
+        en.pos = em.tag + "pe" + std::to_string(m);
+        (k ? em.loop : em.pre) << "    const bool " << en.pos << " = " << e.name << " >= 0.0f;\n";
+        (k ? em.cnt_loop : em.cnt_pre)[0] += 1;
+        en.em = em.def(k, "__builtin_amdgcn_exp2f(-BL * " + en.ae + ")", 3).name;
+        (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+        Val den = em.def(k, en.em + " + 1.0f", 0);
+        en.r = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3).name;
+        energy[m] = en;
+        if (c.taylor_order == 0 && (em.act[0] || em.act[2])) mom_bnf[m] = em.def(k, "BETA * " + nF(m), 1).name;
         return energy[m];
+    }
+
+    // nF(eps) and 1 - nF(eps) of a momentum
+    std::map<int, std::string> mom_nf, mom_omnf;
+    const std::string& nF(int m) {
+        auto it = mom_nf.find(m);
+        if (it != mom_nf.end()) return it->second;
+        const Energy& en = E(m);
+        Val p = em.def(en.k, en.em + " * " + en.r, 1);
+        return mom_nf[m] = em.def(en.k, en.pos + " ? " + p.name + " : " + en.r, 0).name;
+    }
+    const std::string& omnF(int m) {
+        auto it = mom_omnf.find(m);
+        if (it != mom_omnf.end()) return it->second;
+        const Energy& en = E(m);
+        Val p = em.def(en.k, en.em + " * " + en.r, 1);
+        return mom_omnf[m] = em.def(en.k, en.pos + " ? " + en.r + " : " + p.name, 0).name;
+    }
+
+    // |G0| = 2^(-|eps| S) / (1 + 2^(-beta |eps|)) of the propagator from line a to line b (a != b)
+    Val gmag(int m, int a, int b) {
+        const bool k = is_k(m);
+        Val sv = S(m, a, b);
+        const Energy& en = E(m);
+        Val ex = em.def(k, "__builtin_amdgcn_exp2f(-" + en.ae + " * " + sv.name + ")", 3);
+        (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+        return em.def(k, ex.name + " * " + en.r, 1);
     }
 
     // ---- Taylor mode (eq. taylor_node; eq. green_ct and eq. interaction_ct are the leaves' series) ----
     std::map<int, std::string> bfac_;                         // beta^i / i!
     std::map<std::pair<int, int>, std::vector<std::string>> tser_;  // tau'^i / i! per time pair
-    std::map<int, std::string> mom_nf;                        // nF(eps) per momentum
 
     const std::string& bfac(int i) {
         auto it = bfac_.find(i);
@@ -612,9 +733,11 @@ struct Builder {
     }
 
     // G0 as a series in dmu: eps = |p|^2 - mu - dmu, so G0(eps) = +-exp(-eps tau') D(eps) with
-    // D = 1 / (1 + exp(-beta eps)) (or nF at equal time).  exp(dmu tau') has coefficients tau'^i / i!;
-    // D's coefficients follow from (1 + e exp(beta dmu)) D = 1: d_0 = D, d_j = -nF sum_{i=1..j} beta^i/i! d_{j-i}
-    // (nF = e D).  The k tangent of coefficient m is -(m + 1) g_{m+1} d|p|^2/dk.
+    // D = 1 / (1 + exp(-beta eps)) = 1 - nF (or nF at equal time).  exp(dmu tau') has coefficients tau'^i / i!;
+    // D's coefficients relative to D follow from (1 + e exp(beta dmu)) D = 1: delta_0 = 1,
+    // delta_j = -nF sum_{i=1..j} beta^i/i! delta_{j-i}, and G0's coefficient j is
+    // |G0| sum_{i=0..j} tau'^i/i! delta_{j-i} (with the sign).  The k tangent of coefficient m is
+    // -(m + 1) g_{m+1} d|p|^2/dk.
     int g_leaf_taylor(const Line& ln) {
         int m = momentum(ln.mom);
         int a = ln.src / 2, b = ln.dst / 2;
@@ -622,47 +745,45 @@ struct Builder {
         auto it = gleaf.find(key);
         if (it != gleaf.end()) return it->second;
         const bool k = is_k(m);
-        auto en = E(m);
+        E(m);
         const bool kt = em.act[2] && k;
         const int M = coefs.max_m + (kt ? 1 : 0);
         std::vector<std::string> dser(M + 1);
-        dser[0] = en[2].name;
-        std::string nf;
-        if (M >= 1 || a == b) {
-            auto nit = mom_nf.find(m);
-            if (nit == mom_nf.end()) nit = mom_nf.emplace(m, em.def(k, en[1].name + " * " + en[2].name, 1).name).first;
-            nf = nit->second;
-        }
+        dser[0] = "1.0f";
+        const std::string nf = M >= 1 ? nF(m) : std::string();
         for (int j = 1; j <= M; ++j) {
             std::string acc;
             int t = 0;
             for (int i = 1; i <= j; ++i) {
-                acc = acc.empty() ? bfac(i) + " * " + dser[j - i]
-                                  : "__builtin_fmaf(" + bfac(i) + ", " + dser[j - i] + ", " + acc + ")";
+                if (i == j) {
+                    acc = acc.empty() ? bfac(i) : acc + " + " + bfac(i);
+                } else {
+                    acc = acc.empty() ? bfac(i) + " * " + dser[j - i]
+                                      : "__builtin_fmaf(" + bfac(i) + ", " + dser[j - i] + ", " + acc + ")";
+                }
                 ++t;
             }
-            std::string sum = t == 1 ? em.def(k, acc, 1).name : em.def(k, acc, 2, t - 1).name;
-            if (t > 1) (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+            std::string sum = t == 1 ? acc : em.def(k, acc, 2, t - 1).name;
             dser[j] = em.def(k, "-" + nf + " * " + sum, 1).name;
         }
         std::vector<std::string> g(M + 1);
         Val v;
         if (a == b) {
-            // equal time (0^-): nF(eps - dmu) = 1 - D(eps - dmu)
-            v = Val{nf, k, std::vector<std::string>(em.nco() - 1)};
-            for (int j = 1; j <= M; ++j) g[j] = em.def(k, "-" + dser[j], -1).name;
+            // equal time (0^-): nF(eps - dmu) = 1 - D(eps - dmu), D = 1 - nF
+            const std::string d0 = omnF(m);
+            v = Val{nF(m), k, std::vector<std::string>(em.nco() - 1)};
+            for (int j = 1; j <= M; ++j) g[j] = em.def(k, "-" + d0 + " * " + dser[j], 1).name;
         } else {
             auto tp = T(a, b);
-            Val ex = em.def(k, "__builtin_amdgcn_exp2f(__builtin_fmaf(" + en[0].name + ", -" + tp.first + ", " + tmu(a, b) + "))", 3);
-            (k ? em.cnt_loop : em.cnt_pre)[2] += 1;  // the exponent's fused multiply-add
-            Val g0 = em.def(k, ex.name + " * " + en[2].name, 1);
+            Val g0 = gmag(m, a, b);
             v = k ? g0 : em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
             const auto& ts = tser(a, b, M);
             for (int j = 1; j <= M; ++j) {
                 std::string acc = dser[j];
-                for (int i = 1; i <= j; ++i) acc = "__builtin_fmaf(" + ts[i] + ", " + dser[j - i] + ", " + acc + ")";
+                for (int i = 1; i <= j; ++i)
+                    acc = i == j ? acc + " + " + ts[i] : "__builtin_fmaf(" + ts[i] + ", " + dser[j - i] + ", " + acc + ")";
                 Val u = em.def(k, acc, 2, j);
-                Val gj = em.def(k, ex.name + " * " + u.name, 1);
+                Val gj = em.def(k, g0.name + " * " + u.name, 1);
                 g[j] = k ? gj.name : em.def(k, tp.second + " ? -" + gj.name + " : " + gj.name, 0).name;
             }
         }
@@ -726,25 +847,23 @@ struct Builder {
         auto it = gleaf.find(key);
         if (it != gleaf.end()) return it->second;
         bool k = is_k(m);
-        auto en = E(m);
+        E(m);
         Val v;
         std::string tprime;  // tau' (the propagator's time shifted into (0, beta])
         if (a == b) {
-            // equal time (0^-): nF(eps) = e^{-beta eps} / (1 + e^{-beta eps})
-            v = em.def(k, en[1].name + " * " + en[2].name, 1);
+            // equal time (0^-): nF(eps)
+            v = Val{nF(m), k, std::vector<std::string>(em.nco() - 1)};
             tprime = "BETA";
         } else {
             auto tp = T(a, b);
-            Val ex = em.def(k, "__builtin_amdgcn_exp2f(__builtin_fmaf(" + en[0].name + ", -" + tp.first + ", " + tmu(a, b) + "))", 3);
-            (k ? em.cnt_loop : em.cnt_pre)[2] += 1;  // the exponent's fused multiply-add
-            Val g = em.def(k, ex.name + " * " + en[2].name, 1);
+            Val g = gmag(m, a, b);
             v = k ? g : em.def(k, tp.second + " ? -" + g.name + " : " + g.name, 0);
             tprime = tp.first + " * 0.693147181f";
         }
         if (em.act[0] || (em.act[2] && k)) {
             // d G0 / d mu = G0 (tau' - beta nF);  d G0 / dk = -(d G0 / d mu) d|p|^2/dk.  At equal
-            // time tau' = beta and tau' - beta nF = beta (1 - nF) = beta D, taken without cancellation.
-            Val lg = a == b ? em.def(k, "BETA * " + en[2].name, 1)
+            // time tau' = beta and tau' - beta nF = beta (1 - nF), taken without cancellation.
+            Val lg = a == b ? em.def(k, "BETA * " + omnF(m), 1)
                             : em.def(k, tprime + " - " + mom_bnf[m], 0, 2);
             Val gm = em.def(k, v.name + " * " + lg.name, 1);
             if (em.act[0]) v.d[em.dir(0) - 1] = gm.name;
@@ -1144,7 +1263,9 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     std::vector<Part> pc;
     int64_t epi_ops[4] = {0, 0, 0, 0};
     for (size_t pi = 0; pi < parts.size(); ++pi) {
-        Builder b(c, n_groups);
+        // a kernel in parts builds each part for one lambda group, passed at run time
+        const int pg = split ? 1 : n_groups;
+        Builder b(c, pg);
         if (split) {
             b.em.tag = "p" + std::to_string(pi) + "_";
             b.em.prefix = b.em.tag + "v";
@@ -1154,8 +1275,8 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         std::sort(pcls.begin(), pcls.end());
         pcls.erase(std::unique(pcls.begin(), pcls.end()), pcls.end());
         // roots[g][class index within the part]
-        std::vector<std::vector<Builder::SVal>> roots(n_groups);
-        for (int g = 0; g < n_groups; ++g) {
+        std::vector<std::vector<Builder::SVal>> roots(pg);
+        for (int g = 0; g < pg; ++g) {
             for (int r : pcls) {
                 std::vector<Term> terms;
                 for (int di : parts[pi]) {
@@ -1180,7 +1301,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         // every derivative root (the phases and scale depend on none of mu, lambda, k)
         std::ostringstream epi;
         std::vector<std::string> fplain;
-        for (int g = 0; g < n_groups; ++g) {
+        for (int g = 0; g < pg; ++g) {
             for (int ro = 0; ro < NR; ++ro) {
                 std::string fr, fi, frp, fip;  // with J folded in (one straight-line part), and without
                 for (size_t ri = 0; ri < pcls.size(); ++ri) {
@@ -1227,9 +1348,9 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                     fplain.push_back(frp);
                     fplain.push_back(fip);
                 } else {
-                    const int slot = (g * NR + ro) * 2;
-                    if (!fr.empty()) epi << "        st[(kq * SPK + " << slot << ") * 64] += " << fr << ";\n";
-                    if (!fi.empty()) epi << "        st[(kq * SPK + " << slot + 1 << ") * 64] += " << fi << ";\n";
+                    const int slot = ro * 2;
+                    if (!fr.empty()) epi << "        st[(kq * SPK1 + " << slot << ") * 64] += " << fr << ";\n";
+                    if (!fi.empty()) epi << "        st[(kq * SPK1 + " << slot + 1 << ") * 64] += " << fi << ";\n";
                     epi_ops[0] += (!fr.empty()) + (!fi.empty());
                 }
             }
@@ -1268,12 +1389,12 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     s << "\n";
     s << "#define KERNEL_NAME " << kernel_name(c, n_groups) << "\n";
     s << "#define DIM " << c.dim << "\n#define NGRP " << n_groups << "\n#define NROOT " << NR << "\n#define SPK " << SPK
-      << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n";
+      << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n#define SPK1 " << 2 * NR << "\n";
     s << R"K(
 struct EvalArgs {
     const float* x; long long ld; const float* jac; long long n;
     double* partial; unsigned int* nonfinite; float* f_out; float* imp_out;
-    int n_k; int s_total; int pad0; int pad1;
+    int n_k; int s_total; int kc; int pad1;
     float mu, beta, bl, blmu, inv2beta, pad2;
     float lam[8]; float scale[8];
     float k[64];
@@ -1294,27 +1415,26 @@ struct EvalArgs {
             const std::string tg = "p" + std::to_string(pi) + "_";
             s << "\n// part " << pi << " (" << parts[pi].size() << " diagrams)\n";
             s << "__device__ __attribute__((noinline)) void dmc_part_" << pi
-              << "(const EvalArgs* __restrict__ ap, const float* __restrict__ in, float* __restrict__ st, const int kb) {\n";
+              << "(const EvalArgs* __restrict__ ap, const float* __restrict__ in, float* __restrict__ st, const int kb, "
+                 "const int nkc, const int grp) {\n";
             s << "    const float MU = ap->mu, BL = ap->bl, BLMU = ap->blmu, BETA = ap->beta;\n";
             s << "    (void)MU; (void)BL; (void)BLMU; (void)BETA;\n";
-            for (int g = 0; g < n_groups; ++g) s << "    const float LAM" << g << " = ap->lam[" << g << "];\n";
+            s << "    const float LAM0 = ap->lam[grp];\n";
             for (size_t i = 0; i < ins.size(); ++i)
                 s << "    const float " << tg << ins[i] << " = in[" << i * 64 << "];\n";
-            for (int g = 0; g < n_groups; ++g)
-                for (int r : pc[pi].cls) {
-                    if (r == 0) {
-                        s << "    const float PC" << g << "_0 = ap->scale[" << g << "];\n";
-                    } else {
-                        s << "    float sn" << g << "_" << r << ", cs" << g << "_" << r << ";\n";
-                        s << "    sincospif(" << tg << "t" << r << " * (2.0f * ap->inv2beta), &sn" << g << "_" << r << ", &cs"
-                          << g << "_" << r << ");\n";
-                        s << "    const float PC" << g << "_" << r << " = ap->scale[" << g << "] * cs" << g << "_" << r << ";\n";
-                        s << "    const float PS" << g << "_" << r << " = ap->scale[" << g << "] * sn" << g << "_" << r << ";\n";
-                    }
+            for (int r : pc[pi].cls) {
+                if (r == 0) {
+                    s << "    const float PC0_0 = ap->scale[grp];\n";
+                } else {
+                    s << "    float sn0_" << r << ", cs0_" << r << ";\n";
+                    s << "    sincospif(" << tg << "t" << r << " * (2.0f * ap->inv2beta), &sn0_" << r << ", &cs0_" << r << ");\n";
+                    s << "    const float PC0_" << r << " = ap->scale[grp] * cs0_" << r << ";\n";
+                    s << "    const float PS0_" << r << " = ap->scale[grp] * sn0_" << r << ";\n";
                 }
+            }
             s << pc[pi].pre;
-            // external momenta past the last one are skipped (their stage slots stay zero)
-            s << "    for (int kq = 0; kq < KC && kb + kq < ap->n_k; ++kq) {\n";
+            // the part's k-independent values are computed once and serve every momentum of the chunk
+            s << "    for (int kq = 0; kq < nkc; ++kq) {\n";
             s << "        const int ki = kb + kq;\n";
             s << "        const float kk = ap->k[ki];\n";
             indent(s, pc[pi].loop, "    ");
@@ -1325,13 +1445,15 @@ struct EvalArgs {
     // small single-part value graphs (orders 1-3) are held to 5 waves per SIMD: order 3 otherwise takes 98
     // registers, 4 waves, and the fifth hides more of the transcendentals' latency
     const bool five = !split && NR == 1 && n <= 3;
+    // floats of stage per wave: a kernel in parts stages a run-time chunk of a.kc momenta for one group
+    const std::string sfw = split ? "(a.kc * SPK1 * 64)" : "(16 * MST * 64)";
     s << "\nextern \"C\" __global__ void __launch_bounds__(256" << (five ? ", 5" : "") << ") KERNEL_NAME(const EvalArgs a) {";
     s << R"K(
 
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float* stage = smem + wv * (16 * MST * 64);
-    double* tot = (double*)(smem + 4 * 16 * MST * 64) + wv * (2 * a.s_total);
+    float* stage = smem + wv * )K" << sfw << R"K(;
+    double* tot = (double*)(smem + 4 * )K" << sfw << R"K() + wv * (2 * a.s_total);
     for (int i = lane; i < 2 * a.s_total; i += 64) tot[i] = 0.0;
     unsigned int nonfin = 0;
     const float MU = a.mu, BL = a.bl, BLMU = a.blmu, BETA = a.beta;
@@ -1405,36 +1527,81 @@ struct EvalArgs {
                 }
         s << "            }\n";
     } else {
-        // partitioned: every part adds its roots into the stage; each part's k-independent code is
-        // recomputed per chunk of KC external momenta so that no part's values stay live across parts
-        s << "        float* cin = (float*)((double*)(smem + 4 * 16 * MST * 64) + 4 * 2 * a.s_total) + wv * "
+        // partitioned: for each chunk of a.kc external momenta and each lambda group, every part adds its
+        // roots into the stage (its k-independent code runs once per chunk and group), then the group's
+        // weights are formed, checked and folded
+        s << "        float* cin = (float*)((double*)(smem + 4 * " << sfw << ") + 4 * 2 * a.s_total) + wv * "
           << ins.size() * 64 << " + lane;\n";
         for (size_t i = 0; i < ins.size(); ++i) s << "        cin[" << i * 64 << "] = " << ins[i] << ";\n";
         s << R"K(        float imp = 0.0f;
-        for (int kb = 0; kb < a.n_k; kb += KC) {
-            float impc = 0.0f, chk = 0.0f;  // this chunk's importance, and the sum of the other weights
-            for (int i = 0; i < SCH; ++i) stage[i * 64 + lane] = 0.0f;
+        for (int kb = 0; kb < a.n_k; kb += a.kc) {
+            const int nkc = min(a.kc, a.n_k - kb), nsl = nkc * SPK1;
+            for (int grp = 0; grp < NGRP; ++grp) {
+                float impc = 0.0f, chk = 0.0f;  // this chunk's importance, and the sum of the other weights
+                for (int i = 0; i < nsl; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
         for (size_t pi = 0; pi < pc.size(); ++pi)
-            s << "            dmc_part_" << pi << "(&a, cin, stage + lane, kb);\n";
-        s << "            for (int kq = 0; kq < KC; ++kq) {\n";
-        s << "                const int ki = kb + kq;\n";
-        s << "                const bool kv = ki < a.n_k;\n";
-        for (int g = 0; g < n_groups; ++g)
-            for (int ro = 0; ro < NR; ++ro)
-                for (int comp = 0; comp < 2; ++comp) {
-                    int slot = (g * NR + ro) * 2 + comp;
-                    s << "                {\n";
-                    s << "                    const float f = stage[(kq * SPK + " << slot << ") * 64 + lane];\n";
-                    s << "                    const float w = kv ? f * J : 0.0f;\n";
-                    s << "                    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
-                    s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
-                    s << "                    if (a.f_out && valid && kv) a.f_out[(((long long)(" << (g * NR + ro)
-                      << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
-                    s << "                }\n";
+            s << "                dmc_part_" << pi << "(&a, cin, stage + lane, kb, nkc, grp);\n";
+        s << "                for (int kq = 0; kq < nkc; ++kq) {\n";
+        s << "                    const int ki = kb + kq;\n";
+        for (int ro = 0; ro < NR; ++ro)
+            for (int comp = 0; comp < 2; ++comp) {
+                const int slot = ro * 2 + comp;
+                s << "                    {\n";
+                s << "                        const float f = stage[(kq * SPK1 + " << slot << ") * 64 + lane];\n";
+                s << "                        const float w = f * J;\n";
+                s << "                        " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
+                s << "                        stage[(kq * SPK1 + " << slot << ") * 64 + lane] = w;\n";
+                s << "                        if (a.f_out && valid) a.f_out[(((long long)(grp * NROOT + " << ro
+                  << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
+                s << "                    }\n";
+            }
+        s << "                }\n";
+        s << R"K(                if (!__builtin_isfinite(impc + chk)) {
+                    impc = 0.0f;
+                    for (int sl = 0; sl < nsl; ++sl) {
+                        float v = stage[sl * 64 + lane];
+                        if (!__builtin_isfinite(v)) {
+                            if (valid) nonfin += 1u;
+                            v = 0.0f;
+                            stage[sl * 64 + lane] = 0.0f;
+                        }
+                        if ((sl % SPK1) < 2) impc += __builtin_fabsf(v);
+                    }
                 }
-        s << "            }\n";
+                imp += impc;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int m = 0; 16 * m < nsl; ++m) {
+                    const int sl = (lane >> 2) + 16 * m;
+                    double s1 = 0.0, s2 = 0.0;
+                    if (sl < nsl) {
+                        const float4* src = (const float4*)(stage + sl * 64 + (lane & 3) * 16);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float4 v = src[j];
+                            double d = (double)v.x; s1 += d; s2 = __builtin_fma(d, d, s2);
+                            d = (double)v.y; s1 += d; s2 = __builtin_fma(d, d, s2);
+                            d = (double)v.z; s1 += d; s2 = __builtin_fma(d, d, s2);
+                            d = (double)v.w; s1 += d; s2 = __builtin_fma(d, d, s2);
+                        }
+                    }
+                    s1 += __shfl_xor(s1, 1); s2 += __shfl_xor(s2, 1);
+                    s1 += __shfl_xor(s1, 2); s2 += __shfl_xor(s2, 2);
+                    // device slot order [k][group][root][comp]
+                    const int gs = (kb + sl / SPK1) * SPK + grp * SPK1 + sl % SPK1;
+                    if ((lane & 3) == 0 && sl < nsl) { tot[2 * gs] += s1; tot[2 * gs + 1] += s2; }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        if (a.imp_out && valid) a.imp_out[s] = imp;
+)K";
     }
+    if (!split) {
     // a weight that is not finite makes the chunk's sums non-finite: only then (rarely, per lane) are this
     // lane's staged weights scanned, each non-finite one zeroed and counted (valid samples only), and the
     // chunk's importance recomputed
@@ -1484,6 +1651,7 @@ struct EvalArgs {
         }
         if (a.imp_out && valid) a.imp_out[s] = imp;
 )K";
+    }
     if (zero_slots) s << "        nonfin += jbad * (unsigned int)(a.n_k * " << zero_slots << ");\n";
     s << R"K(    }
     // fold the four waves in a fixed order into one FP64 partial per slot
@@ -1491,7 +1659,7 @@ struct EvalArgs {
     __shared__ unsigned int nf_w[4];
     if (lane == 0) nf_w[wv] = nonfin;
     __syncthreads();
-    const double* t0 = (const double*)(smem + 4 * 16 * MST * 64);
+    const double* t0 = (const double*)(smem + 4 * )K" << sfw << R"K();
     const int st2 = 2 * a.s_total;
     for (int i = threadIdx.x; i < st2; i += 256)
         a.partial[(long long)blockIdx.x * st2 + i] = ((t0[i] + t0[st2 + i]) + t0[2 * st2 + i]) + t0[3 * st2 + i];

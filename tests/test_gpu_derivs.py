@@ -32,11 +32,13 @@ def test_derivative_roots_per_sample(n, N, K):
     for j, k in enumerate(ks):
         kk = float(np.float32(k))
         ref = [a.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)]
-        scale = [a.real.sum(axis=0) for a in ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs,
-                                                                    absolute=True)]
+        absd = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs, absolute=True)
+        C = ig.exponent_condition(x64, n, kk, BETA, MU, diagrams=dgs)
+        scale = [a.real.sum(axis=0) for a in absd]
         for r in range(4):
             err = np.abs(f[0, r, j] - ref[r])
-            ok = err <= 1e-5 * scale[r] + 1e-30
+            # the per-sample rule of the value, with the terms' magnitudes of the derivative
+            ok = err <= 1e-5 * scale[r] + 2 * ig.U32 * (absd[r].real * C).sum(axis=0) + 1e-30
             assert np.all(ok), f"root {r} k={k}: worst {np.max(err / (scale[r] + 1e-300))}"
             m = scale[r] > 1e-30
             if np.any(m):
@@ -109,8 +111,10 @@ def test_k_derivative_order6_per_sample():
         kk = float(np.float32(k))
         vals = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
         scales = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs, absolute=True)
+        C = ig.exponent_condition(x64, n, kk, BETA, MU, diagrams=dgs)
         for r, src in [(0, 0), (1, 3)]:
             ref = vals[src].sum(axis=0)
             scale = scales[src].real.sum(axis=0)
             err = np.abs(f[0, r, j] - ref)
-            assert np.all(err <= 1e-5 * scale + 1e-30), f"root {r} k={k}: worst {np.max(err / (scale + 1e-300))}"
+            tol = 1e-5 * scale + 2 * ig.U32 * (scales[src].real * C).sum(axis=0) + 1e-30
+            assert np.all(err <= tol), f"root {r} k={k}: worst {np.max(err / (scale + 1e-300))}"

@@ -88,7 +88,7 @@ def test_partitioned_graphs():
     assert i.n_parts == 5 and i.part_size == 40
     src = g.source(1)
     assert "_p5" in src and src.count("// part ") == 5
-    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, cin, stage + lane, kb);" in src
+    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, cin, stage + lane, kb, nkc, grp);" in src
     # every diagram lands in exactly one part
     import re
     sizes = [int(m) for m in re.findall(r"// part \d+ \((\d+) diagrams\)", src)]
@@ -126,7 +126,7 @@ def test_factoring_keeps_multipliers_out_of_the_momentum_loop():
     # over external momenta: no sign select, no lambda add and no mu subtraction inside it, and the sample's
     # Jacobian sits in the per-sample phase factors; issue slots per (sample, k) (transcendentals twice)
     # stay at or below the factored counts
-    for n, most in [(2, 26), (3, 97), (4, 488)]:
+    for n, most in [(2, 27), (3, 62), (4, 140)]:
         g = dmc.Graph(n)
         src = g.source(1)
         loop = _k_loop(src)

@@ -180,16 +180,22 @@ def test_rainbow_time_integral():
             x[:, 3:6] = q1
             x[:, 6] = t
             tot += np.sum(0.5 * (b - a) * wg * ig.diagram_values(x, 2, k, BETA, MU, LAM, GAMMA, [d])[0])
-        # identify which loop momentum sits on the two outer propagators (chord rule)
-        p, q = q0, q1
+        # the momenta of the lines from the diagram's own routing: both outer propagators carry p,
+        # the equal-time one q
+        kv = np.array([0.0, 0.0, k])
+
+        def mom(ln):
+            return ln.mom[0] * q0 + ln.mom[1] * q1 + ln.mom[2] * kv
+
         outer = [l for l in d.lines if l.kind == "G" and l.src // 2 != l.dst // 2]
-        if outer[0].mom[:2] == (0, 1):
-            p, q = q1, q0
+        inner = [l for l in d.lines if l.kind == "G" and l.src // 2 == l.dst // 2]
+        assert len(outer) == 2 and len(inner) == 1
+        p, q = mom(outer[0]), mom(inner[0])
+        assert np.allclose(np.abs(mom(outer[1])), np.abs(p))
         ep = p @ p - MU
         n_p = ph.nF(ep, BETA)
-        ref = ((2 * math.pi) ** -6 * ph.V(np.sum((np.array([0, 0, k]) - p) ** 2), LAM, GAMMA)
-               * ph.V(np.sum((p - q) ** 2), LAM, GAMMA) * ph.nF(q @ q - MU, BETA)
-               * (-BETA * n_p * (1 - n_p)))
+        vv = np.prod([ph.V(np.sum(mom(l) ** 2), LAM, GAMMA) for l in d.lines if l.kind == "V"])
+        ref = (2 * math.pi) ** -6 * vv * ph.nF(q @ q - MU, BETA) * (-BETA * n_p * (1 - n_p))
         assert abs(tot - ref) < 1e-10 * abs(ref) + 1e-300
 
 

@@ -115,7 +115,7 @@ def test_higher_and_mixed_coefficients_against_finite_differences(n):
         (2, 0, 0): _fd(lambda h: F(dmu=h), 2e-3, 2),
         (3, 0, 0): _fd(lambda h: F(dmu=h), 1e-3, 3),   # mu varies on the scale 1/beta
         (0, 2, 0): _fd(lambda h: F(dlam=h), 2e-2, 2),
-        (0, 3, 0): _fd(lambda h: F(dlam=h), 4e-2, 3),
+        (0, 3, 0): _fd(lambda h: F(dlam=h), 2e-2, 3),   # truncation ~ (h / (|p|^2 + lambda))^2
         (1, 1, 0): _fd(lambda h: _fd(lambda g: F(dmu=g, dlam=h), 2e-3, 1), 2e-2, 1),
         (2, 1, 0): _fd(lambda h: _fd(lambda g: F(dmu=g, dlam=h), 2e-3, 2), 2e-2, 1),
         (1, 0, 1): _fd(lambda h: _fd(lambda g: F(dmu=g, dk=h), 2e-3, 1), 2e-3, 1),
@@ -124,7 +124,8 @@ def test_higher_and_mixed_coefficients_against_finite_differences(n):
     }
     for key, ref in checks.items():
         err = np.abs(roots[key] - ref)
-        assert np.all(err <= 2e-5 * scale[key] + 1e-12 * np.abs(ref)), (key, float((err / scale[key]).max()))
+        # 1e-300: below it FP64 values are subnormal and lose relative precision
+        assert np.all(err <= 2e-5 * scale[key] + 1e-12 * np.abs(ref) + 1e-300), (key, float((err / scale[key]).max()))
 
 
 def test_fock_taylor_closed_form_against_finite_differences():
