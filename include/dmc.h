@@ -66,6 +66,11 @@ typedef struct {
                               eq. sigma_xi_dmu_dlambda): every d^m/dmu^m d^l/dlambda^l with m + l <= T
                               along the masked directions among mu and lambda, and with DMC_D_K also
                               the k derivative of each (eq. deltam_partitions) */
+    int32_t deriv_k;       /* 0: derivative roots at every external momentum; m in 1..DMC_MAX_K: only at the
+                              first m external momenta of each evaluation (the effective mass needs them at
+                              k_F alone, Sec. VI.A eq. eff_mass_ratio); the other momenta's derivative slots
+                              receive zero sums (estimate 0 +- 0) and f_out zeros.  Derivative-only code
+                              then runs at those m momenta only. */
 } dmc_graph_spec;
 
 typedef struct {
@@ -86,6 +91,11 @@ typedef struct {
     int64_t ops_k_exec[4];
     int32_t n_roots;      /* roots per (lambda group, k, Re/Im): the accumulator's n_roots */
     int32_t taylor_order; /* as in the spec */
+    /* the part of ops_k (and ops_k_exec) that only forms the derivative roots: with spec.deriv_k = m it runs
+     * at m momenta, the rest of ops_k at every momentum */
+    int64_t ops_k_deriv[4];
+    int64_t ops_k_deriv_exec[4];
+    int32_t deriv_k;      /* as in the spec */
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that

@@ -1,5 +1,6 @@
 """Build step of the C part of the oracle (test infrastructure): the brute-force diagram
-enumerator oracle/enumerate.c -> oracle/enumerate_topologies (gcc, OpenMP)."""
+enumerator oracle/enumerate.c -> oracle/enumerate_topologies, and the diagram-by-diagram FP64
+integrand oracle/evaluate.c -> oracle/liboracle_eval.so (gcc, OpenMP)."""
 from __future__ import annotations
 
 import os
@@ -8,15 +9,29 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "enumerate.c")
 EXE = os.path.join(HERE, "enumerate_topologies")
+EVAL_SRC = os.path.join(HERE, "evaluate.c")
+EVAL_LIB = os.path.join(HERE, "liboracle_eval.so")
+
+
+def _gcc(args, what):
+    r = subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-Wall", *args], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle {what} build failed:\n" + r.stdout + r.stderr)
 
 
 def build() -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-Wall", "-o", EXE + ".tmp", SRC]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("oracle enumerator build failed:\n" + r.stdout + r.stderr)
+    _gcc(["-o", EXE + ".tmp", SRC], "enumerator")
     os.replace(EXE + ".tmp", EXE)
+    _gcc(["-shared", "-fPIC", "-o", EVAL_LIB + ".tmp", EVAL_SRC, "-lm"], "evaluator")
+    os.replace(EVAL_LIB + ".tmp", EVAL_LIB)
     return EXE
+
+
+def eval_library() -> str:
+    """The C evaluator, built if it is missing or older than its source."""
+    if not os.path.exists(EVAL_LIB) or os.path.getmtime(EVAL_LIB) < os.path.getmtime(EVAL_SRC):
+        build()
+    return EVAL_LIB
 
 
 def executable() -> str:

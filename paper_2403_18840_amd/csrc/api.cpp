@@ -140,8 +140,8 @@ dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
     auto g = std::make_unique<dmc_graph>();
     std::string err;
     try {
-        if (!dmc::compile(spec->order, spec->deriv_mask, spec->taylor_order, spec->diagram_index, spec->part_size, g->c,
-                          err))
+        if (!dmc::compile(spec->order, spec->deriv_mask, spec->taylor_order, spec->diagram_index, spec->part_size,
+                          spec->deriv_k, g->c, err))
             return fail(DMC_E_INVALID, err);
         g->exported = dmc::export_text(g->c);
     } catch (const std::bad_alloc&) {
@@ -166,9 +166,12 @@ dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
         o->ops_naive[i] = g->c.stats.naive[i];
         o->ops_sample_exec[i] = g->c.stats.sample_exec[i];
         o->ops_k_exec[i] = g->c.stats.k_exec[i];
+        o->ops_k_deriv[i] = g->c.stats.k_deriv[i];
+        o->ops_k_deriv_exec[i] = g->c.stats.k_deriv_exec[i];
     }
     o->n_roots = g->c.n_roots;
     o->taylor_order = g->c.taylor_order;
+    o->deriv_k = g->c.deriv_k;
     return DMC_OK;
 }
 
@@ -409,12 +412,21 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
             if (nb > 0) jk->max_blocks_per_cu = nb;
         }
     } else {
+        // staged floats per lane for a chunk of c momenta: 2 NR for each of the first momenta that carry
+        // derivative roots (spec.deriv_k; all of them when 0), 2 for the others.  The chunk holds at
+        // least the derivative momenta, so that they all fall into the first chunk.
+        const int KD = NR > 1 ? g->c.deriv_k : 0;
+        auto stage_for = [&](int c) {
+            const int ml = KD ? std::min(KD, c) : c;
+            return ml * 2 * NR + (c - ml) * 2;
+        };
+        const int cmin = KD ? std::min(KD, n_k) : 1;
         if (!jk->kc[n_k]) {
-            const int best = blocks_for(smem_for(2 * NR));
+            const int best = blocks_for(smem_for(stage_for(cmin)));
             if (best < 1) return fail(DMC_E_INVALID, "too many accumulator slots for one workgroup");
-            int pick = 1, pick_nb = best;
-            for (int c = n_k; c >= 1; --c) {
-                const int nb = blocks_for(smem_for(c * 2 * NR));
+            int pick = cmin, pick_nb = best;
+            for (int c = n_k; c >= cmin; --c) {
+                const int nb = blocks_for(smem_for(stage_for(c)));
                 if (nb >= best) {
                     pick = c;
                     pick_nb = nb;
@@ -425,7 +437,7 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
             jk->kc_blocks[n_k] = pick_nb;
         }
         kc = jk->kc[n_k];
-        smem = smem_for(kc * 2 * NR);
+        smem = smem_for(stage_for(kc));
         jk->max_blocks_per_cu = jk->kc_blocks[n_k];
     }
     const int64_t ntiles = (n + 255) / 256;

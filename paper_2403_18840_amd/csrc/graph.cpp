@@ -349,8 +349,27 @@ struct Val {
 
 class Emitter {
    public:
-    std::ostringstream pre, loop;
-    int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0};  // add mul fma trans
+    std::ostringstream pre, loop, loopd;
+    int64_t cnt_pre[4] = {0, 0, 0, 0}, cnt_loop[4] = {0, 0, 0, 0}, cnt_loopd[4] = {0, 0, 0, 0};  // add mul fma trans
+    // With split_deriv, k-dependent code that forms a coefficient entry j > 0 (a derivative root's
+    // value) goes to loopd, which the kernel runs only at the momenta that carry derivative roots;
+    // dlevel > 0 while such code is emitted.  Cached helpers that value code may share are created with
+    // dlevel 0 (ValueScope).
+    bool split_deriv = false;
+    int dlevel = 0;
+    struct DerivScope {
+        Emitter& e;
+        explicit DerivScope(Emitter& em) : e(em) { ++e.dlevel; }
+        ~DerivScope() { --e.dlevel; }
+    };
+    struct ValueScope {
+        Emitter& e;
+        int saved;
+        explicit ValueScope(Emitter& em) : e(em), saved(em.dlevel) { e.dlevel = 0; }
+        ~ValueScope() { e.dlevel = saved; }
+    };
+    bool to_d(bool kdep) const { return kdep && split_deriv && dlevel > 0; }
+    int64_t* cnt(bool kdep) { return to_d(kdep) ? cnt_loopd : kdep ? cnt_loop : cnt_pre; }
     bool act[3] = {false, false, false};  // directions with a first-order entry (mu, lambda, k)
     const CoefSet* cs = nullptr;
 
@@ -370,8 +389,8 @@ class Emitter {
 
     Val def(bool kdep, const std::string& expr, int opclass, int nops = 1) {
         std::string nm = prefix + std::to_string(tmp_++);
-        (kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
-        if (opclass >= 0) (kdep ? cnt_loop : cnt_pre)[opclass] += nops;
+        (to_d(kdep) ? loopd : kdep ? loop : pre) << "    const float " << nm << " = " << expr << ";\n";
+        if (opclass >= 0) cnt(kdep)[opclass] += nops;
         return {nm, kdep, std::vector<std::string>(nco() - 1)};
     }
     Val hashed(const std::string& key, bool kdep, const std::string& expr, int opclass,
@@ -379,7 +398,10 @@ class Emitter {
         auto it = cse_.find(key);
         if (it != cse_.end()) return it->second;
         Val v = def(kdep, expr, opclass);
-        tangents(v);
+        {
+            DerivScope ds(*this);
+            tangents(v);
+        }
         cse_[key] = v;
         return v;
     }
@@ -402,7 +424,7 @@ class Emitter {
                     v.d[j - 1] = def(kd, acc, 1).name;
                 } else {
                     v.d[j - 1] = def(kd, acc, 2, t - 1).name;
-                    (kd ? cnt_loop : cnt_pre)[1] += 1;
+                    cnt(kd)[1] += 1;
                 }
             }
         });
@@ -520,6 +542,7 @@ struct Builder {
     }
 
     std::array<std::string, 3> Q(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_q.find(m);
         if (it != mom_q.end()) return it->second;
         std::array<std::string, 3> r;
@@ -548,6 +571,7 @@ struct Builder {
     }
 
     Val q2(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_q2.find(m);
         if (it != mom_q2.end()) return it->second;
         auto q = Q(m);
@@ -561,6 +585,7 @@ struct Builder {
 
     // Qx^2 + Qy^2 of a k-dependent momentum Q + ck k z (hoisted)
     Val qxy2(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_qxy2.find(m);
         if (it != mom_qxy2.end()) return it->second;
         auto q = Q(m);
@@ -573,6 +598,7 @@ struct Builder {
     // |Q + ck k z|^2 = Qx^2 + Qy^2 + (Qz + ck k)^2 is formed without cancelling against |Q|^2; and
     // d|p|^2/dk = 2 ck (Qz + ck k)
     const std::string& kz(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_t.find(m);
         if (it != mom_t.end()) return it->second;
         auto q = Q(m);
@@ -585,6 +611,7 @@ struct Builder {
     }
 
     Val p2(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_p2.find(m);
         if (it != mom_p2.end()) return it->second;
         Val v;
@@ -601,6 +628,7 @@ struct Builder {
     // |p|^2 + lambda_g, the interaction's denominator: for a k-dependent momentum lambda joins the hoisted
     // Qx^2 + Qy^2, so that the loop spends one fused multiply-add on it
     Val p2_lam(int m, int grp) {
+        Emitter::ValueScope vs_(em);
         const std::string lam = "LAM" + std::to_string(grp);
         if (!is_k(m)) return em.def(false, p2(m).name + " + " + lam, 0);
         Val base = em.def(false, qxy2(m).name + " + " + lam, 0);
@@ -610,6 +638,7 @@ struct Builder {
 
     // time pair: propagator from interaction line a to line b (a != b)
     std::pair<std::string, std::string> T(int a, int b) {
+        Emitter::ValueScope vs_(em);
         auto key = std::make_pair(a, b);
         auto it = tpair.find(key);
         if (it != tpair.end()) return it->second;
@@ -633,6 +662,7 @@ struct Builder {
     // the exponent's time for a propagator from line a to line b: tau' when eps >= 0, beta - tau' when
     // eps < 0 (log2 units), so that G0 = s 2^(-|eps| S) / (1 + 2^(-beta |eps|)) has no factor above 1
     Val S(int m, int a, int b) {
+        Emitter::ValueScope vs_(em);
         T(a, b);
         const auto& en = E(m);
         return em.def(is_k(m), en.pos + " ? " + tpair[{a, b}].first + " : " + tcomp[{a, b}], 0);
@@ -649,6 +679,7 @@ struct Builder {
     // the sign of the propagator from line a to line b (-1 when b precedes a) as a hoisted factor: a
     // k-dependent propagator is computed without it and the sign joins the hoisted multipliers
     int sign_factor(int a, int b) {
+        Emitter::ValueScope vs_(em);
         auto key = std::make_pair(a, b);
         auto it = sgn_id_.find(key);
         if (it != sgn_id_.end()) return it->second;
@@ -659,6 +690,7 @@ struct Builder {
     }
 
     const Energy& E(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = energy.find(m);
         if (it != energy.end()) return it->second;
         const bool k = is_k(m);
@@ -669,19 +701,19 @@ struct Builder {
         en.ae = "__builtin_fabsf(" + e.name + ")";  // an operand modifier: free
         en.pos = em.tag + "pe" + std::to_string(m);
         (k ? em.loop : em.pre) << "    const bool " << en.pos << " = " << e.name << " >= 0.0f;\n";
-        (k ? em.cnt_loop : em.cnt_pre)[0] += 1;
+        em.cnt(k)[0] += 1;
         en.em = em.def(k, "__builtin_amdgcn_exp2f(-BL * " + en.ae + ")", 3).name;
-        (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+        em.cnt(k)[1] += 1;
         Val den = em.def(k, en.em + " + 1.0f", 0);
         en.r = em.def(k, "__builtin_amdgcn_rcpf(" + den.name + ")", 3).name;
         energy[m] = en;
-        if (c.taylor_order == 0 && (em.act[0] || em.act[2])) mom_bnf[m] = em.def(k, "BETA * " + nF(m), 1).name;
         return energy[m];
     }
 
     // nF(eps) and 1 - nF(eps) of a momentum
     std::map<int, std::string> mom_nf, mom_omnf;
     const std::string& nF(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_nf.find(m);
         if (it != mom_nf.end()) return it->second;
         const Energy& en = E(m);
@@ -689,6 +721,7 @@ struct Builder {
         return mom_nf[m] = em.def(en.k, en.pos + " ? " + p.name + " : " + en.r, 0).name;
     }
     const std::string& omnF(int m) {
+        Emitter::ValueScope vs_(em);
         auto it = mom_omnf.find(m);
         if (it != mom_omnf.end()) return it->second;
         const Energy& en = E(m);
@@ -698,11 +731,12 @@ struct Builder {
 
     // |G0| = 2^(-|eps| S) / (1 + 2^(-beta |eps|)) of the propagator from line a to line b (a != b)
     Val gmag(int m, int a, int b) {
+        Emitter::ValueScope vs_(em);
         const bool k = is_k(m);
         Val sv = S(m, a, b);
         const Energy& en = E(m);
         Val ex = em.def(k, "__builtin_amdgcn_exp2f(-" + en.ae + " * " + sv.name + ")", 3);
-        (k ? em.cnt_loop : em.cnt_pre)[1] += 1;
+        em.cnt(k)[1] += 1;
         return em.def(k, ex.name + " * " + en.r, 1);
     }
 
@@ -711,6 +745,7 @@ struct Builder {
     std::map<std::pair<int, int>, std::vector<std::string>> tser_;  // tau'^i / i! per time pair
 
     const std::string& bfac(int i) {
+        Emitter::ValueScope vs_(em);
         auto it = bfac_.find(i);
         if (it != bfac_.end()) return it->second;
         std::string v = i == 1 ? std::string("BETA") : em.def(false, bfac(i - 1) + " * BETA * " + fstr(1.0 / i), 1, 2).name;
@@ -719,6 +754,7 @@ struct Builder {
 
     // tau'^i / i!, i = 0..M, for the propagator from line a to line b (tau' in (0, beta])
     const std::vector<std::string>& tser(int a, int b, int M) {
+        Emitter::ValueScope vs_(em);
         auto key = std::make_pair(a, b);
         auto& t = tser_[key];
         if (t.empty()) {
@@ -751,6 +787,11 @@ struct Builder {
         std::vector<std::string> dser(M + 1);
         dser[0] = "1.0f";
         const std::string nf = M >= 1 ? nF(m) : std::string();
+        const std::string d0 = a == b ? omnF(m) : std::string();
+        Val g0;
+        if (a != b) g0 = gmag(m, a, b);
+        if (a != b) tser(a, b, M);
+        Emitter::DerivScope ds(em);
         for (int j = 1; j <= M; ++j) {
             std::string acc;
             int t = 0;
@@ -770,13 +811,14 @@ struct Builder {
         Val v;
         if (a == b) {
             // equal time (0^-): nF(eps - dmu) = 1 - D(eps - dmu), D = 1 - nF
-            const std::string d0 = omnF(m);
             v = Val{nF(m), k, std::vector<std::string>(em.nco() - 1)};
             for (int j = 1; j <= M; ++j) g[j] = em.def(k, "-" + d0 + " * " + dser[j], 1).name;
         } else {
             auto tp = T(a, b);
-            Val g0 = gmag(m, a, b);
-            v = k ? g0 : em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
+            {
+                Emitter::ValueScope vs(em);
+                v = k ? g0 : em.def(k, tp.second + " ? -" + g0.name + " : " + g0.name, 0);
+            }
             const auto& ts = tser(a, b, M);
             for (int j = 1; j <= M; ++j) {
                 std::string acc = dser[j];
@@ -820,6 +862,7 @@ struct Builder {
         const int L = coefs.max_l + (kt ? 1 : 0);
         std::vector<std::string> c(L + 1);
         c[0] = v.name;
+        Emitter::DerivScope ds(em);
         for (int l = 1; l <= L; ++l) c[l] = em.def(k, "-" + c[l - 1] + " * " + v.name, 1).name;
         for (int l = 1; l <= coefs.max_l; ++l) {
             const int e = coefs.find(0, l, 0);
@@ -861,10 +904,13 @@ struct Builder {
             tprime = tp.first + " * 0.693147181f";
         }
         if (em.act[0] || (em.act[2] && k)) {
+            Emitter::DerivScope ds(em);
             // d G0 / d mu = G0 (tau' - beta nF);  d G0 / dk = -(d G0 / d mu) d|p|^2/dk.  At equal
             // time tau' = beta and tau' - beta nF = beta (1 - nF), taken without cancellation.
+            auto bi = mom_bnf.find(m);
+            if (a != b && bi == mom_bnf.end()) bi = mom_bnf.emplace(m, em.def(k, "BETA * " + nF(m), 1).name).first;
             Val lg = a == b ? em.def(k, "BETA * " + omnF(m), 1)
-                            : em.def(k, tprime + " - " + mom_bnf[m], 0, 2);
+                            : em.def(k, tprime + " - " + bi->second, 0, 2);
             Val gm = em.def(k, v.name + " * " + lg.name, 1);
             if (em.act[0]) v.d[em.dir(0) - 1] = gm.name;
             if (em.act[2] && k) v.d[em.dir(2) - 1] = em.def(true, "-" + gm.name + " * " + mom_dp2[m], 1).name;
@@ -885,6 +931,7 @@ struct Builder {
         Val s = p2_lam(m, grp);
         Val v = em.def(k, "__builtin_amdgcn_rcpf(" + s.name + ")", 3);
         if (em.act[1] || (em.act[2] && k)) {
+            Emitter::DerivScope ds(em);
             // d V / d lambda = -V^2 (times 8 pi gamma, applied at the end); d V / dk = -V^2 d|p|^2/dk
             Val vl = em.def(k, "-" + v.name + " * " + v.name, 1);
             if (em.act[1]) v.d[em.dir(1) - 1] = vl.name;
@@ -1094,8 +1141,8 @@ struct Builder {
 
 int default_part_size(int order, int n_diagrams, int n_roots);
 
-bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, Compiled& out,
-             std::string& err) {
+bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
+             Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -1108,7 +1155,12 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         err = "taylor_order must be in 0..6";
         return false;
     }
+    if (deriv_k < 0 || deriv_k > 64) {
+        err = "deriv_k must be in 0..64";
+        return false;
+    }
     out = Compiled{};
+    out.deriv_k = deriv_k;
     out.order = order;
     out.dim = 4 * order - 1;
     out.deriv_mask = deriv_mask;
@@ -1137,6 +1189,7 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
     for (int i = 0; i < 4; ++i) {
         st.sample_exec[i] = st.sample[i];
         st.k_exec[i] = st.k[i];
+        st.k_deriv_exec[i] = st.k_deriv[i];
     }
     if (st.parts > 1) {
         // algorithmic counts: the same graph emitted as one part (no leaf evaluated twice)
@@ -1147,6 +1200,7 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         for (int i = 0; i < 4; ++i) {
             st.sample[i] = one.sample[i];
             st.k[i] = one.k[i];
+            st.k_deriv[i] = one.k_deriv[i];
         }
     }
     out.stats = st;
@@ -1254,18 +1308,22 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     const auto parts = diagram_parts(c, c.part_size);
     const bool split = parts.size() > 1;
 
+    // derivative roots (coefficient entries j > 0) are emitted apart from the value (root 0): their
+    // k-dependent code and epilogue run only at the first KD external momenta (all of them when KD is 0)
+    const int KD = NR > 1 ? c.deriv_k : 0;
     struct Part {
         std::vector<int> cls;
-        std::string pre, loop, epi;
+        std::string pre, loop, epi, loopd, epid;
         std::vector<std::string> fplain;  // one straight-line part: f per (group, root, component) without J
-        int64_t cnt_pre[4], cnt_loop[4];
+        int64_t cnt_pre[4], cnt_loop[4], cnt_loopd[4];
     };
     std::vector<Part> pc;
-    int64_t epi_ops[4] = {0, 0, 0, 0};
+    int64_t epi_ops[4] = {0, 0, 0, 0}, epi_ops_d[4] = {0, 0, 0, 0};
     for (size_t pi = 0; pi < parts.size(); ++pi) {
         // a kernel in parts builds each part for one lambda group, passed at run time
         const int pg = split ? 1 : n_groups;
         Builder b(c, pg);
+        b.em.split_deriv = NR > 1;
         if (split) {
             b.em.tag = "p" + std::to_string(pi) + "_";
             b.em.prefix = b.em.tag + "v";
@@ -1299,10 +1357,12 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         }
         // epilogue: f = sum_r root_r * (scale_g cos, scale_g sin)(pi tau_r / beta), and the same for
         // every derivative root (the phases and scale depend on none of mu, lambda, k)
-        std::ostringstream epi;
+        std::ostringstream epi, epid;
         std::vector<std::string> fplain;
         for (int g = 0; g < pg; ++g) {
             for (int ro = 0; ro < NR; ++ro) {
+                std::ostringstream& eo = ro == 0 ? epi : epid;
+                int64_t* eops = ro == 0 ? epi_ops : epi_ops_d;
                 std::string fr, fi, frp, fip;  // with J folded in (one straight-line part), and without
                 for (size_t ri = 0; ri < pcls.size(); ++ri) {
                     int r = pcls[ri];
@@ -1332,26 +1392,26 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
                     auto term = [](std::string& acc, const std::string& x, const std::string& y) {
                         acc = acc.empty() ? x + " * " + y : "__builtin_fmaf(" + x + ", " + y + ", " + acc + ")";
                     };
-                    epi_ops[fr.empty() ? 1 : 2]++;
+                    eops[fr.empty() ? 1 : 2]++;
                     term(fr, rv, pcj);
                     term(frp, rv, pcn);
                     if (r == 0) continue;
-                    epi_ops[fi.empty() ? 1 : 2]++;
+                    eops[fi.empty() ? 1 : 2]++;
                     term(fi, rv, psj);
                     term(fip, rv, psn);
                 }
                 if (!split) {
                     if (fr.empty()) fr = frp = "0.0f";
                     if (fi.empty()) fi = fip = "0.0f";
-                    epi << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
-                    epi << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
+                    eo << "        const float FR" << g << "_" << ro << " = " << fr << ";\n";
+                    eo << "        const float FI" << g << "_" << ro << " = " << fi << ";\n";
                     fplain.push_back(frp);
                     fplain.push_back(fip);
                 } else {
                     const int slot = ro * 2;
-                    if (!fr.empty()) epi << "        st[(kq * SPK1 + " << slot << ") * 64] += " << fr << ";\n";
-                    if (!fi.empty()) epi << "        st[(kq * SPK1 + " << slot + 1 << ") * 64] += " << fi << ";\n";
-                    epi_ops[0] += (!fr.empty()) + (!fi.empty());
+                    if (!fr.empty()) eo << "        st[(row + " << slot << ") * 64] += " << fr << ";\n";
+                    if (!fi.empty()) eo << "        st[(row + " << slot + 1 << ") * 64] += " << fi << ";\n";
+                    eops[0] += (!fr.empty()) + (!fi.empty());
                 }
             }
         }
@@ -1360,10 +1420,13 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
         p.pre = b.em.pre.str();
         p.loop = b.em.loop.str();
         p.epi = epi.str();
+        p.loopd = b.em.loopd.str();
+        p.epid = epid.str();
         p.fplain = fplain;
         for (int i = 0; i < 4; ++i) {
             p.cnt_pre[i] = b.em.cnt_pre[i];
             p.cnt_loop[i] = b.em.cnt_loop[i];
+            p.cnt_loopd[i] = b.em.cnt_loopd[i];
         }
         pc.push_back(std::move(p));
     }
@@ -1389,7 +1452,8 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
     s << "\n";
     s << "#define KERNEL_NAME " << kernel_name(c, n_groups) << "\n";
     s << "#define DIM " << c.dim << "\n#define NGRP " << n_groups << "\n#define NROOT " << NR << "\n#define SPK " << SPK
-      << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n#define SPK1 " << 2 * NR << "\n";
+      << "\n#define KC " << KC << "\n#define SCH " << SCH << "\n#define MST " << M << "\n#define SPK1 " << 2 * NR
+      << "\n#define KD " << KD << "\n";
     s << R"K(
 struct EvalArgs {
     const float* x; long long ld; const float* jac; long long n;
@@ -1416,7 +1480,7 @@ struct EvalArgs {
             s << "\n// part " << pi << " (" << parts[pi].size() << " diagrams)\n";
             s << "__device__ __attribute__((noinline)) void dmc_part_" << pi
               << "(const EvalArgs* __restrict__ ap, const float* __restrict__ in, float* __restrict__ st, const int kb, "
-                 "const int nkc, const int grp) {\n";
+                 "const int nkc, const int grp, const int ml) {\n";
             s << "    const float MU = ap->mu, BL = ap->bl, BLMU = ap->blmu, BETA = ap->beta;\n";
             s << "    (void)MU; (void)BL; (void)BLMU; (void)BETA;\n";
             s << "    const float LAM0 = ap->lam[grp];\n";
@@ -1437,8 +1501,16 @@ struct EvalArgs {
             s << "    for (int kq = 0; kq < nkc; ++kq) {\n";
             s << "        const int ki = kb + kq;\n";
             s << "        const float kk = ap->k[ki];\n";
+            s << "        const int row = kq < ml ? kq * SPK1 : ml * SPK1 + (kq - ml) * 2;  // this momentum's stage rows\n";
+            s << "        (void)ki;\n";
             indent(s, pc[pi].loop, "    ");
             indent(s, pc[pi].epi, "");
+            if (!pc[pi].loopd.empty() || !pc[pi].epid.empty()) {
+                s << "        if (kq < ml) {\n";
+                indent(s, pc[pi].loopd, "        ");
+                indent(s, pc[pi].epid, "    ");
+                s << "        }\n";
+            }
             s << "    }\n}\n";
         }
     }
@@ -1508,23 +1580,46 @@ struct EvalArgs {
 )K";
         indent(s, pc[0].loop, "            ");
         indent(s, pc[0].epi, "            ");
+        // the staging of one (group, root, component) slot: weight f J into the stage, f into f_out
+        auto stage_slot = [&](std::ostringstream& o, int g, int ro, int comp, bool zero, const std::string& pad) {
+            const std::string fo = "if (a.f_out && valid) a.f_out[(((long long)(" + std::to_string(g * NR + ro) +
+                                   ") * a.n_k + ki) * 2 + " + std::to_string(comp) + ") * a.n + s] = ";
+            if (real_only && comp == 1) {
+                o << pad << fo << "0.0f;\n";
+                return;
+            }
+            const int slot = real_only ? g * NR + ro : (g * NR + ro) * 2 + comp;
+            if (zero) {
+                o << pad << "stage[(kq * SPK + " << slot << ") * 64 + lane] = 0.0f;\n";
+                o << pad << fo << "0.0f;\n";
+                return;
+            }
+            o << pad << "{\n";
+            o << pad << "    const float w = " << (comp ? "FI" : "FR") << g << "_" << ro << ";  // f J\n";
+            o << pad << "    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
+            o << pad << "    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
+            o << pad << "    " << fo << pc[0].fplain[(g * NR + ro) * 2 + comp] << ";\n";
+            o << pad << "}\n";
+        };
         for (int g = 0; g < n_groups; ++g)
-            for (int ro = 0; ro < NR; ++ro)
-                for (int comp = 0; comp < 2; ++comp) {
-                    const std::string fo = "if (a.f_out && valid) a.f_out[(((long long)(" + std::to_string(g * NR + ro) +
-                                           ") * a.n_k + ki) * 2 + " + std::to_string(comp) + ") * a.n + s] = ";
-                    if (real_only && comp == 1) {
-                        s << "                " << fo << "0.0f;\n";
-                        continue;
-                    }
-                    int slot = real_only ? g * NR + ro : (g * NR + ro) * 2 + comp;
-                    s << "                {\n";
-                    s << "                    const float w = " << (comp ? "FI" : "FR") << g << "_" << ro << ";  // f J\n";
-                    s << "                    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
-                    s << "                    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
-                    s << "                    " << fo << pc[0].fplain[(g * NR + ro) * 2 + comp] << ";\n";
-                    s << "                }\n";
-                }
+            for (int comp = 0; comp < 2; ++comp) stage_slot(s, g, 0, comp, false, "                ");
+        if (NR > 1) {
+            // derivative roots: at every momentum (KD = 0) or at the first KD only (zeros elsewhere)
+            const std::string pad = KD ? "                    " : "                ";
+            if (KD) s << "                if (ki < KD) {\n";
+            indent(s, pc[0].loopd, KD ? "                " : "            ");
+            indent(s, pc[0].epid, KD ? "                " : "            ");
+            for (int g = 0; g < n_groups; ++g)
+                for (int ro = 1; ro < NR; ++ro)
+                    for (int comp = 0; comp < 2; ++comp) stage_slot(s, g, ro, comp, false, pad);
+            if (KD) {
+                s << "                } else {\n";
+                for (int g = 0; g < n_groups; ++g)
+                    for (int ro = 1; ro < NR; ++ro)
+                        for (int comp = 0; comp < 2; ++comp) stage_slot(s, g, ro, comp, true, pad);
+                s << "                }\n";
+            }
+        }
         s << "            }\n";
     } else {
         // partitioned: for each chunk of a.kc external momenta and each lambda group, every part adds its
@@ -1535,26 +1630,33 @@ struct EvalArgs {
         for (size_t i = 0; i < ins.size(); ++i) s << "        cin[" << i * 64 << "] = " << ins[i] << ";\n";
         s << R"K(        float imp = 0.0f;
         for (int kb = 0; kb < a.n_k; kb += a.kc) {
-            const int nkc = min(a.kc, a.n_k - kb), nsl = nkc * SPK1;
+            const int nkc = min(a.kc, a.n_k - kb);
+            // momenta with derivative roots in this chunk (the first ml), and the staged slots: SPK1 per such
+            // momentum, 2 (the value) per other
+            const int ml = KD ? max(0, min(nkc, KD - kb)) : nkc;
+            const int nsl = ml * SPK1 + (nkc - ml) * 2;
             for (int grp = 0; grp < NGRP; ++grp) {
                 float impc = 0.0f, chk = 0.0f;  // this chunk's importance, and the sum of the other weights
                 for (int i = 0; i < nsl; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
         for (size_t pi = 0; pi < pc.size(); ++pi)
-            s << "                dmc_part_" << pi << "(&a, cin, stage + lane, kb, nkc, grp);\n";
+            s << "                dmc_part_" << pi << "(&a, cin, stage + lane, kb, nkc, grp, ml);\n";
         s << "                for (int kq = 0; kq < nkc; ++kq) {\n";
         s << "                    const int ki = kb + kq;\n";
+        s << "                    const int row = kq < ml ? kq * SPK1 : ml * SPK1 + (kq - ml) * 2;\n";
         for (int ro = 0; ro < NR; ++ro)
             for (int comp = 0; comp < 2; ++comp) {
                 const int slot = ro * 2 + comp;
-                s << "                    {\n";
-                s << "                        const float f = stage[(kq * SPK1 + " << slot << ") * 64 + lane];\n";
+                const std::string fo = "if (a.f_out && valid) a.f_out[(((long long)(grp * NROOT + " + std::to_string(ro) +
+                                       ") * a.n_k + ki) * 2 + " + std::to_string(comp) + ") * a.n + s] = ";
+                s << "                    " << (ro ? "if (kq < ml) {" : "{") << "\n";
+                s << "                        const float f = stage[(row + " << slot << ") * 64 + lane];\n";
                 s << "                        const float w = f * J;\n";
                 s << "                        " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
-                s << "                        stage[(kq * SPK1 + " << slot << ") * 64 + lane] = w;\n";
-                s << "                        if (a.f_out && valid) a.f_out[(((long long)(grp * NROOT + " << ro
-                  << ") * a.n_k + ki) * 2 + " << comp << ") * a.n + s] = f;\n";
-                s << "                    }\n";
+                s << "                        stage[(row + " << slot << ") * 64 + lane] = w;\n";
+                s << "                        " << fo << "f;\n";
+                s << "                    }" << (ro ? " else {\n                        " + fo + "0.0f;\n                    }" : "")
+                  << "\n";
             }
         s << "                }\n";
         s << R"K(                if (!__builtin_isfinite(impc + chk)) {
@@ -1566,7 +1668,8 @@ struct EvalArgs {
                             v = 0.0f;
                             stage[sl * 64 + lane] = 0.0f;
                         }
-                        if ((sl % SPK1) < 2) impc += __builtin_fabsf(v);
+                        const int slot = sl < ml * SPK1 ? sl % SPK1 : (sl - ml * SPK1) % 2;
+                        if (slot < 2) impc += __builtin_fabsf(v);
                     }
                 }
                 imp += impc;
@@ -1590,7 +1693,9 @@ struct EvalArgs {
                     s1 += __shfl_xor(s1, 1); s2 += __shfl_xor(s2, 1);
                     s1 += __shfl_xor(s1, 2); s2 += __shfl_xor(s2, 2);
                     // device slot order [k][group][root][comp]
-                    const int gs = (kb + sl / SPK1) * SPK + grp * SPK1 + sl % SPK1;
+                    const int kq = sl < ml * SPK1 ? sl / SPK1 : ml + (sl - ml * SPK1) / 2;
+                    const int slot = sl < ml * SPK1 ? sl % SPK1 : (sl - ml * SPK1) % 2;
+                    const int gs = (kb + kq) * SPK + grp * SPK1 + slot;
                     if ((lane & 3) == 0 && sl < nsl) { tot[2 * gs] += s1; tot[2 * gs + 1] += s2; }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1671,9 +1776,13 @@ struct EvalArgs {
         for (auto& p : pc)
             for (int i = 0; i < 4; ++i) {
                 stats->sample[i] += p.cnt_pre[i];
-                stats->k[i] += p.cnt_loop[i];
+                stats->k[i] += p.cnt_loop[i] + p.cnt_loopd[i];
+                stats->k_deriv[i] += p.cnt_loopd[i];
             }
-        for (int i = 0; i < 4; ++i) stats->k[i] += epi_ops[i];
+        for (int i = 0; i < 4; ++i) {
+            stats->k[i] += epi_ops[i] + epi_ops_d[i];
+            stats->k_deriv[i] += epi_ops_d[i];
+        }
         stats->parts = (int)parts.size();
         // naive: every diagram as a plain product of its lines, every leaf evaluated per diagram
         for (auto& d : c.diagrams) {

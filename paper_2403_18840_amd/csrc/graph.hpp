@@ -40,10 +40,12 @@ enum class Op : uint8_t { Leaf, Mul, Fma, Add, MulC };
 struct CodeStats {
     int64_t sample[4] = {0, 0, 0, 0};  // add, mul, fma, trans per sample (k-independent)
     int64_t k[4] = {0, 0, 0, 0};       // per (sample, k)
+    int64_t k_deriv[4] = {0, 0, 0, 0}; // the part of k that only forms derivative roots
     int64_t naive[4] = {0, 0, 0, 0};   // plain sum of products per (sample, k)
     int parts = 1;                       // straight-line parts of the generated kernel
     int64_t sample_exec[4] = {0, 0, 0, 0};  // as executed by a kernel in parts (leaves recomputed
     int64_t k_exec[4] = {0, 0, 0, 0};       // per part); equal to sample / k for one part
+    int64_t k_deriv_exec[4] = {0, 0, 0, 0};
 };
 
 struct Compiled {
@@ -55,6 +57,7 @@ struct Compiled {
     // per root, the coefficient it holds: d^m/dmu^m d^l/dlambda^l (d/dk)^e of the self-energy
     std::vector<std::array<int, 3>> root_orders;
     int part_size = 0;  // diagrams per straight-line part; 0 = one part
+    int deriv_k = 0;    // derivative roots only at the first deriv_k external momenta (0: at all of them)
     std::vector<Diagram> diagrams;
     CodeStats stats;
 };
@@ -64,8 +67,8 @@ struct Compiled {
 // part_size: diagrams per straight-line part of the kernel; 0 chooses by size.
 // taylor_order T >= 1 builds every derivative d^m/dmu^m d^l/dlambda^l with m + l <= T along the masked
 // directions (mu bit 0, lambda bit 1), and with the k bit also the k derivative of each of them.
-bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, Compiled& out,
-             std::string& err);
+bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
+             Compiled& out, std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);

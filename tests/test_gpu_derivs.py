@@ -118,3 +118,68 @@ def test_k_derivative_order6_per_sample():
             err = np.abs(f[0, r, j] - ref)
             tol = 1e-5 * scale + 2 * ig.U32 * (scales[src].real * C).sum(axis=0) + 1e-30
             assert np.all(err <= tol), f"root {r} k={k}: worst {np.max(err / (scale + 1e-300))}"
+
+
+@pytest.mark.parametrize("n,mask,part_size,N,K", [(2, ALL, 0, 300, 5), (4, dmc.D_K, 40, 200, 6), (3, ALL, 0, 260, 3)])
+def test_derivative_roots_at_first_momenta_only(n, mask, part_size, N, K):
+    """spec.deriv_k = 2: derivative roots at the first two external momenta (per sample against the oracle),
+    zeros at the others; the value at every momentum.  Single-part kernels and a kernel in parts."""
+    x = synth.loop_points(n, N, seed=320 + n)
+    ks = synth.k_grid(K)[::-1].copy()
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, mask, part_size=part_size, deriv_k=2)
+    assert g.info().deriv_k == 2
+    f, acc, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
+    x64 = x.astype(np.float64)
+    dgs = oracle_diagrams(n)
+    srcs = [0] + [i + 1 for i in range(3) if mask & (1 << i)]
+    for j, k in enumerate(ks):
+        kk = float(np.float32(k))
+        vals = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
+        absd = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs, absolute=True)
+        C = ig.exponent_condition(x64, n, kk, BETA, MU, diagrams=dgs)
+        for r, src in enumerate(srcs):
+            if r > 0 and j >= 2:
+                assert np.all(f[0, r, j] == 0), (r, j)
+                continue
+            err = np.abs(f[0, r, j] - vals[src].sum(axis=0))
+            tol = 1e-5 * absd[src].real.sum(axis=0) + 2 * ig.U32 * (absd[src].real * C).sum(axis=0) + 1e-30
+            assert np.all(err <= tol), f"root {r} k={k}"
+    m, e, ns, nf = acc.estimate(1)
+    assert np.all(m[0, 1:, 2:] == 0) and np.all(e[0, 1:, 2:] == 0)
+
+
+def test_order6_effective_mass_shape_per_sample():
+    """The shape of the order-6 effective-mass workload: d Sigma / dk (spec.deriv_k = 1, at k_F, the first
+    external momentum), three lambda groups in one launch, r_s = 1..5 as gamma^n rescalings, per sample against
+    the oracle's C evaluator (FP64, diagram by diagram) for every group, momentum and root."""
+    from oracle import cevaluate as ce
+    n, N = 6, 48
+    x = synth.loop_points(n, N, seed=3060)
+    ks = np.array([1.0, 0.0, 2.5], dtype=np.float32)
+    lams = [0.5, 1.0, 2.0]
+    inst = [(BETA, MU, lam, ph.coupling(rs)) for lam in lams for rs in (1.0, 2.0, 3.0, 4.0, 5.0)]
+    g = dmc.Graph(n, dmc.D_K, deriv_k=1)
+    f, acc, _ = gpu_integrand(g, x, ks, inst)
+    assert f.shape[:3] == (3, 2, 3)
+    x64 = x.astype(np.float64)
+    dgs = oracle_diagrams(n)
+    tab = ce.table(dgs, n)
+    for gi, lam in enumerate(lams):
+        gamma = ph.coupling(1.0)
+        for j, k in enumerate(ks):
+            o = ce.evaluate(x64, n, float(k), BETA, MU, lam, gamma, dgs, derivs=(j == 0), tab=tab)
+            for r, q in [(0, 0), (1, 3)]:
+                if r == 1 and j > 0:
+                    assert np.all(f[gi, r, j] == 0)
+                    continue
+                ref = o[:, q, 0] + 1j * o[:, q, 1]
+                tol = 1e-5 * o[:, q, 2] + 2 * 2.0 ** -24 * o[:, q, 3] + 1e-30
+                err = np.abs(f[gi, r, j] - ref)
+                assert np.all(err <= tol), f"lambda {lam} k={k} root {r}: worst {np.max(err / (o[:, q, 2] + 1e-300))}"
+    # the r_s instances of one lambda group are that group's estimate times (r_s)^n
+    m, e, ns, nf = acc.estimate(len(inst))
+    for gi in range(3):
+        base = m[5 * gi]
+        for ri, rs in enumerate((1.0, 2.0, 3.0, 4.0, 5.0)):
+            assert np.allclose(m[5 * gi + ri], base * rs ** n, rtol=1e-12, atol=0)
