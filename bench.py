@@ -32,7 +32,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz; packed FP32 is disabled in this build
+PEAK_FP32_TFLOPS = 157.3  # MI355X's published FP32 vector peak (dense)
+PEAK_ALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz: the unpacked issue rate (packed FP32 is off)
 PEAK_BF16_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 # affine-coupling flow, 8 layers of 16 -> 128 -> 128 -> 32 (FMA = 2 FLOP); the products as executed
 FLOW_FLOP_PER_SAMPLE = 8 * 2 * (16 * 128 + 128 * 128 + 128 * 32)
@@ -43,17 +44,19 @@ def flops(ops):
     return ops[0] + ops[1] + 2 * ops[2] + ops[3]
 
 
-def traffic_for(graph, n_groups=1):
-    """HBM bytes per launch from the committed counter runs, if the generated kernel is the one
-    that was measured (same source), else None."""
+def traffic_for(graph, n_groups=1, n_samples=None, name="eval_o3_hbm_traffic.json"):
+    """HBM bytes per launch from the committed counter runs (profiles/<name>), if the generated kernel is the one
+    that was measured (same source) on as many samples, else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "eval_o3_hbm_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     src = graph.source(n_groups)
     if hashlib.sha1(src.encode()).hexdigest() != d.get("kernel_source_sha1"):
+        return None
+    if n_samples is not None and d.get("samples_per_launch") not in (None, n_samples):
         return None
     return d["hbm_bytes_per_launch"]
 
@@ -149,7 +152,8 @@ def measured_peaks():
     return {"fp32_fma_tflops": 2 * best(0, 4096) / 1e12, "exp2_per_cu_clock": best(1, 1024) / per_clk,
             "rcp_per_cu_clock": best(2, 1024) / per_clk, "fma_per_cu_clock": best(0, 4096) / per_clk,
             "hbm_copy_tbs": best(3, 1 << 30) / 1e12,
-            "assumed": {"fp32_vector_tflops": PEAK_ALU_TFLOPS, "hbm_tbs": 8.0, "clock_ghz": 2.4, "cus": 256}}
+            "assumed": {"fp32_vector_tflops": PEAK_FP32_TFLOPS, "fp32_unpacked_tflops": PEAK_ALU_TFLOPS, "hbm_tbs": 8.0,
+                        "clock_ghz": 2.4, "cus": 256}}
 
 
 def _make_flow(D, kind):
@@ -166,7 +170,8 @@ def _make_flow(D, kind):
     return f
 
 
-def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004, train="is", kind="affine"):
+def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x2403188400000004, train="is", kind="affine",
+                  graph=None, inst=None, ks=None, epochs=4, steps=64):
     """Learned proposal at one order: Re Sigma(k_F, i omega_0) from `batches` independent batches of N
     samples drawn from the adapted VEGAS grid alone and from the trained flow's defensive mixture
     (0.85 flow + 0.10 grid + 0.05 uniform), each with its wall time (GPU-synchronised).  sigma is the
@@ -184,11 +189,14 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     import synth
 
     dev = torch.device("cuda:0")
-    ks = np.linspace(0.0, 3.0, K).astype(np.float32)
+    ks = np.linspace(0.0, 3.0, K).astype(np.float32) if ks is None else np.asarray(ks, dtype=np.float32)
     jf = int(np.argmin(np.abs(ks - 1.0)))
-    inst = [(beta, mu, lam, gamma)]
+    inst = [(beta, mu, lam, gamma)] if inst is None else inst
+    # the figure of merit: Re Sigma(k_F) of the instance with this lambda and gamma
+    i_fom = [i for i, p in enumerate(inst) if p[2] == lam and p[3] == gamma][0]
+    groups = len(set(p[2] for p in inst))
     D = dmc.dim(order)
-    g = dmc.Graph(order)
+    g = dmc.Graph(order) if graph is None else graph
     s = dmc.Sampler(dmc.SAMPLER_VEGAS, order, n_bins=50, beta=beta, qmax=6.0)
     a_f, a_u = 0.85, 0.05
 
@@ -206,13 +214,13 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     def run(draw):
         means, sig, nonfin = [], [], 0
         for b in range(batches):
-            acc = dmc.Accumulator(1, K, 1)
+            acc = dmc.Accumulator(groups, len(ks), g.n_roots)
             draw(b)
             dmc.eval_batch(g, inst, ks, X, J, acc)
             dmc.accumulate(acc)
-            m, e, _, nf = acc.estimate(1)
-            means.append(m[0, 0, jf].real)
-            sig.append(e[0, 0, jf].real)
+            m, e, _, nf = acc.estimate(len(inst))
+            means.append(m[i_fom, 0, jf].real)
+            sig.append(e[i_fom, 0, jf].real)
             nonfin += nf
         means = np.array(means)
         mad = 1.4826 * float(np.median(np.abs(means - np.median(means))))
@@ -222,7 +230,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
 
     vg, t_v = timed(lambda: run(lambda b: s.sample(seed + 1, b * N, X, J)))
     f = _make_flow(D, kind)
-    epochs, steps, mb = 4, 64, 1 << 17
+    mb = 1 << 17
     if train == "mcmc":
         losses, t_train = timed(lambda: dmc.train_flow_mcmc(g, inst, ks, s, f, rounds=epochs, n_chains=mb, thermal=200,
                                                              collect=8, stride=10, steps=steps, lr=1e-3,
@@ -243,7 +251,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     if kind == "spline":
         # conditioner multiply-adds per sample (2 FLOP each): 32 dA + 32 x 32 + 23 dB x 32 per layer
         per = sum(2 * (32 * int(m.sum()) + 32 * 32 + 23 * (D - int(m.sum())) * 32) for m in f.masks)
-        flop, peak, bound, kname = N * per, PEAK_ALU_TFLOPS, "alu", f"dmc_nsf_sample_kernel (D = {D})"
+        flop, peak, bound, kname = N * per, PEAK_FP32_TFLOPS, "alu", f"dmc_nsf_sample_kernel (D = {D})"
     else:
         flop, peak, bound, kname = N * FLOW_FLOP_PER_SAMPLE, PEAK_BF16_TFLOPS, "mfma", f"dmc_flow_sample_kernel<{D}>"
     ev, ef = vg["sigma"], fl["sigma"]
@@ -400,13 +408,173 @@ def effective_mass_leg(N, rs, lam_R, beta, log2_samples, batches):
             "seconds": time.perf_counter() - t0}
 
 
+def cpu_baseline_c5(order, ks, lams, beta, mu, gamma, seconds=15.0):
+    """The oracle's C integrand (oracle/evaluate.c: FP64, diagram by diagram, OpenMP over samples on the host's
+    threads) on a bounded sample of the order-n workload: samples drawn like the tests' inputs, every lambda
+    group, the momenta ks; batches double until about `seconds` of work.  Rate in samples x diagrams x k x
+    lambda per second."""
+    import numpy as np
+
+    import synth
+    from oracle import cevaluate as ce
+    from golden_diagrams import oracle_diagrams
+
+    dgs = oracle_diagrams(order)
+    tab = ce.table(dgs, order)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    N, done, spent = 16, 0, 0.0
+    while spent < seconds:
+        x = synth.loop_points(order, N, seed=4000 + done).astype(np.float64)
+        t0 = time.perf_counter()
+        for lam in lams:
+            for k in ks:
+                ce.evaluate(x, order, float(k), beta, mu, lam, gamma, dgs, tab=tab)
+        spent += time.perf_counter() - t0
+        done += N
+        N = min(2 * N, 4096)
+    units = done * len(dgs) * len(ks) * len(lams)
+    return {"value": units / spent, "unit": "samples·diagrams/s", "cores": threads, "kind": "oracle",
+            "sample": f"order {order}: {done} samples x {len(ks)} k x {len(lams)} lambda in {spent:.1f} s "
+                      f"(C FP64 diagram-by-diagram integrand, OpenMP, {threads} threads)",
+            "cpu_model": _cpu_model()}
+
+
+def run_c5(args):
+    """The order-6 effective-mass workload: all 31130 order-6 diagrams, d Sigma / dk at k_F (the effective mass'
+    a coefficient), lambda in {0.5, 1, 2} with r_s 1..5 as gamma^n rescalings (15 instances, 3 evaluated), one
+    launch for all of them; importance sampling from the trained affine flow's defensive mixture; 2^26 samples
+    per iteration.  One step = one iteration: flow sampling, evaluation, FP64 fold, estimate."""
+    import numpy as np
+    import torch
+
+    import paper_2403_18840_amd as dmc
+    import synth
+
+    dev = torch.device("cuda:0")
+    order, beta, mu = 6, 25.0, 1.0
+    lams, rs_list = [0.5, 1.0, 2.0], [1.0, 2.0, 3.0, 4.0, 5.0]
+    inst = [(beta, mu, lam, dmc.coupling(rs)) for lam in lams for rs in rs_list]
+    # k_F first (it carries the derivative root), then 32 momenta in [0, 3 k_F]
+    ks = np.concatenate([[1.0], np.linspace(0.0, 3.0, 32)]).astype(np.float32)
+    K = len(ks)
+    N = 1 << args.log2_samples
+    D = dmc.dim(order)
+    t_setup = time.perf_counter()
+    g = dmc.Graph(order, deriv_mask=dmc.D_K, deriv_k=1)
+    inf = g.info()
+    s = dmc.Sampler(dmc.SAMPLER_VEGAS, order, n_bins=50, beta=beta, qmax=6.0)
+    log = lambda m: print(f"[c5] {m}", file=sys.stderr, flush=True)
+    seed0 = 0x2403188400000005
+    # setup (untimed): adapt the grid, then train the flow on it (the first evaluation compiles the kernel)
+    nxt = dmc.adapt_grid(g, inst, ks, s, 1 << 21, 4, seed=seed0)
+    log(f"grid adapted ({time.perf_counter() - t_setup:.1f} s incl. compilation)")
+    masks = synth.flow_masks(D, 8, 5)
+    flow = dmc.Flow(D, masks)
+    flow.set_params(synth.flow_params(masks, 6, last_scale=0.0))
+    a_f, a_u = 0.85, 0.05
+    losses = dmc.train_flow(g, inst, ks, s, flow, epochs=args.c5_train_epochs, steps=32, minibatch=1 << 17, lr=1e-3,
+                            alpha=a_f, uniform=a_u, seed=seed0 + 1)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log(f"flow trained, setup {t_setup:.1f} s, losses {[round(float(x), 3) for x in losses]}")
+    X = torch.empty((D, N), dtype=torch.float32, device=dev)
+    J = torch.empty(N, dtype=torch.float32, device=dev)
+    acc = dmc.Accumulator(len(lams), K, g.n_roots)
+    stream = torch.cuda.current_stream()
+    state = {}
+
+    def step(it, ev=None):
+        acc.reset()
+        flow.sample(s, seed0 + 2, it * N, X, J, alpha=a_f, uniform=a_u)
+        if ev is not None:
+            ev[0].record(stream)
+        dmc.eval_batch(g, inst, ks, X, J, acc)
+        if ev is not None:
+            ev[1].record(stream)
+        dmc.accumulate(acc)
+        state["last"] = acc.estimate(len(inst))
+
+    for w in range(args.warmup):
+        step(w)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, ev=evs[i])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    units = N * inf.n_diagrams * K * len(lams)
+    # algorithmic FLOP per launch: per lambda group, the k-independent graph once per sample, the value's
+    # k-dependent part at every momentum and the derivative-only part at k_F (FMA = 2)
+    per_group = flops(list(inf.ops_sample)) + K * (flops(list(inf.ops_k)) - flops(list(inf.ops_k_deriv))) \
+        + 1 * flops(list(inf.ops_k_deriv))
+    fl_launch = N * len(lams) * per_group
+    achieved = fl_launch / (kern_ms * 1e-3) / 1e12
+    m, e, ns, nf = state["last"]
+    i1 = inst.index((beta, mu, 1.0, dmc.coupling(1.0)))
+    w0 = math.pi / beta
+    out = {
+        "metric": "samples·diagrams/s",
+        "value": units / dt,
+        "unit": "samples·diagrams/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"UEG self-energy order 6 (all {inf.n_diagrams} 1PI diagrams, D = 23) with d Sigma/dk at k_F, "
+                        f"Yukawa lambda 0.5/1/2 x r_s 1..5 (15 instances, 3 evaluated) in one launch, beta E_F = 25, "
+                        f"{K} |k| (k_F and 32 in [0, 3 k_F]), affine-flow proposal (8 layers, 0.85 flow + 0.10 VEGAS "
+                        f"grid + 0.05 uniform), 2^{args.log2_samples} samples/iteration",
+            "order": order, "n_k": K, "samples_per_iteration": N, "lambda_evaluated": lams, "rs": rs_list,
+            "derivative": "d/dk at k_F", "kernel_parts": inf.n_parts, "setup_seconds": t_setup,
+        },
+        "roofline": {
+            "bound": "alu", "kernel": f"dmc_eval_o6_g3_r2 ({inf.n_parts} parts)", "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic_for(g, len(lams), N, "eval_o6_c5_hbm_traffic.json"),
+            "kernel_ms": kern_ms, "flop_per_launch": fl_launch,
+            "flop_per_sample_per_group": per_group,
+            "frac_of_unpacked_issue_rate": achieved / PEAK_ALU_TFLOPS,
+        },
+        "estimate": {"lambda": 1.0, "rs": 1.0, "k": 1.0, "order": order,
+                     "re": float(m[i1, 0, 0].real), "re_err": float(e[i1, 0, 0].real),
+                     "im": float(m[i1, 0, 0].imag), "im_err": float(e[i1, 0, 0].imag),
+                     "dre_dk": float(m[i1, 1, 0].real), "dre_dk_err": float(e[i1, 1, 0].real),
+                     # the order-6 coefficients of the effective mass: a = (m/k_F) dRe/dk (m/k_F = 1/2), b = Im/w0
+                     "a": 0.5 * float(m[i1, 1, 0].real), "b": float(m[i1, 0, 0].imag) / w0,
+                     "nonfinite": int(nf)},
+    }
+    if not args.no_peaks:
+        out["peaks"] = measured_peaks()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_c5(order, [float(ks[0]), float(ks[1])], lams, beta, mu, dmc.coupling(1.0),
+                                              seconds=args.cpu_seconds)
+    if args.flow_order:
+        log("flow vs VEGAS at order 6")
+        out["flow_vs_vegas"] = flow_vs_vegas(order, K, 1 << args.flow_log2_samples, args.flow_batches, beta, mu,
+                                             1.0, dmc.coupling(1.0), train=args.flow_train, kind=args.flow_kind,
+                                             graph=g, inst=inst, ks=ks, epochs=args.c5_train_epochs, steps=32)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["c5", "c2"], default="c5",
+                    help="c5: order 6 with d/dk at k_F, 3 lambda x 5 r_s, flow proposal, 2^26 samples (the default "
+                         "line); c2: orders 1-3, r_s 1,2, VEGAS, 2^24 samples per order")
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (c5: 3, c2: 10)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed iterations first (c5: 1, c2: 5)")
     ap.add_argument("--orders", default="1,2,3")
-    ap.add_argument("--log2-samples", type=int, default=24)
+    ap.add_argument("--log2-samples", type=int, default=None, help="samples per iteration (c5: 26, c2: 24)")
+    ap.add_argument("--c5-train-epochs", type=int, default=3)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -414,16 +582,17 @@ def main():
     ap.add_argument("--cpu-workers", type=int,
                     default=min(16, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))),
                     help="processes of the all-cores oracle timing (the host's CPU share; 1 or less skips it)")
-    ap.add_argument("--flow-order", type=int, default=4,
-                    help="order of the learned-proposal comparison (0 skips it)")
-    ap.add_argument("--flow-batches", type=int, default=64)
+    ap.add_argument("--flow-order", type=int, default=None,
+                    help="order of the learned-proposal comparison (0 skips it; c5: 6, on its own graph; c2: 4)")
+    ap.add_argument("--flow-batches", type=int, default=None)
     ap.add_argument("--flow-log2-samples", type=int, default=22)
     ap.add_argument("--flow-kind", choices=["affine", "spline"], default="affine",
                     help="learned proposal of the flow and NF-MCMC legs")
     ap.add_argument("--flow-train", choices=["is", "mcmc"], default="is",
                     help="training data of the flow: importance-weighted draws or Markov-chain samples of |f|")
-    ap.add_argument("--mcmc-orders", default="2",
-                    help="orders of the Markov-chain vs VEGAS comparison, comma-separated (empty skips it)")
+    ap.add_argument("--mcmc-orders", default=None,
+                    help="orders of the Markov-chain vs VEGAS comparison, comma-separated (empty skips it; "
+                         "c5: empty, c2: 2)")
     ap.add_argument("--mcmc-log2-chains", type=int, default=16)
     ap.add_argument("--mcmc-steps", type=int, default=1024)
     ap.add_argument("--mcmc-thermal", type=int, default=2000)
@@ -443,12 +612,41 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    c5 = args.workload == "c5"
+    for name, v5, v2 in [("steps", 3, 10), ("warmup", 1, 5), ("log2_samples", 26, 24), ("flow_order", 6, 4),
+                         ("flow_batches", 32, 64), ("mcmc_orders", "", "2")]:
+        if getattr(args, name) is None:
+            setattr(args, name, v5 if c5 else v2)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    if c5:
+        import torch
+        torch.cuda.set_device(torch.device("cuda:0"))
+        if args.copy_mib:
+            src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        out = run_c5(args)
+        if args.mcmc_orders:
+            import paper_2403_18840_amd as dmc
+            out["mcmc_vs_vegas"] = [mcmc_vs_vegas(int(n), 25.0, 1.0, 1.0, dmc.coupling(1.0),
+                                                  n_chains=1 << args.mcmc_log2_chains, steps=args.mcmc_steps,
+                                                  thermal=args.mcmc_thermal, flow=not args.mcmc_no_flow,
+                                                  flow_kind=args.flow_kind, walk_every=args.mcmc_walk_every,
+                                                  walk_sigma=args.mcmc_walk_sigma)
+                                    for n in args.mcmc_orders.split(",")]
+        if args.mass_order:
+            out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, 25.0,
+                                                       args.mass_log2_samples, args.mass_batches)
+        print(json.dumps(out), flush=True)
+        return
 
     import numpy as np
     import torch
 
     import paper_2403_18840_amd as dmc
-    from oracle import physics as ph  # only for the coupling constant alpha r_s
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -464,7 +662,7 @@ def main():
     K = args.k
     beta, mu, lam = 25.0, 1.0, 1.0
     rs_list = [1.0, 2.0]
-    inst = [(beta, mu, lam, ph.coupling(rs)) for rs in rs_list]
+    inst = [(beta, mu, lam, dmc.coupling(rs)) for rs in rs_list]
     ks = np.linspace(0.0, 3.0, K).astype(np.float32)
     Dmax = dmc.dim(max(orders))
     X = torch.empty((Dmax, N), dtype=torch.float32, device=dev)
@@ -539,7 +737,8 @@ def main():
         },
         "roofline": {
             "bound": "alu", "kernel": f"dmc_eval (order {dom['n']})", "achieved": achieved,
-            "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac_of_unpacked_issue_rate": achieved / PEAK_ALU_TFLOPS,
             "traffic": traffic_for(dom["g"]) if dom["n"] == 3 and N == (1 << 24) else None,
             "kernel_ms": kern_ms, "flop_per_launch": fl_launch,
         },

@@ -322,6 +322,49 @@ dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* 
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
 void dmc_chains_destroy(dmc_chains* c);
 
+/* ---- estimates across iterations and from Markov chains (host, FP64) ---- */
+/* Equal-weight combination of n_iter independent iteration estimates of n_values quantities, the way frozen-grid
+ * VEGAS iterations are combined (Sec. IV cites Lepage's VEGAS; equal weights avoid the bias of inverse-variance
+ * weights estimated from the same samples): means, errs host double[n_iter][n_values]; mean[v] = the average,
+ * err[v] = sqrt(sum_i errs[i][v]^2) / n_iter, chi2_dof[v] = sum_i (means[i][v] - mean[v])^2 / errs[i][v]^2 / (n_iter - 1)
+ * (NaN with one iteration or a zero error); chi2_dof near 1 says the iterations agree within their errors.
+ * DMC_E_INVALID for null pointers or non-positive sizes. */
+dmc_status dmc_combine_iterations(int32_t n_iter, int32_t n_values, const double* means, const double* errs,
+                                  double* mean, double* err, double* chi2_dof);
+/* The ratio estimator of eq. nf_mcmc_estimator_qft_final_revised from the batch sums of dmc_chains_read (host
+ * double[n_batches][S + 1][2], S = n_groups n_roots n_k 2): for every slot, I = (sum_b sum f/pi) / (sum_b sum q/pi),
+ * error = the scatter of the batch ratios over sqrt(n_batches); per instance (host dmc_instance[n_inst], grouped by
+ * lambda in order of first appearance as in dmc_eval_batch) scaled by (gamma / gamma_group)^order.  mean, err: host
+ * double[n_inst][n_roots][n_k][2].  Sums of part of a run (e.g. the difference of two reads) give that part's
+ * estimate.  DMC_E_INVALID for null pointers, n_batches < 2 or instances whose lambda count is not n_groups;
+ * DMC_E_NUMERIC when no chain weight was measured. */
+dmc_status dmc_chains_ratio(int32_t n_batches, int32_t n_groups, int32_t n_roots, int32_t n_k, const double* sums,
+                            int32_t order, const dmc_instance* inst, int32_t n_inst, double* mean, double* err);
+/* The effective-mass coefficients of one order from its graph's root estimates at k_F (Sec. VI.A,
+ * eq. deltam_partitions, eq. deltas_partitions): root_orders host int32[3 n_roots] as dmc_graph_root_orders gives
+ * them, est host double[n_roots][2] the (Re, Im) estimates at k_F, w_0 = pi / beta.  For every root (m, l, e = 0):
+ * nml = (order, m, l), sigma = Re, b = Im / w_0, and a = (m_e / k_F) Re of the root (m, l, 1) (m_e / k_F = 1/2 with
+ * eps_k = k^2; 0 without it).  Outputs host [n_roots] (nml [3 n_roots]); *n_out receives the entries written: the
+ * input of dmc_effective_mass.  DMC_E_INVALID for null pointers, order or n_roots < 1, beta <= 0. */
+dmc_status dmc_mass_table(int32_t order, const int32_t* root_orders, int32_t n_roots, const double* est, double beta,
+                          int32_t* nml, double* sigma, double* a, double* b, int32_t* n_out);
+
+/* ---- checkpoint and resume of an integration ----
+ * The state that determines what an integration does next, so that a resumed run computes bit for bit what the
+ * uninterrupted one would: the sampler's VEGAS grid and the histogram gathered since its last refinement; the
+ * flow's FP32 master weights, Adam moments and step count (its BF16 copies are rebuilt from the masters); the
+ * accumulator's FP64 sums, sample and non-finite counts and last instances; and the caller's Philox position
+ * (seed and the next sample index: the stream is counter-based, so these two numbers are all of it).  Any handle
+ * may be NULL (its section is left out on save, not read on load).  Host buffer; native byte order; synchronises
+ * `stream`.  Save: with buf NULL (or cap too small: DMC_E_INVALID) *len receives the size needed.  Load: the
+ * handles must have the shapes saved (kind, order, bins, beta, q_max; flow kind, dimension, layers, masks;
+ * accumulator shape), else DMC_E_INVALID and no handle changes; DMC_E_STATE while an evaluation waits for
+ * dmc_accumulate. */
+dmc_status dmc_checkpoint_save(const dmc_sampler* s, const dmc_flow* f, const dmc_accum* acc, uint64_t seed,
+                               uint64_t next_index, void* buf, size_t cap, size_t* len, void* stream);
+dmc_status dmc_checkpoint_load(dmc_sampler* s, dmc_flow* f, dmc_accum* acc, uint64_t* seed, uint64_t* next_index,
+                               const void* buf, size_t len, void* stream);
+
 /* ---- throughput probes (the roofline denominators on the device at hand) ----
  * kind 0: FP32 fused multiply-add (unpacked), 1: the hardware 2^x, 2: the hardware reciprocal; each runs
  * 8 x (compute units) blocks of 256 lanes, every lane 8 independent chains of 16 x `work` operations

@@ -26,13 +26,15 @@ ABI_SYMBOLS = [
     "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_vegas_refine",
-    "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_accumulate", "dmc_estimate",
+    "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch",
+    "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_create_spline", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_walk", "dmc_flow_train_step", "dmc_flow_destroy",
     "dmc_chains_create", "dmc_chains_step", "dmc_chains_step_walk", "dmc_chains_read", "dmc_chains_reset",
     "dmc_chains_destroy",
     "dmc_chains_training_data",
-    "dmc_effective_mass", "dmc_probe",
+    "dmc_effective_mass", "dmc_probe", "dmc_combine_iterations", "dmc_chains_ratio", "dmc_mass_table",
+    "dmc_checkpoint_save", "dmc_checkpoint_load",
 ]
 
 
@@ -104,6 +106,11 @@ def lib():
         "dmc_sampler_read_histogram": (I32, [P, P, P]),
         "dmc_sampler_destroy": (None, [P]),
         "dmc_eval_batch": (I32, [P, P, I32, P, I32, P, I64, P, I64, P, P, P, P]),
+        "dmc_combine_iterations": (I32, [I32, I32, P, P, P, P, P]),
+        "dmc_chains_ratio": (I32, [I32, I32, I32, I32, P, I32, P, I32, P, P]),
+        "dmc_mass_table": (I32, [I32, P, I32, P, F64, P, P, P, P, P]),
+        "dmc_checkpoint_save": (I32, [P, P, P, U64, U64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]),
+        "dmc_checkpoint_load": (I32, [P, P, P, ctypes.POINTER(U64), ctypes.POINTER(U64), P, ctypes.c_size_t, P]),
         "dmc_accumulate": (I32, [P, P, P, P]),
         "dmc_estimate": (I32, [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
         "dmc_accum_read": (I32, [P, P, ctypes.POINTER(I64), P]),
@@ -716,22 +723,8 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
             lam_of.append(p[2])
 
     def ratio(sm):
-        # per-batch and overall ratio estimates, per instance (r_s copies scale by (gamma / gamma_group)^n
-        # like eval)
-        num = sm[:, :S, 0].reshape(n_batches, G, R, K, 2)
-        est = (num[..., 0] + 1j * num[..., 1]) / sm[:, S, 0].reshape(n_batches, 1, 1, 1)
-        tot = num.sum(axis=0)
-        mean_g = (tot[..., 0] + 1j * tot[..., 1]) / sm[:, S, 0].sum()
-        err_g = (est.real.std(axis=0, ddof=1) + 1j * est.imag.std(axis=0, ddof=1)) / math.sqrt(n_batches)
-        out_m = np.empty((len(inst), R, K), dtype=complex)
-        out_e = np.empty((len(inst), R, K), dtype=complex)
-        for i, p in enumerate(inst):
-            g = lam_of.index(p[2])
-            gam0 = next(q[3] for q in inst if q[2] == p[2])
-            fac = (p[3] / gam0) ** graph.order
-            out_m[i] = mean_g[g] * fac
-            out_e[i] = err_g[g] * fac
-        return out_m, out_e
+        # the ratio estimator with its batch errors and the r_s rescaling, in the library (dmc_chains_ratio)
+        return chains_ratio(sm, G, R, K, graph.order, inst)
 
     m, e = ratio(sums)
     m1, e1 = ratio(half)
@@ -743,6 +736,72 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
     mi, ei, _, _ = acc.estimate(len(inst))
     return McmcResult(m, e, accepted / (n_chains * steps), mi, ei, ((m1, e1), (m2, e2), z))
 
+
+
+def chains_ratio(sums, n_groups: int, n_roots: int, n_k: int, order: int, inst):
+    """dmc_chains_ratio: (mean, err) complex [n_inst][n_roots][n_k] of the Markov-chain ratio estimator from batch
+    sums [n_batches][S + 1][2] (dmc_chains_read), with each instance's (gamma / gamma_group)^order."""
+    import numpy as np
+    sm = np.ascontiguousarray(sums, dtype=np.float64)
+    arr = instances(inst)
+    m = np.zeros((len(inst), n_roots, n_k, 2))
+    e = np.zeros_like(m)
+    _check(lib().dmc_chains_ratio(sm.shape[0], n_groups, n_roots, n_k, sm.ctypes.data_as(P), order, arr, len(arr),
+                                  m.ctypes.data_as(P), e.ctypes.data_as(P)))
+    return m[..., 0] + 1j * m[..., 1], e[..., 0] + 1j * e[..., 1]
+
+
+def combine_iterations(means, errs):
+    """dmc_combine_iterations: equal-weight combination of iteration estimates [n_iter][...] (real arrays): returns
+    (mean, err, chi2_dof) of the trailing shape."""
+    import numpy as np
+    mm = np.ascontiguousarray(means, dtype=np.float64)
+    ee = np.ascontiguousarray(errs, dtype=np.float64)
+    if mm.shape != ee.shape or mm.ndim < 1:
+        raise ValueError("means and errs must have one shape [n_iter, ...]")
+    nv = int(np.prod(mm.shape[1:])) if mm.ndim > 1 else 1
+    out = [np.empty(nv) for _ in range(3)]
+    _check(lib().dmc_combine_iterations(mm.shape[0], nv, mm.ctypes.data_as(P), ee.ctypes.data_as(P),
+                                        *[o.ctypes.data_as(P) for o in out]))
+    return tuple(o.reshape(mm.shape[1:]) for o in out)
+
+
+def mass_table(order: int, root_orders, est, beta: float):
+    """dmc_mass_table: {(n, m, l): value} tables (sigma, a, b) of one order from its roots' estimates at k_F
+    (complex [n_roots])."""
+    import numpy as np
+    ro = np.ascontiguousarray(np.asarray(root_orders, dtype=np.int32).reshape(-1))
+    R = ro.size // 3
+    ev = np.ascontiguousarray(np.stack([np.real(est), np.imag(est)], axis=-1), dtype=np.float64)
+    nml = np.zeros(3 * R, dtype=np.int32)
+    sg, aa, bb = np.zeros(R), np.zeros(R), np.zeros(R)
+    n_out = I32()
+    _check(lib().dmc_mass_table(order, ro.ctypes.data_as(P), R, ev.ctypes.data_as(P), beta, nml.ctypes.data_as(P),
+                                sg.ctypes.data_as(P), aa.ctypes.data_as(P), bb.ctypes.data_as(P), ctypes.byref(n_out)))
+    keys = [tuple(int(v) for v in nml[3 * i: 3 * i + 3]) for i in range(n_out.value)]
+    return ({k: float(sg[i]) for i, k in enumerate(keys)}, {k: float(aa[i]) for i, k in enumerate(keys)},
+            {k: float(bb[i]) for i, k in enumerate(keys)})
+
+
+def checkpoint_save(sampler=None, flow=None, acc=None, seed: int = 0, next_index: int = 0, stream=None) -> bytes:
+    """dmc_checkpoint_save: the integration state (any of sampler, flow, accumulator, plus the Philox position) as
+    bytes."""
+    n = ctypes.c_size_t()
+    hs = [h.h if h is not None else None for h in (sampler, flow, acc)]
+    st = _stream(stream) if any(hs) else None   # the position alone touches no device
+    _check(lib().dmc_checkpoint_save(*hs, seed, next_index, None, 0, ctypes.byref(n), st))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().dmc_checkpoint_save(*hs, seed, next_index, buf, n.value, ctypes.byref(n), st))
+    return buf.raw[: n.value]
+
+
+def checkpoint_load(data: bytes, sampler=None, flow=None, acc=None, stream=None):
+    """dmc_checkpoint_load into the given handles; returns (seed, next_index)."""
+    sd, nx = U64(), U64()
+    hs = [h.h if h is not None else None for h in (sampler, flow, acc)]
+    st = _stream(stream) if any(hs) else None
+    _check(lib().dmc_checkpoint_load(*hs, ctypes.byref(sd), ctypes.byref(nx), data, len(data), st))
+    return sd.value, nx.value
 
 
 def vegas_refine(edges, hist, alpha: float = 0.5):
@@ -793,7 +852,6 @@ def mass_coefficients(N: int, rs: float, lambda_R: float, beta: float = 25.0, mu
     dev = torch.device("cuda", torch.cuda.current_device())
     inst = [(beta, mu, lambda_R, coupling(rs))]
     ks = np.array([1.0], dtype=np.float32)
-    w0 = math.pi / beta
     tables = [({}, {}, {}) for _ in range(batches)]
     for n in range(1, N + 1):
         T = N - n
@@ -810,14 +868,9 @@ def mass_coefficients(N: int, rs: float, lambda_R: float, beta: float = 25.0, mu
             eval_batch(g, inst, ks, X, J, acc)
             accumulate(acc)
             m_, _, _, _ = acc.estimate(1)
-            sig, a, b = tables[bi]
-            for r, (mm, ll, e) in enumerate(orders):
-                v = m_[0, r, 0]
-                if e == 0:
-                    sig[(n, mm, ll)] = float(v.real)
-                    b[(n, mm, ll)] = float(v.imag) / w0
-                else:
-                    a[(n, mm, ll)] = 0.5 * float(v.real)  # m_e / k_F = 1/2 (eps_k = k^2)
+            ts, ta, tb = mass_table(n, orders, m_[0, :, 0], beta)
+            for t, part in zip(tables[bi], (ts, ta, tb)):
+                t.update(part)
     return tables
 
 

@@ -314,6 +314,8 @@ dmc_status dmc_accum_create(int32_t n_groups, int32_t n_k, int32_t n_roots, dmc_
         n_roots > DMC_MAX_ROOTS)
         return fail(DMC_E_INVALID, "accumulator shape out of range");
     auto a = std::make_unique<dmc_accum>();
+    a->inst_group.reserve(DMC_MAX_INSTANCES);
+    a->inst_factor.reserve(DMC_MAX_INSTANCES);
     a->n_groups = n_groups;
     a->n_k = n_k;
     a->n_roots = n_roots;
@@ -346,9 +348,13 @@ void dmc_accum_destroy(dmc_accum* a) {
 }
 
 // ------------------------------------------------------------------------------ evaluation
-dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
-                          const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
-                          float* imp_out, void* stream) {
+// The evaluation launch shared by dmc_eval_batch and the allocation-free entry point.  With `fixed`
+// (a device buffer of fixed_bytes for the block partials and non-finite counts) nothing is
+// allocated: the kernel must already be loaded, the block count is capped by the buffer, and the
+// partials are folded into the accumulator right away.
+static dmc_status eval_launch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
+                              const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
+                              float* imp_out, void* stream, void* fixed, size_t fixed_bytes) {
     if (!g || !inst || !k_ext || !x || !jac || !acc) return fail(DMC_E_INVALID, "null argument");
     if (n_inst < 1 || n_inst > DMC_MAX_INSTANCES) return fail(DMC_E_INVALID, "n_inst out of range");
     if (n_k < 1 || n_k > DMC_MAX_K) return fail(DMC_E_INVALID, "n_k out of range");
@@ -356,30 +362,42 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     if (acc->pending_blocks) return fail(DMC_E_STATE, "dmc_accumulate must follow each dmc_eval_batch");
     const double beta = inst[0].beta, mu = inst[0].mu;
     if (!(beta > 0) || !(beta * std::fabs(mu) < 80.0)) return fail(DMC_E_INVALID, "need beta > 0, beta |mu| < 80");
-    std::vector<double> lam, gam;
-    std::vector<int> grp(n_inst);
-    std::vector<double> fac(n_inst);
+    // lambda groups (fixed-size arrays: no allocation)
+    double lam[DMC_MAX_GROUPS], gam[DMC_MAX_GROUPS];
+    int grp[DMC_MAX_INSTANCES];
+    double fac[DMC_MAX_INSTANCES];
+    int ng = 0;
     for (int i = 0; i < n_inst; ++i) {
         if (inst[i].beta != beta || inst[i].mu != mu) return fail(DMC_E_INVALID, "instances must share beta and mu");
         if (!(inst[i].lambda > 0) || !(inst[i].gamma > 0)) return fail(DMC_E_INVALID, "need lambda > 0, gamma > 0");
         int gi = -1;
-        for (size_t j = 0; j < lam.size(); ++j)
-            if (lam[j] == inst[i].lambda) gi = (int)j;
+        for (int j = 0; j < ng; ++j)
+            if (lam[j] == inst[i].lambda) gi = j;
         if (gi < 0) {
-            if ((int)lam.size() == DMC_MAX_GROUPS) return fail(DMC_E_INVALID, "too many distinct lambda values");
-            gi = (int)lam.size();
-            lam.push_back(inst[i].lambda);
-            gam.push_back(inst[i].gamma);
+            if (ng == DMC_MAX_GROUPS) return fail(DMC_E_INVALID, "too many distinct lambda values");
+            gi = ng++;
+            lam[gi] = inst[i].lambda;
+            gam[gi] = inst[i].gamma;
         }
         grp[i] = gi;
         fac[i] = std::pow(inst[i].gamma / gam[gi], g->c.order);
     }
-    const int ng = (int)lam.size();
     if (ng != acc->n_groups || n_k != acc->n_k || g->c.n_roots != acc->n_roots)
         return fail(DMC_E_INVALID, "accumulator shape does not match graph, lambda groups and n_k");
     JitKernel* jk = nullptr;
-    dmc_status st = get_kernel(g, ng, &jk);
-    if (st != DMC_OK) return st;
+    if (fixed) {
+        // the allocation-free path never compiles or loads a module
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        auto it = g->jit.find(std::make_pair(dev, ng));
+        if (it == g->jit.end())
+            return fail(DMC_E_STATE, "the graph's kernel for this many lambda groups is not loaded on this device yet "
+                                     "(one dmc_eval_batch call loads it)");
+        jk = &it->second;
+    } else {
+        dmc_status st = get_kernel(g, ng, &jk);
+        if (st != DMC_OK) return st;
+    }
 
     const int NR = g->c.n_roots;
     const bool split = g->c.stats.parts > 1;
@@ -441,9 +459,21 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
         jk->max_blocks_per_cu = jk->kc_blocks[n_k];
     }
     const int64_t ntiles = (n + 255) / 256;
-    const int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 8);
+    int64_t cap = (int64_t)cu_count() * std::min(jk->max_blocks_per_cu, 8);
+    double* partial = acc->partial;
+    unsigned int* nonfin_part = acc->nonfin_part;
+    if (fixed) {
+        // per block: 2 s_total FP64 partial sums and one non-finite count
+        const size_t per = sizeof(double) * 2 * (size_t)acc->s_total + sizeof(unsigned int);
+        const int64_t fit = (int64_t)(fixed_bytes / per);
+        if (fit < 1) return fail(DMC_E_INVALID, "the accumulator's slots exceed the static scratch of one block");
+        cap = std::min(cap, fit);
+    }
     const int nb = (int)std::min<int64_t>(ntiles, cap);
-    if (nb > acc->cap_blocks) {
+    if (fixed) {
+        partial = static_cast<double*>(fixed);
+        nonfin_part = reinterpret_cast<unsigned int*>(partial + (size_t)2 * acc->s_total * nb);
+    } else if (nb > acc->cap_blocks) {
         (void)hipFree(acc->partial);
         (void)hipFree(acc->nonfin_part);
         acc->partial = nullptr;
@@ -452,6 +482,8 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
         HIP_ALLOC(hipMalloc(&acc->partial, sizeof(double) * 2 * acc->s_total * (size_t)nb));
         HIP_ALLOC(hipMalloc(&acc->nonfin_part, sizeof(unsigned int) * (size_t)nb));
         acc->cap_blocks = nb;
+        partial = acc->partial;
+        nonfin_part = acc->nonfin_part;
     }
     EvalArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -459,8 +491,8 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     a.ld = ld;
     a.jac = jac;
     a.n = n;
-    a.partial = acc->partial;
-    a.nonfinite = acc->nonfin_part;
+    a.partial = partial;
+    a.nonfinite = nonfin_part;
     a.f_out = f_out;
     a.imp_out = imp_out;
     a.n_k = n_k;
@@ -480,11 +512,23 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     for (int j = 0; j < n_k; ++j) a.k[j] = k_ext[j];
     void* params[] = {&a};
     HIP_TRY(hipModuleLaunchKernel(jk->fn, nb, 1, 1, 256, 1, 1, (unsigned)smem, S(stream), params, nullptr));
+    // the accumulator's instance vectors hold DMC_MAX_INSTANCES entries of capacity: assign does not allocate
+    acc->inst_group.assign(grp, grp + n_inst);
+    acc->inst_factor.assign(fac, fac + n_inst);
+    if (fixed) {
+        HIP_TRY(dmc::launch_fold(partial, nb, 2 * acc->s_total, acc->totals, nonfin_part, acc->nonfin_tot, S(stream)));
+        acc->n_samples += n;
+        return DMC_OK;
+    }
     acc->pending_blocks = nb;
     acc->pending_n = n;
-    acc->inst_group = grp;
-    acc->inst_factor = fac;
     return DMC_OK;
+}
+
+dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
+                          const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
+                          float* imp_out, void* stream) {
+    return eval_launch(g, inst, n_inst, k_ext, n_k, x, ld, jac, n, acc, f_out, imp_out, stream, nullptr, 0);
 }
 
 dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* s, const float* imp, void* stream) {
@@ -1656,3 +1700,190 @@ dmc_status dmc_probe(int32_t kind, int64_t work, double* ms, double* ops, void* 
     *ms = t;
     return done();
 }
+
+// ------------------------------------------------------------------------------ checkpoint
+// Layout (native byte order): "DMCCKPT1", u64 seed, u64 next_index, u32 sections (1 sampler, 2 flow, 4
+// accumulator), then each present section in that order.
+//   sampler: i32 kind, order, dim, n_bins; f64 beta, qmax; f64 edges[dim (n_bins + 1)]; f64 hist[dim n_bins]
+//   flow:    i32 kind, dim, n_layers, pad; i64 n_params, step; i8 masks[n_layers dim]; f32 master, m, v [n_params]
+//   accum:   i32 n_groups, n_k, n_roots, n_inst; i64 n_samples; u64 nonfinite; i32 group[n_inst];
+//            f64 factor[n_inst]; f64 totals[2 s_total]
+namespace {
+struct Writer {
+    unsigned char* p;
+    size_t cap, len = 0;
+    template <class T>
+    void put(const T* v, size_t n) {
+        const size_t b = sizeof(T) * n;
+        if (p && len + b <= cap) std::memcpy(p + len, v, b);
+        len += b;
+    }
+    template <class T>
+    void put1(T v) { put(&v, 1); }
+};
+struct Reader {
+    const unsigned char* p;
+    size_t len, pos = 0;
+    template <class T>
+    bool get(T* v, size_t n) {
+        const size_t b = sizeof(T) * n;
+        if (pos + b > len) return false;
+        std::memcpy(v, p + pos, b);
+        pos += b;
+        return true;
+    }
+    template <class T>
+    bool get1(T& v) { return get(&v, 1); }
+};
+size_t flow_param_len(const dmc_flow* f) {
+    return f->kind == 1 ? (size_t)f->n_params : (size_t)f->n_layers * dmc::LAYER_SIZE;
+}
+}  // namespace
+
+extern "C" {
+
+dmc_status dmc_checkpoint_save(const dmc_sampler* s, const dmc_flow* f, const dmc_accum* acc, uint64_t seed,
+                               uint64_t next_index, void* buf, size_t cap, size_t* len, void* stream) {
+    if (!len) return fail(DMC_E_INVALID, "null length");
+    if (acc && acc->pending_blocks) return fail(DMC_E_STATE, "an evaluation is waiting for dmc_accumulate");
+    if (s || f || acc) HIP_TRY(hipStreamSynchronize(S(stream)));
+    Writer w{static_cast<unsigned char*>(buf), buf ? cap : 0};
+    w.put("DMCCKPT1", 8);
+    w.put1(seed);
+    w.put1(next_index);
+    w.put1((uint32_t)((s ? 1 : 0) | (f ? 2 : 0) | (acc ? 4 : 0)));
+    if (s) {
+        const int32_t hdr[4] = {s->kind, s->order, s->dim, s->n_bins};
+        w.put(hdr, 4);
+        w.put1(s->beta);
+        w.put1(s->qmax);
+        w.put(s->edges.data(), s->edges.size());
+        std::vector<double> h((size_t)s->dim * s->n_bins);
+        HIP_TRY(hipMemcpy(h.data(), s->d_hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+        w.put(h.data(), h.size());
+    }
+    if (f) {
+        const int32_t hdr[4] = {f->kind, f->dim, f->n_layers, 0};
+        w.put(hdr, 4);
+        const size_t P = flow_param_len(f);
+        w.put1((int64_t)P);
+        w.put1(f->step);
+        w.put(f->masks.data(), f->masks.size());
+        std::vector<float> t(P);
+        for (float* src : {f->master, f->m, f->v}) {
+            HIP_TRY(hipMemcpy(t.data(), src, sizeof(float) * P, hipMemcpyDeviceToHost));
+            w.put(t.data(), P);
+        }
+    }
+    if (acc) {
+        const int32_t hdr[4] = {acc->n_groups, acc->n_k, acc->n_roots, (int32_t)acc->inst_group.size()};
+        w.put(hdr, 4);
+        w.put1(acc->n_samples);
+        unsigned long long nf = 0;
+        HIP_TRY(hipMemcpy(&nf, acc->nonfin_tot, sizeof(nf), hipMemcpyDeviceToHost));
+        w.put1((uint64_t)nf);
+        w.put(acc->inst_group.data(), acc->inst_group.size());
+        w.put(acc->inst_factor.data(), acc->inst_factor.size());
+        std::vector<double> t(2 * (size_t)acc->s_total);
+        HIP_TRY(hipMemcpy(t.data(), acc->totals, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
+        w.put(t.data(), t.size());
+    }
+    *len = w.len;
+    if (buf && w.len > cap) return fail(DMC_E_INVALID, "buffer too small for the checkpoint");
+    return DMC_OK;
+}
+
+dmc_status dmc_checkpoint_load(dmc_sampler* s, dmc_flow* f, dmc_accum* acc, uint64_t* seed, uint64_t* next_index,
+                               const void* buf, size_t len, void* stream) {
+    if (!buf) return fail(DMC_E_INVALID, "null buffer");
+    Reader r{static_cast<const unsigned char*>(buf), len};
+    char magic[8];
+    uint64_t sd = 0, nx = 0;
+    uint32_t sec = 0;
+    if (!r.get(magic, 8) || std::memcmp(magic, "DMCCKPT1", 8) != 0 || !r.get1(sd) || !r.get1(nx) || !r.get1(sec))
+        return fail(DMC_E_INVALID, "not a checkpoint");
+    if ((s && !(sec & 1)) || (f && !(sec & 2)) || (acc && !(sec & 4)))
+        return fail(DMC_E_INVALID, "the checkpoint lacks a section for a handle passed");
+    if (acc && acc->pending_blocks) return fail(DMC_E_STATE, "an evaluation is waiting for dmc_accumulate");
+    // parse everything first, so that a malformed or mismatching checkpoint changes no handle
+    std::vector<double> edges, hist, totals, factor;
+    std::vector<float> fm, fmm, fv;
+    std::vector<int32_t> group;
+    std::vector<int8_t> masks;
+    int64_t fstep = 0, n_samples = 0;
+    uint64_t nonfin = 0;
+    if (sec & 1) {
+        int32_t h[4];
+        double beta, qmax;
+        if (!r.get(h, 4) || !r.get1(beta) || !r.get1(qmax)) return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (h[2] < 1 || h[3] < 1 || h[2] > 64 || h[3] > 4096) return fail(DMC_E_INVALID, "corrupt sampler section");
+        edges.resize((size_t)h[2] * (h[3] + 1));
+        hist.resize((size_t)h[2] * h[3]);
+        if (!r.get(edges.data(), edges.size()) || !r.get(hist.data(), hist.size()))
+            return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (s && (h[0] != s->kind || h[1] != s->order || h[2] != s->dim || h[3] != s->n_bins || beta != s->beta ||
+                  qmax != s->qmax))
+            return fail(DMC_E_INVALID, "the sampler does not match the checkpoint");
+    }
+    if (sec & 2) {
+        int32_t h[4];
+        int64_t P = 0;
+        if (!r.get(h, 4) || !r.get1(P) || !r.get1(fstep)) return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (h[1] < 1 || h[1] > 64 || h[2] < 1 || h[2] > 64 || P < 1 || P > (int64_t)1 << 28)
+            return fail(DMC_E_INVALID, "corrupt flow section");
+        masks.resize((size_t)h[2] * h[1]);
+        fm.resize(P);
+        fmm.resize(P);
+        fv.resize(P);
+        if (!r.get(masks.data(), masks.size()) || !r.get(fm.data(), P) || !r.get(fmm.data(), P) || !r.get(fv.data(), P))
+            return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (f && (h[0] != f->kind || h[1] != f->dim || h[2] != f->n_layers || (size_t)P != flow_param_len(f) ||
+                  masks != f->masks))
+            return fail(DMC_E_INVALID, "the flow does not match the checkpoint");
+    }
+    if (sec & 4) {
+        int32_t h[4];
+        if (!r.get(h, 4) || !r.get1(n_samples) || !r.get1(nonfin)) return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (h[0] < 1 || h[0] > DMC_MAX_GROUPS || h[1] < 1 || h[1] > DMC_MAX_K || h[2] < 1 || h[2] > DMC_MAX_ROOTS ||
+            h[3] < 0 || h[3] > DMC_MAX_INSTANCES)
+            return fail(DMC_E_INVALID, "corrupt accumulator section");
+        group.resize(h[3]);
+        factor.resize(h[3]);
+        totals.resize(2 * (size_t)h[1] * 2 * h[0] * h[2]);
+        if (!r.get(group.data(), group.size()) || !r.get(factor.data(), factor.size()) ||
+            !r.get(totals.data(), totals.size()))
+            return fail(DMC_E_INVALID, "truncated checkpoint");
+        if (acc && (h[0] != acc->n_groups || h[1] != acc->n_k || h[2] != acc->n_roots))
+            return fail(DMC_E_INVALID, "the accumulator does not match the checkpoint");
+    }
+    if (s || f || acc) HIP_TRY(hipStreamSynchronize(S(stream)));
+    if (s) {
+        s->edges = edges;
+        std::vector<float> ef(edges.begin(), edges.end());
+        HIP_TRY(hipMemcpy(s->d_edges, ef.data(), sizeof(float) * ef.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_hist, hist.data(), sizeof(double) * hist.size(), hipMemcpyHostToDevice));
+        s->last_n = -1;
+    }
+    if (f) {
+        const size_t P = fm.size();
+        HIP_TRY(hipMemcpy(f->master, fm.data(), sizeof(float) * P, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(f->m, fmm.data(), sizeof(float) * P, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(f->v, fv.data(), sizeof(float) * P, hipMemcpyHostToDevice));
+        f->step = fstep;
+        if (f->kind == 0) HIP_TRY(dmc::launch_flow_shadow(f->master, f->shadow, f->n_layers, cu_count(), S(stream)));
+    }
+    if (acc) {
+        HIP_TRY(hipMemcpy(acc->totals, totals.data(), sizeof(double) * totals.size(), hipMemcpyHostToDevice));
+        const unsigned long long nf = nonfin;
+        HIP_TRY(hipMemcpy(acc->nonfin_tot, &nf, sizeof(nf), hipMemcpyHostToDevice));
+        acc->n_samples = n_samples;
+        acc->inst_group.assign(group.begin(), group.end());
+        acc->inst_factor.assign(factor.begin(), factor.end());
+    }
+    if (seed) *seed = sd;
+    if (next_index) *next_index = nx;
+    if (s || f || acc) HIP_TRY(hipStreamSynchronize(S(stream)));
+    return DMC_OK;
+}
+
+}  // extern "C"

@@ -1285,16 +1285,14 @@ static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_s
 }
 
 int default_part_size(int order, int n_diagrams, int n_roots) {
-    // Measured on MI355X (2^24 samples, 32 k, the factoring with pending hoisted multipliers): order 5
-    // runs in 313 ms in parts of 800 diagrams (their hoisted multipliers spill), 100 ms in parts of
-    // 450, 104 ms in parts of 400, 118 ms in parts of 200; order 6 in 1109 ms in parts of 400, 1185 ms
-    // in parts of 300; order 4 with three derivative roots in 61 ms in parts of 100, 71 ms in parts of
-    // 50, 92 ms in parts of 200; order 5 with them in 580 ms in parts of 100, 674 ms in parts of 60.
-    // Parts of about 800 / R^1.5 diagrams (R roots) keep a part's live set within the register file
-    // without recomputing more leaves than needed; single-root graphs from order 5 on, whose diagrams
-    // have more lines, take smaller parts.
-    const double base = order >= 6 ? 400.0 : order == 5 && n_roots == 1 ? 450.0 : 800.0;
-    const int per = std::max(16, (int)(base / std::pow((double)n_roots, 1.5)));
+    // Measured on MI355X per 2^22 samples x 32 k, with the external momentum on a path of chords (so a part's
+    // k-independent code dominates and runs once per chunk of momenta): order 5 in one part 3.1 ms, in 3
+    // parts 5.0 ms, in 5 parts 6.1 ms; order 6 in parts of 400, 800, 1600, 3200 diagrams 65.8, 43.7, 37.1,
+    // 40.3 ms (with d/dk at one momentum 74.1, 49.0, 40.2, 43.5 ms; run-time compilation 15, 17, 45, 90 s).
+    // Bigger parts evaluate fewer leaves twice; past 1600 diagrams their register pressure costs more.  More
+    // roots (derivative or Taylor coefficients) multiply a part's live values: parts shrink as R^1.5.
+    const double base = order >= 6 ? 1600.0 : 2400.0;
+    const int per = std::max(16, (int)(base / std::pow(std::max(1.0, n_roots / 2.0), 1.5)));
     return n_diagrams <= per ? 0 : per;
 }
 
@@ -1517,14 +1515,19 @@ struct EvalArgs {
     // small single-part value graphs (orders 1-3) are held to 5 waves per SIMD: order 3 otherwise takes 98
     // registers, 4 waves, and the fifth hides more of the transcendentals' latency
     const bool five = !split && NR == 1 && n <= 3;
-    // floats of stage per wave: a kernel in parts stages a run-time chunk of a.kc momenta for one group
-    const std::string sfw = split ? "(a.kc * SPK1 * 64)" : "(16 * MST * 64)";
+    // floats of stage per wave: a kernel in parts stages a run-time chunk of a.kc momenta for one group,
+    // SPK1 floats per lane for each of the first min(KD, kc) momenta (all kc when KD is 0), 2 for the others;
+    // the host sizes the block's LDS by the same count
+    const std::string sfw = split ? "(SFL * 64)" : "(16 * MST * 64)";
     s << "\nextern \"C\" __global__ void __launch_bounds__(256" << (five ? ", 5" : "") << ") KERNEL_NAME(const EvalArgs a) {";
     s << R"K(
 
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float* stage = smem + wv * )K" << sfw << R"K(;
+)K";
+    if (split)
+        s << "    const int ML0 = KD ? min(KD, a.kc) : a.kc, SFL = ML0 * SPK1 + (a.kc - ML0) * 2;\n";
+    s << R"K(    float* stage = smem + wv * )K" << sfw << R"K(;
     double* tot = (double*)(smem + 4 * )K" << sfw << R"K() + wv * (2 * a.s_total);
     for (int i = lane; i < 2 * a.s_total; i += 64) tot[i] = 0.0;
     unsigned int nonfin = 0;

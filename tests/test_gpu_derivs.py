@@ -20,7 +20,7 @@ ALL = dmc.D_MU | dmc.D_LAMBDA | dmc.D_K
 def test_derivative_roots_per_sample(n, N, K):
     """Each derivative against the oracle's dual numbers, judged against the size of the
     derivative's terms before cancellation (the condition-aware reading of 1e-5 relative).
-    Orders 4 and 5 run the partitioned kernel (2 and 23 parts)."""
+    Order 5 runs a kernel in parts (3 parts of 848 diagrams)."""
     x = synth.loop_points(n, N, seed=300 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
@@ -97,7 +97,7 @@ def test_autograd_function_backward_and_finite_differences():
 
 
 def test_k_derivative_order6_per_sample():
-    """d Sigma / dk at order 6 (31130 diagrams; a kernel of 221 parts, about a minute of run-time
+    """d Sigma / dk at order 6 (31130 diagrams; a kernel of 20 parts, about a minute of run-time
     compilation) against the oracle's dual numbers at k near k_F."""
     n, N = 6, 24
     x = synth.loop_points(n, N, seed=306)

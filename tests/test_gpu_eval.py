@@ -32,7 +32,7 @@ def _oracle_f(x, n, k, lam, gamma):
                                              (4, 300, 10, 40), (5, 300, 3, 0), (6, 40, 2, 0)])
 def test_integrand_per_sample(n, N, K, part_size):
     """Several 256-sample tiles plus a ragged tail; K spans a partial chunk of k values.  Order 4
-    in parts of 40 diagrams, order 5 (3 parts) and order 6 (31130 diagrams in 78 parts; about
+    in parts of 40 diagrams and order 6 (31130 diagrams in 20 parts; about
     two minutes of run-time compilation) cover the partitioned kernel."""
     x = synth.loop_points(n, N, seed=100 + n)
     ks = synth.k_grid(K)

@@ -25,7 +25,7 @@ TOL = 2e-5
 
 @pytest.mark.parametrize("n,T,N,K", [(1, 4, 600, 3), (2, 4, 400, 3), (3, 3, 250, 2), (4, 2, 96, 2)])
 def test_taylor_roots_per_sample(n, T, N, K):
-    """Orders 3 and 4 run the partitioned kernel (2 and 10 parts)."""
+    """Order 4 runs a kernel in parts (2 parts)."""
     x = synth.loop_points(n, N, seed=700 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
