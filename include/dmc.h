@@ -331,6 +331,16 @@ void dmc_chains_destroy(dmc_chains* c);
  * DMC_E_INVALID for null pointers or non-positive sizes. */
 dmc_status dmc_combine_iterations(int32_t n_iter, int32_t n_values, const double* means, const double* errs,
                                   double* mean, double* err, double* chi2_dof);
+/* The fallback from a learned proposal to the VEGAS grid (Sec. IV: a proposal is judged by the product of its
+ * variance and its cost).  From one probe iteration of each proposal with the same sample count: err_flow,
+ * err_grid host double[n_values] (the standard errors of the quantities that matter, e.g. every (instance, k,
+ * Re/Im) of the value root), t_flow, t_grid the probes' times in any one unit, nonfinite_flow the flow probe's
+ * dropped weights.  gain = (sum err_grid^2 t_grid) / (sum err_flow^2 t_flow) (0 if either sum is not finite);
+ * use_flow = 1 iff nonfinite_flow == 0 and gain >= min_gain.  DMC_E_INVALID for null pointers, n_values < 1,
+ * non-positive or non-finite times or a negative min_gain. */
+dmc_status dmc_proposal_select(int32_t n_values, const double* err_flow, const double* err_grid, double t_flow,
+                               double t_grid, int64_t nonfinite_flow, double min_gain, int32_t* use_flow,
+                               double* gain);
 /* The ratio estimator of eq. nf_mcmc_estimator_qft_final_revised from the batch sums of dmc_chains_read (host
  * double[n_batches][S + 1][2], S = n_groups n_roots n_k 2): for every slot, I = (sum_b sum f/pi) / (sum_b sum q/pi),
  * error = the scatter of the batch ratios over sqrt(n_batches); per instance (host dmc_instance[n_inst], grouped by

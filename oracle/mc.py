@@ -88,3 +88,52 @@ def importance_mc(n, ks, beta, mu, lam, gamma, diagrams, N=1 << 20, seed=777, ch
     mean = means.mean(axis=0)
     err = (means.real.std(axis=0, ddof=1) + 1j * means.imag.std(axis=0, ddof=1)) / np.sqrt(batches)
     return mean, err
+
+
+def vegas_mc(n, ks, beta, mu, lam, gamma, diagrams, N=1 << 18, adapt=5, N_adapt=1 << 16, bins=50, batches=32,
+             seed=4321, R=6.0, chunk=1 << 15, alpha=0.5):
+    """Sigma^(n)(k, i w_0) by VEGAS importance sampling with the oracle's own grid (sampler.py's map and
+    refinement, numpy PCG64 uniforms, every sample through the C integrand): `adapt` refinements on N_adapt
+    points each (importance sum_k |Re f| + |Im f| times the Jacobian; histogram of its square per bin), then N
+    points from the frozen grid in `batches` independent batches; the error is the scatter of the batch means.
+    Returns (mean[K], stderr[K]) complex."""
+    from . import cevaluate as ce
+    from . import sampler as osp
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = np.atleast_1d(np.asarray(ks, dtype=np.float64))
+    D = ig.dim(n)
+    tab = ce.table(diagrams, n)
+    edges = np.tile(np.linspace(0.0, 1.0, bins + 1), (D, 1))
+
+    def weights(m):
+        u = rng.random((m, D)).astype(np.float32).astype(np.float64)
+        y, JV, b = osp.vegas_map_float(u, edges)
+        x, JP = ig.physical_map(y, n, beta, R)
+        w = [ce.integrand(x, n, k, beta, mu, lam, gamma, diagrams, tab=tab) * (JV * JP) for k in ks]
+        return np.array(w), b
+
+    for _ in range(adapt):
+        hist = np.zeros((D, bins))
+        done = 0
+        while done < N_adapt:
+            m = min(chunk, N_adapt - done)
+            w, b = weights(m)
+            imp2 = (np.abs(w.real) + np.abs(w.imag)).sum(axis=0) ** 2
+            for d in range(D):
+                hist[d] += np.bincount(b[:, d], weights=imp2, minlength=bins)
+            done += m
+        edges = osp.refine_grid(edges, hist, alpha)
+    per = N // batches
+    means = np.zeros((batches, len(ks)), dtype=np.complex128)
+    for bi in range(batches):
+        s = np.zeros(len(ks), dtype=np.complex128)
+        done = 0
+        while done < per:
+            m = min(chunk, per - done)
+            w, _ = weights(m)
+            s += w.sum(axis=1)
+            done += m
+        means[bi] = s / per
+    mean = means.mean(axis=0)
+    err = (means.real.std(axis=0, ddof=1) + 1j * means.imag.std(axis=0, ddof=1)) / np.sqrt(batches)
+    return mean, err

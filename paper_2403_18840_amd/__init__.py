@@ -34,7 +34,7 @@ ABI_SYMBOLS = [
     "dmc_chains_destroy",
     "dmc_chains_training_data",
     "dmc_effective_mass", "dmc_probe", "dmc_combine_iterations", "dmc_chains_ratio", "dmc_mass_table",
-    "dmc_checkpoint_save", "dmc_checkpoint_load",
+    "dmc_checkpoint_save", "dmc_checkpoint_load", "dmc_proposal_select",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
         "dmc_sampler_destroy": (None, [P]),
         "dmc_eval_batch": (I32, [P, P, I32, P, I32, P, I64, P, I64, P, P, P, P]),
         "dmc_combine_iterations": (I32, [I32, I32, P, P, P, P, P]),
+        "dmc_proposal_select": (I32, [I32, P, P, F64, F64, I64, F64, ctypes.POINTER(I32), ctypes.POINTER(F64)]),
         "dmc_chains_ratio": (I32, [I32, I32, I32, I32, P, I32, P, I32, P, P]),
         "dmc_mass_table": (I32, [I32, P, I32, P, F64, P, P, P, P, P]),
         "dmc_checkpoint_save": (I32, [P, P, P, U64, U64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]),
@@ -452,7 +453,7 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
 def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int = 5, seed: int = 1,
               kind: int = SAMPLER_VEGAS, n_bins: int = 50, beta: float = 25.0, qmax: float = 6.0, alpha: float = 0.5,
               flow: "Flow | None" = None, flow_alpha: float = 0.85, flow_uniform: float = 0.05,
-              train: dict | None = None, train_k=None):
+              train: dict | None = None, train_k=None, fallback: float | None = 1.0, report: dict | None = None):
     """Importance-sampling estimate of Sigma (and derivative roots) with the library's sampler.
 
     `adapt` iterations refine the VEGAS grid (their samples are discarded).  With a `flow`, it is
@@ -460,7 +461,15 @@ def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int 
     momenta train_k, default all; None skips training) and the estimate draws from the mixture
     flow_alpha q_flow + flow_uniform q_uniform + (rest) q_grid.  The next `iters`
     iterations accumulate into one FP64 accumulator, whose mean over all estimation samples is the
-    estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K]."""
+    estimate.  Returns (mean, stderr) complex [n_inst][n_roots][K].
+
+    Fallback to VEGAS (with a flow and `fallback` not None): one probe iteration of each proposal, on points
+    of their own that are discarded like the adaptation's, decides through dmc_proposal_select whether the
+    flow beats the grid by the factor `fallback` in variance times time; if not, or if its probe dropped a
+    non-finite weight, the estimate draws from the grid.  A flow iteration that drops a non-finite weight
+    switches the remaining iterations to the grid (the switch depends on earlier iterations only, so each
+    iteration's estimate stays unbiased).  `report`, a dict, receives "proposal" ("flow" or "vegas"),
+    "gain" and "switched_at" (the iteration of a switch, or None)."""
     import numpy as np
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -480,16 +489,40 @@ def integrate(graph: Graph, inst, k_ext, n_samples: int, iters: int, adapt: int 
     acc = Accumulator(_n_groups(inst), len(ks), graph.n_roots)
     X = torch.empty((D, n_samples), dtype=torch.float32, device=dev)
     J = torch.empty(n_samples, dtype=torch.float32, device=dev)
-    est_seed = seed + 2 if flow is not None else seed
-    for _ in range(iters):
-        if flow is not None:
+    use_flow, gain, switched = flow is not None, None, None
+    if use_flow and fallback is not None:
+        errs, times, nfs = [], [], []
+        for which in ("flow", "grid"):
+            pacc = Accumulator(_n_groups(inst), len(ks), graph.n_roots)
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            if which == "flow":
+                flow.sample(s, seed + 4, 0, X, J, alpha=flow_alpha, uniform=flow_uniform)
+            else:
+                s.sample(seed + 5, 0, X, J)
+            eval_batch(graph, inst, ks, X, J, pacc)
+            accumulate(pacc)
+            t1.record()
+            t1.synchronize()
+            _, e, _, nf = pacc.estimate(len(inst))
+            errs.append(np.stack([e[:, 0].real, e[:, 0].imag]))
+            times.append(t0.elapsed_time(t1))
+            nfs.append(nf)
+        use_flow, gain = proposal_select(errs[0], errs[1], times[0], times[1], nfs[0], fallback)
+    est_seed = seed + 2 if use_flow else seed
+    for it in range(iters):
+        if use_flow:
             flow.sample(s, est_seed, first, X, J, alpha=flow_alpha, uniform=flow_uniform)
         else:
             s.sample(seed, first, X, J)
         eval_batch(graph, inst, ks, X, J, acc)
         accumulate(acc)
         first += n_samples
+        if use_flow and fallback is not None and it + 1 < iters and acc.estimate(len(inst))[3] > 0:
+            use_flow, switched = False, it + 1
     m, e, ns, nf = acc.estimate(len(inst))
+    if report is not None:
+        report.update(proposal="flow" if use_flow else "vegas", gain=gain, switched_at=switched)
     return m, e
 
 
@@ -764,6 +797,20 @@ def combine_iterations(means, errs):
     _check(lib().dmc_combine_iterations(mm.shape[0], nv, mm.ctypes.data_as(P), ee.ctypes.data_as(P),
                                         *[o.ctypes.data_as(P) for o in out]))
     return tuple(o.reshape(mm.shape[1:]) for o in out)
+
+
+def proposal_select(err_flow, err_grid, t_flow: float, t_grid: float, nonfinite_flow: int, min_gain: float = 1.0):
+    """dmc_proposal_select: (use_flow, gain) from the standard errors (real arrays of one shape) and times of one
+    probe iteration of the flow mixture and of the VEGAS grid."""
+    import numpy as np
+    ef = np.ascontiguousarray(err_flow, dtype=np.float64).reshape(-1)
+    eg = np.ascontiguousarray(err_grid, dtype=np.float64).reshape(-1)
+    if ef.shape != eg.shape:
+        raise ValueError("err_flow and err_grid must have one shape")
+    use, gain = I32(), F64()
+    _check(lib().dmc_proposal_select(ef.size, ef.ctypes.data_as(P), eg.ctypes.data_as(P), t_flow, t_grid,
+                                     nonfinite_flow, min_gain, ctypes.byref(use), ctypes.byref(gain)))
+    return bool(use.value), gain.value
 
 
 def mass_table(order: int, root_orders, est, beta: float):

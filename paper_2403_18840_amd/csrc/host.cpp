@@ -120,3 +120,31 @@ dmc_status dmc_mass_table(int32_t order, const int32_t* root_orders, int32_t n_r
 }
 
 }  // extern "C"
+
+extern "C" {
+
+dmc_status dmc_proposal_select(int32_t n_values, const double* err_flow, const double* err_grid, double t_flow,
+                               double t_grid, int64_t nonfinite_flow, double min_gain, int32_t* use_flow,
+                               double* gain) {
+    if (!err_flow || !err_grid || !use_flow || !gain) return dmc::set_error(DMC_E_INVALID, "null argument");
+    if (n_values < 1) return dmc::set_error(DMC_E_INVALID, "need n_values >= 1");
+    if (!(t_flow > 0) || !(t_grid > 0) || !std::isfinite(t_flow) || !std::isfinite(t_grid))
+        return dmc::set_error(DMC_E_INVALID, "probe times must be positive and finite");
+    if (!(min_gain >= 0)) return dmc::set_error(DMC_E_INVALID, "min_gain must be >= 0");
+    double vf = 0.0, vg = 0.0;
+    for (int v = 0; v < n_values; ++v) {
+        vf += err_flow[v] * err_flow[v];
+        vg += err_grid[v] * err_grid[v];
+    }
+    // efficiency of the flow over the grid: (variance x time) of the grid over that of the flow
+    double g = 0.0;
+    if (std::isfinite(vf) && std::isfinite(vg)) {
+        if (vf > 0) g = (vg * t_grid) / (vf * t_flow);
+        else g = vg > 0 ? std::numeric_limits<double>::infinity() : 1.0;
+    }
+    *gain = g;
+    *use_flow = (nonfinite_flow == 0 && g >= min_gain) ? 1 : 0;
+    return DMC_OK;
+}
+
+}  // extern "C"

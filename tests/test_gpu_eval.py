@@ -136,6 +136,54 @@ def test_reduction_matches_fsum_and_is_deterministic():
     assert np.array_equal(sums, sums2)
 
 
+@pytest.mark.parametrize("path", ["partitioned", "single"])
+def test_fold_over_many_tiles_matches_fsum(path):
+    """The FP64 fold at production size: 2^20 + 37 samples (thousands of tiles per block's running totals, a
+    ragged last tile), two lambda groups, six momenta.  The partitioned kernel stages w = fp32(f J) with f the
+    value it writes to f_out, so its weights are known exactly for a general (log-normal) Jacobian; the
+    one-part kernel folds J into its per-sample factors, exact for powers of two.  Either way the sums must
+    equal math.fsum of the staged weights within the FP64 error of any summation order, (N - 1) u_64 sum |w|,
+    and repeat bit for bit."""
+    torch, dev = torch_dev()
+    n, N = 3, (1 << 20) + 37
+    x = synth.loop_points(n, N, seed=29)
+    rng = np.random.default_rng(31)
+    if path == "partitioned":
+        g = dmc.Graph(n, part_size=8)
+        assert g.info().n_parts > 1
+        jac = np.exp(rng.normal(0.0, 1.5, N)).astype(np.float32)
+    else:
+        g = dmc.Graph(n)
+        assert g.info().n_parts == 1
+        jac = (2.0 ** rng.integers(-3, 4, N)).astype(np.float32)
+    ks = synth.k_grid(6)
+    inst = [(BETA, MU, 0.5, ph.coupling(1.0)), (BETA, MU, 2.0, ph.coupling(1.0))]
+    f, acc, imp = gpu_integrand(g, x, ks, inst, jac=jac)
+    sums, ns = acc.read()
+    assert ns == N
+    gamma_n = (N - 1) * 2.0 ** -53 / (1 - (N - 1) * 2.0 ** -53)
+    worst = 0.0
+    w_abs = np.zeros(N, dtype=np.float64)
+    for gi in range(2):
+        for j in range(len(ks)):
+            for c, part in enumerate([f[gi, 0, j].real, f[gi, 0, j].imag]):
+                w32 = part.astype(np.float32) * jac          # the staged weight (RNE product, as on the device)
+                w = w32.astype(np.float64)
+                w_abs += np.abs(w)
+                a1 = math.fsum(np.abs(w))
+                s1, s2 = math.fsum(w), math.fsum(w * w)
+                e1 = abs(sums[gi, 0, j, c, 0] - s1)
+                e2 = abs(sums[gi, 0, j, c, 1] - s2)
+                assert e1 <= gamma_n * a1 + 1e-300, (gi, j, c, sums[gi, 0, j, c, 0], s1, e1, gamma_n * a1)
+                assert e2 <= gamma_n * s2 + 1e-300, (gi, j, c, sums[gi, 0, j, c, 1], s2, e2, gamma_n * s2)
+                worst = max(worst, e1 / max(a1, 1e-300))
+    # importance: the FP32 sum over groups, momenta and Re/Im of |w| (24 positive terms)
+    assert np.allclose(imp, w_abs, rtol=24 * 2.0 ** -24, atol=0)
+    print(f"{path}: {N} samples, worst |fold - fsum| / sum|w| = {worst:.2e} (bound {gamma_n:.2e})")
+    _, acc2, _ = gpu_integrand(g, x, ks, inst, jac=jac)
+    assert np.array_equal(sums, acc2.read()[0])
+
+
 @pytest.mark.parametrize("n,mask,part,N,bad", [(1, 0, 0, 512, [3, 300]), (2, 0, 0, 300, [0, 299]),
                                                (2, 7, 0, 300, [5, 299]), (1, 7, 0, 70, [69]),
                                                (4, 0, 40, 300, [7, 299])])

@@ -118,10 +118,17 @@ def test_gradient_matches_oracle(D, N):
     print(f"D={D}: loss {loss:.6f} vs {rl:.6f}; |grad - ref| / |ref| = {rel:.2e}")
     assert abs(loss - rl) < 1e-4 * max(1.0, abs(rl))
     assert rel < 1e-2
-    # per-layer blocks agree too (none is silently zero)
+    # element by element, each layer against its largest entry (none is silently zero): the oracle rounds the
+    # same operands to BF16, so what remains is FP32 summation order and the rare rounding flip it causes
+    worst = 0.0
     for l in range(L):
         sl = slice(l * ofl.LAYER_SIZE, (l + 1) * ofl.LAYER_SIZE)
-        assert np.linalg.norm(g[sl] - rg[sl]) <= 2e-2 * np.linalg.norm(rg[sl]) + 1e-12
+        scale = np.max(np.abs(rg[sl]))
+        assert scale > 0
+        err = np.max(np.abs(g[sl] - rg[sl])) / scale
+        worst = max(worst, err)
+        assert err <= 1e-3, (l, err)
+    print(f"D={D}: worst per-element |grad - ref| / max |ref| of its layer = {worst:.2e}")
 
 
 def test_training_lowers_the_loss_and_adam_matches_oracle_step():
@@ -306,3 +313,24 @@ def test_three_way_mixture_matches_oracle():
     assert np.max(np.abs(ug[fs] - up)) < 2e-3
     assert np.median(np.abs(lqg[fs] - lq)) < 1e-4 and np.max(np.abs(lqg[fs] - lq)) < 5e-3
     _flow_share_matches(xg[fs], jg[fs], ug[fs], up, lq, g32, n, a_f, a_u)
+
+
+def test_integrate_falls_back_to_vegas():
+    """An untrained (identity) flow has the grid's variance at a higher cost per point, so the probe's gain is
+    below 1 and integrate() draws from the grid: its estimate is then bit for bit the flow-free one.  With the
+    bar at 0 the flow is kept."""
+    n = 2
+    D = dmc.dim(n)
+    ks = [0.5, 1.0]
+    inst = [(BETA, 1.0, 1.0, dmc.coupling(1.0))]
+    g = dmc.Graph(n)
+    f = dmc.Flow(D, synth.flow_masks(D, L, 3))
+    rep = {}
+    m1, e1 = dmc.integrate(g, inst, ks, 1 << 16, iters=3, adapt=2, seed=9, flow=f, report=rep)
+    print(rep)
+    assert rep["proposal"] == "vegas" and rep["gain"] < 1 and rep["switched_at"] is None
+    m0, e0 = dmc.integrate(g, inst, ks, 1 << 16, iters=3, adapt=2, seed=9)
+    assert np.array_equal(m1, m0) and np.array_equal(e1, e0)
+    rep = {}
+    m2, _ = dmc.integrate(g, inst, ks, 1 << 16, iters=3, adapt=2, seed=9, flow=f, fallback=0.0, report=rep)
+    assert rep["proposal"] == "flow" and not np.array_equal(m2, m0)

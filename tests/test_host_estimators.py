@@ -31,6 +31,22 @@ def test_combine_iterations_mean_error_and_chi2():
         dmc.combine_iterations(means[:0], errs[:0])
 
 
+def test_proposal_select_rule():
+    ef = np.array([1.0, 2.0, 0.5])
+    eg = 3.0 * ef                               # the grid's variance is 9x the flow's
+    use, gain = dmc.proposal_select(ef, eg, 3.0, 1.0, 0)
+    assert use and gain == pytest.approx(3.0, rel=1e-15)        # 9 x (1 / 3)
+    assert dmc.proposal_select(ef, eg, 3.0, 1.0, 0, min_gain=3.5) == (False, pytest.approx(3.0))
+    assert not dmc.proposal_select(ef, eg, 1.0, 1.0, 1)[0]       # a dropped weight rules the flow out
+    assert dmc.proposal_select(np.zeros(3), eg, 1.0, 1.0, 0) == (True, math.inf)
+    assert dmc.proposal_select(np.full(3, np.nan), eg, 1.0, 1.0, 0) == (False, 0.0)
+    for bad in [dict(t_flow=0.0), dict(t_grid=-1.0), dict(min_gain=-1.0), dict(t_flow=math.inf)]:
+        args = dict(err_flow=ef, err_grid=eg, t_flow=1.0, t_grid=1.0, nonfinite_flow=0, min_gain=1.0)
+        args.update(bad)
+        with pytest.raises(dmc.DmcError):
+            dmc.proposal_select(**args)
+
+
 def test_chains_ratio_matches_oracle_and_rescales_rs():
     rng = np.random.default_rng(9)
     B, G, R, K = 8, 2, 2, 3
