@@ -187,6 +187,25 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
  * the sampler's last dmc_sample call (the bins are recomputed from the Philox counters). */
 dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* sampler, const float* imp, void* stream);
 
+/* ---- evaluation that allocates nothing ----
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): dmc_eval_batch followed by dmc_accumulate(acc, NULL, NULL, stream) in
+ * one call, with the per-block FP64 partial sums and non-finite counts in a static device array of the
+ * library (4 MiB, DMC_SCRATCH_BYTES; each GPU the library runs on holds its own copy until the process
+ * ends) instead of memory the accumulator allocates on demand.  Same arguments and results as that pair
+ * (the block count may be smaller, so FP64 sums can differ in their last bits).  It calls no hipMalloc,
+ * hipFree or other allocating routine and compiles nothing: the graph's kernel for this number of lambda
+ * groups must already be loaded on the current device (one dmc_eval_batch call with the same graph and
+ * groups loads it), else DMC_E_STATE; the accumulator must have no pending evaluation (DMC_E_STATE).
+ * DMC_E_INVALID when one block's partial sums (2 x 8 B per accumulator slot, plus 4 B) exceed the
+ * scratch, and for the argument errors of dmc_eval_batch.  The scratch keeps the last call's contents;
+ * every call overwrites what it reads.  Calls on one GPU share the scratch: calls that overlap on one
+ * GPU (from any stream or thread) race, so the caller serialises them. */
+#define DMC_SCRATCH_BYTES (4u << 20)
+dmc_status dmc_eval_accumulate_noalloc(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext,
+                                       int32_t n_k, const float* x, int64_t ld, const float* jac, int64_t n,
+                                       dmc_accum* acc, float* f_out, float* imp_out, void* stream);
+
 /* Mean and standard error of the mean per instance, root, k and Re/Im:
  * mean, stderr_: host double[n_inst][n_roots][n_k][2].  n_nonfinite: host (nullable).  Uses the
  * instances of the last eval_batch.  Synchronises `stream`.  Returns DMC_E_NUMERIC (with valid

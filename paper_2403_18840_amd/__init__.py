@@ -26,7 +26,7 @@ ABI_SYMBOLS = [
     "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_vegas_refine",
-    "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch",
+    "dmc_sampler_read_histogram", "dmc_sampler_destroy", "dmc_eval_batch", "dmc_eval_accumulate_noalloc",
     "dmc_accumulate", "dmc_estimate",
     "dmc_accum_read", "dmc_flow_create", "dmc_flow_create_spline", "dmc_flow_param_count", "dmc_flow_set_params", "dmc_flow_get_params",
     "dmc_flow_sample", "dmc_flow_log_density", "dmc_flow_walk", "dmc_flow_train_step", "dmc_flow_destroy",
@@ -106,6 +106,7 @@ def lib():
         "dmc_sampler_read_histogram": (I32, [P, P, P]),
         "dmc_sampler_destroy": (None, [P]),
         "dmc_eval_batch": (I32, [P, P, I32, P, I32, P, I64, P, I64, P, P, P, P]),
+        "dmc_eval_accumulate_noalloc": (I32, [P, P, I32, P, I32, P, I64, P, I64, P, P, P, P]),
         "dmc_combine_iterations": (I32, [I32, I32, P, P, P, P, P]),
         "dmc_proposal_select": (I32, [I32, P, P, F64, F64, I64, F64, ctypes.POINTER(I32), ctypes.POINTER(F64)]),
         "dmc_chains_ratio": (I32, [I32, I32, I32, I32, P, I32, P, I32, P, P]),
@@ -323,6 +324,21 @@ def eval_batch(graph: Graph, inst, k_ext, x, jac, acc: Accumulator, f_out=None, 
                                 x.shape[1], _dptr(jac, "float32", "jac"), n, acc.h,
                                 _dptr(f_out, "float32", "f_out"), _dptr(imp_out, "float32", "imp_out"),
                                 _stream(stream)))
+
+
+def eval_accumulate_noalloc(graph: Graph, inst, k_ext, x, jac, acc: Accumulator, f_out=None, imp_out=None,
+                            stream=None):
+    """dmc_eval_accumulate_noalloc: eval_batch + accumulate with the library's static device scratch (the
+    graph's kernel must have been loaded by an eval_batch call)."""
+    import numpy as np
+    arr = instances(inst)
+    k = np.ascontiguousarray(k_ext, dtype=np.float32)
+    if x.dim() != 2:
+        raise ValueError("x must be [D, ld]")
+    _check(lib().dmc_eval_accumulate_noalloc(graph.h, arr, len(arr), k.ctypes.data_as(P), len(k),
+                                             _dptr(x, "float32", "x"), x.shape[1], _dptr(jac, "float32", "jac"),
+                                             jac.numel(), acc.h, _dptr(f_out, "float32", "f_out"),
+                                             _dptr(imp_out, "float32", "imp_out"), _stream(stream)))
 
 
 def accumulate(acc: Accumulator, sampler: Sampler | None = None, imp=None, stream=None):

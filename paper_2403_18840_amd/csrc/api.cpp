@@ -531,6 +531,31 @@ dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst
     return eval_launch(g, inst, n_inst, k_ext, n_k, x, ld, jac, n, acc, f_out, imp_out, stream, nullptr, 0);
 }
 
+// The static device scratch (kernels.hip) as a device address, per device, taken once with that device
+// current: in host code the array's name is not a device address.
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {nullptr};
+
+dmc_status dmc_eval_accumulate_noalloc(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext,
+                                       int32_t n_k, const float* x, int64_t ld, const float* jac, int64_t n,
+                                       dmc_accum* acc, float* f_out, float* imp_out, void* stream) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(DMC_E_DEVICE, "device index out of range for the static scratch");
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            HIP_TRY(dmc::scratch_address(&p));
+            g_scratch_ptr[dev] = p;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return eval_launch(g, inst, n_inst, k_ext, n_k, x, ld, jac, n, acc, f_out, imp_out, stream, ptr,
+                       dmc::kScratchBytes);
+}
+
 dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* s, const float* imp, void* stream) {
     if (!acc) return fail(DMC_E_INVALID, "null accumulator");
     if (!acc->pending_blocks) return fail(DMC_E_STATE, "no dmc_eval_batch to fold");

@@ -205,6 +205,12 @@ hipError_t launch_sample(const SampleArgs& a, int n_cu, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Block partials of the allocation-free evaluation (dmc_eval_accumulate_noalloc): FP64 partial sums and
+// non-finite counts.  Host code reaches it only through scratch_address.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
+
 hipError_t launch_fold(const double* partial, int nb, int st2, double* totals, const unsigned int* nonfin_part,
                        unsigned long long* nonfin_tot, hipStream_t st) {
     hipLaunchKernelGGL(dmc_fold_kernel, dim3(st2 + 1), dim3(256), 0, st, partial, nb, st2, totals, nonfin_part,

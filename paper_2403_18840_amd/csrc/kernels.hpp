@@ -34,4 +34,9 @@ hipError_t launch_fold(const double* partial, int nb, int st2, double* totals, c
                        unsigned long long* nonfin_tot, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, int n_cu, hipStream_t st);
 
+// The allocation-free evaluation's block partials live in a static device array of this size (each GPU
+// holds its own copy until the process ends); scratch_address gives the current device's copy.
+constexpr size_t kScratchBytes = 4u << 20;
+hipError_t scratch_address(void** out);
+
 }  // namespace dmc
