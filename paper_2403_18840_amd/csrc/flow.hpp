@@ -52,9 +52,21 @@ __device__ __forceinline__ int frag_slot(int sg_base, int row, int c) {
     return SH_FRAG + (sg_base + sg) * 512 + (32 * h + row) * 8 + t;
 }
 
+// BF16 of an FP32 master by round-to-nearest-even on its bit pattern.  The shadow must be a function of the
+// stored FP32 value alone: a plain conversion lets the compiler fuse it with the FP64 -> FP32 rounding of
+// the Adam update into one correctly rounded FP64 -> BF16 conversion, which differs from rounding the
+// stored master at BF16 ties, so a shadow rebuilt from the masters (set_params, checkpoint load) would
+// not equal the one Adam wrote.  Masters are finite (set_params refuses others, Adam skips non-finite
+// gradients).
+__device__ __forceinline__ __bf16 master_to_bf16(float th) {
+    unsigned u = __builtin_bit_cast(unsigned, th);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+}
+
 __device__ __forceinline__ void write_shadow(__bf16* shadow, int l, int q, float th) {
     __bf16* s = shadow + (size_t)l * SHADOW_LAYER;
-    const __bf16 b = (__bf16)th;
+    const __bf16 b = master_to_bf16(th);
     if (q < OFF_W2T) {
         const int r = q / FKIN, k = q % FKIN;
         s[SH_W1T + r * FKIN + k] = b;
