@@ -36,7 +36,13 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X's published FP32 vector peak (dense)
 PEAK_ALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz: the unpacked issue rate (packed FP32 is off)
 PEAK_BF16_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 # affine-coupling flow, 8 layers of 16 -> 128 -> 128 -> 32 (FMA = 2 FLOP); the products as executed
-FLOW_FLOP_PER_SAMPLE = 8 * 2 * (16 * 128 + 128 * 128 + 128 * 32)
+
+
+def affine_flow_flop(masks):
+    """Algorithmic FLOP per sample of the affine flow (multiply-add = 2): per layer the network on the dA
+    conditioning inputs plus the bias input, its 128 x 128 hidden product, and the 2 dB outputs (s and t of the
+    transformed dimensions).  The kernel's MFMA tiles pad the input to 16 and the output to 32."""
+    return sum(2 * ((int(m.sum()) + 1) * 128 + 128 * 128 + 128 * 2 * (len(m) - int(m.sum()))) for m in masks)
 
 
 def flops(ops):
@@ -253,7 +259,7 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
         per = sum(2 * (32 * int(m.sum()) + 32 * 32 + 23 * (D - int(m.sum())) * 32) for m in f.masks)
         flop, peak, bound, kname = N * per, PEAK_FP32_TFLOPS, "alu", f"dmc_nsf_sample_kernel (D = {D})"
     else:
-        flop, peak, bound, kname = N * FLOW_FLOP_PER_SAMPLE, PEAK_BF16_TFLOPS, "mfma", f"dmc_flow_sample_kernel<{D}>"
+        flop, peak, bound, kname = N * affine_flow_flop(f.masks), PEAK_BF16_TFLOPS, "mfma", f"dmc_flow_sample_kernel<{D}>"
     ev, ef = vg["sigma"], fl["sigma"]
     vg["seconds"] = t_v
     fl.update({"seconds": t_f, "kind": kind, "layers": f.n_layers,

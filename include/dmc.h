@@ -329,7 +329,9 @@ dmc_status dmc_chains_step_walk(dmc_chains* c, const float* f_prop, int64_t ld, 
 /* sums: host double[n_batches][S + 1][2], S = n_groups n_roots n_k 2 slots in the f_out order, per batch:
  * [b][s][0] = sum f_s/pi, [b][s][1] = sum (f_s/pi)^2; row S: sum q/pi and its squares.  n_measured: chain
  * states added (all batches);
- * n_accepted: proposals taken since the last reset.  Synchronises `stream`. */
+ * n_accepted: proposals taken since the last reset.  Measured steps add to per-block running sums on the
+ * device (one launch per step); this call folds them into the totals in a fixed order first, so a step costs
+ * no fold.  Synchronises `stream`. */
 dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream);
 /* The chain states as training data for a proposal density (Appendix A: samples that represent |f|,
  * generated by MCMC): u (device float[dim_u][ld], ld >= n) receives the states' coordinates and w

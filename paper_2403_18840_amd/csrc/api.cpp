@@ -1503,13 +1503,14 @@ struct dmc_chains {
     float* u_state = nullptr;     // device [D][n] (D > 0)
     double* q_state = nullptr;    // device [n]
     double* pi_state = nullptr;   // device [n]
-    double* partial = nullptr;    // device [nblk][n_batches][S + 1][2]
+    double* partial = nullptr;    // device [nblk][n_batches][S + 1][2]: per-block running sums since the last fold
     double* totals = nullptr;     // device [n_batches][S + 1][2]
     unsigned int* zeros = nullptr;              // device [nblk] (the fold's count column, unused)
     unsigned long long* nonfin = nullptr;       // device, the fold's count (unused)
     unsigned long long* n_acc = nullptr;        // device: accepted proposals since the last reset
     int nblk = 0, chunk = 0;      // accumulate blocks per batch, chains per block
     int64_t steps = 0, measured = 0;
+    bool unfolded = false;        // partial holds measured steps not yet in totals
     size_t totals_len() const { return (size_t)n_batches * (S + 1) * 2; }
 };
 
@@ -1542,6 +1543,7 @@ dmc_status dmc_chains_create(int64_t n, int32_t n_batches, int32_t n_groups, int
     HIP_ALLOC(hipMalloc(&c->nonfin, sizeof(unsigned long long)));
     HIP_ALLOC(hipMalloc(&c->n_acc, sizeof(unsigned long long)));
     HIP_TRY(hipMemset(c->totals, 0, sizeof(double) * c->totals_len()));
+    HIP_TRY(hipMemset(c->partial, 0, sizeof(double) * (size_t)c->nblk * c->totals_len()));
     HIP_TRY(hipMemset(c->zeros, 0, sizeof(unsigned int) * (size_t)c->nblk));
     HIP_TRY(hipMemset(c->nonfin, 0, sizeof(unsigned long long)));
     HIP_TRY(hipMemset(c->n_acc, 0, sizeof(unsigned long long)));
@@ -1590,8 +1592,7 @@ static dmc_status chains_step(dmc_chains* c, const float* f_prop, int64_t ld, co
         m.partial = c->partial;
         m.chunk = c->chunk;
         HIP_TRY(dmc::launch_mcmc_accumulate(m, c->nblk, S(stream)));
-        HIP_TRY(dmc::launch_fold(c->partial, c->nblk, (int)c->totals_len(), c->totals, c->zeros, c->nonfin,
-                                 S(stream)));
+        c->unfolded = true;
         c->measured += c->n;
     }
     return DMC_OK;
@@ -1621,9 +1622,20 @@ dmc_status dmc_chains_step_walk(dmc_chains* c, const float* f_prop, int64_t ld, 
                        stream);
 }
 
+// the per-block running sums into the totals (fixed order), then cleared
+static dmc_status chains_fold(dmc_chains* c, void* stream) {
+    if (!c->unfolded) return DMC_OK;
+    HIP_TRY(dmc::launch_fold(c->partial, c->nblk, (int)c->totals_len(), c->totals, c->zeros, c->nonfin, S(stream)));
+    HIP_TRY(hipMemsetAsync(c->partial, 0, sizeof(double) * (size_t)c->nblk * c->totals_len(), S(stream)));
+    c->unfolded = false;
+    return DMC_OK;
+}
+
 dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int64_t* n_accepted, void* stream) {
     if (!c || !sums) return fail(DMC_E_INVALID, "null argument");
     unsigned long long acc = 0;
+    dmc_status st = chains_fold(c, stream);
+    if (st != DMC_OK) return st;
     HIP_TRY(hipStreamSynchronize(S(stream)));
     HIP_TRY(hipMemcpy(sums, c->totals, sizeof(double) * c->totals_len(), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&acc, c->n_acc, sizeof(acc), hipMemcpyDeviceToHost));
@@ -1656,6 +1668,8 @@ dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* 
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream) {
     if (!c) return fail(DMC_E_INVALID, "null argument");
     HIP_TRY(hipMemsetAsync(c->totals, 0, sizeof(double) * c->totals_len(), S(stream)));
+    HIP_TRY(hipMemsetAsync(c->partial, 0, sizeof(double) * (size_t)c->nblk * c->totals_len(), S(stream)));
+    c->unfolded = false;
     HIP_TRY(hipMemsetAsync(c->n_acc, 0, sizeof(unsigned long long), S(stream)));
     c->measured = 0;
     return DMC_OK;

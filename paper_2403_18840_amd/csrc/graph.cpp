@@ -1247,10 +1247,14 @@ std::string kernel_name(const Compiled& c, int n_groups) {
            (np > 1 ? "_p" + std::to_string(np) : "");
 }
 
-// Diagram parts of a partitioned kernel: diagrams sorted by root class and by the leaves that
-// carry the external momentum (diagrams in one part share their k-dependent leaves), then cut into
-// parts of at most part_size diagrams.  One part = the whole graph when it fits.
+// Diagram parts of a partitioned kernel.  Every part re-evaluates the leaves its diagrams use (and the
+// products they share), so parts are grown around shared leaves: diagrams are ranked by root class and by the
+// leaves that carry the external momentum; each part then repeatedly takes the unplaced diagram whose leaves
+// not yet in the part cost least (a leaf that carries k weighs kKLeafWeight, being evaluated once per external
+// momentum; the others 1; ties by rank), starting from an empty part, until it holds part_size diagrams.  One
+// part = the whole graph when it fits.
 static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_size) {
+    constexpr int kKLeafWeight = 8;
     const int n = c.order;
     const int nd = (int)c.diagrams.size();
     std::vector<std::vector<int>> parts;
@@ -1277,21 +1281,71 @@ static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_s
         keyed.push_back({key, i});
     }
     std::stable_sort(keyed.begin(), keyed.end());
+    std::vector<int> rank(nd);
+    for (int r = 0; r < nd; ++r) rank[keyed[r].second] = r;
+    // leaves: a propagator by its time pair and momentum (up to sign), an interaction by its momentum
+    std::map<std::vector<int>, int> leaf_id;
+    std::vector<std::vector<std::pair<int, int>>> dl(nd);  // (leaf, weight)
     for (int i = 0; i < nd; ++i) {
-        if (i % part_size == 0) parts.emplace_back();
-        parts.back().push_back(keyed[i].second);
+        for (auto& ln : c.diagrams[i].lines) {
+            Mom m = normalise(ln.mom, n);
+            const bool g = ln.kind == 'G';
+            std::vector<int> key{g ? 0 : 1, g ? ln.src / 2 : 0, g ? ln.dst / 2 : 0};
+            key.insert(key.end(), m.begin(), m.begin() + n + 1);
+            const int id = leaf_id.emplace(key, (int)leaf_id.size()).first->second;
+            dl[i].push_back({id, m[n] != 0 ? kKLeafWeight : 1});
+        }
+        std::sort(dl[i].begin(), dl[i].end());
+        dl[i].erase(std::unique(dl[i].begin(), dl[i].end()), dl[i].end());
+    }
+    std::vector<std::vector<int>> users(leaf_id.size());
+    for (int i = 0; i < nd; ++i)
+        for (auto [l, w] : dl[i]) users[l].push_back(i);
+    std::vector<char> placed(nd, 0);
+    std::vector<int> cost(nd, 0);
+    int left = nd;
+    while (left > 0) {
+        std::set<std::pair<int, int>> q;  // (cost of the leaves it would add, rank) of every unplaced diagram
+        for (int i = 0; i < nd; ++i)
+            if (!placed[i]) {
+                cost[i] = 0;
+                for (auto [l, w] : dl[i]) cost[i] += w;
+                q.insert({cost[i], rank[i]});
+            }
+        std::vector<char> in(leaf_id.size(), 0);
+        parts.emplace_back();
+        int next = keyed[q.begin()->second].second;
+        while (true) {
+            q.erase({cost[next], rank[next]});
+            placed[next] = 1;
+            --left;
+            parts.back().push_back(next);
+            for (auto [l, w] : dl[next]) {
+                if (in[l]) continue;
+                in[l] = 1;
+                for (int j : users[l])
+                    if (!placed[j]) {
+                        q.erase({cost[j], rank[j]});
+                        cost[j] -= w;
+                        q.insert({cost[j], rank[j]});
+                    }
+            }
+            if ((int)parts.back().size() >= part_size || q.empty()) break;
+            next = keyed[q.begin()->second].second;
+        }
     }
     return parts;
 }
 
 int default_part_size(int order, int n_diagrams, int n_roots) {
-    // Measured on MI355X per 2^22 samples x 32 k, with the external momentum on a path of chords (so a part's
-    // k-independent code dominates and runs once per chunk of momenta): order 5 in one part 3.1 ms, in 3
-    // parts 5.0 ms, in 5 parts 6.1 ms; order 6 in parts of 400, 800, 1600, 3200 diagrams 65.8, 43.7, 37.1,
-    // 40.3 ms (with d/dk at one momentum 74.1, 49.0, 40.2, 43.5 ms; run-time compilation 15, 17, 45, 90 s).
-    // Bigger parts evaluate fewer leaves twice; past 1600 diagrams their register pressure costs more.  More
-    // roots (derivative or Taylor coefficients) multiply a part's live values: parts shrink as R^1.5.
-    const double base = order >= 6 ? 1600.0 : 2400.0;
+    // Measured on MI355X with the external momentum on a path of chords (a part's k-independent code dominates
+    // and runs once per chunk of momenta) and leaf-grown parts.  Per 2^22 samples x 32 k: order 5 in one part
+    // 3.1 ms, in 3 parts 5.0 ms; order 6 in parts of 1600, 2400, 3200 diagrams 32.4, 31.7, 33.6 ms (sorted, not
+    // grown: 37.1 ms at 1600).  The order-6 d/dk graph at k_F with 3 lambda groups and 33 k, per 2^26 samples:
+    // 1697, 1603, 1684 ms (sorted, not grown: 1881 ms at 1600).  Bigger parts evaluate fewer leaves twice; past
+    // ~2400 diagrams their register pressure costs more.  More roots (derivative or Taylor coefficients) multiply
+    // a part's live values: parts shrink as R^1.5.
+    const double base = 2400.0;
     const int per = std::max(16, (int)(base / std::pow(std::max(1.0, n_roots / 2.0), 1.5)));
     return n_diagrams <= per ? 0 : per;
 }

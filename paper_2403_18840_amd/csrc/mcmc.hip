@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accept_kernel(McmcArgs a) {
 }
 
 // block (j B + b, s): chains [c0 + j chunk, ...) of batch b = [b n / B, (b + 1) n / B); v = f_s / pi
-// (s < S) or q / pi (s = S).  partial[j B + b] is row j, column block b of [blocks][B][S + 1][2].
+// (s < S) or q / pi (s = S).  partial[j B + b] is row j, column block b of [blocks][B][S + 1][2]; each block adds
+// its step's sums to its own running totals there (steps in order), folded across blocks only when read.
 __global__ void __launch_bounds__(256) dmc_mcmc_accumulate_kernel(McmcAccArgs a) {
     const int s = blockIdx.y;
     const int b = (int)(blockIdx.x % (unsigned)a.n_batches), j = (int)(blockIdx.x / (unsigned)a.n_batches);
@@ -126,8 +127,8 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accumulate_kernel(McmcAccArgs a)
     }
     if (threadIdx.x == 0) {
         const int64_t o = ((int64_t)blockIdx.x * (a.S + 1) + s) * 2;
-        a.partial[o] = r1[0];
-        a.partial[o + 1] = r2[0];
+        a.partial[o] += r1[0];
+        a.partial[o + 1] += r2[0];
     }
 }
 
