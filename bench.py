@@ -217,22 +217,32 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     X = torch.empty((D, N), dtype=torch.float32, device=dev)
     J = torch.empty(N, dtype=torch.float32, device=dev)
 
+    imp = torch.empty(N, dtype=torch.float32, device=dev)
+
     def run(draw):
-        means, sig, nonfin = [], [], 0
+        means, sig, nonfin, ess, wmax = [], [], 0, [], []
         for b in range(batches):
             acc = dmc.Accumulator(groups, len(ks), g.n_roots)
             draw(b)
-            dmc.eval_batch(g, inst, ks, X, J, acc)
+            dmc.eval_batch(g, inst, ks, X, J, acc, imp_out=imp)
             dmc.accumulate(acc)
             m, e, _, nf = acc.estimate(len(inst))
             means.append(m[i_fom, 0, jf].real)
             sig.append(e[i_fom, 0, jf].real)
             nonfin += nf
+            # weight diagnostics of the batch from its importances (sum over k, Re/Im of |f| J): the effective
+            # sample size fraction (sum w)^2 / (N sum w^2) and the largest weight over the mean
+            w = imp.double()
+            s1, s2 = float(w.sum()), float((w * w).sum())
+            ess.append(s1 * s1 / (N * s2) if s2 > 0 else 0.0)
+            wmax.append(float(w.max()) * N / s1 if s1 > 0 else 0.0)
         means = np.array(means)
         mad = 1.4826 * float(np.median(np.abs(means - np.median(means))))
         return {"re": float(means.mean()), "sigma": float(means.std(ddof=1) / math.sqrt(batches)),
                 "sigma_mad": mad / math.sqrt(batches),
-                "sigma_in_run": float(math.sqrt(np.mean(np.square(sig)) / batches)), "nonfinite": int(nonfin)}
+                "sigma_in_run": float(math.sqrt(np.mean(np.square(sig)) / batches)), "nonfinite": int(nonfin),
+                "ess_fraction_median": float(np.median(ess)), "max_weight_over_mean_median": float(np.median(wmax)),
+                "max_weight_over_mean_max": float(np.max(wmax))}
 
     vg, t_v = timed(lambda: run(lambda b: s.sample(seed + 1, b * N, X, J)))
     f = _make_flow(D, kind)

@@ -22,6 +22,35 @@ def _flow(D, scale=0.03, seed=1):
     return f, m, th.astype(np.float64)
 
 
+def _maps_on_gpu_points(xg, jg, ug, lqg, g32, n, a_f=1.0, a_u=0.0):
+    """Every sample, with no selection: the grid and physical maps and the weight applied to the kernel's own u'
+    and log q (read back), against the oracle's maps in FP64 after the same FP32 bin decision.  The network is
+    compared separately (u' and log q against the oracle flow); this isolates the maps, in the coordinates where
+    FP32 is well conditioned: the radius |q| = R y_r (relative), cos(theta) = q_z / |q| = 2 y_c - 1 and
+    phi = 2 pi y_phi (absolute; phi only where |q| sin(theta) is not tiny), the times beta y_t, and the weight
+    (relative, a few FP32 roundings per dimension)."""
+    y, JV, _ = osp.vegas_map_float(ug, g32)
+    _, Jp = ig.physical_map(y, n, BETA, 6.0)
+    for i in range(n):
+        q = xg[:, 3 * i: 3 * i + 3]
+        r = np.linalg.norm(q, axis=1)
+        assert np.all(np.abs(r - 6.0 * y[:, 3 * i]) <= 2e-6 * (6.0 * y[:, 3 * i]) + 1e-6), i
+        ok = r > 1e-5
+        c = q[ok, 2] / r[ok]
+        assert np.all(np.abs(c - (2.0 * y[ok, 3 * i + 1] - 1.0)) <= 4e-6), i
+        rho = np.hypot(q[:, 0], q[:, 1])
+        okp = rho > 1e-4
+        dphi = np.angle(np.exp(1j * (np.arctan2(q[okp, 1], q[okp, 0]) - 2 * np.pi * y[okp, 3 * i + 2])))
+        assert np.all(np.abs(dphi) <= 4e-6 + 2e-7 / rho[okp]), i
+    for j in range(n - 1):
+        assert np.all(np.abs(xg[:, 3 * n + j] - BETA * y[:, 3 * n + j]) <= 4e-7 * BETA + 2e-6), j
+    ref = ofl.mixture_weight(JV * Jp, lqg, a_f, a_u, JV) if a_f < 1.0 else JV * Jp * np.exp(-lqg)
+    # a few roundings per dimension in the Jacobians, and the hardware exponential of log q (error ~ |log q| u)
+    D = xg.shape[1]
+    u = 2.0 ** -24
+    assert np.all(np.abs(np.log(jg) - np.log(ref)) <= 4 * D * u + 4 * u * np.abs(lqg) + 1e-6)
+
+
 @pytest.mark.parametrize("D", [3, 7, 15, 23])
 def test_log_density_matches_oracle(D):
     torch, dev = torch_dev()
@@ -75,6 +104,7 @@ def test_flow_samples_match_oracle(D, n):
     assert np.median(rx) < 5e-4 and np.quantile(rx, 0.99) < 5e-2, (np.median(rx), np.quantile(rx, 0.99))
     lerr = np.abs(np.log(jg) - np.log(JV * Jp * np.exp(-lq)))[same]
     assert np.median(lerr) < 2e-4 and lerr.max() < 2e-2, (np.median(lerr), lerr.max())
+    _maps_on_gpu_points(xg, jg, ug, lqg, grid.astype(np.float32).astype(np.float64), n)
     # forward density = inverse density on the GPU
     lq2 = torch.empty(N, dtype=torch.float32, device=dev)
     f.log_density(Uo, lq2)
@@ -210,6 +240,7 @@ def test_mixture_samples_match_oracle(alpha, N):
     assert np.max(np.abs(ug[n_g:] - up)) < 2e-3
     assert np.median(np.abs(lqg[n_g:] - lq)) < 1e-4 and np.max(np.abs(lqg[n_g:] - lq)) < 5e-3
     _flow_share_matches(xg[n_g:], jg[n_g:], ug[n_g:], up, lq, g32, n, alpha, 0.0)
+    _maps_on_gpu_points(xg[n_g:], jg[n_g:], ug[n_g:], lqg[n_g:], g32, n, alpha, 0.0)
     # bounded weights: never above the grid's own weight / (1 - alpha)
     assert np.all(jg[:n_g] <= jp_g * jv_g / (1 - alpha) * (1 + 1e-4))
 
