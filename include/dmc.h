@@ -339,6 +339,23 @@ dmc_status dmc_chains_read(dmc_chains* c, double* sums, int64_t* n_measured, int
  * chains sample |f| itself; 0 for a chain without a valid state).  Feed them to dmc_flow_train_step.
  * DMC_E_STATE before the first step. */
 dmc_status dmc_chains_training_data(dmc_chains* c, float* u, int64_t ld, float* w, void* stream);
+/* The chains' whole independence-sampler loop in the library (Sec. IV: Metropolis–Hastings with independent
+ * proposals, eq. target_distr_nf_mcmc_qft_revised), thermal + steps steps with no host round trip: each step
+ * draws n proposals from the frozen grid sampler s (dmc_sample) or, with a flow, from its mixture (dmc_flow_sample
+ * with mix_flow, mix_uniform), evaluates them (dmc_eval_batch into acc, folded by dmc_accumulate: the
+ * importance-sampling estimate of the same proposals, and f, device float[S][n], the chains' observables) and takes
+ * one dmc_chains_step.  Step t (from 0 in this call) draws Philox counters first + t n of key seed, uses the
+ * acceptance key accept_seed and the rotation offset splitmix64(offset_key, t) mod n; steps t < thermal are not
+ * measured, and the sums and acceptance count are reset after them.  x (device float[D][ld], ld >= n), jac
+ * (device float[n]), f and u (device float[D][ld], needed with a flow when the chains keep coordinates, ignored
+ * otherwise) are the caller's buffers.  DMC_E_INVALID for null pointers, negative counts, alpha outside [0, 1],
+ * an accumulator or k list whose shape differs from the chains', or chains that keep coordinates without a flow;
+ * errors of the calls it makes are passed on (the chains keep the steps already taken). */
+dmc_status dmc_chains_run(dmc_chains* c, dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext,
+                          int32_t n_k, dmc_sampler* s, dmc_flow* flow, double mix_flow, double mix_uniform,
+                          uint64_t seed, uint64_t first, int64_t thermal, int64_t steps, double alpha,
+                          uint64_t accept_seed, uint64_t offset_key, float* x, int64_t ld, float* jac, float* f,
+                          float* u, dmc_accum* acc, void* stream);
 /* Zero the sums and the accepted count (the chain states are kept). */
 dmc_status dmc_chains_reset(dmc_chains* c, void* stream);
 void dmc_chains_destroy(dmc_chains* c);

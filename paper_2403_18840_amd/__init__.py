@@ -34,7 +34,7 @@ ABI_SYMBOLS = [
     "dmc_chains_destroy",
     "dmc_chains_training_data",
     "dmc_effective_mass", "dmc_probe", "dmc_combine_iterations", "dmc_chains_ratio", "dmc_mass_table",
-    "dmc_checkpoint_save", "dmc_checkpoint_load", "dmc_proposal_select",
+    "dmc_checkpoint_save", "dmc_checkpoint_load", "dmc_proposal_select", "dmc_chains_run",
 ]
 
 
@@ -133,6 +133,8 @@ def lib():
         "dmc_vegas_refine": (I32, [I32, I32, P, P, F64, P]),
         "dmc_chains_training_data": (I32, [P, P, I64, P, P]),
         "dmc_chains_read": (I32, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
+        "dmc_chains_run": (I32, [P, P, P, I32, P, I32, P, P, F64, F64, U64, U64, I64, I64, F64, U64, U64, P, I64, P, P,
+                                 P, P, P]),
         "dmc_chains_reset": (I32, [P, P]),
         "dmc_chains_destroy": (None, [P]),
         "dmc_effective_mass": (I32, [I32, F64, I32, P, P, P, P, P, P, P, P, P]),
@@ -740,9 +742,26 @@ def mcmc_integrate(graph: Graph, inst, k_ext, sampler: Sampler, n_chains: int, s
         JFS = torch.empty(n_chains, dtype=torch.float32, device=dev)
         WS = torch.empty(n_chains, dtype=torch.float32, device=dev)
         acc_walk = Accumulator(G, K, R)  # walk proposals are no draws from q: kept out of the IS estimate
-    offsets = np.random.default_rng([seed, 0x0FF5E7]).integers(0, n_chains, size=thermal + steps)
-    half = None
-    for t in range(thermal + steps):
+    if not walk:
+        # the whole loop in the library (dmc_chains_run), in two halves for the trend check
+        arr = instances(inst)
+        kk = np.ascontiguousarray(ks, dtype=np.float32)
+        h1 = steps // 2
+
+        def run(first, n_thermal, n_steps, key):
+            _check(lib().dmc_chains_run(ch.h, graph.h, arr, len(arr), kk.ctypes.data_as(P), len(kk), sampler.h,
+                                        flow.h if flow is not None else None, flow_alpha, flow_uniform, seed, first,
+                                        n_thermal, n_steps, alpha, seed + 0x5EED, key, _dptr(X, "float32", "x"),
+                                        X.shape[1], _dptr(J, "float32", "jac"), _dptr(F, "float32", "f"), None,
+                                        acc.h, _stream(None)))
+        run(0, thermal, h1, seed ^ 0x0FF5E7)
+        half = ch.read()[0]
+        run((thermal + h1) * n_chains, 0, steps - h1, (seed ^ 0x0FF5E7) + 0x100000000)
+        offsets = ()
+    else:
+        offsets = np.random.default_rng([seed, 0x0FF5E7]).integers(0, n_chains, size=thermal + steps)
+        half = None
+    for t in range(len(offsets)):
         if walk and t > 0 and t % walk_every == walk_every - 1:
             ch.training_data(US, WS)
             flow.walk(sampler, US, walk_sigma, seed + 0x3A1C, t * n_chains, X, J, JF, U, JFS, alpha=flow_alpha,

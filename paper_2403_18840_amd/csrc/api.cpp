@@ -1675,6 +1675,49 @@ dmc_status dmc_chains_reset(dmc_chains* c, void* stream) {
     return DMC_OK;
 }
 
+// the rotation offset of step t: splitmix64 (Steele, Lea and Flood 2014) of the key and step, reduced to [0, n)
+static int64_t chain_offset(uint64_t key, uint64_t t, int64_t n) {
+    uint64_t z = key + (t + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (int64_t)(((unsigned __int128)z * (uint64_t)n) >> 64);
+}
+
+dmc_status dmc_chains_run(dmc_chains* c, dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext,
+                          int32_t n_k, dmc_sampler* s, dmc_flow* flow, double mix_flow, double mix_uniform,
+                          uint64_t seed, uint64_t first, int64_t thermal, int64_t steps, double alpha,
+                          uint64_t accept_seed, uint64_t offset_key, float* x, int64_t ld, float* jac, float* f,
+                          float* u, dmc_accum* acc, void* stream) {
+    if (!c || !g || !inst || !k_ext || !s || !x || !jac || !f || !acc) return fail(DMC_E_INVALID, "null argument");
+    if (thermal < 0 || steps < 0) return fail(DMC_E_INVALID, "thermal and steps must be >= 0");
+    if (ld < c->n) return fail(DMC_E_INVALID, "ld must be at least the chain count");
+    if (c->D > 0 && (!flow || !u)) return fail(DMC_E_INVALID, "chains that keep coordinates need a flow and u");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(DMC_E_INVALID, "alpha must be in [0, 1]");
+    if (acc->n_groups != c->n_groups || acc->n_k != c->n_k || acc->n_roots != c->n_roots || n_k != c->n_k)
+        return fail(DMC_E_INVALID, "the accumulator and the chains must have one observable shape");
+    const int64_t n = c->n;
+    for (int64_t t = 0; t < thermal + steps; ++t) {
+        const uint64_t idx = first + (uint64_t)t * (uint64_t)n;
+        dmc_status st = flow ? dmc_flow_sample(flow, s, seed, idx, n, x, ld, jac, c->D > 0 ? u : nullptr, nullptr,
+                                               mix_flow, mix_uniform, stream)
+                             : dmc_sample(s, seed, idx, n, x, ld, jac, stream);
+        if (st != DMC_OK) return st;
+        st = dmc_eval_batch(g, inst, n_inst, k_ext, n_k, x, ld, jac, n, acc, f, nullptr, stream);
+        if (st != DMC_OK) return st;
+        st = dmc_accumulate(acc, nullptr, nullptr, stream);
+        if (st != DMC_OK) return st;
+        st = chains_step(c, f, n, jac, nullptr, nullptr, c->D > 0 ? u : nullptr, ld, chain_offset(offset_key, t, n),
+                         alpha, accept_seed, t >= thermal, stream);
+        if (st != DMC_OK) return st;
+        if (thermal > 0 && t + 1 == thermal) {
+            st = dmc_chains_reset(c, stream);
+            if (st != DMC_OK) return st;
+        }
+    }
+    return DMC_OK;
+}
+
 void dmc_chains_destroy(dmc_chains* c) {
     if (!c) return;
     (void)hipFree(c->f_state);
