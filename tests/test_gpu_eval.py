@@ -298,3 +298,51 @@ def test_order1_estimate_matches_fock_closed_form():
         z = (m[0, 0, j].real - ref) / e[0, 0, j].real
         assert abs(z) < 3.0, f"k={k}: z={z}"
         assert m[0, 0, j].imag == 0.0
+
+
+def test_limits_and_degenerate_batches():
+    """The largest observable shape one launch takes (DMC_MAX_K = 64 momenta, DMC_MAX_GROUPS = 8 lambda groups,
+    order 2: 2048 staged slots) per sample against the oracle, on a ragged batch (257 samples: one full tile and
+    one sample); a batch of one sample; and the refused shapes (no samples, ld < n, no momenta, 65 momenta,
+    9 groups), which must leave the accumulator untouched."""
+    torch, dev = torch_dev()
+    n, N = 2, 257
+    x = synth.loop_points(n, N, seed=41)
+    ks = synth.k_grid(64)
+    lams = [0.25 * (i + 1) for i in range(8)]
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n)
+    f, acc, _ = gpu_integrand(g, x, ks, [(BETA, MU, lam, gamma) for lam in lams])
+    x64 = x.astype(np.float64)
+    for gi, lam in enumerate(lams):
+        for j in range(0, 64, 7):
+            k = float(np.float32(ks[j]))
+            ref = ig.integrand(x64, n, k, BETA, MU, lam, gamma, diagrams=oracle_diagrams(n))
+            tol, _ = ig.fp32_tolerance(x64, n, k, BETA, MU, lam, gamma, diagrams=oracle_diagrams(n))
+            assert np.all(np.abs(f[gi, 0, j] - ref) <= tol), (lam, k)
+    assert acc.read()[1] == N
+    # one sample
+    f1, acc1, _ = gpu_integrand(g, x[:1], ks[:3], [(BETA, MU, LAM, gamma)])
+    for j in range(3):
+        k = float(np.float32(ks[j]))
+        ref = ig.integrand(x64[:1], n, k, BETA, MU, LAM, gamma, diagrams=oracle_diagrams(n))
+        tol, _ = ig.fp32_tolerance(x64[:1], n, k, BETA, MU, LAM, gamma, diagrams=oracle_diagrams(n))
+        assert np.all(np.abs(f1[0, 0, j] - ref) <= tol)
+    m, e, ns, nf = acc1.estimate(1)
+    assert ns == 1 and nf == 0 and np.all(e == 0)
+    # refused shapes
+    X = to_soa(x)
+    J = torch.ones(N, dtype=torch.float32, device=dev)
+    a = dmc.Accumulator(1, 4, 1)
+    inst = [(BETA, MU, LAM, gamma)]
+    bad = [dict(x=X, jac=J[:0], ks=ks[:4], inst=inst),                                   # no samples
+           dict(x=X[:, :100].contiguous(), jac=J, ks=ks[:4], inst=inst),                 # ld < n
+           dict(x=X, jac=J, ks=ks[:0], inst=inst),                                       # no momenta
+           dict(x=X, jac=J, ks=np.linspace(0, 3, 65), inst=inst),                        # 65 momenta
+           dict(x=X, jac=J, ks=ks[:4], inst=[(BETA, MU, 0.1 * (i + 1), gamma) for i in range(9)])]  # 9 groups
+    for b in bad:
+        with pytest.raises(dmc.DmcError) as err:
+            dmc.eval_batch(g, b["inst"], b["ks"], b["x"], b["jac"], a)
+        assert err.value.status == -1
+    torch.cuda.synchronize()
+    assert a.read()[1] == 0
