@@ -176,7 +176,8 @@ void dmc_sampler_destroy(dmc_sampler* s);
  * partial sums into `acc` (folded by dmc_accumulate).  Instances: host array of n_inst; all must
  * share beta and mu.
  * f_out (nullable): device float[n_groups][n_roots][n_k][2][n]: the integrand f without J.
- * imp_out (nullable): device float[n]: sum over groups, k, Re/Im of |w|, for VEGAS adaptation. */
+ * imp_out (nullable): device float[n]: sum over groups, k, Re/Im and the graph's leading importance roots
+ * (dmc_graph_set_importance; the value root alone by default) of |w|, for VEGAS adaptation and flow training. */
 dmc_status dmc_eval_batch(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext, int32_t n_k,
                           const float* x, int64_t ld, const float* jac, int64_t n, dmc_accum* acc, float* f_out,
                           float* imp_out, void* stream);
@@ -205,6 +206,12 @@ dmc_status dmc_accumulate(dmc_accum* acc, dmc_sampler* sampler, const float* imp
 dmc_status dmc_eval_accumulate_noalloc(dmc_graph* g, const dmc_instance* inst, int32_t n_inst, const float* k_ext,
                                        int32_t n_k, const float* x, int64_t ld, const float* jac, int64_t n,
                                        dmc_accum* acc, float* f_out, float* imp_out, void* stream);
+
+/* The roots whose weights make up the importance that dmc_eval_batch writes to imp_out: the first n_roots
+ * (1..the graph's roots) in root order; 1 (the value alone) after dmc_compile_graph.  A proposal adapted to
+ * the importance concentrates where those roots' integrands are large: the separable VEGAS grid does best on
+ * the value alone, a learned flow can follow the derivative roots too.  DMC_E_INVALID outside that range. */
+dmc_status dmc_graph_set_importance(dmc_graph* g, int32_t n_roots);
 
 /* Mean and standard error of the mean per instance, root, k and Re/Im:
  * mean, stderr_: host double[n_inst][n_roots][n_k][2].  n_nonfinite: host (nullable).  Uses the

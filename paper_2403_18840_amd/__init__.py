@@ -22,7 +22,8 @@ SAMPLER_UNIFORM, SAMPLER_VEGAS = 0, 1
 
 # every symbol include/dmc.h declares
 ABI_SYMBOLS = [
-    "dmc_last_error", "dmc_version", "dmc_compile_graph", "dmc_graph_query", "dmc_graph_export_diagrams",
+    "dmc_last_error", "dmc_version", "dmc_compile_graph", "dmc_graph_query", "dmc_graph_set_importance",
+    "dmc_graph_export_diagrams",
     "dmc_graph_source", "dmc_graph_root_orders", "dmc_graph_destroy", "dmc_accum_create", "dmc_accum_reset", "dmc_accum_destroy",
     "dmc_sampler_create", "dmc_sample", "dmc_sampler_get_grid", "dmc_sampler_set_grid", "dmc_sampler_refine",
     "dmc_vegas_refine",
@@ -91,6 +92,7 @@ def lib():
         "dmc_version": (ctypes.c_char_p, []),
         "dmc_compile_graph": (I32, [ctypes.POINTER(GraphSpec), ctypes.POINTER(P)]),
         "dmc_graph_query": (I32, [P, ctypes.POINTER(GraphInfo)]),
+        "dmc_graph_set_importance": (I32, [P, I32]),
         "dmc_graph_export_diagrams": (I32, [P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
         "dmc_graph_source": (I32, [P, I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
         "dmc_graph_destroy": (None, [P]),
@@ -198,12 +200,18 @@ class Graph:
         self.deriv_mask = deriv_mask
         self.taylor_order = taylor_order
         self.n_roots = self.info().n_roots
+        self.importance_roots = 1
 
     def root_orders(self):
         """[(m, l, e)] per root: d^m/dmu^m d^l/dlambda^l (d/dk)^e of the self-energy."""
         buf = (I32 * (3 * self.n_roots))()
         _check(lib().dmc_graph_root_orders(self.h, buf, 3 * self.n_roots))
         return [tuple(buf[3 * r: 3 * r + 3]) for r in range(self.n_roots)]
+
+    def set_importance(self, n_roots: int):
+        """dmc_graph_set_importance: the leading roots whose |w| eval_batch sums into imp_out (1: the value)."""
+        _check(lib().dmc_graph_set_importance(self.h, int(n_roots)))
+        self.importance_roots = int(n_roots)
 
     def info(self) -> GraphInfo:
         gi = GraphInfo()
@@ -419,7 +427,8 @@ def train_flow(graph: Graph, inst, k_ext, sampler: Sampler, flow: "Flow", epochs
     integrand by the weighted forward KL of Appendix A, with Adam on the device.
 
     Every step draws `minibatch` new points, evaluates the graph on them (the training weight of a
-    point is its importance value, sum |f| J over the proposal density) and takes one step.  The
+    point is its importance value, sum |f| J over the graph's importance roots (the value alone unless
+    Graph.set_importance adds derivative roots) over the proposal density) and takes one step.  The
     first epoch draws from the grid alone; later epochs from the mixture alpha q_flow + uniform
     q_uniform + (rest) q_grid of the current flow, so the training points follow the flow as it
     sharpens.  k_ext selects the external momenta whose |Sigma| integrand the flow learns (the figure

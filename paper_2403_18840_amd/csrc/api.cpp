@@ -86,7 +86,7 @@ struct EvalArgs {
     unsigned int* nonfinite;
     float* f_out;
     float* imp_out;
-    int n_k, s_total, kc, pad1;
+    int n_k, s_total, kc, imp_roots;
     float mu, beta, bl, blmu, inv2beta, pad2;
     float lam[8];
     float scale[8];
@@ -99,6 +99,7 @@ struct dmc_graph {
     dmc::Compiled c;
     std::map<std::pair<int, int>, JitKernel> jit;  // (device, n_groups)
     std::string exported;
+    int imp_roots = 1;  // leading roots whose |w| make up the importance (imp_out)
 };
 
 struct dmc_accum {
@@ -148,6 +149,13 @@ dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
         return fail(DMC_E_NOMEM, "host allocation failed");
     }
     *out = g.release();
+    return DMC_OK;
+}
+
+dmc_status dmc_graph_set_importance(dmc_graph* g, int32_t n_roots) {
+    if (!g) return fail(DMC_E_INVALID, "null graph");
+    if (n_roots < 1 || n_roots > g->c.n_roots) return fail(DMC_E_INVALID, "need 1 <= n_roots <= the graph's roots");
+    g->imp_roots = n_roots;
     return DMC_OK;
 }
 
@@ -498,6 +506,7 @@ static dmc_status eval_launch(dmc_graph* g, const dmc_instance* inst, int32_t n_
     a.n_k = n_k;
     a.s_total = acc->s_total;
     a.kc = kc;
+    a.imp_roots = g->imp_roots;
     a.mu = (float)mu;
     a.beta = (float)beta;
     a.bl = (float)(beta * M_LOG2E);

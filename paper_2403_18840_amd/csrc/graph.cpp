@@ -1510,7 +1510,7 @@ std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats) 
 struct EvalArgs {
     const float* x; long long ld; const float* jac; long long n;
     double* partial; unsigned int* nonfinite; float* f_out; float* imp_out;
-    int n_k; int s_total; int kc; int pad1;
+    int n_k; int s_total; int kc; int imp_roots;
     float mu, beta, bl, blmu, inv2beta, pad2;
     float lam[8]; float scale[8];
     float k[64];
@@ -1653,7 +1653,10 @@ struct EvalArgs {
             }
             o << pad << "{\n";
             o << pad << "    const float w = " << (comp ? "FI" : "FR") << g << "_" << ro << ";  // f J\n";
-            o << pad << "    " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
+            if (ro == 0)
+                o << pad << "    impc += __builtin_fabsf(w);\n";
+            else
+                o << pad << "    chk += w; if (a.imp_roots > " << ro << ") impc += __builtin_fabsf(w);\n";
             o << pad << "    stage[(kq * SPK + " << slot << ") * 64 + lane] = w;\n";
             o << pad << "    " << fo << pc[0].fplain[(g * NR + ro) * 2 + comp] << ";\n";
             o << pad << "}\n";
@@ -1709,7 +1712,10 @@ struct EvalArgs {
                 s << "                    " << (ro ? "if (kq < ml) {" : "{") << "\n";
                 s << "                        const float f = stage[(row + " << slot << ") * 64 + lane];\n";
                 s << "                        const float w = f * J;\n";
-                s << "                        " << (ro == 0 ? "impc += __builtin_fabsf(w);" : "chk += w;") << "\n";
+                if (ro == 0)
+                    s << "                        impc += __builtin_fabsf(w);\n";
+                else
+                    s << "                        chk += w; if (a.imp_roots > " << ro << ") impc += __builtin_fabsf(w);\n";
                 s << "                        stage[(row + " << slot << ") * 64 + lane] = w;\n";
                 s << "                        " << fo << "f;\n";
                 s << "                    }" << (ro ? " else {\n                        " + fo + "0.0f;\n                    }" : "")
@@ -1726,7 +1732,7 @@ struct EvalArgs {
                             stage[sl * 64 + lane] = 0.0f;
                         }
                         const int slot = sl < ml * SPK1 ? sl % SPK1 : (sl - ml * SPK1) % 2;
-                        if (slot < 2) impc += __builtin_fabsf(v);
+                        if (slot < 2 * a.imp_roots) impc += __builtin_fabsf(v);
                     }
                 }
                 imp += impc;
@@ -1767,7 +1773,7 @@ struct EvalArgs {
     // a weight that is not finite makes the chunk's sums non-finite: only then (rarely, per lane) are this
     // lane's staged weights scanned, each non-finite one zeroed and counted (valid samples only), and the
     // chunk's importance recomputed
-    const std::string imp_slot = real_only ? "(j % NROOT) == 0" : "((j >> 1) % NROOT) == 0";
+    const std::string imp_slot = real_only ? "(j % NROOT) < a.imp_roots" : "((j >> 1) % NROOT) < a.imp_roots";
     s << R"K(            if (!__builtin_isfinite(impc + chk)) {
                 impc = 0.0f;
                 for (int sl = 0; sl < SCH; ++sl) {

@@ -346,3 +346,27 @@ def test_limits_and_degenerate_batches():
         assert err.value.status == -1
     torch.cuda.synchronize()
     assert a.read()[1] == 0
+
+
+@pytest.mark.parametrize("part,kd", [(0, 0), (1, 2)])
+def test_importance_roots_setting(part, kd):
+    """imp_out sums |f J| over the graph's leading importance roots: the value alone by default, every root after
+    set_importance(R); in one part and in parts with derivative roots at the first kd momenta only."""
+    torch, dev = torch_dev()
+    n, N = 2, 300
+    x = synth.loop_points(n, N, seed=17)
+    ks = synth.k_grid(4)
+    g = dmc.Graph(n, deriv_mask=dmc.D_MU | dmc.D_LAMBDA | dmc.D_K, part_size=part, deriv_k=kd)
+    assert (g.info().n_parts > 1) == (part > 0)
+    inst = [(BETA, MU, LAM, ph.coupling(1.0))]
+    R = g.n_roots
+    for nr in (1, R, 2):
+        g.set_importance(nr)
+        f, _, imp = gpu_integrand(g, x, ks, inst)
+        w = np.abs(f[0, :nr].real) + np.abs(f[0, :nr].imag)     # [roots][k][N], J = 1
+        ref = w.sum(axis=(0, 1))
+        assert np.allclose(imp, ref, rtol=4 * R * len(ks) * 2.0 ** -24, atol=2.0 ** -126), nr
+    with pytest.raises(dmc.DmcError):
+        g.set_importance(R + 1)
+    with pytest.raises(dmc.DmcError):
+        g.set_importance(0)
