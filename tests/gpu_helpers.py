@@ -37,3 +37,17 @@ def gpu_integrand(graph, x_np, ks, inst, jac=None):
     torch.cuda.synchronize()
     fr = f.view(G, R, K, 2, N).cpu().numpy().astype(np.float64)
     return fr[:, :, :, 0, :] + 1j * fr[:, :, :, 1, :], acc, imp.cpu().numpy()
+
+
+def parity_points(n, N, seed):
+    """Per-sample parity inputs [N, D] float32.  Orders 1-3: the default draw.  Orders >= 4: half the rows
+    from the default draw (with its edge cases), half with every loop momentum within 0.05 of the Fermi
+    surface.  With momenta anywhere in the ball, the product of many propagators at beta = 25 puts most
+    order-4..6 samples far below the 1e-30 floor of the per-sample rule; on the shell the integrand is
+    1e-15..1e-10 at order 6, so the rule's relative part is what decides."""
+    import synth
+    if n <= 3:
+        return synth.loop_points(n, N, seed=seed)
+    h = N // 2
+    return np.concatenate([synth.loop_points(n, h, seed=seed),
+                           synth.loop_points(n, N - h, seed=seed + 7919, fermi_fraction=1.0, special=False)])

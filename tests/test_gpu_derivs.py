@@ -9,7 +9,7 @@ import synth
 from oracle import integrand as ig
 from oracle import physics as ph
 
-from gpu_helpers import BETA, LAM, MU, gpu_integrand, to_soa, torch_dev
+from gpu_helpers import BETA, LAM, MU, gpu_integrand, parity_points, to_soa, torch_dev
 from golden_diagrams import oracle_diagrams
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +21,7 @@ def test_derivative_roots_per_sample(n, N, K):
     """Each derivative against the oracle's dual numbers, judged against the size of the
     derivative's terms before cancellation (the condition-aware reading of 1e-5 relative).
     Order 5 runs a kernel in parts (3 parts of 848 diagrams)."""
-    x = synth.loop_points(n, N, seed=300 + n)
+    x = parity_points(n, N, seed=300 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
     f, acc, _ = gpu_integrand(dmc.Graph(n, ALL), x, ks, [(BETA, MU, LAM, gamma)])
@@ -96,35 +96,41 @@ def test_autograd_function_backward_and_finite_differences():
         assert abs(got - fd) <= 5e-3 * max(abs(fd), 1e-6), (got, fd)
 
 
-def test_k_derivative_order6_per_sample():
-    """d Sigma / dk at order 6 (31130 diagrams; a kernel of 20 parts, about a minute of run-time
-    compilation) against the oracle's dual numbers at k near k_F."""
-    n, N = 6, 24
-    x = synth.loop_points(n, N, seed=306)
+def test_all_derivatives_order6_per_sample():
+    """d/dmu, d/dlambda and d/dk at order 6 (31130 diagrams, four roots: a kernel of many small parts) per
+    sample against the oracle's C evaluator (FP64 dual numbers diagram by diagram, pinned to the numpy
+    dual-number oracle at orders 1-5), with the rule of the value and the absolute-mode term scales."""
+    from oracle import cevaluate as ce
+    n, N = 6, 32
+    x = parity_points(n, N, seed=306)
     ks = np.array([0.0, 1.0], dtype=np.float32)
     gamma = ph.coupling(1.0)
-    f, acc, _ = gpu_integrand(dmc.Graph(n, dmc.D_K), x, ks, [(BETA, MU, LAM, gamma)])
-    assert f.shape[1] == 2
+    g = dmc.Graph(n, ALL)
+    assert g.n_roots == 4 and g.info().n_parts > 1
+    f, acc, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
     x64 = x.astype(np.float64)
     dgs = oracle_diagrams(n)
+    tab = ce.table(dgs, n)
+    worst = [0.0] * 4
     for j, k in enumerate(ks):
-        kk = float(np.float32(k))
-        vals = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
-        scales = ig.diagram_values_dual(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs, absolute=True)
-        C = ig.exponent_condition(x64, n, kk, BETA, MU, diagrams=dgs)
-        for r, src in [(0, 0), (1, 3)]:
-            ref = vals[src].sum(axis=0)
-            scale = scales[src].real.sum(axis=0)
+        o = ce.evaluate(x64, n, float(np.float32(k)), BETA, MU, LAM, gamma, dgs, derivs=True, tab=tab)
+        for r in range(4):
+            ref = o[:, r, 0] + 1j * o[:, r, 1]
+            scale = o[:, r, 2]
+            tol = 1e-5 * scale + 2 * ig.U32 * o[:, r, 3] + 1e-30
             err = np.abs(f[0, r, j] - ref)
-            tol = 1e-5 * scale + 2 * ig.U32 * (scales[src].real * C).sum(axis=0) + 1e-30
             assert np.all(err <= tol), f"root {r} k={k}: worst {np.max(err / (scale + 1e-300))}"
+            live = scale > 1e-30
+            if np.any(live):
+                worst[r] = max(worst[r], float(np.max(err[live] / scale[live])))
+    print("order 6 worst |err| / scale per root (value, dmu, dlambda, dk):", ["%.2e" % w for w in worst])
 
 
 @pytest.mark.parametrize("n,mask,part_size,N,K", [(2, ALL, 0, 300, 5), (4, dmc.D_K, 40, 200, 6), (3, ALL, 0, 260, 3)])
 def test_derivative_roots_at_first_momenta_only(n, mask, part_size, N, K):
     """spec.deriv_k = 2: derivative roots at the first two external momenta (per sample against the oracle),
     zeros at the others; the value at every momentum.  Single-part kernels and a kernel in parts."""
-    x = synth.loop_points(n, N, seed=320 + n)
+    x = parity_points(n, N, seed=320 + n)
     ks = synth.k_grid(K)[::-1].copy()
     gamma = ph.coupling(1.0)
     g = dmc.Graph(n, mask, part_size=part_size, deriv_k=2)
@@ -155,7 +161,7 @@ def test_order6_effective_mass_shape_per_sample():
     the oracle's C evaluator (FP64, diagram by diagram) for every group, momentum and root."""
     from oracle import cevaluate as ce
     n, N = 6, 48
-    x = synth.loop_points(n, N, seed=3060)
+    x = parity_points(n, N, seed=3060)
     ks = np.array([1.0, 0.0, 2.5], dtype=np.float32)
     lams = [0.5, 1.0, 2.0]
     inst = [(BETA, MU, lam, ph.coupling(rs)) for lam in lams for rs in (1.0, 2.0, 3.0, 4.0, 5.0)]

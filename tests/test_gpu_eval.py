@@ -10,7 +10,7 @@ from oracle import integrand as ig
 from oracle import physics as ph
 from oracle import sampler as osp
 
-from gpu_helpers import BETA, LAM, MU, gpu_integrand, to_soa, torch_dev
+from gpu_helpers import BETA, LAM, MU, gpu_integrand, parity_points, to_soa, torch_dev
 from golden_diagrams import oracle_diagrams
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +34,7 @@ def test_integrand_per_sample(n, N, K, part_size):
     """Several 256-sample tiles plus a ragged tail; K spans a partial chunk of k values.  Order 4
     in parts of 40 diagrams and order 6 (31130 diagrams in 20 parts; about
     two minutes of run-time compilation) cover the partitioned kernel."""
-    x = synth.loop_points(n, N, seed=100 + n)
+    x = parity_points(n, N, seed=100 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
     g = dmc.Graph(n, part_size=part_size)

@@ -10,7 +10,7 @@ import synth
 from oracle import physics as ph
 from oracle import taylor as ty
 
-from gpu_helpers import BETA, LAM, MU, gpu_integrand, torch_dev
+from gpu_helpers import BETA, LAM, MU, gpu_integrand, parity_points, torch_dev
 from golden_diagrams import oracle_diagrams
 
 pytestmark = pytest.mark.gpu
@@ -26,7 +26,7 @@ TOL = 2e-5
 @pytest.mark.parametrize("n,T,N,K", [(1, 4, 600, 3), (2, 4, 400, 3), (3, 3, 250, 2), (4, 2, 96, 2)])
 def test_taylor_roots_per_sample(n, T, N, K):
     """Order 4 runs a kernel in parts (2 parts)."""
-    x = synth.loop_points(n, N, seed=700 + n)
+    x = parity_points(n, N, seed=700 + n)
     ks = synth.k_grid(K)
     gamma = ph.coupling(1.0)
     g = dmc.Graph(n, ALL, taylor_order=T)
