@@ -71,7 +71,20 @@ typedef struct {
                               k_F alone, Sec. VI.A eq. eff_mass_ratio); the other momenta's derivative slots
                               receive zero sums (estimate 0 +- 0) and f_out zeros.  Derivative-only code
                               then runs at those m momenta only. */
+    int32_t routing;       /* the integration variables of each diagram (every choice integrates to the same
+                              self-energy over unbounded momenta; the ball |q| <= 6 cuts each routing off
+                              differently, so estimates agree to the cutoff's tail):
+                              DMC_ROUTING_PATH: the canonical labelling, loop momenta on chords next to the
+                              external momentum's shortest path (most of each diagram independent of k);
+                              DMC_ROUTING_BLOCKS: interaction lines and loop momenta taken from the diagram's
+                              building blocks (Sec. II.C: eq. sigma_pq, eq. Dyson, eq. vertex3,
+                              eq. parquet_eqns, eq. phi_ph, eq. phi_phbar, eq. phi_pp), so that a block shared
+                              by many diagrams is evaluated once; k on the shortest path.  Fewer k-independent
+                              operations, more per external momentum (graph_query's op counts tell which is
+                              cheaper for a launch).  Any other value: DMC_E_INVALID. */
 } dmc_graph_spec;
+
+enum { DMC_ROUTING_PATH = 0, DMC_ROUTING_BLOCKS = 1 };
 
 typedef struct {
     int32_t order, dim, n_diagrams, n_root_classes;
@@ -96,6 +109,7 @@ typedef struct {
     int64_t ops_k_deriv[4];
     int64_t ops_k_deriv_exec[4];
     int32_t deriv_k;      /* as in the spec */
+    int32_t routing;      /* as in the spec */
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that

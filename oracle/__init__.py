@@ -33,6 +33,9 @@ Modules, and what pins each (tests/test_oracle_*.py, tests/test_library_cpu.py):
               closed forms of n_F, G0 and V series, finite differences.
   renorm      counterterm recursion, xi series and the effective mass (Secs. III.B, VI.A).  Pinned: the
               tree-function (Lagrange inversion) and hand-expanded cases.
+  blocks      building-block variables of each diagram by the Dyson-Schwinger and parquet decomposition (Sec.
+              II.C).  Pinned: same topology and a unit-Jacobian change of variables against the canonical routing,
+              the Dyson count of bare-vertex diagrams, the envelope as the first irreducible block.
   cevaluate   the same integrand in C (evaluate.c, OpenMP) for orders 4-6.  Pinned per sample to
               integrand.py at orders 1-5.
   enumerate.c (built by build.py) the brute-force diagram enumeration in C, for orders 5-6.  Pinned to

@@ -1142,7 +1142,7 @@ struct Builder {
 int default_part_size(int order, int n_diagrams, int n_roots);
 
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             Compiled& out, std::string& err) {
+             int routing, Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -1159,8 +1159,13 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         err = "deriv_k must be in 0..64";
         return false;
     }
+    if (routing != 0 && routing != 1) {
+        err = "routing must be 0 (path) or 1 (building blocks)";
+        return false;
+    }
     out = Compiled{};
     out.deriv_k = deriv_k;
+    out.routing = routing;
     out.order = order;
     out.dim = 4 * order - 1;
     out.deriv_mask = deriv_mask;
@@ -1169,6 +1174,18 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
     out.root_orders = cs.idx;
     out.n_roots = (int)cs.idx.size();
     out.diagrams = enumerate_sigma(order);
+    if (routing == 1) {
+        // loop momenta and interaction lines from the building blocks, k along the shortest path
+        for (auto& d : out.diagrams) {
+            Diagram r;
+            if (!relabel_building_blocks(d, r, err)) return false;
+            int nf;
+            auto es = internal_edges(r.sigma, nf);
+            for (auto& ln : r.lines) ln.mom[order] = 0;
+            for (auto [e, sg] : k_path(2 * order, es, r.out_vertex)) r.lines[e].mom[order] += sg;
+            d = std::move(r);
+        }
+    }
     if (diagram_index >= 0) {
         if (diagram_index >= (int)out.diagrams.size()) {
             err = "diagram_index out of range";

@@ -34,6 +34,11 @@ struct Diagram {
 // order n in canonical labelling, routed.
 std::vector<Diagram> enumerate_sigma(int n);
 
+// The same diagram with its interaction lines and loop momenta taken from its building blocks
+// (self-energy, dressed line, three- and four-point vertices, parquet channels); false with a
+// message when the decomposition fails.
+bool relabel_building_blocks(const Diagram& d, Diagram& out, std::string& err);
+
 // ---- graph IR and code generation ----
 enum class Op : uint8_t { Leaf, Mul, Fma, Add, MulC };
 
@@ -58,6 +63,7 @@ struct Compiled {
     std::vector<std::array<int, 3>> root_orders;
     int part_size = 0;  // diagrams per straight-line part; 0 = one part
     int deriv_k = 0;    // derivative roots only at the first deriv_k external momenta (0: at all of them)
+    int routing = 0;    // 0 path routing, 1 building-block variables
     std::vector<Diagram> diagrams;
     CodeStats stats;
 };
@@ -67,8 +73,10 @@ struct Compiled {
 // part_size: diagrams per straight-line part of the kernel; 0 chooses by size.
 // taylor_order T >= 1 builds every derivative d^m/dmu^m d^l/dlambda^l with m + l <= T along the masked
 // directions (mu bit 0, lambda bit 1), and with the k bit also the k derivative of each of them.
+// routing 0: loop momenta on chords next to the external momentum's shortest path; 1: from the building
+// blocks of the diagram (relabel_building_blocks), k on the shortest path.
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             Compiled& out, std::string& err);
+             int routing, Compiled& out, std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);
