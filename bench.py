@@ -292,6 +292,46 @@ def flow_vs_vegas(order, K, N, batches, beta, mu, lam, gamma, seed=0x24031884000
     }
 
 
+def routing_compare(orders, n_samples=1 << 22, reps=5, ks_list=(1, 32)):
+    """Path routing against building-block variables (dmc_graph_spec.routing): eval_batch + accumulate of one
+    lambda group on n_samples uniform samples, at one external momentum (k_F) and at 32 in [0, 3 k_F]; the mean of
+    `reps` launches by HIP events, with each graph's executed op counts per sample and per (sample, k)."""
+    import numpy as np
+    import torch
+
+    import paper_2403_18840_amd as dmc
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    inst = [(25.0, 1.0, 1.0, dmc.coupling(1.0))]
+    rows = []
+    for n in orders:
+        s = dmc.Sampler(dmc.SAMPLER_UNIFORM, n)
+        X = torch.empty((dmc.dim(n), n_samples), dtype=torch.float32, device=dev)
+        J = torch.empty(n_samples, dtype=torch.float32, device=dev)
+        s.sample(1, 0, X, J)
+        for routing, name in ((dmc.ROUTING_PATH, "path"), (dmc.ROUTING_BLOCKS, "blocks")):
+            g = dmc.Graph(n, routing=routing)
+            info = g.info()
+            for K in ks_list:
+                ks = np.array([1.0], dtype=np.float32) if K == 1 else np.linspace(0.0, 3.0, K).astype(np.float32)
+                acc = dmc.Accumulator(1, K, 1)
+                dmc.eval_batch(g, inst, ks, X, J, acc, stream=stream)
+                dmc.accumulate(acc, stream=stream)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(reps):
+                    dmc.eval_batch(g, inst, ks, X, J, acc, stream=stream)
+                    dmc.accumulate(acc, stream=stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                rows.append({"order": n, "routing": name, "n_k": K, "samples": n_samples,
+                             "ms": a.elapsed_time(b) / reps, "parts": info.n_parts,
+                             "ops_sample_exec": int(sum(info.ops_sample_exec)), "ops_k_exec": int(sum(info.ops_k_exec))})
+                print(f"[routing] {name} order {n} K {K}: {rows[-1]['ms']:.3f} ms", file=sys.stderr, flush=True)
+    return rows
+
+
 def _ratio(a, b):
     return float(a / b) if b > 0 and math.isfinite(b) else None
 
@@ -622,6 +662,8 @@ def main():
     ap.add_argument("--mass-lambda", type=float, default=1.0)
     ap.add_argument("--mass-log2-samples", type=int, default=22)
     ap.add_argument("--mass-batches", type=int, default=16)
+    ap.add_argument("--routing-orders", default="",
+                    help="orders at which to time path routing against building-block variables (empty skips it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -656,6 +698,8 @@ def main():
         if args.mass_order:
             out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, 25.0,
                                                        args.mass_log2_samples, args.mass_batches)
+        if args.routing_orders:
+            out["routing_compare"] = routing_compare([int(n) for n in args.routing_orders.split(",")])
         print(json.dumps(out), flush=True)
         return
 
@@ -781,6 +825,8 @@ def main():
     if args.mass_order:
         out["effective_mass"] = effective_mass_leg(args.mass_order, args.mass_rs, args.mass_lambda, beta,
                                                    args.mass_log2_samples, args.mass_batches)
+    if args.routing_orders:
+        out["routing_compare"] = routing_compare([int(n) for n in args.routing_orders.split(",")])
     print(json.dumps(out), flush=True)
 
 

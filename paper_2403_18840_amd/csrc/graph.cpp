@@ -1261,7 +1261,7 @@ std::string kernel_name(const Compiled& c, int n_groups) {
     const int np = c.part_size > 0 && nd > c.part_size ? (nd + c.part_size - 1) / c.part_size : 1;
     return "dmc_eval_o" + std::to_string(c.order) + "_g" + std::to_string(n_groups) + "_r" + std::to_string(c.n_roots) +
            (c.taylor_order > 0 ? "_t" + std::to_string(c.taylor_order) : "") + (nd == 1 ? "_single" : "") +
-           (np > 1 ? "_p" + std::to_string(np) : "");
+           (np > 1 ? "_p" + std::to_string(np) : "") + (c.routing == 1 ? "_b" : "");
 }
 
 // Diagram parts of a partitioned kernel.  Every part re-evaluates the leaves its diagrams use (and the

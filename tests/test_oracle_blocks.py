@@ -138,5 +138,8 @@ def test_building_block_routing_op_counts():
     a = dmc.Graph(5).info()
     b = dmc.Graph(5, routing=dmc.ROUTING_BLOCKS).info()
     assert b.routing == 1 and a.routing == 0
+    # the kernel names tell the routings apart in a profiler's trace
+    name = lambda g: g.source(1).splitlines()[1].split()[-1]
+    assert name(dmc.Graph(5, routing=dmc.ROUTING_BLOCKS)) == name(dmc.Graph(5)) + "_b"
     assert sum(b.ops_sample) < 0.9 * sum(a.ops_sample)
     assert sum(b.ops_k) > sum(a.ops_k)
