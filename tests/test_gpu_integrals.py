@@ -118,6 +118,52 @@ def test_same_samples_integral(n, N):
         print(f"order {n} k {k}: gpu {m[0, 0, j]:.6e} oracle {ref:.6e} |diff| {abs(m[0, 0, j] - ref):.2e} bound {bound:.2e}")
 
 
+@pytest.mark.parametrize("n,N_gpu,N_ora", [(2, 1 << 21, 1 << 20), (3, 1 << 21, 1 << 19)])
+def test_blocks_estimates_match_oracle_family_rule(n, N_gpu, N_ora):
+    """With building-block variables (DMC_ROUTING_BLOCKS): the GPU's VEGAS estimate against the oracle's own VEGAS
+    estimate over its own relabelling of the diagrams, by the family rule."""
+    from oracle import blocks
+    ks = np.array([0.0, 1.0, 2.0], dtype=np.float32)
+    gamma = ph.coupling(1.0)
+    inst = [(BETA, MU, LAM, gamma)]
+    m, e = _gpu_batches(dmc.Graph(n, routing=dmc.ROUTING_BLOCKS), inst, ks, N_gpu, 16, seed=41 + n)
+    dgs = blocks.block_diagrams(oracle_diagrams(n))
+    om, oe = mc.vegas_mc(n, ks.astype(np.float64), BETA, MU, LAM, gamma, dgs, N=N_ora,
+                         N_adapt=max(N_ora // 8, 1 << 12), seed=4321 + n)
+    ok, msg = family_rule(_z(m, e, om, oe))
+    print(f"order {n} (building blocks): {msg}; gpu {m} +- {e}; oracle {om} +- {oe}")
+    assert ok, msg
+
+
+def test_blocks_same_samples_integral_order5():
+    """Oracle-drawn points through the GPU's building-block graph at order 5 against the oracle's FP64 mean over the
+    same points with its own relabelling (the bound of test_same_samples_integral)."""
+    from oracle import blocks
+    torch, dev = torch_dev()
+    n, N = 5, 1 << 12
+    rng = np.random.Generator(np.random.PCG64(99))
+    x, w = mc.radial_mixture_points(n, N, rng, BETA)
+    x = x.astype(np.float32)
+    jac = w.astype(np.float32)
+    ks = np.array([1.0, 0.3], dtype=np.float32)
+    gamma = ph.coupling(1.0)
+    acc = dmc.Accumulator(1, len(ks), 1)
+    dmc.eval_batch(dmc.Graph(n, routing=dmc.ROUTING_BLOCKS), [(BETA, MU, LAM, gamma)], ks, to_soa(x),
+                   torch.from_numpy(jac).to(dev), acc)
+    dmc.accumulate(acc)
+    m, _, ns, nf = acc.estimate(1)
+    assert ns == N and nf == 0
+    dgs = blocks.block_diagrams(oracle_diagrams(n))
+    tab = ce.table(dgs, n)
+    x64, j64 = x.astype(np.float64), jac.astype(np.float64)
+    for j, k in enumerate(ks):
+        f = ce.integrand(x64, n, float(k), BETA, MU, LAM, gamma, dgs, tab=tab)
+        tol, _ = ce.fp32_tolerance(x64, n, float(k), BETA, MU, LAM, gamma, dgs, tab=tab)
+        ref = np.mean(f * j64)
+        bound = np.sum((tol + 2.0 ** -24 * np.abs(f)) * j64) / N
+        assert abs(m[0, 0, j].real - ref.real) <= bound and abs(m[0, 0, j].imag - ref.imag) <= bound, (k, m[0, 0, j], ref)
+
+
 def test_order2_rainbow_matches_quadrature():
     """The rainbow diagram alone (its exported index) by VEGAS on the GPU against the deterministic quadrature of
     the first-order expansion of the Fock term."""
