@@ -79,3 +79,50 @@ def test_blocks_order6_per_sample():
     assert np.all(err <= tol), f"worst {np.max(err / (o[:, 0, 2] + 1e-300))}"
     # the shell half is live (line momenta are sums of shell momenta, so some fall off the shell)
     assert np.sum(o[:, 0, 2] > 1e-20) >= N // 3
+
+
+def test_blocks_taylor_roots_per_sample():
+    """Taylor mode (T = 2, mu, lambda and k) with building-block variables at order 3 against the oracle's truncated
+    series over its own relabelling.  The rule: the Taylor tests' 2e-5 of the term scale per derivative step, plus
+    the per-sample rule's exponent term 2u sum_d scale_d C_d on each root's own term scales (as for the first-order
+    derivative roots).  That term decides on the exponentially small samples of the default draw."""
+    from oracle import taylor as ty
+    n, T, N = 3, 2, 200
+    x = parity_points(n, N, seed=941)
+    ks = synth.k_grid(2)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, ALL, taylor_order=T, routing=dmc.ROUTING_BLOCKS)
+    f, _, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
+    dgs = blocks.block_diagrams(oracle_diagrams(n))
+    x64 = x.astype(np.float64)
+    for j, k in enumerate(ks):
+        kk = float(np.float32(k))
+        ref = ty.derivative_roots(x64, n, kk, BETA, MU, LAM, gamma, T, True, True, True, diagrams=dgs)
+        scale = ty.derivative_scale(x64, n, kk, BETA, MU, LAM, gamma, T, True, True, True, diagrams=dgs)
+        C = ig.exponent_condition(x64, n, kk, BETA, MU, diagrams=dgs)
+        per = [ty.derivative_scale(x64, n, kk, BETA, MU, LAM, gamma, T, True, True, True, diagrams=[d]) for d in dgs]
+        for r, ((key, rv), (_, sc)) in enumerate(zip(ref, scale)):
+            steps = key[0] + key[1] + key[2] + 1
+            expo = sum(p[r][1] * C[i] for i, p in enumerate(per))
+            err = np.abs(f[0, r, j] - rv)
+            assert np.all(err <= 2e-5 * steps * sc + 2 * ig.U32 * steps * expo + 1e-30), (key, k)
+
+
+def test_blocks_partitioned_order4_per_sample():
+    """Order 4 with building-block variables in parts of 40 diagrams, two lambda groups."""
+    n, N = 4, 300
+    x = parity_points(n, N, seed=944)
+    ks = synth.k_grid(3)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, part_size=40, routing=dmc.ROUTING_BLOCKS)
+    assert g.info().n_parts == 5
+    lams = [0.5, 2.0]
+    f, _, _ = gpu_integrand(g, x, ks, [(BETA, MU, lam, gamma) for lam in lams])
+    dgs = blocks.block_diagrams(oracle_diagrams(n))
+    x64 = x.astype(np.float64)
+    for gi, lam in enumerate(lams):
+        for j, k in enumerate(ks):
+            kk = float(np.float32(k))
+            ref = ig.integrand(x64, n, kk, BETA, MU, lam, gamma, diagrams=dgs)
+            tol, _ = ig.fp32_tolerance(x64, n, kk, BETA, MU, lam, gamma, diagrams=dgs)
+            assert np.all(np.abs(f[gi, 0, j] - ref) <= tol), (lam, k)
