@@ -82,6 +82,10 @@ typedef struct {
                               by many diagrams is evaluated once; k on the shortest path.  Fewer k-independent
                               operations, more per external momentum (graph_query's op counts tell which is
                               cheaper for a launch).  Any other value: DMC_E_INVALID. */
+    int32_t spin_deg;      /* the factor of each closed fermion loop in a diagram's weight (-1)^(n+F) g^F (Sec. II.A,
+                              eq. sigma_integration; F closed loops): 2 for the electron gas's spin-1/2 fermions (0
+                              also means 2), 1 for spinless fermions; any other value: DMC_E_INVALID.  The
+                              observable is always Sigma(k, i w_0) at the lowest fermionic Matsubara frequency. */
 } dmc_graph_spec;
 
 enum { DMC_ROUTING_PATH = 0, DMC_ROUTING_BLOCKS = 1 };
@@ -110,6 +114,7 @@ typedef struct {
     int64_t ops_k_deriv_exec[4];
     int32_t deriv_k;      /* as in the spec */
     int32_t routing;      /* as in the spec */
+    int32_t spin_deg;     /* as in the spec (2 when the spec held 0) */
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that

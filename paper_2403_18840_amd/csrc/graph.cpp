@@ -1142,7 +1142,7 @@ struct Builder {
 int default_part_size(int order, int n_diagrams, int n_roots);
 
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             int routing, Compiled& out, std::string& err) {
+             int routing, int spin_deg, Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -1163,9 +1163,14 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         err = "routing must be 0 (path) or 1 (building blocks)";
         return false;
     }
+    if (spin_deg != 1 && spin_deg != 2) {
+        err = "spin_deg must be 1 or 2";
+        return false;
+    }
     out = Compiled{};
     out.deriv_k = deriv_k;
     out.routing = routing;
+    out.spin_deg = spin_deg;
     out.order = order;
     out.dim = 4 * order - 1;
     out.deriv_mask = deriv_mask;
@@ -1174,6 +1179,8 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
     out.root_orders = cs.idx;
     out.n_roots = (int)cs.idx.size();
     out.diagrams = enumerate_sigma(order);
+    if (spin_deg == 1)  // spinless: each closed fermion loop gives its sign only
+        for (auto& d : out.diagrams) d.weight = (order + d.n_fermion_loops) % 2 ? -1.0 : 1.0;
     if (routing == 1) {
         // loop momenta and interaction lines from the building blocks, k along the shortest path
         for (auto& d : out.diagrams) {

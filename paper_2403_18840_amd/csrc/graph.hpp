@@ -64,6 +64,7 @@ struct Compiled {
     int part_size = 0;  // diagrams per straight-line part; 0 = one part
     int deriv_k = 0;    // derivative roots only at the first deriv_k external momenta (0: at all of them)
     int routing = 0;    // 0 path routing, 1 building-block variables
+    int spin_deg = 2;   // factor per closed fermion loop
     std::vector<Diagram> diagrams;
     CodeStats stats;
 };
@@ -75,8 +76,9 @@ struct Compiled {
 // directions (mu bit 0, lambda bit 1), and with the k bit also the k derivative of each of them.
 // routing 0: loop momenta on chords next to the external momentum's shortest path; 1: from the building
 // blocks of the diagram (relabel_building_blocks), k on the shortest path.
+// spin_deg: the factor of each closed fermion loop (2 for spin 1/2, 1 for spinless fermions).
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             int routing, Compiled& out, std::string& err);
+             int routing, int spin_deg, Compiled& out, std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);

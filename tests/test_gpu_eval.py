@@ -370,3 +370,23 @@ def test_importance_roots_setting(part, kd):
         g.set_importance(R + 1)
     with pytest.raises(dmc.DmcError):
         g.set_importance(0)
+
+
+@pytest.mark.parametrize("n,N,K", [(2, 600, 5), (3, 400, 4)])
+def test_spinless_integrand_per_sample(n, N, K):
+    """spec.spin_deg = 1 (spinless fermions: a closed loop gives its sign only) against the oracle's diagrams with
+    the weights (-1)^(n+F) of that definition."""
+    import dataclasses
+    x = parity_points(n, N, seed=950 + n)
+    ks = synth.k_grid(K)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, spin_deg=1)
+    f, _, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
+    dgs = [dataclasses.replace(d, weight=float((-1) ** (n + d.n_loops_f))) for d in oracle_diagrams(n)]
+    assert any(d.n_loops_f > 0 for d in dgs)
+    x64 = x.astype(np.float64)
+    for j, k in enumerate(ks):
+        kk = float(np.float32(k))
+        ref = ig.integrand(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
+        tol, _ = ig.fp32_tolerance(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
+        assert np.all(np.abs(f[0, 0, j] - ref) <= tol), f"k={k}"

@@ -169,3 +169,17 @@ def test_host_vegas_refine_matches_oracle():
         assert np.allclose(got, want, rtol=0, atol=1e-12), (D, B, alpha, np.abs(got - want).max())
     with pytest.raises(dmc.DmcError):
         dmc.vegas_refine(np.zeros((2, 3)), np.zeros((2, 2)), -1.0)
+
+
+def test_spin_degeneracy_weights():
+    """spec.spin_deg: 2 (and 0) gives (-1)^(n+F) 2^F, 1 gives the spinless (-1)^(n+F); other values are refused."""
+    for n in (2, 3, 4):
+        two = _parse_export(dmc.Graph(n).export(), n)
+        assert two == _parse_export(dmc.Graph(n, spin_deg=0).export(), n)
+        one = _parse_export(dmc.Graph(n, spin_deg=1).export(), n)
+        assert dmc.Graph(n, spin_deg=0).info().spin_deg == 2 and dmc.Graph(n, spin_deg=1).info().spin_deg == 1
+        loops = {d.sigma: d.n_loops_f for d in oracle_diagrams(n)}
+        assert {(s, (-1.0) ** (n + loops[s]), e, l) for s, w, e, l in two} == {(s, w / 2.0 ** loops[s], e, l) for s, w, e, l in two}
+        assert one == {(s, (-1.0) ** (n + loops[s]), e, l) for s, w, e, l in two}
+    with pytest.raises(dmc.DmcError):
+        dmc.Graph(2, spin_deg=3)
