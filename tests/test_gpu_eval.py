@@ -82,6 +82,38 @@ def test_integrand_seeded_sweep(n):
           f"within 1e-5 |f| {n_strict}/{n_live}; within the rule {n_rule}/{N * len(ks)}")
 
 
+@pytest.mark.parametrize("n,N", [(4, 1 << 13), (5, 1 << 11)])
+def test_integrand_seeded_sweep_high_orders(n, N):
+    """The sweep at orders 4 and 5 on the parity inputs' recipe (half the rows on the Fermi shell), seeds outside the
+    other tests, 4 external momenta, against the oracle's C evaluator: every sample within the rule; prints the worst
+    |err| / A and the fractions meeting 1e-5 A and the plain 1e-5 |f| among samples with A > 1e-20."""
+    from oracle import cevaluate as ce
+    x = parity_points(n, N, seed=6000 + n)
+    ks = np.array([0.0, 0.95, 1.05, 3.0], dtype=np.float32)
+    gamma = ph.coupling(1.0)
+    f, _, _ = gpu_integrand(dmc.Graph(n), x, ks, [(BETA, MU, LAM, gamma)])
+    dgs = oracle_diagrams(n)
+    tab = ce.table(dgs, n)
+    x64 = x.astype(np.float64)
+    worst, n_live, n_a, n_strict = 0.0, 0, 0, 0
+    for j, k in enumerate(ks):
+        o = ce.evaluate(x64, n, float(k), BETA, MU, LAM, gamma, dgs, tab=tab)
+        ref = o[:, 0, 0] + 1j * o[:, 0, 1]
+        A = o[:, 0, 2]
+        tol = 1e-5 * A + 2 * ig.U32 * o[:, 0, 3] + 1e-30
+        err = np.abs(f[0, 0, j] - ref)
+        bad = np.where(~(err <= tol))[0]
+        assert len(bad) == 0, f"k={k}: sample {bad[0]} gpu {f[0, 0, j][bad[0]]} oracle {ref[bad[0]]} bound {tol[bad[0]]}"
+        live = A > 1e-20
+        worst = max(worst, float(np.max(err[live] / A[live])))
+        n_live += int(live.sum())
+        n_a += int(np.sum(err[live] <= REL * A[live]))
+        n_strict += int(np.sum(err[live] <= REL * np.abs(ref[live])))
+    assert n_live >= N * len(ks) // 3
+    print(f"order {n}: {N} samples x {len(ks)} k: worst |err|/A {worst:.2e}; within 1e-5 A {n_a}/{n_live}; "
+          f"within 1e-5 |f| {n_strict}/{n_live}")
+
+
 def test_integrand_two_lambda_groups_and_rs_scaling():
     # instances sharing lambda are one evaluation scaled by (r_s'/r_s)^n; distinct lambdas are groups
     n, N = 2, 300
