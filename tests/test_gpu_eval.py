@@ -82,9 +82,9 @@ def test_integrand_seeded_sweep(n):
           f"within 1e-5 |f| {n_strict}/{n_live}; within the rule {n_rule}/{N * len(ks)}")
 
 
-@pytest.mark.parametrize("n,N", [(4, 1 << 13), (5, 1 << 11)])
+@pytest.mark.parametrize("n,N", [(4, 1 << 13), (5, 1 << 11), (6, 1 << 9)])
 def test_integrand_seeded_sweep_high_orders(n, N):
-    """The sweep at orders 4 and 5 on the parity inputs' recipe (half the rows on the Fermi shell), seeds outside the
+    """The sweep at orders 4-6 on the parity inputs' recipe (half the rows on the Fermi shell), seeds outside the
     other tests, 4 external momenta, against the oracle's C evaluator: every sample within the rule; prints the worst
     |err| / A and the fractions meeting 1e-5 A and the plain 1e-5 |f| among samples with A > 1e-20."""
     from oracle import cevaluate as ce
