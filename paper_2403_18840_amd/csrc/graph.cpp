@@ -1139,7 +1139,7 @@ struct Builder {
 
 }  // namespace
 
-int default_part_size(int order, int n_diagrams, int n_roots);
+int default_part_size(int n_diagrams, int n_roots);
 
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
              int routing, int spin_deg, Compiled& out, std::string& err) {
@@ -1207,7 +1207,7 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         err = "part_size must be >= 0";
         return false;
     }
-    out.part_size = part_size > 0 ? part_size : default_part_size(order, (int)out.diagrams.size(), out.n_roots);
+    out.part_size = part_size > 0 ? part_size : default_part_size((int)out.diagrams.size(), out.n_roots);
     CodeStats st;
     emit_eval_source(out, 1, &st);
     for (int i = 0; i < 4; ++i) {
@@ -1361,7 +1361,7 @@ static std::vector<std::vector<int>> diagram_parts(const Compiled& c, int part_s
     return parts;
 }
 
-int default_part_size(int order, int n_diagrams, int n_roots) {
+int default_part_size(int n_diagrams, int n_roots) {
     // Measured on MI355X with the external momentum on a path of chords (a part's k-independent code dominates
     // and runs once per chunk of momenta) and leaf-grown parts.  Per 2^22 samples x 32 k: order 5 in one part
     // 3.1 ms, in 3 parts 5.0 ms; order 6 in parts of 1600, 2400, 3200 diagrams 32.4, 31.7, 33.6 ms (sorted, not
