@@ -91,8 +91,6 @@ __device__ __forceinline__ float philox_logit(uint32_t w) {
 
 // ---------------------------------------------------------------- LDS geometry
 // Row strides padded by 8 BF16 (16 B) so that 16 lanes reading 16 B each hit distinct banks.
-constexpr int W1S = FKIN + 8;   // 24
-constexpr int W2S = FH + 8;     // 136
 constexpr int XS = FKIN + 8;    // 24
 constexpr int HS = FH + 8;      // 136
 constexpr int OS = FNOUT + 4;   // 36 floats
@@ -918,7 +916,7 @@ __global__ void __launch_bounds__(1024) dmc_flow_sums_kernel(const float* w, int
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) dmc_mcmc_accumulate_kernel(McmcAccArgs a)
     r2[threadIdx.x] = s2;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             r1[threadIdx.x] += r1[threadIdx.x + o];
             r2[threadIdx.x] += r2[threadIdx.x + o];
         }

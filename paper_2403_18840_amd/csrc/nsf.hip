@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(1024) dmc_nsf_loss_kernel(const float* w, cons
     r1[threadIdx.x] = s1;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             r0[threadIdx.x] += r0[threadIdx.x + o];
             r1[threadIdx.x] += r1[threadIdx.x + o];
         }
