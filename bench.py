@@ -549,6 +549,8 @@ def run_c5(args):
             ev[1].record(stream)
         dmc.accumulate(acc)
         state["last"] = acc.estimate(len(inst))
+        if ev is not None:
+            state.setdefault("iters", []).append(state["last"])
 
     for w in range(args.warmup):
         step(w)
@@ -557,6 +559,8 @@ def run_c5(args):
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(args.warmup + i, ev=evs[i])
+        if (i + 1) % 10 == 0:
+            log(f"{i + 1} of {args.steps} timed iterations")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
@@ -567,9 +571,14 @@ def run_c5(args):
         + 1 * flops(list(inf.ops_k_deriv))
     fl_launch = N * len(lams) * per_group
     achieved = fl_launch / (kern_ms * 1e-3) / 1e12
-    m, e, ns, nf = state["last"]
     i1 = inst.index((beta, mu, 1.0, dmc.coupling(1.0)))
     w0 = math.pi / beta
+    # the timed iterations combined with equal weights (dmc_combine_iterations): Re, Im of Sigma and of d Sigma/dk
+    # at k_F for lambda = 1, r_s = 1
+    its = state["iters"]
+    pick = lambda a: [a[i1, 0, 0].real, a[i1, 0, 0].imag, a[i1, 1, 0].real, a[i1, 1, 0].imag]
+    cm, ce, chi = dmc.combine_iterations([pick(it[0]) for it in its], [pick(it[1]) for it in its])
+    nf = int(sum(it[3] for it in its))
     out = {
         "metric": "samples·diagrams/s",
         "value": units / dt,
@@ -599,12 +608,14 @@ def run_c5(args):
             "flop_per_sample_per_group": per_group,
             "frac_of_unpacked_issue_rate": achieved / PEAK_ALU_TFLOPS,
         },
-        "estimate": {"lambda": 1.0, "rs": 1.0, "k": 1.0, "order": order,
-                     "re": float(m[i1, 0, 0].real), "re_err": float(e[i1, 0, 0].real),
-                     "im": float(m[i1, 0, 0].imag), "im_err": float(e[i1, 0, 0].imag),
-                     "dre_dk": float(m[i1, 1, 0].real), "dre_dk_err": float(e[i1, 1, 0].real),
+        "estimate": {"lambda": 1.0, "rs": 1.0, "k": 1.0, "order": order, "iterations": len(its),
+                     "re": float(cm[0]), "re_err": float(ce[0]), "im": float(cm[1]), "im_err": float(ce[1]),
+                     "dre_dk": float(cm[2]), "dre_dk_err": float(ce[2]),
                      # the order-6 coefficients of the effective mass: a = (m/k_F) dRe/dk (m/k_F = 1/2), b = Im/w0
-                     "a": 0.5 * float(m[i1, 1, 0].real), "b": float(m[i1, 0, 0].imag) / w0,
+                     "a": 0.5 * float(cm[2]), "a_err": 0.5 * float(ce[2]), "b": float(cm[1]) / w0,
+                     "b_err": float(ce[1]) / w0,
+                     # chi^2/dof of the iterations about their combination (Re, Im, dRe/dk); nan with one iteration
+                     "chi2_dof": [float(c) if math.isfinite(c) else None for c in chi[:3]],
                      "nonfinite": int(nf)},
     }
     if not args.no_peaks:
