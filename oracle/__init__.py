@@ -36,8 +36,8 @@ Modules, and what pins each (tests/test_oracle_*.py, tests/test_library_cpu.py):
   blocks      building-block variables of each diagram by the Dyson-Schwinger and parquet decomposition (Sec.
               II.C).  Pinned: same topology and a unit-Jacobian change of variables against the canonical routing,
               the Dyson count of bare-vertex diagrams, the envelope as the first irreducible block.
-  construct   the bottom-up construction of the diagram set from the same equations.  Pinned: the brute-force set,
-              each topology once, at orders 1-4; at order 5 it misses exactly the envelope diagrams.
+  construct   the bottom-up construction of the diagram set from the same equations, with the fully irreducible
+              vertices from an orderly generation.  Pinned: the brute-force set, each topology once, at orders 1-6.
   cevaluate   the same integrand in C (evaluate.c, OpenMP) for orders 4-6.  Pinned per sample to
               integrand.py at orders 1-5.
   enumerate.c (built by build.py) the brute-force diagram enumeration in C, for orders 5-6.  Pinned to

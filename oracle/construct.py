@@ -13,8 +13,9 @@ with the rules of the library's building-block variables (the channel cuts, and 
 block's out1 being where the fermion entering at in1 leaves it), so every diagram comes out once and keeps its own
 sign (the zeta and 1/2 of the antisymmetrised equations do not appear).
 
-The fully irreducible vertex is taken as the bare interaction only: the first larger one (the envelope, four
-interaction lines) enters a self-energy at order 5, so the construction is complete through order 4.
+The fully irreducible vertices come from a brute force over four-point topologies (`irreducible_vertices`):
+the bare interaction, none with two or three lines, the envelopes with four.  Through four lines they make the
+construction complete through order 5; at order 6 the five-line ones would be needed as well.
 
 A fragment is a set of interaction lines (pairs of vertex ids, both ends at the line's time) and internal
 propagators (a successor map); its legs are vertex ids.  A finished self-energy is turned into the permutation
@@ -28,6 +29,10 @@ import itertools
 from . import diagrams as dg
 
 _ids = itertools.count()
+
+# fully irreducible four-point vertices are taken through this many interaction lines: the construction is then
+# complete through order MAX_IRREDUCIBLE_LINES + 1
+MAX_IRREDUCIBLE_LINES = 5
 
 
 def _new():
@@ -140,12 +145,10 @@ def gamma4(j, kind):
     eq. parquet_eqns (I + the three channels); "ph", "phbar", "pp" are the vertices irreducible in that channel
     (I + the other two)."""
     out = []
-    if j == 0 and kind in ("full", "ph", "phbar", "pp"):
-        # the bare interaction, direct (in1 and out1 at one end) and exchange (in1 and out2 at one end)
-        x, y = _new(), _new()
-        out.append((Frag([(x, y)]), x, y, x, y))
-        x, y = _new(), _new()
-        out.append((Frag([(x, y)]), x, y, y, x))
+    if j + 1 <= MAX_IRREDUCIBLE_LINES:
+        # the fully irreducible vertices (the bare interaction in its direct and exchange forms, none with two or
+        # three lines, the envelopes with four), found by brute force
+        out += list(irreducible_vertices(j + 1))
     channels = [c for c in ("ph", "phbar", "pp") if kind == "full" or c != kind]
     for c in channels:
         out += _reducible(j, c)
@@ -212,3 +215,149 @@ def sigma_topologies(N):
         c = dg.canonical(to_sigma(frag, a, b))
         out[c] = out.get(c, 0) + 1
     return out
+
+
+def _four_point_key(sg, nv):
+    """Canonical key of a four-point topology: nodes 0..nv-1 are vertices (line t = 2t, 2t + 1), node nv closes
+    out1 -> in1 and node nv + 1 closes out2 -> in2 (sg is the successor map on nv + 2 nodes).  Breadth-first
+    relabelling from in1's vertex (out-propagator, partner, in-propagator), each line's first-found end even."""
+    P1, P2 = nv, nv + 1
+    pred = [0] * (nv + 2)
+    for v, w in enumerate(sg):
+        pred[w] = v
+    lab, order = {}, [sg[P1]]
+    seen = {sg[P1]}
+    nxt = 0
+    j = 0
+    while j < len(order):
+        v = order[j]
+        j += 1
+        if v not in lab and (v ^ 1) not in lab:
+            lab[v], lab[v ^ 1] = 2 * nxt, 2 * nxt + 1
+            nxt += 1
+        for w in (sg[v] if sg[v] < nv else None, v ^ 1, pred[v] if pred[v] < nv else None):
+            if w is not None and w not in seen:
+                seen.add(w)
+                order.append(w)
+    if len(lab) != nv:
+        return None                                   # not connected
+    name = lambda w: lab[w] if w < nv else ("o1" if w == P1 else "o2")
+    out = [None] * nv
+    for v in range(nv):
+        out[lab[v]] = name(sg[v])
+    return tuple(out) + (lab[sg[P2]],)
+
+
+def _irreducible_ok(sg, nv):
+    """Amputated (no propagator bridge), no tadpole (no interaction-line bridge with a leg-free side) and
+    irreducible in the three channels (no two propagators separate {in1,out1}|{in2,out2}, {in1,out2}|{in2,out1}
+    or {in1,in2}|{out1,out2})."""
+    P1, P2 = nv, nv + 1
+    pred = [0] * (nv + 2)
+    for v, w in enumerate(sg):
+        pred[w] = v
+    legs = {"in1": sg[P1], "in2": sg[P2], "out1": pred[P1], "out2": pred[P2]}
+    props = [v for v in range(nv) if sg[v] < nv]
+
+    def comp(start, off_g, off_v):
+        got, todo = {start}, [start]
+        while todo:
+            v = todo.pop()
+            nb = []
+            if sg[v] < nv and v not in off_g:
+                nb.append(sg[v])
+            if pred[v] < nv and pred[v] not in off_g:
+                nb.append(pred[v])
+            if v // 2 not in off_v:
+                nb.append(v ^ 1)
+            for w in nb:
+                if w not in got:
+                    got.add(w)
+                    todo.append(w)
+        return got
+
+    for x in props:                                     # propagator bridges: an insertion on a leg
+        if len(comp(0, {x}, set())) != nv:
+            return False
+    for t in range(nv // 2):                            # interaction-line bridges with a leg-free side
+        c = comp(2 * t, set(), {t})
+        if len(c) != nv:
+            side = c if not any(l in c for l in legs.values()) else set(range(nv)) - c
+            if not any(l in side for l in legs.values()):
+                return False
+    for i in range(len(props)):
+        for k in range(i + 1, len(props)):
+            c = comp(legs["in1"], {props[i], props[k]}, set())
+            if len(c) == nv:
+                continue
+            inside = {name for name, v in legs.items() if v in c}
+            if inside in ({"in1", "out1"}, {"in1", "out2"}, {"in1", "in2"}):
+                rest = set(range(nv)) - c
+                if len(comp(next(iter(rest)), {props[i], props[k]}, set()) | c) == nv:
+                    return False
+    return True
+
+
+def _four_point_maps(lines):
+    """Successor maps of connected four-point topologies with `lines` interaction lines, in1 entering vertex 0:
+    the vertices are visited in label order and the propagator leaving the visited vertex enters a labelled vertex
+    not yet entered (never vertex 0, in1's), opens the next line (whose ends take the next two labels) or leaves
+    by out1 or out2; in2 then enters the one vertex left without an incoming propagator.  Every connected topology
+    comes out at least once (in the labelling in which a breadth-first walk along out-propagators and partners
+    from in1's vertex meets the lines in order); duplicates are removed by the canonical key."""
+    nv = 2 * lines
+    P1, P2 = nv, nv + 1
+    sg = [None] * (nv + 2)
+    entered = [False] * nv
+
+    def rec(j, labelled, outs):
+        if j == labelled:
+            if labelled == nv and outs == 3:
+                free = [v for v in range(1, nv) if not entered[v]]
+                if len(free) == 1:
+                    full = list(sg)
+                    full[P1], full[P2] = 0, free[0]
+                    yield full
+            return
+        for w in range(1, labelled):
+            if not entered[w]:
+                entered[w] = True
+                sg[j] = w
+                yield from rec(j + 1, labelled, outs)
+                entered[w] = False
+        if labelled < nv:
+            entered[labelled] = True
+            sg[j] = labelled
+            yield from rec(j + 1, labelled + 2, outs)
+            entered[labelled] = False
+        for o, bit in ((P1, 1), (P2, 2)):
+            if not outs & bit:
+                sg[j] = o
+                yield from rec(j + 1, labelled, outs | bit)
+        sg[j] = None
+
+    yield from rec(0, 2, 0)
+
+
+@functools.lru_cache(maxsize=None)
+def irreducible_vertices(lines):
+    """The fully irreducible four-point topologies with `lines` interaction lines and distinct legs (connected,
+    amputated, tadpole free, irreducible in the three channels): [(fragment, in1, in2, out1, out2)]."""
+    nv = 2 * lines
+    P1, P2 = nv, nv + 1
+    keys = {}
+    for sg in _four_point_maps(lines):
+        key = _four_point_key(sg, nv)
+        if key is None or key in keys:
+            continue
+        keys[key] = sg if _irreducible_ok(sg, nv) else None
+    out = []
+    for sg in keys.values():
+        if sg is None:
+            continue
+        ids = [_new() for _ in range(nv)]
+        pred = {w: v for v, w in enumerate(sg)}
+        f = Frag([(ids[2 * t], ids[2 * t + 1]) for t in range(lines)],
+                 {ids[v]: ids[sg[v]] for v in range(nv) if sg[v] < nv})
+        out.append((f, ids[sg[P1]], ids[sg[P2]], ids[pred[P1]], ids[pred[P2]]))
+    return tuple(out)
