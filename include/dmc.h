@@ -86,7 +86,15 @@ typedef struct {
                               eq. sigma_integration; F closed loops): 2 for the electron gas's spin-1/2 fermions (0
                               also means 2), 1 for spinless fermions; any other value: DMC_E_INVALID.  The
                               observable is always Sigma(k, i w_0) at the lowest fermionic Matsubara frequency. */
+    int32_t generation;    /* where the diagram set comes from (the same set, ordered differently): DMC_GENERATE_ENUMERATE,
+                              the orderly enumeration of bridgeless permutations; DMC_GENERATE_CONSTRUCT, the bottom-up
+                              construction of Sec. II.C (eq. sigma_pq, eq. Dyson, eq. vertex3, eq. parquet_eqns,
+                              eq. phi_ph, eq. phi_phbar, eq. phi_pp, with the fully irreducible four-point vertices
+                              from an orderly generation), sorted by canonical permutation.  Any other value:
+                              DMC_E_INVALID. */
 } dmc_graph_spec;
+
+enum { DMC_GENERATE_ENUMERATE = 0, DMC_GENERATE_CONSTRUCT = 1 };
 
 enum { DMC_ROUTING_PATH = 0, DMC_ROUTING_BLOCKS = 1 };
 
@@ -115,6 +123,7 @@ typedef struct {
     int32_t deriv_k;      /* as in the spec */
     int32_t routing;      /* as in the spec */
     int32_t spin_deg;     /* as in the spec (2 when the spec held 0) */
+    int32_t generation;   /* as in the spec */
 } dmc_graph_info;
 
 /* One physical instance: all instances in one eval_batch share beta and mu; instances that

@@ -20,6 +20,7 @@ STATUS = {0: "DMC_OK", -1: "DMC_E_INVALID", -2: "DMC_E_NOMEM", -3: "DMC_E_DEVICE
 D_MU, D_LAMBDA, D_K = 1, 2, 4
 SAMPLER_UNIFORM, SAMPLER_VEGAS = 0, 1
 ROUTING_PATH, ROUTING_BLOCKS = 0, 1
+GENERATE_ENUMERATE, GENERATE_CONSTRUCT = 0, 1
 
 # every symbol include/dmc.h declares
 ABI_SYMBOLS = [
@@ -49,7 +50,7 @@ class DmcError(RuntimeError):
 class GraphSpec(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("deriv_mask", ctypes.c_uint32), ("diagram_index", ctypes.c_int32),
                 ("part_size", ctypes.c_int32), ("taylor_order", ctypes.c_int32), ("deriv_k", ctypes.c_int32),
-                ("routing", ctypes.c_int32), ("spin_deg", ctypes.c_int32)]
+                ("routing", ctypes.c_int32), ("spin_deg", ctypes.c_int32), ("generation", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -61,7 +62,8 @@ class GraphInfo(ctypes.Structure):
                 ("ops_sample_exec", ctypes.c_int64 * 4), ("ops_k_exec", ctypes.c_int64 * 4),
                 ("n_roots", ctypes.c_int32), ("taylor_order", ctypes.c_int32),
                 ("ops_k_deriv", ctypes.c_int64 * 4), ("ops_k_deriv_exec", ctypes.c_int64 * 4),
-                ("deriv_k", ctypes.c_int32), ("routing", ctypes.c_int32), ("spin_deg", ctypes.c_int32)]
+                ("deriv_k", ctypes.c_int32), ("routing", ctypes.c_int32), ("spin_deg", ctypes.c_int32),
+                ("generation", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -194,9 +196,10 @@ class Graph:
     """A compiled diagram graph (dmc_compile_graph)."""
 
     def __init__(self, order: int, deriv_mask: int = 0, diagram_index: int = -1, part_size: int = 0,
-                 taylor_order: int = 0, deriv_k: int = 0, routing: int = 0, spin_deg: int = 2):
+                 taylor_order: int = 0, deriv_k: int = 0, routing: int = 0, spin_deg: int = 2, generation: int = 0):
         self.h = P()
-        spec = GraphSpec(order, deriv_mask, diagram_index, part_size, taylor_order, deriv_k, routing, spin_deg)
+        spec = GraphSpec(order, deriv_mask, diagram_index, part_size, taylor_order, deriv_k, routing, spin_deg,
+                         generation)
         _check(lib().dmc_compile_graph(ctypes.byref(spec), ctypes.byref(self.h)))
         self.order = order
         self.deriv_mask = deriv_mask

@@ -32,7 +32,7 @@ def build(verbose: bool = False) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
     objs = []
-    for src, lang in [("graph.cpp", "c++"), ("blocks.cpp", "c++"), ("api.cpp", "c++"), ("renorm.cpp", "c++"), ("host.cpp", "c++"),
+    for src, lang in [("graph.cpp", "c++"), ("blocks.cpp", "c++"), ("construct.cpp", "c++"), ("api.cpp", "c++"), ("renorm.cpp", "c++"), ("host.cpp", "c++"),
                       ("kernels.hip", "hip"),
                       ("flow.hip", "hip"), ("mcmc.hip", "hip"), ("nsf.hip", "hip"), ("probe.hip", "hip")]:
         o = os.path.join(obj, src + ".o")

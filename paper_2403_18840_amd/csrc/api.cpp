@@ -142,7 +142,8 @@ dmc_status dmc_compile_graph(const dmc_graph_spec* spec, dmc_graph** out) {
     std::string err;
     try {
         if (!dmc::compile(spec->order, spec->deriv_mask, spec->taylor_order, spec->diagram_index, spec->part_size,
-                          spec->deriv_k, spec->routing, spec->spin_deg == 0 ? 2 : spec->spin_deg, g->c, err))
+                          spec->deriv_k, spec->routing, spec->spin_deg == 0 ? 2 : spec->spin_deg, spec->generation,
+                          g->c, err))
             return fail(DMC_E_INVALID, err);
         g->exported = dmc::export_text(g->c);
     } catch (const std::bad_alloc&) {
@@ -182,6 +183,7 @@ dmc_status dmc_graph_query(const dmc_graph* g, dmc_graph_info* o) {
     o->deriv_k = g->c.deriv_k;
     o->routing = g->c.routing;
     o->spin_deg = g->c.spin_deg;
+    o->generation = g->c.generation;
     return DMC_OK;
 }
 

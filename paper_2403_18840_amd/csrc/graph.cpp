@@ -1142,7 +1142,7 @@ struct Builder {
 int default_part_size(int n_diagrams, int n_roots);
 
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             int routing, int spin_deg, Compiled& out, std::string& err) {
+             int routing, int spin_deg, int generation, Compiled& out, std::string& err) {
     if (order < 1 || order > kMaxOrder) {
         err = "order must be in 1..6";
         return false;
@@ -1167,10 +1167,15 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
         err = "spin_deg must be 1 or 2";
         return false;
     }
+    if (generation != 0 && generation != 1) {
+        err = "generation must be 0 (enumeration) or 1 (construction)";
+        return false;
+    }
     out = Compiled{};
     out.deriv_k = deriv_k;
     out.routing = routing;
     out.spin_deg = spin_deg;
+    out.generation = generation;
     out.order = order;
     out.dim = 4 * order - 1;
     out.deriv_mask = deriv_mask;
@@ -1178,7 +1183,14 @@ bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index
     const CoefSet cs = taylor_order > 0 ? CoefSet::taylor(deriv_mask, taylor_order) : CoefSet::first_order(deriv_mask);
     out.root_orders = cs.idx;
     out.n_roots = (int)cs.idx.size();
-    out.diagrams = enumerate_sigma(order);
+    if (generation == 1) {
+        std::vector<std::vector<int>> sigmas;
+        if (!construct_sigma(order, sigmas, err)) return false;
+        out.diagrams.clear();
+        for (auto& sg : sigmas) out.diagrams.push_back(route(sg));
+    } else {
+        out.diagrams = enumerate_sigma(order);
+    }
     if (spin_deg == 1)  // spinless: each closed fermion loop gives its sign only
         for (auto& d : out.diagrams) d.weight = (order + d.n_fermion_loops) % 2 ? -1.0 : 1.0;
     if (routing == 1) {

@@ -34,6 +34,10 @@ struct Diagram {
 // order n in canonical labelling, routed.
 std::vector<Diagram> enumerate_sigma(int n);
 
+// The canonical permutations of the order-n self-energies built bottom-up from the Dyson-Schwinger and parquet
+// equations (every diagram exactly once, sorted); false with a message on an inconsistency.
+bool construct_sigma(int n, std::vector<std::vector<int>>& out, std::string& err);
+
 // The same diagram with its interaction lines and loop momenta taken from its building blocks
 // (self-energy, dressed line, three- and four-point vertices, parquet channels); false with a
 // message when the decomposition fails.
@@ -65,6 +69,7 @@ struct Compiled {
     int deriv_k = 0;    // derivative roots only at the first deriv_k external momenta (0: at all of them)
     int routing = 0;    // 0 path routing, 1 building-block variables
     int spin_deg = 2;   // factor per closed fermion loop
+    int generation = 0; // 0 orderly enumeration, 1 bottom-up construction
     std::vector<Diagram> diagrams;
     CodeStats stats;
 };
@@ -77,8 +82,9 @@ struct Compiled {
 // routing 0: loop momenta on chords next to the external momentum's shortest path; 1: from the building
 // blocks of the diagram (relabel_building_blocks), k on the shortest path.
 // spin_deg: the factor of each closed fermion loop (2 for spin 1/2, 1 for spinless fermions).
+// generation 0: the orderly enumeration; 1: the bottom-up construction (construct_sigma).
 bool compile(int order, uint32_t deriv_mask, int taylor_order, int diagram_index, int part_size, int deriv_k,
-             int routing, int spin_deg, Compiled& out, std::string& err);
+             int routing, int spin_deg, int generation, Compiled& out, std::string& err);
 
 // Device source for the evaluation kernel specialised to `n_groups` lambda groups.
 std::string emit_eval_source(const Compiled& c, int n_groups, CodeStats* stats);

@@ -422,3 +422,19 @@ def test_spinless_integrand_per_sample(n, N, K):
         ref = ig.integrand(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
         tol, _ = ig.fp32_tolerance(x64, n, kk, BETA, MU, LAM, gamma, diagrams=dgs)
         assert np.all(np.abs(f[0, 0, j] - ref) <= tol), f"k={k}"
+
+
+@pytest.mark.parametrize("n,N,K", [(3, 400, 4), (5, 200, 2)])
+def test_constructed_graph_per_sample(n, N, K):
+    """A graph whose diagram list comes from the bottom-up construction (spec.generation = 1, another order of the
+    same diagrams, so another kernel) per sample against the oracle."""
+    x = parity_points(n, N, seed=970 + n)
+    ks = synth.k_grid(K)
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, generation=dmc.GENERATE_CONSTRUCT)
+    f, _, _ = gpu_integrand(g, x, ks, [(BETA, MU, LAM, gamma)])
+    x64 = x.astype(np.float64)
+    for j, k in enumerate(ks):
+        ref = _oracle_f(x, n, k, LAM, gamma)
+        tol, _ = ig.fp32_tolerance(x64, n, float(np.float32(k)), BETA, MU, LAM, gamma, diagrams=oracle_diagrams(n))
+        assert np.all(np.abs(f[0, 0, j] - ref) <= tol), f"k={k}"

@@ -183,3 +183,15 @@ def test_spin_degeneracy_weights():
         assert one == {(s, (-1.0) ** (n + loops[s]), e, l) for s, w, e, l in two}
     with pytest.raises(dmc.DmcError):
         dmc.Graph(2, spin_deg=3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_bottom_up_construction_equals_enumeration(n):
+    """spec.generation = DMC_GENERATE_CONSTRUCT: the library's Dyson-Schwinger/parquet construction gives the same
+    diagrams, signs and routing as its orderly enumeration (and so as the oracle's brute force)."""
+    g = dmc.Graph(n, generation=dmc.GENERATE_CONSTRUCT)
+    assert g.info().generation == 1 and g.info().n_diagrams == len(oracle_diagrams(n))
+    assert _parse_export(g.export(), n) == _parse_export(dmc.Graph(n).export(), n)
+    if n == 2:
+        with pytest.raises(dmc.DmcError):
+            dmc.Graph(2, generation=2)
