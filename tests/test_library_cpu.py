@@ -195,3 +195,10 @@ def test_bottom_up_construction_equals_enumeration(n):
     if n == 2:
         with pytest.raises(dmc.DmcError):
             dmc.Graph(2, generation=2)
+
+
+def test_constructed_graph_compiles_to_the_same_kernel():
+    """The graph builder does not depend on the order of the diagram list: the bottom-up construction's graph emits
+    the same kernel source as the enumeration's."""
+    for n in (3, 5):
+        assert dmc.Graph(n, generation=dmc.GENERATE_CONSTRUCT).source(1) == dmc.Graph(n).source(1)
