@@ -1563,11 +1563,14 @@ struct EvalArgs {
         // every part is a function of its own (never inlined): the compiler allocates registers and
         // schedules each part alone, so compile time and register use grow with the part, not
         // with the whole graph.  in: this lane's inputs (stride 64); st: this lane's stage column.
+        s << "typedef __attribute__((address_space(3))) float LdsF;\n";
         for (size_t pi = 0; pi < pc.size(); ++pi) {
             const std::string tg = "p" + std::to_string(pi) + "_";
             s << "\n// part " << pi << " (" << parts[pi].size() << " diagrams)\n";
+            // the inputs and the stage live in LDS: typed as such, the part reads and writes them with ds_
+            // instructions instead of flat ones (a flat access waits on both the vector-memory and LDS counters)
             s << "__device__ __attribute__((noinline)) void dmc_part_" << pi
-              << "(const EvalArgs* __restrict__ ap, const float* __restrict__ in, float* __restrict__ st, const int kb, "
+              << "(const EvalArgs* __restrict__ ap, const LdsF* __restrict__ in, LdsF* __restrict__ st, const int kb, "
                  "const int nkc, const int grp, const int ml) {\n";
             s << "    const float MU = ap->mu, BL = ap->bl, BLMU = ap->blmu, BETA = ap->beta;\n";
             s << "    (void)MU; (void)BL; (void)BLMU; (void)BETA;\n";
@@ -1736,7 +1739,7 @@ struct EvalArgs {
                 for (int i = 0; i < nsl; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
         for (size_t pi = 0; pi < pc.size(); ++pi)
-            s << "                dmc_part_" << pi << "(&a, cin, stage + lane, kb, nkc, grp, ml);\n";
+            s << "                dmc_part_" << pi << "(&a, (const LdsF*)cin, (LdsF*)(stage + lane), kb, nkc, grp, ml);\n";
         s << "                for (int kq = 0; kq < nkc; ++kq) {\n";
         s << "                    const int ki = kb + kq;\n";
         s << "                    const int row = kq < ml ? kq * SPK1 : ml * SPK1 + (kq - ml) * 2;\n";

@@ -88,7 +88,7 @@ def test_partitioned_graphs():
     assert i.n_parts == 5 and i.part_size == 40
     src = g.source(1)
     assert "_p5" in src and src.count("// part ") == 5
-    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, cin, stage + lane, kb, nkc, grp, ml);" in src
+    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, (const LdsF*)cin, (LdsF*)(stage + lane), kb, nkc, grp, ml);" in src
     # every diagram lands in exactly one part
     import re
     sizes = [int(m) for m in re.findall(r"// part \d+ \((\d+) diagrams\)", src)]
