@@ -1570,8 +1570,12 @@ struct EvalArgs {
             // the inputs and the stage live in LDS: typed as such, the part reads and writes them with ds_
             // instructions instead of flat ones (a flat access waits on both the vector-memory and LDS counters)
             s << "__device__ __attribute__((noinline)) void dmc_part_" << pi
-              << "(const EvalArgs* __restrict__ ap, const LdsF* __restrict__ in, LdsF* __restrict__ st, const int kb, "
-                 "const int nkc, const int grp, const int ml) {\n";
+              << "(const EvalArgs* __restrict__ ap, const LdsF* __restrict__ in, LdsF* __restrict__ st, "
+                 "const LdsF* __restrict__ kl, const int kb_, const int nkc_, const int grp_, const int ml_) {\n";
+            // a device function receives its arguments in vector registers; the chunk and group indices are the same
+            // in every lane, and saying so keeps the momentum loop and its branches scalar
+            s << "    const int kb = __builtin_amdgcn_readfirstlane(kb_), nkc = __builtin_amdgcn_readfirstlane(nkc_);\n";
+            s << "    const int grp = __builtin_amdgcn_readfirstlane(grp_), ml = __builtin_amdgcn_readfirstlane(ml_);\n";
             s << "    const float MU = ap->mu, BL = ap->bl, BLMU = ap->blmu, BETA = ap->beta;\n";
             s << "    (void)MU; (void)BL; (void)BLMU; (void)BETA;\n";
             s << "    const float LAM0 = ap->lam[grp];\n";
@@ -1591,7 +1595,9 @@ struct EvalArgs {
             // the part's k-independent values are computed once and serve every momentum of the chunk
             s << "    for (int kq = 0; kq < nkc; ++kq) {\n";
             s << "        const int ki = kb + kq;\n";
-            s << "        const float kk = ap->k[ki];\n";
+            // the momentum comes from the block's LDS copy (one broadcast ds_ load), where ap, the kernel's
+            // private copy of its arguments, would cost a flat load and a full wait on every pass
+            s << "        const float kk = kl[ki];\n";
             s << "        const int row = kq < ml ? kq * SPK1 : ml * SPK1 + (kq - ml) * 2;  // this momentum's stage rows\n";
             s << "        (void)ki;\n";
             indent(s, pc[pi].loop, "    ");
@@ -1618,8 +1624,13 @@ struct EvalArgs {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 )K";
-    if (split)
+    if (split) {
         s << "    const int ML0 = KD ? min(KD, a.kc) : a.kc, SFL = ML0 * SPK1 + (a.kc - ML0) * 2;\n";
+        // the external momenta, copied once per block into LDS for the parts (every thread reaches the barrier)
+        s << "    __shared__ float kl_s[64];\n";
+        s << "    if ((int)threadIdx.x < a.n_k) kl_s[threadIdx.x] = a.k[threadIdx.x];\n";
+        s << "    __syncthreads();\n";
+    }
     s << R"K(    float* stage = smem + wv * )K" << sfw << R"K(;
     double* tot = (double*)(smem + 4 * )K" << sfw << R"K() + wv * (2 * a.s_total);
     for (int i = lane; i < 2 * a.s_total; i += 64) tot[i] = 0.0;
@@ -1739,7 +1750,7 @@ struct EvalArgs {
                 for (int i = 0; i < nsl; ++i) stage[i * 64 + lane] = 0.0f;
 )K";
         for (size_t pi = 0; pi < pc.size(); ++pi)
-            s << "                dmc_part_" << pi << "(&a, (const LdsF*)cin, (LdsF*)(stage + lane), kb, nkc, grp, ml);\n";
+            s << "                dmc_part_" << pi << "(&a, (const LdsF*)cin, (LdsF*)(stage + lane), (const LdsF*)kl_s, kb, nkc, grp, ml);\n";
         s << "                for (int kq = 0; kq < nkc; ++kq) {\n";
         s << "                    const int ki = kb + kq;\n";
         s << "                    const int row = kq < ml ? kq * SPK1 : ml * SPK1 + (kq - ml) * 2;\n";

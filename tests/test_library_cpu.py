@@ -88,7 +88,11 @@ def test_partitioned_graphs():
     assert i.n_parts == 5 and i.part_size == 40
     src = g.source(1)
     assert "_p5" in src and src.count("// part ") == 5
-    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, (const LdsF*)cin, (LdsF*)(stage + lane), kb, nkc, grp, ml);" in src
+    assert src.count("__attribute__((noinline)) void dmc_part_") == 5 and "dmc_part_4(&a, (const LdsF*)cin, (LdsF*)(stage + lane), (const LdsF*)kl_s, kb, nkc, grp, ml);" in src
+    # the parts read the momenta from the block's LDS copy; a device function has no kernel-argument pointer
+    # of its own (the compiler gives it a null base), so the parts must never ask for one
+    assert src.count("const float kk = kl[ki];") == 5 and "kernarg_segment_ptr" not in src
+    assert src.count("__builtin_amdgcn_readfirstlane(kb_)") == 5
     # every diagram lands in exactly one part
     import re
     sizes = [int(m) for m in re.findall(r"// part \d+ \((\d+) diagrams\)", src)]
