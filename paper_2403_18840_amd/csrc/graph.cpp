@@ -1378,7 +1378,8 @@ int default_part_size(int n_diagrams, int n_roots) {
     // and runs once per chunk of momenta) and leaf-grown parts.  Per 2^22 samples x 32 k: order 5 in one part
     // 3.1 ms, in 3 parts 5.0 ms; order 6 in parts of 1600, 2400, 3200 diagrams 32.4, 31.7, 33.6 ms (sorted, not
     // grown: 37.1 ms at 1600).  The order-6 d/dk graph at k_F with 3 lambda groups and 33 k, per 2^26 samples:
-    // 1697, 1603, 1684 ms (sorted, not grown: 1881 ms at 1600).  Bigger parts evaluate fewer leaves twice; past
+    // 1697, 1603, 1684 ms (sorted, not grown: 1881 ms at 1600); with the momentum loop in scalar control, parts
+    // of 2000, 2400, 2800 diagrams: 1433, 1414, 1418 ms.  Bigger parts evaluate fewer leaves twice; past
     // ~2400 diagrams their register pressure costs more.  More roots (derivative or Taylor coefficients) multiply
     // a part's live values: parts shrink as R^1.5.
     const double base = 2400.0;
