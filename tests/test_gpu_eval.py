@@ -380,6 +380,28 @@ def test_limits_and_degenerate_batches():
     assert a.read()[1] == 0
 
 
+def test_partitioned_kernel_at_the_largest_shape():
+    """The kernel in parts at DMC_MAX_K = 64 momenta and DMC_MAX_GROUPS = 8 lambda groups (order 2 cut into its
+    3 one-diagram parts), per sample against the oracle on a ragged batch of 257 samples: the block's LDS copy of
+    the momenta is filled to its last entry, and every part reads the last momentum and the last group."""
+    n, N = 2, 257
+    x = synth.loop_points(n, N, seed=43)
+    ks = synth.k_grid(64)
+    lams = [0.25 * (i + 1) for i in range(8)]
+    gamma = ph.coupling(1.0)
+    g = dmc.Graph(n, part_size=1)
+    assert g.info().n_parts == 3
+    f, acc, _ = gpu_integrand(g, x, ks, [(BETA, MU, lam, gamma) for lam in lams])
+    x64 = x.astype(np.float64)
+    for gi, lam in enumerate(lams):
+        for j in list(range(0, 64, 9)) + [63]:
+            k = float(np.float32(ks[j]))
+            ref = ig.integrand(x64, n, k, BETA, MU, lam, gamma, diagrams=oracle_diagrams(n))
+            tol, _ = ig.fp32_tolerance(x64, n, k, BETA, MU, lam, gamma, diagrams=oracle_diagrams(n))
+            assert np.all(np.abs(f[gi, 0, j] - ref) <= tol), (lam, k)
+    assert acc.read()[1] == N
+
+
 @pytest.mark.parametrize("part,kd", [(0, 0), (1, 2)])
 def test_importance_roots_setting(part, kd):
     """imp_out sums |f J| over the graph's leading importance roots: the value alone by default, every root after
